@@ -1,0 +1,76 @@
+/*
+ * CPU FP64 oracle of the explicit step of the PVD phase-field model
+ * (Materials and Methods, "Phase-field modeling of physical vapor
+ * deposition"; the three evolution equations for c, phi and rho).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This code exists to check the GPU library.
+ * Only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark may load it; the product path never does.  It shares no code,
+ * header, table or constant with the GPU library.
+ *
+ * Everything is double precision, single realisation at a time, plain
+ * loops over cells in the order the equations state them.  Fields are
+ * stored [batch][ny][nx], x fastest; x is periodic; j = 0 is next to the
+ * substrate and j = ny-1 next to the vapour inlet.
+ */
+#ifndef PF_ORACLE_H
+#define PF_ORACLE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum { OR_BC_PVD = 0, OR_BC_PERIODIC = 1 };
+
+typedef struct or_params {
+    int32_t nx, ny, batch;
+    int32_t bc_mode;   /* OR_BC_PVD or OR_BC_PERIODIC */
+    int32_t flux_on;   /* 0: incident vapour velocity v = 0 */
+    int32_t pad0;
+    uint64_t seed;
+    double h, dt;
+    /* free energy: double wells and gradient energies */
+    double W_c, W_phi, kappa_c, kappa_phi;
+    /* composition mobility M_c(phi, c) and order-parameter mobility */
+    double MA_bulk, MB_bulk, MA_surf, MB_surf, sigma_surf, M_phi, M_scale;
+    /* vapour transport */
+    double D_rho, v0, theta_deg, rho_in;
+    /* initial condition */
+    double c0, c_noise, film_h;
+} or_params;
+
+/* Frozen-coefficient explicit-Euler stability bound; vmax is the largest
+ * incident speed over the batch.  Returns 0, or -1 on bad parameters. */
+int or_dt_limit(const or_params* p, double vmax, double* dt_lim);
+
+/* SplitMix64: the (n+1)-th output of the generator started at `seed`. */
+uint64_t or_splitmix64(uint64_t seed, uint64_t n);
+
+/* Seeded initial condition for every realisation.  c0_per: [batch] mean
+ * compositions, or NULL for p->c0. */
+void or_init(const or_params* p, const double* c0_per,
+             double* c, double* phi, double* rho);
+
+/* Chemical potentials and composition mobility of one realisation. */
+void or_potentials(const or_params* p, const double* c, const double* phi,
+                   double* mu_c, double* mu_phi, double* Mc);
+
+/* n explicit Euler steps of every realisation, in place.  v0_per: [batch]
+ * incident speeds, or NULL for p->v0.  Q: [batch] cumulative inflow. */
+void or_step_n(const or_params* p, const double* v0_per, int64_t n,
+               double* c, double* phi, double* rho, double* Q);
+
+/* out[b][4] = h^2 sum c, h^2 sum phi, h^2 sum rho, Q[b]. */
+void or_mass(const or_params* p, const double* c, const double* phi,
+             const double* rho, const double* Q, double* out);
+
+/* out[b] = discrete free energy F_h of realisation b. */
+void or_energy(const or_params* p, const double* c, const double* phi,
+               double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
