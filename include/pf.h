@@ -1,0 +1,158 @@
+/*
+ * pf.h - C ABI of the MI355X (gfx950) explicit PVD phase-field stepper.
+ *
+ * The library advances the phase-field model of physical vapour deposition
+ * stated in the paper's Materials and Methods ("Phase-field modeling of
+ * physical vapor deposition"): a Cahn-Hilliard equation for the composition
+ * c with mobility M_c = M^Bulk + M^Surf, a Cahn-Hilliard equation with the
+ * deposition source S = grad(phi).(rho v) for the order parameter phi
+ * (solid +1, vapour -1), and convection-diffusion of the vapour density rho
+ * with the matching sink -S.  Spatial derivatives are second-order central
+ * differences (Materials and Methods, "Dataset"); time stepping is explicit
+ * Euler.  The readings where the paper defers to another reference or is
+ * garbled (free energy, switching function, surface mobility, boundary
+ * conditions, stability limit) are listed with the parameter struct below.
+ *
+ * Memory: all field buffers are caller-owned device memory (for example
+ * torch tensors), contiguous [batch][ny][nx] with x fastest, element type
+ * float (PF_F32) or double (PF_F64), 16-byte aligned.  The caller also
+ * provides a device workspace of pf_workspace_bytes() bytes, 256-byte
+ * aligned.  The library never allocates or frees device memory; a handle
+ * owns only host-side metadata.  All host arrays passed in are read during
+ * the call and not retained.
+ *
+ * Streams: every device operation of a handle is enqueued on the stream
+ * given to pf_init (a hipStream_t passed as void*; NULL is the default
+ * stream).  pf_step_n returns without waiting; pf_mass and pf_energy wait
+ * for the stream.  One handle per stream; a handle is not thread-safe.
+ *
+ * Errors: every int-returning call returns PF_OK (0) or a negative code.
+ * Argument errors are detected before anything is enqueued.  No C++
+ * exception crosses this interface.
+ */
+#ifndef PF_H
+#define PF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pf_handle pf_handle;
+
+enum pf_status {
+    PF_OK = 0,
+    PF_EINVAL = -1,      /* null/misaligned pointer, bad shape, bad enum, bad n */
+    PF_EUNSTABLE = -2,   /* dt above the stability limit and allow_unstable == 0 */
+    PF_ENONFINITE = -3,  /* a diagnostic came out NaN or infinite */
+    PF_EDEVICE = -4      /* a HIP call failed; see pf_last_hip_error */
+};
+
+enum pf_precision { PF_F32 = 0, PF_F64 = 1 };
+enum pf_bc { PF_BC_PVD = 0, PF_BC_PERIODIC = 1 };
+enum pf_init_mode { PF_INIT_SEEDED = 0, PF_INIT_KEEP = 1 };
+
+/*
+ * Problem definition.  Units are dimensionless, as in the paper's dataset.
+ *
+ * Model readings (the paper gives no expression for these):
+ *   free energy density f = W_c p(phi) g(c) + (W_phi/4)(1 - phi^2)^2 with
+ *     p(phi) = (2 - phi)(1 + phi)^2 / 4 and g(c) = c^2 (1 - c)^2, plus
+ *     (kappa_c/2)|grad c|^2 + (kappa_phi/2)|grad phi|^2;
+ *   M_c = M_scale [ p(phi~)(H MA_bulk + (1-H) MB_bulk)
+ *                   + exp(-(phi~/sigma_surf)^2)(H MA_surf + (1-H) MB_surf) ]
+ *     with H = x^3 (6x^2 - 15x + 10), x = clamp(c,0,1), phi~ = clamp(phi,-1,1)
+ *     (the paper's M^Surf subtracts itself; that trailing term is dropped);
+ *   phi mobility M_phi constant; face mobilities are arithmetic means;
+ *   v = v0 (cos theta, -sin theta), theta in degrees from the substrate;
+ *   PF_BC_PVD: x periodic; mirror ghosts for c and phi at the substrate
+ *     (j = 0) and the top (j = ny-1); rho has no flux through the substrate
+ *     and the fixed value rho_in above the top row (vapour inlet);
+ *   PF_BC_PERIODIC: periodic in x and y, no inlet (a test mode).
+ */
+typedef struct pf_params {
+    int32_t nx, ny, batch;        /* grid cells and independent realisations */
+    int32_t precision;            /* pf_precision: storage and arithmetic type */
+    int32_t bc_mode;              /* pf_bc */
+    int32_t flux_on;              /* 0: v = 0 (no deposition, no advection) */
+    int32_t init_mode;            /* pf_init_mode */
+    int32_t allow_unstable;       /* 1: accept dt above the stability limit */
+    int32_t temporal_block;       /* steps fused per launch (1..4); 0: library's choice */
+    int32_t reserved0;
+    uint64_t seed;                /* seeded initial condition: realisation b uses seed + b */
+    double h;                     /* grid spacing */
+    double dt;                    /* time step; <= 0 means dt_factor * stability limit */
+    double dt_factor;             /* used when dt <= 0 (0.2 in the standard workloads) */
+    double W_c, W_phi, kappa_c, kappa_phi;
+    double MA_bulk, MB_bulk, MA_surf, MB_surf, sigma_surf, M_phi, M_scale;
+    double D_rho, v0, theta_deg, rho_in;
+    double c0, c_noise, film_h;   /* initial condition; film_h <= 0 means ny h / 8 */
+    const double* v0_per;         /* host [batch] incident speeds, or NULL for v0 */
+    const double* c0_per;         /* host [batch] mean compositions, or NULL for c0 */
+} pf_params;
+
+/* Bytes of device workspace a handle for *p needs (ping-pong copy of the
+ * state, per-column FP64 inflow accumulators, per-realisation constants,
+ * FP64 reduction partials).  Returns 0 if *p is invalid. */
+size_t pf_workspace_bytes(const pf_params* p);
+
+/* Explicit-Euler stability limit of *p on the host, in FP64:
+ * min(dt_c, dt_phi, dt_rho, dt_adv) of the frozen-coefficient von Neumann
+ * bounds with the 5-point symbol at most 8/h^2 (see the model readings).
+ * The largest of v0 / v0_per enters dt_adv.  PF_EINVAL on bad input. */
+int pf_dt_limit(const pf_params* p, double* dt_lim);
+
+/* Create a handle that steps the caller's buffers c, phi, rho in place.
+ * PF_INIT_SEEDED writes the seeded initial condition (c = c0 + c_noise
+ * (2U - 1) from SplitMix64, a flat tanh film of height film_h, rho =
+ * rho_in (1 - phi)/2); PF_INIT_KEEP takes the buffers' contents as the
+ * initial condition.  The inflow accumulators and the step counter start at
+ * zero.  workspace_bytes must be at least pf_workspace_bytes(p).  On
+ * success *out receives a handle to release with pf_destroy. */
+int pf_init(pf_handle** out, const pf_params* p, void* c, void* phi, void* rho,
+            void* workspace, size_t workspace_bytes, void* stream);
+
+/* Enqueue n >= 0 explicit Euler steps of every realisation.  When the
+ * stream reaches the end of this work, the new state is in the caller's
+ * buffers.  Returns without waiting. */
+int pf_step_n(pf_handle* h, int64_t n);
+
+/* Wait for the stream, then write out[4*b + k] for each realisation b:
+ * k = 0..2 the masses h^2 sum c, h^2 sum phi, h^2 sum rho, and k = 3 the
+ * cumulative vapour inflow Q through the top face.  Sums are accumulated in
+ * FP64 in a fixed order (deterministic).  PF_ENONFINITE if any is not
+ * finite. */
+int pf_mass(pf_handle* h, double* out);
+
+/* Wait for the stream, then write out[b] = discrete free energy
+ * F_h = h^2 sum f(c, phi) + (kappa_c/2) sum_faces (dc)^2
+ *       + (kappa_phi/2) sum_faces (dphi)^2 in FP64 (all x faces, interior y
+ * faces, plus the wrap faces in PF_BC_PERIODIC).  PF_ENONFINITE if any is
+ * not finite. */
+int pf_energy(pf_handle* h, double* out);
+
+/* Step counter and time step of a handle (resume support). */
+int pf_get_step(const pf_handle* h, int64_t* step);
+int pf_set_step(pf_handle* h, int64_t step);
+int pf_get_dt(const pf_handle* h, double* dt);
+
+/* Cumulative inflow per realisation: pf_get_inflow waits for the stream and
+ * writes Q[b]; pf_set_inflow enqueues Q[b] as the new cumulative value. */
+int pf_get_inflow(pf_handle* h, double* Q);
+int pf_set_inflow(pf_handle* h, const double* Q);
+
+/* Release a handle (host memory only; the caller's buffers are untouched). */
+void pf_destroy(pf_handle* h);
+
+/* Text of a pf_status code. */
+const char* pf_strerror(int code);
+
+/* Last HIP error code recorded by the handle (0 if none). */
+int pf_last_hip_error(const pf_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

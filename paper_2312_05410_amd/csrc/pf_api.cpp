@@ -1,0 +1,453 @@
+// C-ABI host code of the MI355X phase-field stepper (declared in pf.h).
+//
+// Validation happens before anything is enqueued.  The library never
+// allocates device memory: the state lives in the caller's buffers and the
+// ping-pong copy, inflow accumulators and reduction partials live in the
+// caller's workspace.
+#include "../../include/pf.h"
+#include "pf_kernels.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t round_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+struct Layout {
+    size_t state[3];
+    size_t qcol, real, c0, qstage, partials, results, total;
+};
+
+size_t esize(const pf_params* p) { return p->precision == PF_F64 ? 8 : 4; }
+
+Layout layout(const pf_params* p)
+{
+    Layout L{};
+    const size_t B = (size_t)p->batch, cells = (size_t)p->nx * (size_t)p->ny;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += round_up(bytes);
+        return o;
+    };
+    for (int f = 0; f < 3; ++f) L.state[f] = take(B * cells * esize(p));
+    L.qcol = take(B * (size_t)p->nx * sizeof(double));
+    L.real = take(B * sizeof(pfk::Real));
+    L.c0 = take(B * sizeof(double));
+    L.qstage = take(B * sizeof(double));
+    L.partials = take(B * (size_t)pfk::kRedBlocks * 4 * sizeof(double));
+    L.results = take(B * 5 * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+bool finite_all(std::initializer_list<double> v)
+{
+    for (double x : v)
+        if (!std::isfinite(x)) return false;
+    return true;
+}
+
+int validate(const pf_params* p)
+{
+    if (!p) return PF_EINVAL;
+    if (p->nx < 1 || p->ny < 1 || p->batch < 1 || p->batch > 65535) return PF_EINVAL;
+    if ((int64_t)p->nx * p->ny > (int64_t)1 << 31) return PF_EINVAL;
+    if (p->precision != PF_F32 && p->precision != PF_F64) return PF_EINVAL;
+    if (p->bc_mode != PF_BC_PVD && p->bc_mode != PF_BC_PERIODIC) return PF_EINVAL;
+    if (p->init_mode != PF_INIT_SEEDED && p->init_mode != PF_INIT_KEEP) return PF_EINVAL;
+    if (p->temporal_block < 0 || p->temporal_block > (p->precision == PF_F64 ? 2 : 4)) return PF_EINVAL;
+    if (!finite_all({p->h, p->dt, p->dt_factor, p->W_c, p->W_phi, p->kappa_c, p->kappa_phi, p->MA_bulk,
+                     p->MB_bulk, p->MA_surf, p->MB_surf, p->sigma_surf, p->M_phi, p->M_scale, p->D_rho,
+                     p->v0, p->theta_deg, p->rho_in, p->c0, p->c_noise, p->film_h}))
+        return PF_EINVAL;
+    if (!(p->h > 0) || !(p->sigma_surf > 0)) return PF_EINVAL;
+    if (p->MA_bulk < 0 || p->MB_bulk < 0 || p->MA_surf < 0 || p->MB_surf < 0 || p->M_phi < 0 ||
+        p->M_scale < 0 || p->D_rho < 0 || p->kappa_c < 0 || p->kappa_phi < 0)
+        return PF_EINVAL;
+    if (p->dt <= 0 && !(p->dt_factor > 0)) return PF_EINVAL;
+    if (p->init_mode == PF_INIT_SEEDED && !(p->W_phi > 0)) return PF_EINVAL;
+    for (int b = 0; b < p->batch; ++b) {
+        if (p->v0_per && !std::isfinite(p->v0_per[b])) return PF_EINVAL;
+        if (p->c0_per && !std::isfinite(p->c0_per[b])) return PF_EINVAL;
+    }
+    return PF_OK;
+}
+
+double v0_of(const pf_params* p, int b) { return p->v0_per ? p->v0_per[b] : p->v0; }
+double c0_of(const pf_params* p, int b) { return p->c0_per ? p->c0_per[b] : p->c0; }
+
+// Frozen-coefficient von Neumann bound of explicit Euler with the 5-point
+// operators (symbol at most 8/h^2), taken term by term.
+double stability_limit(const pf_params* p)
+{
+    const double h2 = p->h * p->h, h4 = h2 * h2;
+    double lim = INFINITY;
+    const double mmax = p->M_scale * (std::max(p->MA_bulk, p->MB_bulk) + std::max(p->MA_surf, p->MB_surf));
+    if (mmax > 0) lim = std::min(lim, 2.0 * h4 / (8.0 * mmax * (2.0 * p->W_c * h2 + 8.0 * p->kappa_c)));
+    if (p->M_phi > 0)
+        lim = std::min(lim, 2.0 * h4 / (8.0 * p->M_phi * ((2.0 * p->W_phi + 3.0 * p->W_c / 32.0) * h2 + 8.0 * p->kappa_phi)));
+    if (p->D_rho > 0) lim = std::min(lim, h2 / (4.0 * p->D_rho));
+    if (p->flux_on) {
+        double vmax = 0;
+        for (int b = 0; b < p->batch; ++b) vmax = std::max(vmax, std::fabs(v0_of(p, b)));
+        if (vmax > 0) lim = std::min(lim, p->D_rho > 0 ? 2.0 * p->D_rho / (vmax * vmax) : p->h / vmax);
+    }
+    return lim;
+}
+
+bool aligned(const void* ptr, size_t a) { return ((uintptr_t)ptr % a) == 0; }
+
+}  // namespace
+
+struct pf_handle {
+    pf_params p{};
+    Layout L{};
+    void* f[3] = {nullptr, nullptr, nullptr};   // caller's c, phi, rho
+    void* w[3] = {nullptr, nullptr, nullptr};   // workspace copies
+    char* ws = nullptr;
+    hipStream_t stream = nullptr;
+    double dt = 0;
+    int64_t step = 0;
+    int K = 1;
+    int last_hip = 0;
+    std::vector<pfk::Real> real;
+    std::vector<double> c0;
+    std::vector<double> host_out;
+    std::vector<double> stage;
+};
+
+namespace {
+
+int hip_fail(pf_handle* h, hipError_t e)
+{
+    if (e == hipSuccess) return PF_OK;
+    h->last_hip = (int)e;
+    return PF_EDEVICE;
+}
+
+template <typename T>
+pfk::Coef<T> make_coef(const pf_params* p, double dt)
+{
+    pfk::Coef<T> k{};
+    const double h2 = p->h * p->h;
+    k.Wc = (T)p->W_c;
+    k.Wphi = (T)p->W_phi;
+    k.kc = (T)(p->kappa_c / h2);
+    k.kp = (T)(p->kappa_phi / h2);
+    k.MBb = (T)(p->M_scale * p->MB_bulk);
+    k.dMb = (T)(p->M_scale * (p->MA_bulk - p->MB_bulk));
+    k.MBs = (T)(p->M_scale * p->MB_surf);
+    k.dMs = (T)(p->M_scale * (p->MA_surf - p->MB_surf));
+    const double inv_s2 = 1.0 / (p->sigma_surf * p->sigma_surf);
+    // float: exp(-x) = exp2(-x log2 e)
+    k.esurf = sizeof(T) == 4 ? (T)(inv_s2 * 1.4426950408889634074) : (T)inv_s2;
+    k.half_ih2 = (T)(0.5 / h2);
+    k.mphi_h2 = (T)(p->M_phi / h2);
+    k.D_h2 = (T)(p->D_rho / h2);
+    k.dt = (T)dt;
+    k.rho_in = (T)p->rho_in;
+    return k;
+}
+
+template <typename T>
+int enqueue_steps(pf_handle* h, int64_t n)
+{
+    const pf_params* p = &h->p;
+    const pfk::TileCfg cfg = pfk::tile_cfg<T>(h->K);
+    pfk::StepArgs<T> a{};
+    a.Qcol = (double*)(h->ws + h->L.qcol);
+    a.real = (const pfk::Real*)(h->ws + h->L.real);
+    a.k = make_coef<T>(p, h->dt);
+    a.nx = p->nx;
+    a.ny = p->ny;
+    a.tiles_x = (p->nx + cfg.tx - 1) / cfg.tx;
+    a.tiles_y = (p->ny + cfg.ty - 1) / cfg.ty;
+    a.pvd = p->bc_mode == PF_BC_PVD;
+
+    // Launch plan: blocks of K sub-steps; an even number of launches keeps
+    // the result in the caller's buffers, so split one block when possible.
+    const int K = h->K;
+    int64_t L = (n + K - 1) / K;
+    const int last_sub = (int)(n - (L - 1) * K);
+    int first_split = 0, last_split = 0;   // sub-steps of an extra leading/trailing launch
+    if (L % 2 == 1) {
+        if (last_sub >= 2) last_split = last_sub / 2;
+        else if (L >= 2 && K >= 2) first_split = K / 2;
+    }
+    auto launch = [&](int nsub, int parity) -> int {
+        void* const* src = parity == 0 ? h->f : h->w;
+        void* const* dst = parity == 0 ? h->w : h->f;
+        a.c = (const T*)src[0];
+        a.phi = (const T*)src[1];
+        a.rho = (const T*)src[2];
+        a.c_out = (T*)dst[0];
+        a.phi_out = (T*)dst[1];
+        a.rho_out = (T*)dst[2];
+        a.nsub = nsub;
+        return hip_fail(h, pfk::launch_step<T>(a, K, p->batch, h->stream));
+    };
+    int parity = 0, rc;
+    for (int64_t l = 0; l < L; ++l) {
+        int nsub = l + 1 < L ? K : last_sub;
+        if (l == 0 && first_split) {
+            if ((rc = launch(first_split, parity))) return rc;
+            parity ^= 1;
+            nsub -= first_split;
+        }
+        if (l + 1 == L && last_split) {
+            if ((rc = launch(last_split, parity))) return rc;
+            parity ^= 1;
+            nsub -= last_split;
+        }
+        if ((rc = launch(nsub, parity))) return rc;
+        parity ^= 1;
+    }
+    if (parity == 1) {
+        // odd number of single-step launches: copy the result back
+        const size_t bytes = (size_t)p->batch * p->nx * p->ny * sizeof(T);
+        for (int f = 0; f < 3; ++f)
+            if ((rc = hip_fail(h, hipMemcpyAsync(h->f[f], h->w[f], bytes, hipMemcpyDeviceToDevice, h->stream))))
+                return rc;
+    }
+    return PF_OK;
+}
+
+int run_reduce(pf_handle* h)
+{
+    const pf_params* p = &h->p;
+    pfk::RedArgs a{};
+    a.nx = p->nx;
+    a.ny = p->ny;
+    a.pvd = p->bc_mode == PF_BC_PVD;
+    a.h2 = p->h * p->h;
+    a.Wc = p->W_c;
+    a.Wphi = p->W_phi;
+    a.half_kc = 0.5 * p->kappa_c;
+    a.half_kp = 0.5 * p->kappa_phi;
+    double* partials = (double*)(h->ws + h->L.partials);
+    double* res = (double*)(h->ws + h->L.results);
+    const double* Qcol = (const double*)(h->ws + h->L.qcol);
+    const int nblk = std::min(pfk::kRedBlocks, p->ny);
+    hipError_t e;
+    if (p->precision == PF_F64)
+        e = pfk::launch_reduce<double>((const double*)h->f[0], (const double*)h->f[1], (const double*)h->f[2],
+                                       Qcol, partials, res, a, p->batch, nblk, h->stream);
+    else
+        e = pfk::launch_reduce<float>((const float*)h->f[0], (const float*)h->f[1], (const float*)h->f[2],
+                                      Qcol, partials, res, a, p->batch, nblk, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e);
+    h->host_out.resize((size_t)p->batch * 5);
+    e = hipMemcpyAsync(h->host_out.data(), res, h->host_out.size() * sizeof(double), hipMemcpyDeviceToHost,
+                       h->stream);
+    if (e != hipSuccess) return hip_fail(h, e);
+    e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e);
+    return PF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pf_workspace_bytes(const pf_params* p)
+{
+    if (validate(p) != PF_OK) return 0;
+    return layout(p).total;
+}
+
+int pf_dt_limit(const pf_params* p, double* dt_lim)
+{
+    if (!dt_lim || validate(p) != PF_OK) return PF_EINVAL;
+    const double lim = stability_limit(p);
+    if (!(lim > 0) || std::isinf(lim)) return PF_EINVAL;
+    *dt_lim = lim;
+    return PF_OK;
+}
+
+int pf_init(pf_handle** out, const pf_params* p, void* c, void* phi, void* rho, void* workspace,
+            size_t workspace_bytes, void* stream)
+{
+    if (!out) return PF_EINVAL;
+    *out = nullptr;
+    int rc = validate(p);
+    if (rc) return rc;
+    if (!c || !phi || !rho || !workspace) return PF_EINVAL;
+    if (!aligned(c, 16) || !aligned(phi, 16) || !aligned(rho, 16) || !aligned(workspace, kAlign))
+        return PF_EINVAL;
+    const Layout L = layout(p);
+    if (workspace_bytes < L.total) return PF_EINVAL;
+    const double lim = stability_limit(p);
+    if (!(lim > 0) || std::isinf(lim)) return PF_EINVAL;
+    const double dt = p->dt > 0 ? p->dt : p->dt_factor * lim;
+    if (dt > lim * (1.0 + 1e-12) && !p->allow_unstable) return PF_EUNSTABLE;
+
+    pf_handle* h = new (std::nothrow) pf_handle;
+    if (!h) return PF_EINVAL;
+    h->p = *p;
+    h->p.v0_per = nullptr;
+    h->p.c0_per = nullptr;
+    h->L = L;
+    h->ws = (char*)workspace;
+    h->f[0] = c;
+    h->f[1] = phi;
+    h->f[2] = rho;
+    for (int f = 0; f < 3; ++f) h->w[f] = h->ws + L.state[f];
+    h->stream = (hipStream_t)stream;
+    h->dt = dt;
+    // fused steps per launch: requested, or 1; the mirror ghosts of a
+    // launch must be real rows, so 2K <= ny
+    int K = p->temporal_block > 0 ? p->temporal_block : 1;
+    while (K > 1 && 2 * K > p->ny) --K;
+    h->K = K;
+
+    const double th = p->theta_deg * (3.14159265358979323846 / 180.0);
+    h->real.resize(p->batch);
+    h->c0.resize(p->batch);
+    for (int b = 0; b < p->batch; ++b) {
+        const double v0 = p->flux_on ? v0_of(p, b) : 0.0;
+        const double vx = v0 * std::cos(th), vy = -v0 * std::sin(th);
+        h->real[b].vx2h = vx / (2.0 * p->h);
+        h->real[b].vy2h = vy / (2.0 * p->h);
+        h->real[b].qa = dt * p->h * (-0.5 * vy);
+        h->real[b].qb = dt * p->D_rho;
+        h->c0[b] = c0_of(p, b);
+    }
+    // pf_params says the per-realisation arrays are read during the call
+    hipError_t e = hipMemcpyAsync(h->ws + L.real, h->real.data(), p->batch * sizeof(pfk::Real),
+                                  hipMemcpyHostToDevice, h->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->ws + L.c0, h->c0.data(), p->batch * sizeof(double), hipMemcpyHostToDevice,
+                           h->stream);
+    if (e == hipSuccess) e = pfk::launch_set_inflow((double*)(h->ws + L.qcol), nullptr, p->nx, p->batch, h->stream);
+    if (e == hipSuccess && p->init_mode == PF_INIT_SEEDED) {
+        pfk::InitArgs ia{};
+        ia.seed = p->seed;
+        ia.nx = p->nx;
+        ia.ny = p->ny;
+        ia.h = p->h;
+        ia.c_noise = p->c_noise;
+        ia.H0 = p->film_h > 0 ? p->film_h : p->ny * p->h / 8.0;
+        ia.width = std::sqrt(2.0 * p->kappa_phi / p->W_phi);
+        ia.rho_in = p->rho_in;
+        ia.c0 = (const double*)(h->ws + L.c0);
+        if (p->precision == PF_F64)
+            e = pfk::launch_init<double>((double*)c, (double*)phi, (double*)rho, ia, p->batch, h->stream);
+        else
+            e = pfk::launch_init<float>((float*)c, (float*)phi, (float*)rho, ia, p->batch, h->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) {
+        h->last_hip = (int)e;
+        delete h;
+        return PF_EDEVICE;
+    }
+    *out = h;
+    return PF_OK;
+}
+
+int pf_step_n(pf_handle* h, int64_t n)
+{
+    if (!h || n < 0) return PF_EINVAL;
+    if (n == 0) return PF_OK;
+    const int rc = h->p.precision == PF_F64 ? enqueue_steps<double>(h, n) : enqueue_steps<float>(h, n);
+    if (rc == PF_OK) h->step += n;
+    return rc;
+}
+
+int pf_mass(pf_handle* h, double* out)
+{
+    if (!h || !out) return PF_EINVAL;
+    int rc = run_reduce(h);
+    if (rc) return rc;
+    bool ok = true;
+    for (int b = 0; b < h->p.batch; ++b)
+        for (int m = 0; m < 4; ++m) {
+            out[4 * b + m] = h->host_out[5 * b + m];
+            ok = ok && std::isfinite(out[4 * b + m]);
+        }
+    return ok ? PF_OK : PF_ENONFINITE;
+}
+
+int pf_energy(pf_handle* h, double* out)
+{
+    if (!h || !out) return PF_EINVAL;
+    int rc = run_reduce(h);
+    if (rc) return rc;
+    bool ok = true;
+    for (int b = 0; b < h->p.batch; ++b) {
+        out[b] = h->host_out[5 * b + 4];
+        ok = ok && std::isfinite(out[b]);
+    }
+    return ok ? PF_OK : PF_ENONFINITE;
+}
+
+int pf_get_step(const pf_handle* h, int64_t* step)
+{
+    if (!h || !step) return PF_EINVAL;
+    *step = h->step;
+    return PF_OK;
+}
+
+int pf_set_step(pf_handle* h, int64_t step)
+{
+    if (!h || step < 0) return PF_EINVAL;
+    h->step = step;
+    return PF_OK;
+}
+
+int pf_get_dt(const pf_handle* h, double* dt)
+{
+    if (!h || !dt) return PF_EINVAL;
+    *dt = h->dt;
+    return PF_OK;
+}
+
+int pf_get_inflow(pf_handle* h, double* Q)
+{
+    if (!h || !Q) return PF_EINVAL;
+    int rc = run_reduce(h);
+    if (rc) return rc;
+    for (int b = 0; b < h->p.batch; ++b) Q[b] = h->host_out[5 * b + 3];
+    return PF_OK;
+}
+
+int pf_set_inflow(pf_handle* h, const double* Q)
+{
+    if (!h || !Q) return PF_EINVAL;
+    for (int b = 0; b < h->p.batch; ++b)
+        if (!std::isfinite(Q[b])) return PF_EINVAL;
+    h->stage.assign(Q, Q + h->p.batch);
+    double* dq = (double*)(h->ws + h->L.qstage);
+    hipError_t e = hipMemcpyAsync(dq, h->stage.data(), h->p.batch * sizeof(double), hipMemcpyHostToDevice,
+                                  h->stream);
+    if (e == hipSuccess)
+        e = pfk::launch_set_inflow((double*)(h->ws + h->L.qcol), dq, h->p.nx, h->p.batch, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    return hip_fail(h, e);
+}
+
+void pf_destroy(pf_handle* h) { delete h; }
+
+const char* pf_strerror(int code)
+{
+    switch (code) {
+    case PF_OK: return "ok";
+    case PF_EINVAL: return "invalid argument";
+    case PF_EUNSTABLE: return "time step above the explicit stability limit";
+    case PF_ENONFINITE: return "non-finite diagnostic (state diverged or holds NaN/Inf)";
+    case PF_EDEVICE: return "HIP device error";
+    default: return "unknown pf status";
+    }
+}
+
+int pf_last_hip_error(const pf_handle* h) { return h ? h->last_hip : 0; }
+
+}  // extern "C"

@@ -1,0 +1,87 @@
+// Internal interface between the C-ABI host code and the gfx950 kernels.
+// Not part of the public ABI (that is include/pf.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pfk {
+
+// Model constants in the arithmetic type T of a launch, folded on the host
+// in FP64 (e.g. kappa/h^2) and rounded once to T.
+template <typename T>
+struct Coef {
+    T Wc, Wphi;        // double-well heights
+    T kc, kp;          // kappa_c / h^2, kappa_phi / h^2
+    T MBb, dMb;        // M_scale*MB_bulk, M_scale*(MA_bulk - MB_bulk)
+    T MBs, dMs;        // same for the surface mobilities
+    T esurf;           // 1/sigma^2 (double) or log2(e)/sigma^2 (float, exp2 form)
+    T half_ih2;        // 0.5 / h^2
+    T mphi_h2;         // M_phi / h^2
+    T D_h2;            // D_rho / h^2
+    T dt;
+    T rho_in;
+};
+
+// Per-realisation constants (device array, double): vx/(2h), vy/(2h),
+// and the two inflow weights dt*h*(-vy/2) and dt*D.
+struct Real {
+    double vx2h, vy2h, qa, qb;
+};
+
+template <typename T>
+struct StepArgs {
+    const T* c;
+    const T* phi;
+    const T* rho;
+    T* c_out;
+    T* phi_out;
+    T* rho_out;
+    double* Qcol;        // [B][nx] cumulative inflow per column
+    const Real* real;    // [B]
+    Coef<T> k;
+    int nx, ny;
+    int tiles_x, tiles_y;
+    int pvd;             // 1: substrate + inlet boundaries; 0: periodic in y
+    int nsub;            // sub-steps in this launch (1..K of the kernel)
+};
+
+// Tile configuration of a stepper instantiation.
+struct TileCfg {
+    int tx, ty, k, nthreads;
+};
+
+// Launch one stepper launch of `nsub` sub-steps with fused-step capacity k.
+// Returns hipSuccess or the launch error.
+template <typename T>
+hipError_t launch_step(const StepArgs<T>& a, int k, int batch, hipStream_t s);
+
+template <typename T>
+TileCfg tile_cfg(int k);
+
+// Seeded initial condition.
+struct InitArgs {
+    uint64_t seed;
+    int nx, ny;
+    double h, c_noise, H0, width, rho_in;
+    const double* c0;    // [B] device
+};
+template <typename T>
+hipError_t launch_init(T* c, T* phi, T* rho, const InitArgs& a, int batch, hipStream_t s);
+
+// Qcol[b][i] = (i == 0 ? q[b] : 0)  (q == nullptr: all zero)
+hipError_t launch_set_inflow(double* Qcol, const double* q, int nx, int batch, hipStream_t s);
+
+// Diagnostics: out[b*5 + {0..4}] = h^2 sum c, h^2 sum phi, h^2 sum rho, Q, F_h.
+struct RedArgs {
+    int nx, ny, pvd;
+    double h2, Wc, Wphi, half_kc, half_kp;
+};
+template <typename T>
+hipError_t launch_reduce(const T* c, const T* phi, const T* rho, const double* Qcol,
+                         double* partials, double* out, const RedArgs& a, int batch,
+                         int nblk, hipStream_t s);
+
+constexpr int kRedBlocks = 128;   // partial-sum blocks per realisation
+
+}  // namespace pfk

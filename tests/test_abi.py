@@ -1,0 +1,124 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/pf.h declares, its host-only entry points agree with
+the oracle, and argument errors are reported before anything is enqueued."""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2312_05410_amd import _lib
+from paper_2312_05410_amd.inputs import PFParams, uniform01
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "pf.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pf_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.load()
+    names = declared_functions()
+    assert len(names) >= 14
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(_lib.EXPORTS)
+
+
+def test_params_struct_layout():
+    # int32 x 10, uint64 seed at 40, 21 doubles, 2 pointers
+    assert _lib.PFParamsC.seed.offset == 40
+    assert _lib.PFParamsC.h.offset == 48
+    assert _lib.PFParamsC.v0_per.offset == 48 + 21 * 8
+    assert ctypes.sizeof(_lib.PFParamsC) == 48 + 21 * 8 + 16
+
+
+def test_strerror():
+    L = _lib.load()
+    for code in (0, -1, -2, -3, -4, 7):
+        assert L.pf_strerror(code)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_dt_limit_matches_oracle(seed):
+    """Random parameter sets exercise every field the stability rule reads
+    (also a check that the struct fields line up)."""
+    u = uniform01(100 + seed, np.arange(16))
+    p = PFParams(h=0.5 + u[0], W_c=0.2 + 2 * u[1], W_phi=0.2 + 2 * u[2], kappa_c=0.1 + 2 * u[3],
+                 kappa_phi=0.1 + 3 * u[4], MA_bulk=2 * u[5], MB_bulk=2 * u[6], MA_surf=6 * u[7],
+                 MB_surf=6 * u[8], M_phi=0.1 + u[9], M_scale=0.5 + u[10], D_rho=0.1 + u[11],
+                 v0=3 * u[12] + (5 if seed % 2 else 0), flux_on=seed != 4)
+    assert _lib.dt_limit(p) == pytest.approx(oracle.dt_limit(p), rel=1e-15)
+
+
+def test_dt_limit_batch_uses_fastest_realisation():
+    p = PFParams(batch=3, v0_per=np.array([0.5, 30.0, 1.0]))
+    assert _lib.dt_limit(p) == pytest.approx(2 * p.D_rho / 900.0, rel=1e-15)
+
+
+def test_workspace_bytes():
+    p = PFParams(nx=100, ny=60, batch=2, precision="f32")
+    n = _lib.workspace_bytes(p)
+    assert n >= 3 * 2 * 100 * 60 * 4 + 2 * 100 * 8
+    assert n % 256 == 0
+    assert _lib.workspace_bytes(p.replace(precision="f64")) > n
+
+
+def _init(p, ptrs=(4096, 8192, 12288), ws=1 << 20, wsize=None, **kw):
+    L = _lib.load()
+    s, keep = _lib.to_c(p, **kw)
+    h = ctypes.c_void_p()
+    n = wsize if wsize is not None else L.pf_workspace_bytes(ctypes.byref(s))
+    return L.pf_init(ctypes.byref(h), ctypes.byref(s), ptrs[0], ptrs[1], ptrs[2], ws, n, None), h
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=0), dict(ny=-3), dict(batch=0), dict(precision="f16"), dict(h=0.0), dict(sigma_surf=0.0),
+    dict(MA_bulk=-1.0), dict(D_rho=-0.1), dict(dt=0.0, dt_factor=0.0), dict(W_c=float("nan")),
+    dict(v0=float("inf")),
+])
+def test_init_rejects_bad_params(bad):
+    if bad.get("precision") == "f16":
+        with pytest.raises(KeyError):
+            _lib.to_c(PFParams(**bad))
+        return
+    rc, h = _init(PFParams(**bad))
+    assert rc == _lib.PF_EINVAL and not h.value
+
+
+def test_init_rejects_bad_pointers_and_workspace():
+    p = PFParams(nx=16, ny=16)
+    assert _init(p, ptrs=(0, 8192, 12288))[0] == _lib.PF_EINVAL
+    assert _init(p, ptrs=(4096 + 4, 8192, 12288))[0] == _lib.PF_EINVAL   # misaligned field
+    assert _init(p, ws=0)[0] == _lib.PF_EINVAL
+    assert _init(p, ws=4096 + 64)[0] == _lib.PF_EINVAL                   # workspace not 256-aligned
+    assert _init(p, wsize=1024)[0] == _lib.PF_EINVAL                      # workspace too small
+    assert _init(p, temporal_block=5)[0] == _lib.PF_EINVAL
+    assert _init(p.replace(precision="f64"), temporal_block=3)[0] == _lib.PF_EINVAL
+    L = _lib.load()
+    assert L.pf_step_n(None, 3) == _lib.PF_EINVAL
+    assert L.pf_mass(None, None) == _lib.PF_EINVAL
+
+
+def test_init_rejects_unstable_dt():
+    p = PFParams(nx=16, ny=16)
+    lim = oracle.dt_limit(p)
+    rc, _ = _init(p.replace(dt=1.01 * lim))
+    assert rc == _lib.PF_EUNSTABLE
+
+
+def test_product_path_has_no_oracle_import():
+    """The package never imports the oracle (test infrastructure only)."""
+    pkg = os.path.join(ROOT, "paper_2312_05410_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "pf_oracle" not in text, f

@@ -1,0 +1,302 @@
+"""GPU parity of the HIP stepper (through the C ABI) against the FP64 oracle.
+
+Tolerances: FP64 fields within 1e-12 relative L2 per field; FP32 fields
+within 1e-5 relative L2 per field after 1000 steps (FP32 arithmetic, FP64
+diagnostics).  GPU self-consistency (temporal blocking, batching, resume,
+repeat runs) is bitwise.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2312_05410_amd import workloads
+from paper_2312_05410_amd.inputs import PFParams, initial_state, random_state, realisation_draws
+
+pytestmark = pytest.mark.gpu
+
+F64_TOL = 1e-12
+F32_TOL = 1e-5
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2312_05410_amd import _lib
+
+    _lib.load()  # fails loudly if the HIP library is missing
+
+
+def Sim(*a, **kw):
+    from paper_2312_05410_amd._lib import Simulator
+
+    return Simulator(*a, **kw)
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def announce(msg):
+    print(f"\n[case] {msg}", flush=True)
+
+
+def compare(sim_state, ref: oracle.State, tol, label=""):
+    for name, got, want in zip(("c", "phi", "rho"), sim_state, (ref.c, ref.phi, ref.rho)):
+        e = rel_l2(got, want)
+        assert e <= tol, f"{label} {name}: rel L2 {e:.3e} > {tol:.1e}"
+
+
+def run_pair(p: PFParams, state, n, tol, temporal_block=0, dt=None):
+    dt = oracle.resolve_dt(p) if dt is None else dt
+    p = p.replace(dt=dt)
+    sim = Sim(p, state=state, temporal_block=temporal_block)
+    ref = oracle.State(p, *state, dt=dt)
+    sim.step(n)
+    ref.step(n)
+    compare(sim.state(), ref, tol, f"{p.precision} n={n} K={temporal_block}")
+    return sim, ref
+
+
+# ------------------------------------------------------------ initial condition
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_seeded_init_matches_oracle(prec):
+    announce(f"seeded init {prec}")
+    p = PFParams(nx=96, ny=80, batch=3, seed=11, precision=prec, c0_per=np.array([0.3, 0.5, 0.7]))
+    sim = Sim(p)
+    c, phi, rho = oracle.init(p)
+    gc, gphi, grho = sim.state()
+    if prec == "f64":
+        assert np.array_equal(gc, c)
+        np.testing.assert_allclose(gphi, phi, rtol=0, atol=4e-16)
+        np.testing.assert_allclose(grho, rho, rtol=0, atol=4e-16)
+    else:
+        for g, w in ((gc, c), (gphi, phi), (grho, rho)):
+            np.testing.assert_allclose(g, w.astype(np.float32).astype(np.float64), rtol=0, atol=1.2e-7)
+    np.testing.assert_array_equal(sim.inflow(), np.zeros(3))
+    sim.close()
+
+
+# ----------------------------------------------------- the small DNS workload
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_parity_f64_dns_small(seed):
+    """128^2 FP64, 1000 steps at 0.2 of the stability limit."""
+    announce(f"dns_small f64 seed={seed}")
+    p = workloads.dns_small(seed, "f64")
+    state = initial_state(p)
+    sim, ref = run_pair(p, state, 1000, F64_TOL)
+    m, mr = sim.mass(), ref.mass()
+    np.testing.assert_allclose(m, mr, rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(sim.energy(), ref.energy(), rtol=1e-12)
+    assert sim.step_count == 1000
+    sim.close()
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_parity_f32_dns_small(seed):
+    """Same inputs run in FP32: within 1e-5 relative L2 after 1000 steps."""
+    announce(f"dns_small f32 seed={seed}")
+    p = workloads.dns_small(seed, "f32")
+    dt = oracle.resolve_dt(p)
+    state = initial_state(p)
+    sim, ref = run_pair(p, state, 1000, F32_TOL, dt=dt)
+    np.testing.assert_allclose(sim.mass(), ref.mass(), rtol=2e-6, atol=1e-6)
+    np.testing.assert_allclose(sim.energy(), ref.energy(), rtol=1e-5)
+    sim.close()
+
+
+# ------------------------------------------------ rough states, ragged shapes
+
+@pytest.mark.parametrize("prec,K", [("f64", 1), ("f64", 2), ("f32", 1), ("f32", 2), ("f32", 3), ("f32", 4)])
+@pytest.mark.parametrize("shape", [(100, 77), (64, 32), (130, 50)])
+def test_parity_rough_ragged(prec, K, shape):
+    """Far-from-equilibrium fields (every term active), angled flux, grid
+    sizes that leave ragged tiles in x and y."""
+    nx, ny = shape
+    announce(f"rough {prec} K={K} {nx}x{ny}")
+    p = PFParams(nx=nx, ny=ny, precision=prec, theta_deg=62.0, v0=0.8, seed=3)
+    state = random_state(21, 1, ny, nx)
+    n = 23
+    sim, ref = run_pair(p, state, n, F64_TOL if prec == "f64" else 1e-5, temporal_block=K)
+    np.testing.assert_allclose(sim.inflow(), ref.Q, rtol=1e-12 if prec == "f64" else 1e-5)
+    sim.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_parity_periodic(prec):
+    announce(f"periodic {prec}")
+    p = PFParams(nx=72, ny=40, precision=prec, bc_mode="periodic", theta_deg=45.0, v0=0.7)
+    state = random_state(22, 1, 40, 72, film=False)
+    sim, ref = run_pair(p, state, 31, F64_TOL if prec == "f64" else 1e-5, temporal_block=2)
+    sim.close()
+
+
+@pytest.mark.parametrize("shape", [(8, 8), (5, 4), (1, 16), (200, 3)])
+def test_parity_tiny_grids(shape):
+    nx, ny = shape
+    announce(f"tiny {nx}x{ny}")
+    p = PFParams(nx=nx, ny=ny, precision="f64", theta_deg=70.0, film_h=ny / 2.0)
+    state = random_state(23, 1, ny, nx)
+    sim, ref = run_pair(p, state, 17, F64_TOL, temporal_block=2)
+    sim.close()
+
+
+def test_flux_off_conserves_and_decays():
+    announce("flux off f64")
+    p = workloads.dns_small(0, "f64").replace(flux_on=False)
+    sim = Sim(p)
+    m0, e0 = sim.mass(), sim.energy()
+    for _ in range(10):
+        sim.step(100)
+        e = sim.energy()
+        assert e[0] <= e0[0] + 1e-14 * abs(e0[0])
+        e0 = e
+    m1 = sim.mass()
+    assert abs(m1[0, 0] - m0[0, 0]) <= 1e-12 * abs(m0[0, 0])
+    assert abs(m1[0, 1] - m0[0, 1]) <= 1e-12 * abs(m0[0, 1])
+    sim.close()
+
+
+# ------------------------------------------------------- batched realisations
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_parity_batched(prec):
+    announce(f"batched {prec}")
+    v0, c0 = realisation_draws(5, 4, 0.5)
+    p = PFParams(nx=64, ny=48, batch=4, precision=prec, seed=5, v0_per=v0, c0_per=c0, theta_deg=75.0)
+    run_pair(p, initial_state(p), 200, F64_TOL if prec == "f64" else 1e-5)
+
+
+def test_batch_of_identical_realisations_is_bitwise_identical():
+    announce("batch identical")
+    B = 3
+    p = PFParams(nx=96, ny=64, batch=B, precision="f32", theta_deg=70.0)
+    c, phi, rho = random_state(24, 1, 64, 96)
+    state = tuple(np.repeat(u, B, axis=0) for u in (c, phi, rho))
+    sim = Sim(p, state=state)
+    sim.step(41)
+    out = sim.state()
+    for u in out:
+        for b in range(1, B):
+            assert np.array_equal(u[0], u[b])
+    q = sim.inflow()
+    assert q[0] == q[1] == q[2]
+    sim.close()
+
+
+# --------------------------------------------------- bitwise self-consistency
+
+@pytest.mark.parametrize("prec,Ks", [("f32", (2, 3, 4)), ("f64", (2,))])
+def test_temporal_blocking_is_bitwise(prec, Ks):
+    announce(f"temporal blocking bitwise {prec}")
+    p = PFParams(nx=150, ny=100, precision=prec, theta_deg=58.0, v0=0.9)
+    state = random_state(25, 1, 100, 150)
+    ref = Sim(p, state=state, temporal_block=1)
+    ref.step(37)
+    base = ref.state()
+    qb = ref.inflow()
+    for K in Ks:
+        sim = Sim(p, state=state, temporal_block=K)
+        sim.step(37)
+        for u, v in zip(sim.state(), base):
+            assert np.array_equal(u, v), f"K={K}"
+        assert np.array_equal(sim.inflow(), qb), f"K={K}"
+        sim.close()
+    ref.close()
+
+
+def test_runs_are_deterministic():
+    announce("determinism")
+    p = workloads.dns_small(1, "f32").replace(nx=256, ny=192)
+    out = []
+    for _ in range(2):
+        sim = Sim(p)
+        sim.step(300)
+        out.append((sim.state(), sim.mass(), sim.energy()))
+        sim.close()
+    for u, v in zip(out[0][0], out[1][0]):
+        assert np.array_equal(u, v)
+    assert np.array_equal(out[0][1], out[1][1]) and np.array_equal(out[0][2], out[1][2])
+
+
+def test_resume_is_bitwise():
+    announce("resume")
+    p = workloads.dns_small(2, "f32").replace(nx=160, ny=96)
+    full = Sim(p, temporal_block=2)
+    full.step(120)
+    want = full.state()
+    half = Sim(p, temporal_block=2)
+    half.step(60)
+    mid = half.state()
+    q = half.inflow()
+    resumed = Sim(p.replace(dt=half.dt), state=mid, temporal_block=2)
+    resumed.set_inflow(q)
+    resumed.step(60)
+    for u, v in zip(resumed.state(), want):
+        assert np.array_equal(u, v)
+    np.testing.assert_allclose(resumed.inflow(), full.inflow(), rtol=1e-14)
+    for s in (full, half, resumed):
+        s.close()
+
+
+def test_zero_steps_is_noop_and_nonfinite_is_reported():
+    announce("noop + nonfinite")
+    from paper_2312_05410_amd._lib import PFError, PF_ENONFINITE
+
+    p = PFParams(nx=32, ny=32, precision="f64")
+    sim = Sim(p)
+    before = sim.state()
+    sim.step(0)
+    for u, v in zip(sim.state(), before):
+        assert np.array_equal(u, v)
+    sim.c[0, 5, 7] = float("nan")
+    with pytest.raises(PFError) as ei:
+        sim.mass()
+    assert ei.value.code == PF_ENONFINITE
+    with pytest.raises(PFError):
+        sim.energy()
+    sim.close()
+
+
+# ------------------------------------------- full sizes, bench launch shape
+
+def test_full_size_production_parity():
+    """1024^2 FP32 (the throughput workload) in the launch configuration the
+    benchmark times, from its seeded initial condition, against the oracle on
+    the whole grid."""
+    announce("dns_1024 f32 full-size")
+    p = workloads.dns_production(0)
+    K = workloads.BENCH_TEMPORAL_BLOCK["f32"]
+    sim, ref = run_pair(p, initial_state(p), 10 * K, 1e-6, temporal_block=K)
+    np.testing.assert_allclose(sim.mass(), ref.mass(), rtol=1e-6)
+    sim.close()
+
+
+def test_full_size_batched_sampled():
+    """32 x 512^2 FP32 batched workload in the benchmark's launch shape; the
+    oracle checks a sample of realisations one by one."""
+    announce("batched 32x512 f32 sampled")
+    p = workloads.batched(0)
+    K = workloads.BENCH_TEMPORAL_BLOCK["f32"]
+    dt = oracle.resolve_dt(p)
+    p = p.replace(dt=dt)
+    state = initial_state(p)
+    n = 6 * K
+    sim = Sim(p, state=state, temporal_block=K)
+    sim.step(n)
+    out = sim.state()
+    for b in (0, 13, 31):
+        pb = p.replace(batch=1, seed=p.seed + b, v0=float(p.v0_per[b]), c0=float(p.c0_per[b]),
+                       v0_per=None, c0_per=None)
+        ref = oracle.State(pb, state[0][b:b + 1], state[1][b:b + 1], state[2][b:b + 1], dt=dt)
+        ref.step(n)
+        for name, got, want in zip("c phi rho".split(), out, (ref.c, ref.phi, ref.rho)):
+            e = rel_l2(got[b], want[0])
+            assert e <= 1e-6, f"b={b} {name} {e:.2e}"
+    sim.close()
