@@ -44,6 +44,7 @@ struct StepArgs {
     int tiles_x, tiles_y;
     int pvd;             // 1: substrate + inlet boundaries; 0: periodic in y
     int nsub;            // sub-steps in this launch (1..K of the kernel)
+    int fast;            // set by the launcher: 16-byte vector loads are valid
 };
 
 // Tile configuration of a stepper instantiation.
