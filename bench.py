@@ -39,11 +39,14 @@ def parse():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="dns_1024_f32",
-                    choices=["dns_1024_f32", "batched_32x512_f32", "dns_small_128_f64"])
+                    choices=["dns_1024_f32", "dns_8192_f32", "batched_32x512_f32", "dns_small_128_f64"])
     ap.add_argument("--temporal-block", type=int, default=None)
+    ap.add_argument("--graph-mode", type=int, default=0, help="0: replay HIP graphs of launches; 1: plain launches")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--ref-copy", action="store_true",
+                    help="first run one 512 MiB device copy (reference kernel for counter scaling)")
     return ap.parse_args()
 
 
@@ -52,6 +55,8 @@ def make_params(name: str):
 
     if name == "dns_1024_f32":
         return workloads.dns_production(0), workloads.STEPS[name]
+    if name == "dns_8192_f32":
+        return workloads.dns_production(0, n=8192), workloads.STEPS[name]
     if name == "batched_32x512_f32":
         return workloads.batched(0), workloads.STEPS[name]
     return workloads.dns_small(0, "f64"), workloads.STEPS[name]
@@ -75,17 +80,37 @@ def time_steps(sim, steps: int, warmup: int):
 
 
 def launches_for(steps: int, K: int) -> int:
-    L = -(-steps // K)
-    last = steps - (L - 1) * K
-    if L % 2 == 1 and (last >= 2 or (L >= 2 and K >= 2)):
+    """Number of stepper launches the library issues for `steps` steps with
+    K fused sub-steps (K full launches, the remainder, and one split when
+    the count is odd and a launch has two or more sub-steps)."""
+    q, rem = divmod(steps, K)
+    L = q + (1 if rem else 0)
+    if L % 2 == 1 and (rem >= 2 or (K >= 2 and q >= 1)):
         L += 1
     return L
 
 
+def kernel_name(prec: str, K: int, rows: int) -> str:
+    t = "float" if prec == "f32" else "double"
+    if K == 1:
+        ahead = rows + 1 if rows <= 8 else 4      # load look-ahead rows of the strip-march kernel
+        return f"march_kernel<{t}, {rows}, {ahead}>"
+    return f"step_kernel<{t}, {K}, {rows}>"
+
+
 def gpu_leg(args, p, steps, warmup, K):
+    import torch
+
     from paper_2312_05410_amd._lib import Simulator
 
-    sim = Simulator(p, temporal_block=K)
+    if args.ref_copy:
+        src = torch.ones(128 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    sim = Simulator(p, temporal_block=K, graph_mode=args.graph_mode)
+    Kr, rows = sim.launch
     dt_s, wall = time_steps(sim, steps, warmup)
     m = sim.mass()
     e = sim.energy()
@@ -93,10 +118,31 @@ def gpu_leg(args, p, steps, warmup, K):
     sim.close()
     cells = p.nx * p.ny * p.batch
     glups = cells * steps / dt_s / 1e9
-    return dict(seconds=dt_s, wall=wall, glups=glups, launches=launches_for(steps, K))
+    return dict(seconds=dt_s, wall=wall, glups=glups, launches=launches_for(steps, Kr), K=Kr, rows=rows)
 
 
-def sweep(K, sizes=(1024, 2048, 4096, 8192)):
+def measured_traffic(workload: str, kernel: str):
+    """HBM bytes per launch from the committed counter summary of this
+    workload, if it was taken on the current stepper sources and kernel."""
+    from paper_2312_05410_amd import rocprof_summary
+
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("stepper_source_sha256_16") != rocprof_summary.stepper_hash() or kv.get("kernel") != kernel:
+        return None
+    return float(kv["hbm_bytes_per_launch"])
+
+
+def sweep(K, graph_mode, sizes=(1024, 2048, 4096, 8192)):
+    """GLUPS of the production model at growing sizes, in the library's
+    launch shape for each size (the HBM claim needs working sets well above
+    the 256 MB Infinity Cache: 8192^2 FP32 is 805 MB, 1.6 GB ping-pong)."""
     from paper_2312_05410_amd import workloads
     from paper_2312_05410_amd._lib import Simulator
 
@@ -104,12 +150,14 @@ def sweep(K, sizes=(1024, 2048, 4096, 8192)):
     for n in sizes:
         p = workloads.dns_production(0, n=n)
         steps = max(40, int(4e9 / (n * n)) // 2 * 2)
-        sim = Simulator(p, temporal_block=K)
+        sim = Simulator(p, temporal_block=K, graph_mode=graph_mode)
+        Kr, rows = sim.launch
         dt_s, _ = time_steps(sim, steps, 20)
         sim.close()
         glups = n * n * steps / dt_s / 1e9
         state_mb = 3 * n * n * 4 / 1e6
         out.append(dict(n=n, steps=steps, state_MB=round(state_mb, 1), glups=round(glups, 2),
+                        kernel=kernel_name("f32", Kr, rows),
                         effective_GBs=round(glups * BYTES_PER_LUP["f32"], 1),
                         frac_hbm=round(glups * BYTES_PER_LUP["f32"] / HBM_PEAK_GBS, 4)))
         print(f"# sweep {n}^2: {glups:.1f} GLUPS", file=sys.stderr, flush=True)
@@ -161,6 +209,9 @@ def main():
     launch_s = g["seconds"] / g["launches"]
     bytes_per_launch = BYTES_PER_LUP[prec] * cells * steps / g["launches"]
     achieved = bytes_per_launch / launch_s / 1e9
+    kname = kernel_name(prec, g["K"], g["rows"])
+    tb = measured_traffic(args.workload, kname)
+    traffic = None if tb is None else round(tb / launch_s / 1e9, 1)
     result = {
         "metric": "phase-field GLUPS & %HBM peak",
         "value": round(g["glups"], 3),
@@ -173,19 +224,22 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": prec,
-        "data": "synthetic (seeded; paper's dataset parameter ranges)",
+        "data": "synthetic (seeded; parameter ranges of the paper's dataset)",
         "config": {"workload": args.workload, "nx": p.nx, "ny": p.ny, "batch": p.batch,
-                   "steps_total": total_steps, "temporal_block": K, "launches": g["launches"],
+                   "steps_total": total_steps, "temporal_block": g["K"], "tile_rows": g["rows"],
+                   "launches": g["launches"],
+                   "graph_mode": args.graph_mode,
                    "seed": p.seed, "dt": None},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": f"step_kernel<{'float' if prec == 'f32' else 'double'},K={K}>",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": kname,
                      "avg_launch_us": round(launch_s * 1e6, 3),
-                     "bytes_per_launch": int(bytes_per_launch)},
+                     "bytes_per_launch": int(bytes_per_launch),
+                     "traffic_bytes_per_launch": None if tb is None else int(tb)},
         "host_wall_s": round(g["wall"], 4),
     }
     if not args.no_sweep and prec == "f32":
-        result["size_sweep"] = sweep(K)
+        result["size_sweep"] = sweep(K, args.graph_mode)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_leg(p, args.cpu_seconds)
     print(json.dumps(result), flush=True)

@@ -15,7 +15,8 @@
  *
  * Memory: all field buffers are caller-owned device memory (for example
  * torch tensors), contiguous [batch][ny][nx] with x fastest, element type
- * float (PF_F32) or double (PF_F64), 16-byte aligned.  The caller also
+ * float (PF_F32) or double (PF_F64), 16-byte aligned, one realisation's
+ * field below 2 GiB (nx*ny*sizeof < 2^31).  The caller also
  * provides a device workspace of pf_workspace_bytes() bytes, 256-byte
  * aligned.  The library never allocates or frees device memory; a handle
  * owns only host-side metadata.  All host arrays passed in are read during
@@ -79,8 +80,12 @@ typedef struct pf_params {
     int32_t flux_on;              /* 0: v = 0 (no deposition, no advection) */
     int32_t init_mode;            /* pf_init_mode */
     int32_t allow_unstable;       /* 1: accept dt above the stability limit */
-    int32_t temporal_block;       /* steps fused per launch (1..4); 0: library's choice */
-    int32_t reserved0;
+    int32_t temporal_block;       /* steps fused per launch: 1..4 (FP32), 1..2 (FP64); 0: library's
+                                     choice by precision and grid size; lowered so that 2K <= ny */
+    int32_t graph_mode;           /* 0: long runs replay a HIP graph of launches; 1: plain launches */
+    int32_t tile_rows;            /* single-step kernel: rows per wave (4, 8, 16, 32); 0: library's
+                                     choice by grid size */
+    int32_t reserved0;            /* must be 0 */
     uint64_t seed;                /* seeded initial condition: realisation b uses seed + b */
     double h;                     /* grid spacing */
     double dt;                    /* time step; <= 0 means dt_factor * stability limit */
@@ -145,6 +150,10 @@ int pf_set_inflow(pf_handle* h, const double* Q);
 
 /* Release a handle (host memory only; the caller's buffers are untouched). */
 void pf_destroy(pf_handle* h);
+
+/* Launch shape a handle uses: steps fused per launch (1: single-step
+ * strip-march kernel; 2..4: LDS-tiled kernel) and rows per wave / tile. */
+int pf_get_launch(const pf_handle* h, int32_t* temporal_block, int32_t* tile_rows);
 
 /* Text of a pf_status code. */
 const char* pf_strerror(int code);

@@ -26,7 +26,7 @@ PF_INIT_SEEDED, PF_INIT_KEEP = 0, 1
 EXPORTS = (
     "pf_workspace_bytes", "pf_dt_limit", "pf_init", "pf_step_n", "pf_mass", "pf_energy",
     "pf_get_step", "pf_set_step", "pf_get_dt", "pf_get_inflow", "pf_set_inflow",
-    "pf_destroy", "pf_strerror", "pf_last_hip_error",
+    "pf_destroy", "pf_strerror", "pf_last_hip_error", "pf_get_launch",
 )
 
 
@@ -37,7 +37,8 @@ class PFParamsC(ctypes.Structure):
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("batch", ctypes.c_int32),
         ("precision", ctypes.c_int32), ("bc_mode", ctypes.c_int32), ("flux_on", ctypes.c_int32),
         ("init_mode", ctypes.c_int32), ("allow_unstable", ctypes.c_int32),
-        ("temporal_block", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+        ("temporal_block", ctypes.c_int32), ("graph_mode", ctypes.c_int32),
+        ("tile_rows", ctypes.c_int32), ("reserved0", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
         ("h", ctypes.c_double), ("dt", ctypes.c_double), ("dt_factor", ctypes.c_double),
         ("W_c", ctypes.c_double), ("W_phi", ctypes.c_double),
@@ -98,6 +99,8 @@ def load():
         L.pf_strerror.restype = ctypes.c_char_p
         L.pf_last_hip_error.argtypes = [H]
         L.pf_last_hip_error.restype = ctypes.c_int
+        L.pf_get_launch.argtypes = [H, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
+        L.pf_get_launch.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -114,7 +117,7 @@ _BC = {"pvd": PF_BC_PVD, "periodic": PF_BC_PERIODIC}
 
 
 def to_c(p: PFParams, init_mode: int = PF_INIT_SEEDED, temporal_block: int = 0,
-         allow_unstable: bool = False):
+         allow_unstable: bool = False, graph_mode: int = 0, tile_rows: int = 0):
     """Build the C struct; returns (struct, keep-alive arrays)."""
     keep = []
 
@@ -130,7 +133,7 @@ def to_c(p: PFParams, init_mode: int = PF_INIT_SEEDED, temporal_block: int = 0,
     s = PFParamsC(
         nx=p.nx, ny=p.ny, batch=p.batch, precision=_PREC[p.precision], bc_mode=_BC[p.bc_mode],
         flux_on=int(bool(p.flux_on)), init_mode=init_mode, allow_unstable=int(bool(allow_unstable)),
-        temporal_block=temporal_block, reserved0=0, seed=p.seed & 0xFFFFFFFFFFFFFFFF,
+        temporal_block=temporal_block, graph_mode=graph_mode, tile_rows=tile_rows, reserved0=0, seed=p.seed & 0xFFFFFFFFFFFFFFFF,
         h=p.h, dt=p.dt, dt_factor=p.dt_factor,
         W_c=p.W_c, W_phi=p.W_phi, kappa_c=p.kappa_c, kappa_phi=p.kappa_phi,
         MA_bulk=p.MA_bulk, MB_bulk=p.MB_bulk, MA_surf=p.MA_surf, MB_surf=p.MB_surf,
@@ -163,7 +166,7 @@ class Simulator:
     pf_handle that steps them on the current stream of `device`."""
 
     def __init__(self, p: PFParams, state=None, temporal_block: int = 0, device: str = "cuda",
-                 allow_unstable: bool = False):
+                 allow_unstable: bool = False, graph_mode: int = 0, tile_rows: int = 0):
         import torch
 
         L = load()
@@ -179,7 +182,8 @@ class Simulator:
                 torch.as_tensor(np.asarray(u), dtype=dtype).reshape(shape).to(self.device).contiguous()
                 for u in state)
             mode = PF_INIT_KEEP
-        s, keep = to_c(p, init_mode=mode, temporal_block=temporal_block, allow_unstable=allow_unstable)
+        s, keep = to_c(p, init_mode=mode, temporal_block=temporal_block, allow_unstable=allow_unstable,
+                       graph_mode=graph_mode, tile_rows=tile_rows)
         nbytes = L.pf_workspace_bytes(ctypes.byref(s))
         if nbytes == 0:
             raise PFError(PF_EINVAL, "pf_workspace_bytes")
@@ -228,6 +232,13 @@ class Simulator:
         out = ctypes.c_double()
         self._check(load().pf_get_dt(self._h, ctypes.byref(out)), "pf_get_dt")
         return out.value
+
+    @property
+    def launch(self):
+        """(steps fused per launch, rows per wave or tile) this handle uses."""
+        k, r = ctypes.c_int32(), ctypes.c_int32()
+        self._check(load().pf_get_launch(self._h, ctypes.byref(k), ctypes.byref(r)), "pf_get_launch")
+        return k.value, r.value
 
     @property
     def step_count(self) -> int:

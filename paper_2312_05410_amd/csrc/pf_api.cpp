@@ -17,6 +17,7 @@
 namespace {
 
 constexpr size_t kAlign = 256;
+constexpr int kGraphLen = 64;   // launches per graph replay (even: parity is preserved)
 
 size_t round_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -59,11 +60,17 @@ int validate(const pf_params* p)
 {
     if (!p) return PF_EINVAL;
     if (p->nx < 1 || p->ny < 1 || p->batch < 1 || p->batch > 65535) return PF_EINVAL;
-    if ((int64_t)p->nx * p->ny > (int64_t)1 << 31) return PF_EINVAL;
+
     if (p->precision != PF_F32 && p->precision != PF_F64) return PF_EINVAL;
+    // one realisation's field must stay below 2 GiB (32-bit buffer offsets)
+    if ((int64_t)p->nx * p->ny * (p->precision == PF_F64 ? 8 : 4) >= ((int64_t)1 << 31)) return PF_EINVAL;
     if (p->bc_mode != PF_BC_PVD && p->bc_mode != PF_BC_PERIODIC) return PF_EINVAL;
     if (p->init_mode != PF_INIT_SEEDED && p->init_mode != PF_INIT_KEEP) return PF_EINVAL;
     if (p->temporal_block < 0 || p->temporal_block > (p->precision == PF_F64 ? 2 : 4)) return PF_EINVAL;
+    if (p->graph_mode < 0 || p->graph_mode > 1) return PF_EINVAL;
+    if (p->tile_rows != 0 && p->tile_rows != 4 && p->tile_rows != 8 && p->tile_rows != 16 && p->tile_rows != 32)
+        return PF_EINVAL;
+    if (p->reserved0 != 0) return PF_EINVAL;
     if (!finite_all({p->h, p->dt, p->dt_factor, p->W_c, p->W_phi, p->kappa_c, p->kappa_phi, p->MA_bulk,
                      p->MB_bulk, p->MA_surf, p->MB_surf, p->sigma_surf, p->M_phi, p->M_scale, p->D_rho,
                      p->v0, p->theta_deg, p->rho_in, p->c0, p->c_noise, p->film_h}))
@@ -117,7 +124,10 @@ struct pf_handle {
     double dt = 0;
     int64_t step = 0;
     int K = 1;
+    int march_ty = 16;                   // K == 1: rows per wave of the strip-march kernel
     int last_hip = 0;
+    hipGraph_t graph = nullptr;          // chain of kGraphLen full-K launches
+    hipGraphExec_t gexec = nullptr;
     std::vector<pfk::Real> real;
     std::vector<double> c0;
     std::vector<double> host_out;
@@ -140,6 +150,8 @@ pfk::Coef<T> make_coef(const pf_params* p, double dt)
     const double h2 = p->h * p->h;
     k.Wc = (T)p->W_c;
     k.Wphi = (T)p->W_phi;
+    k.Wc4 = (T)(0.25 * p->W_c);
+    k.Wc34 = (T)(0.75 * p->W_c);
     k.kc = (T)(p->kappa_c / h2);
     k.kp = (T)(p->kappa_phi / h2);
     k.MBb = (T)(p->M_scale * p->MB_bulk);
@@ -157,8 +169,32 @@ pfk::Coef<T> make_coef(const pf_params* p, double dt)
     return k;
 }
 
+// Launch plan of n steps with K sub-steps per launch: full launches first,
+// then the remainder.  An even number of launches leaves the result in the
+// caller's buffers, so when the count is odd one launch is split in two
+// (the remainder, or else the last full launch); only runs of single-step
+// launches end with a copy.
+std::vector<int> launch_plan(int64_t n, int K)
+{
+    const int64_t q = n / K;
+    const int rem = (int)(n % K);
+    std::vector<int> plan((size_t)q, K);
+    if (rem) plan.push_back(rem);
+    if (plan.size() % 2 == 1) {
+        if (rem >= 2) {
+            plan.back() = rem / 2;
+            plan.push_back(rem - rem / 2);
+        } else if (K >= 2 && q >= 1) {
+            const size_t i = (size_t)q - 1;   // the last full launch
+            plan[i] = K / 2;
+            plan.insert(plan.begin() + (long)i + 1, K - K / 2);
+        }
+    }
+    return plan;
+}
+
 template <typename T>
-int enqueue_steps(pf_handle* h, int64_t n)
+pfk::StepArgs<T> step_args(pf_handle* h)
 {
     const pf_params* p = &h->p;
     const pfk::TileCfg cfg = pfk::tile_cfg<T>(h->K);
@@ -171,43 +207,74 @@ int enqueue_steps(pf_handle* h, int64_t n)
     a.tiles_x = (p->nx + cfg.tx - 1) / cfg.tx;
     a.tiles_y = (p->ny + cfg.ty - 1) / cfg.ty;
     a.pvd = p->bc_mode == PF_BC_PVD;
+    return a;
+}
 
-    // Launch plan: blocks of K sub-steps; an even number of launches keeps
-    // the result in the caller's buffers, so split one block when possible.
-    const int K = h->K;
-    int64_t L = (n + K - 1) / K;
-    const int last_sub = (int)(n - (L - 1) * K);
-    int first_split = 0, last_split = 0;   // sub-steps of an extra leading/trailing launch
-    if (L % 2 == 1) {
-        if (last_sub >= 2) last_split = last_sub / 2;
-        else if (L >= 2 && K >= 2) first_split = K / 2;
+template <typename T>
+void set_parity(pf_handle* h, pfk::StepArgs<T>& a, int parity)
+{
+    void* const* src = parity == 0 ? h->f : h->w;
+    void* const* dst = parity == 0 ? h->w : h->f;
+    a.c = (const T*)src[0];
+    a.phi = (const T*)src[1];
+    a.rho = (const T*)src[2];
+    a.c_out = (T*)dst[0];
+    a.phi_out = (T*)dst[1];
+    a.rho_out = (T*)dst[2];
+}
+
+// A graph of kGraphLen full-K launches (caller -> workspace -> caller ...),
+// built once per handle and replayed for long runs.
+template <typename T>
+int ensure_graph(pf_handle* h)
+{
+    if (h->gexec) return PF_OK;
+    pfk::StepArgs<T> a = step_args<T>(h);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipGraphCreate(&g, 0);
+    hipGraphNode_t prev = nullptr;
+    for (int i = 0; i < kGraphLen && e == hipSuccess; ++i) {
+        set_parity<T>(h, a, i & 1);
+        a.nsub = h->K;
+        hipGraphNode_t node = nullptr;
+        e = h->K == 1 ? pfk::graph_add_march<T>(g, &node, prev, a, h->march_ty, h->p.batch)
+                      : pfk::graph_add_step<T>(g, &node, prev, a, h->K, h->p.batch);
+        prev = node;
     }
-    auto launch = [&](int nsub, int parity) -> int {
-        void* const* src = parity == 0 ? h->f : h->w;
-        void* const* dst = parity == 0 ? h->w : h->f;
-        a.c = (const T*)src[0];
-        a.phi = (const T*)src[1];
-        a.rho = (const T*)src[2];
-        a.c_out = (T*)dst[0];
-        a.phi_out = (T*)dst[1];
-        a.rho_out = (T*)dst[2];
-        a.nsub = nsub;
-        return hip_fail(h, pfk::launch_step<T>(a, K, p->batch, h->stream));
-    };
-    int parity = 0, rc;
-    for (int64_t l = 0; l < L; ++l) {
-        int nsub = l + 1 < L ? K : last_sub;
-        if (l == 0 && first_split) {
-            if ((rc = launch(first_split, parity))) return rc;
-            parity ^= 1;
-            nsub -= first_split;
-        }
-        if (l + 1 == L && last_split) {
-            if ((rc = launch(last_split, parity))) return rc;
-            parity ^= 1;
-            nsub -= last_split;
-        }
-        if ((rc = launch(nsub, parity))) return rc;
+    hipGraphExec_t ex = nullptr;
+    if (e == hipSuccess) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        if (g) hipGraphDestroy(g);
+        return hip_fail(h, e);
+    }
+    h->graph = g;
+    h->gexec = ex;
+    return PF_OK;
+}
+
+template <typename T>
+int enqueue_steps(pf_handle* h, int64_t n)
+{
+    const pf_params* p = &h->p;
+    const int K = h->K;
+    pfk::StepArgs<T> a = step_args<T>(h);
+    const std::vector<int> plan = launch_plan(n, K);
+    size_t full = 0;
+    while (full < plan.size() && plan[full] == K) ++full;
+    size_t l = 0;
+    int rc;
+    if (p->graph_mode == 0 && full >= (size_t)kGraphLen) {
+        if ((rc = ensure_graph<T>(h))) return rc;
+        for (; l + kGraphLen <= full; l += kGraphLen)
+            if ((rc = hip_fail(h, hipGraphLaunch(h->gexec, h->stream)))) return rc;
+    }
+    int parity = (int)(l & 1);
+    for (; l < plan.size(); ++l) {
+        set_parity<T>(h, a, parity);
+        a.nsub = plan[l];
+        const hipError_t e = K == 1 ? pfk::launch_march<T>(a, h->march_ty, p->batch, h->stream)
+                                    : pfk::launch_step<T>(a, K, p->batch, h->stream);
+        if ((rc = hip_fail(h, e))) return rc;
         parity ^= 1;
     }
     if (parity == 1) {
@@ -302,11 +369,24 @@ int pf_init(pf_handle** out, const pf_params* p, void* c, void* phi, void* rho, 
     for (int f = 0; f < 3; ++f) h->w[f] = h->ws + L.state[f];
     h->stream = (hipStream_t)stream;
     h->dt = dt;
-    // fused steps per launch: requested, or 1; the mirror ghosts of a
-    // launch must be real rows, so 2K <= ny
-    int K = p->temporal_block > 0 ? p->temporal_block : 1;
+    // Launch shape.  Fused steps per launch K: as requested, else (measured
+    // on MI355X) two steps through the LDS-tiled kernel for FP32 grids of up
+    // to ~3M cells per launch, where one step does not fill the GPU, and the
+    // single-step strip-march kernel otherwise and for FP64.  The mirror
+    // ghosts of a launch must be real rows, so 2K <= ny.
+    const long cells = (long)p->nx * p->ny * p->batch;
+    int K = p->temporal_block;
+    if (K == 0) K = (p->precision == PF_F32 && cells < 3000000L) ? 2 : 1;
     while (K > 1 && 2 * K > p->ny) --K;
     h->K = K;
+    if (p->tile_rows > 0) {
+        h->march_ty = p->tile_rows;
+    } else {
+        // strip-march chunk height: 8 rows when that still gives about four
+        // waves per SIMD, else 4 (shorter chunks cost more row halo)
+        const long strips = (p->nx + 59) / 60;
+        h->march_ty = strips * ((p->ny + 7) / 8) * (long)p->batch >= 4096 ? 8 : 4;
+    }
 
     const double th = p->theta_deg * (3.14159265358979323846 / 180.0);
     h->real.resize(p->batch);
@@ -434,7 +514,13 @@ int pf_set_inflow(pf_handle* h, const double* Q)
     return hip_fail(h, e);
 }
 
-void pf_destroy(pf_handle* h) { delete h; }
+void pf_destroy(pf_handle* h)
+{
+    if (!h) return;
+    if (h->gexec) hipGraphExecDestroy(h->gexec);
+    if (h->graph) hipGraphDestroy(h->graph);
+    delete h;
+}
 
 const char* pf_strerror(int code)
 {
@@ -449,5 +535,14 @@ const char* pf_strerror(int code)
 }
 
 int pf_last_hip_error(const pf_handle* h) { return h ? h->last_hip : 0; }
+
+int pf_get_launch(const pf_handle* h, int32_t* temporal_block, int32_t* tile_rows)
+{
+    if (!h || !temporal_block || !tile_rows) return PF_EINVAL;
+    *temporal_block = h->K;
+    *tile_rows = h->K == 1 ? h->march_ty : pfk::tile_cfg<float>(h->K).ty;
+    if (h->p.precision == PF_F64 && h->K > 1) *tile_rows = pfk::tile_cfg<double>(h->K).ty;
+    return PF_OK;
+}
 
 }  // extern "C"

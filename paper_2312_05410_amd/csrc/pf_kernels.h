@@ -12,6 +12,7 @@ namespace pfk {
 template <typename T>
 struct Coef {
     T Wc, Wphi;        // double-well heights
+    T Wc4, Wc34;       // W_c / 4, 3 W_c / 4
     T kc, kp;          // kappa_c / h^2, kappa_phi / h^2
     T MBb, dMb;        // M_scale*MB_bulk, M_scale*(MA_bulk - MB_bulk)
     T MBs, dMs;        // same for the surface mobilities
@@ -59,6 +60,19 @@ hipError_t launch_step(const StepArgs<T>& a, int k, int batch, hipStream_t s);
 
 template <typename T>
 TileCfg tile_cfg(int k);
+
+// Single-step strip-march kernel (K = 1), chunks of ty in {4, 8, 16, 32} rows.
+template <typename T>
+hipError_t launch_march(const StepArgs<T>& a, int ty, int batch, hipStream_t s);
+template <typename T>
+hipError_t graph_add_march(hipGraph_t g, hipGraphNode_t* node, hipGraphNode_t dep, const StepArgs<T>& a,
+                           int ty, int batch);
+
+// Append one stepper launch as a kernel node of graph g after node dep
+// (dep == nullptr: no dependency).
+template <typename T>
+hipError_t graph_add_step(hipGraph_t g, hipGraphNode_t* node, hipGraphNode_t dep,
+                          const StepArgs<T>& a, int k, int batch);
 
 // Seeded initial condition.
 struct InitArgs {

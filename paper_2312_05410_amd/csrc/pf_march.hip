@@ -1,0 +1,252 @@
+// gfx950 single-step stepper: one wave64 marches down a 64-column strip.
+//
+// Lane i holds column xs + i of the strip (xs = 60 s - 2) and the wave walks
+// the rows of a TY-row chunk from south to north.  North/south neighbours
+// are the previous and next rows, kept in registers; east/west neighbours
+// are the adjacent lanes, fetched with whole-wave DPP shifts (wave_shl:1,
+// wave_shr:1).  Stage 1 (mu_c, mu_phi, M_c) is valid in lanes 1..62 and
+// stage 2 (the Euler update) in lanes 2..61, so each strip writes 60
+// columns and strips overlap by 4.  There is no LDS and no barrier: each
+// wave streams its rows, with the loads of row t issued D rows before they
+// are used, and writes every output cell once.  HBM traffic per step is one
+// read and one write of c, phi, rho plus the 4-column strip overlap and the
+// 4-row chunk halo (mostly L2 hits).
+//
+// The per-cell arithmetic is the shared code of pf_cell.h, so this kernel is
+// bitwise identical to the LDS-tiled kernels.
+#include "pf_cell.h"
+
+namespace pfk {
+namespace {
+
+using namespace cell;
+
+constexpr int kStripOut = 60;   // output columns per 64-lane strip
+
+// lane i <- lane i+1 (east neighbour) / lane i <- lane i-1 (west).  With
+// bound_ctrl set, the lane without a source reads 0 (its results are never
+// used) and the move can fold into the consuming instruction as a DPP
+// operand.
+__device__ __forceinline__ int east_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xf, 0xf, true); }
+__device__ __forceinline__ int west_i(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true); }
+__device__ __forceinline__ float east(float v) { return __builtin_bit_cast(float, east_i(__builtin_bit_cast(int, v))); }
+__device__ __forceinline__ float west(float v) { return __builtin_bit_cast(float, west_i(__builtin_bit_cast(int, v))); }
+__device__ __forceinline__ double east(double v)
+{
+    const int2 w = __builtin_bit_cast(int2, v);
+    return __builtin_bit_cast(double, make_int2(east_i(w.x), east_i(w.y)));
+}
+__device__ __forceinline__ double west(double v)
+{
+    const int2 w = __builtin_bit_cast(int2, v);
+    return __builtin_bit_cast(double, make_int2(west_i(w.x), west_i(w.y)));
+}
+
+// Raw buffer loads and stores: the lane's column is a fixed vector offset
+// and the row offset is a scalar, so no per-access address arithmetic runs
+// on the vector ALU.  A plane must be below 2 GiB (checked on the host).
+template <typename T> struct Buf;
+template <> struct Buf<float> {
+    __device__ static float ld(__amdgpu_buffer_rsrc_t r, int vo, int so)
+    {
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, so, 0));
+    }
+    __device__ static void st(float v, __amdgpu_buffer_rsrc_t r, int vo, int so)
+    {
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, so, 0);
+    }
+};
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+template <> struct Buf<double> {
+    using U = u32x2;
+    __device__ static double ld(__amdgpu_buffer_rsrc_t r, int vo, int so)
+    {
+        return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0));
+    }
+    __device__ static void st(double v, __amdgpu_buffer_rsrc_t r, int vo, int so)
+    {
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(U, v), r, vo, so, 0);
+    }
+};
+
+// gfx9 raw-buffer descriptor word 3 (32-bit data format, no swizzle)
+constexpr int kBufFlags = 0x00020000;
+
+template <typename T>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const T* base, size_t plane)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)(plane * sizeof(T)), kBufFlags);
+}
+
+// One wave per (strip, chunk).  TY output rows; input rows t = 0..TY+3 are
+// global rows y0-2+t; stage 1 runs on t = 1..TY+2, stage 2 on t = 2..TY+1.
+template <typename T, int TY, int D>
+__global__ __launch_bounds__(64) void march_kernel(StepArgs<T> a)
+{
+    constexpr int NR = TY + 4;
+    const int lane = threadIdx.x;
+    const int b = blockIdx.y;
+    const int nx = a.nx, ny = a.ny;
+    const int nstrip = a.tiles_x;
+
+    // XCD-aware order: XCD x gets a contiguous band of (chunk, strip) tiles
+    const int nblk = a.tiles_x * a.tiles_y;
+    const int bid = blockIdx.x;
+    const int xcd = bid & 7, slot = bid >> 3;
+    const int q8 = nblk >> 3, r8 = nblk & 7;
+    const int tileid = xcd * q8 + (xcd < r8 ? xcd : r8) + slot;
+    const int strip = tileid % nstrip;
+    const int y0 = (tileid / nstrip) * TY;
+
+    int gx = strip * kStripOut - 2 + lane;
+    while (gx < 0) gx += nx;
+    while (gx >= nx) gx -= nx;
+    const int ocol = strip * kStripOut + lane - 2;     // output column of this lane
+    const bool out_lane = lane >= 2 && lane < 2 + kStripOut && ocol < nx;
+
+    const size_t plane = (size_t)nx * ny;
+    const auto bc = plane_rsrc(a.c + (size_t)b * plane, plane);
+    const auto bp = plane_rsrc(a.phi + (size_t)b * plane, plane);
+    const auto br = plane_rsrc(a.rho + (size_t)b * plane, plane);
+    const auto oc = plane_rsrc(a.c_out + (size_t)b * plane, plane);
+    const auto op = plane_rsrc(a.phi_out + (size_t)b * plane, plane);
+    const auto orr = plane_rsrc(a.rho_out + (size_t)b * plane, plane);
+    const int vo = gx * (int)sizeof(T);
+    const int row_bytes = nx * (int)sizeof(T);
+    const Coef<T> k = a.k;
+    const Real rl = a.real[b];
+    const T vx2h = (T)rl.vx2h, vy2h = (T)rl.vy2h;
+    const int pvd = a.pvd;
+
+    T c[NR], p[NR], r[NR];
+    T mc[NR], mp[NR], M[NR], pE[NR], pW[NR], FN[NR];
+    const RhoCoef<T> rc = rho_coef(k, vx2h, vy2h);
+
+    // row t of the inputs: mirrored (PVD) or wrapped row index, clamped so
+    // that rows beyond every dependency cone still address the grid
+    auto load_row = [&](int t) {
+        const int gj = y0 - 2 + t;
+        int jj;
+        if (pvd) jj = gj < 0 ? -1 - gj : (gj >= ny ? 2 * ny - 1 - gj : gj);
+        else jj = gj < 0 ? gj + ny : (gj >= ny ? gj - ny : gj);
+        jj = jj < 0 ? 0 : (jj >= ny ? ny - 1 : jj);
+        const int so = jj * row_bytes;
+        c[t] = Buf<T>::ld(bc, vo, so);
+        p[t] = Buf<T>::ld(bp, vo, so);
+        const T rv = Buf<T>::ld(br, vo, so);
+        r[t] = (pvd && gj >= ny) ? k.rho_in : rv;
+    };
+
+#pragma unroll
+    for (int t = 0; t < NR; ++t)
+        if (t < 3 + D) load_row(t);
+
+#pragma unroll
+    for (int t1 = 1; t1 <= TY + 2; ++t1) {
+        if (t1 + 2 + D < NR) load_row(t1 + 2 + D);
+        // stage 1 at row t1
+        {
+            const T cE = east(c[t1]), cW = west(c[t1]);
+            pE[t1] = east(p[t1]);
+            pW[t1] = west(p[t1]);
+            potentials(k, c[t1], cE, cW, c[t1 + 1], c[t1 - 1], p[t1], pE[t1], pW[t1], p[t1 + 1], p[t1 - 1],
+                       mc[t1], mp[t1], M[t1]);
+        }
+        // stage 2 at row t = t1 - 1; each face flux of c is computed once:
+        // the west flux is the west lane's east flux, the south flux is the
+        // previous row's north flux
+        if (t1 >= 3) {
+            const int t = t1 - 1;
+            const int gj = y0 - 2 + t;
+            const bool bottom = pvd && gj == 0;
+            if (t == 2) FN[1] = cflux(M[1], mc[1], M[2], mc[2]);
+            const T FE = cflux(M[t], mc[t], east(M[t]), east(mc[t]));
+            FN[t] = cflux(M[t], mc[t], M[t + 1], mc[t + 1]);
+            T nc, np, nr;
+            update(k, rc, vx2h, vy2h, bottom, c[t],
+                   p[t], pE[t], pW[t], p[t + 1], p[t - 1],
+                   r[t], east(r[t]), west(r[t]), r[t + 1], r[t - 1],
+                   FE, west(FE), FN[t], FN[t - 1],
+                   mp[t], east(mp[t]), west(mp[t]), mp[t + 1], mp[t - 1], nc, np, nr);
+            if (gj < ny) {
+                if (out_lane) {
+                    const int so = gj * row_bytes;
+                    Buf<T>::st(nc, oc, vo, so);
+                    Buf<T>::st(np, op, vo, so);
+                    Buf<T>::st(nr, orr, vo, so);
+                }
+                if (pvd && gj == ny - 1 && out_lane) {
+                    // inflow through the top face: advective + diffusive flux
+                    double* q = a.Qcol + (size_t)b * nx + ocol;
+                    const double rin = (double)k.rho_in, rr = (double)r[t];
+                    *q = *q + (rl.qa * (rr + rin) + rl.qb * (rin - rr));
+                }
+            }
+        }
+    }
+}
+
+// rows of loads in flight ahead of use: short chunks issue all their loads
+// at once, long chunks keep a window of rows in flight
+template <int TY> constexpr int lookahead() { return TY <= 8 ? TY + 1 : 4; }
+
+template <typename T, int TY>
+hipError_t launch_march_ty(StepArgs<T> a, int batch, hipStream_t s)
+{
+    a.tiles_x = (a.nx + kStripOut - 1) / kStripOut;
+    a.tiles_y = (a.ny + TY - 1) / TY;
+    dim3 grid(a.tiles_x * a.tiles_y, batch);
+    hipLaunchKernelGGL((march_kernel<T, TY, lookahead<TY>()>), grid, dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, int TY>
+hipError_t node_march_ty(hipGraph_t g, hipGraphNode_t* node, hipGraphNode_t dep, StepArgs<T> a, int batch)
+{
+    a.tiles_x = (a.nx + kStripOut - 1) / kStripOut;
+    a.tiles_y = (a.ny + TY - 1) / TY;
+    void* args[] = {&a};
+    hipKernelNodeParams kp{};
+    kp.func = (void*)march_kernel<T, TY, lookahead<TY>()>;
+    kp.gridDim = dim3(a.tiles_x * a.tiles_y, batch);
+    kp.blockDim = dim3(64);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    return hipGraphAddKernelNode(node, g, dep ? &dep : nullptr, dep ? 1 : 0, &kp);
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_march(const StepArgs<T>& a, int ty, int batch, hipStream_t s)
+{
+    switch (ty) {
+    case 4: return launch_march_ty<T, 4>(a, batch, s);
+    case 8: return launch_march_ty<T, 8>(a, batch, s);
+    case 16: return launch_march_ty<T, 16>(a, batch, s);
+    case 32: return launch_march_ty<T, 32>(a, batch, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+template hipError_t launch_march<float>(const StepArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_march<double>(const StepArgs<double>&, int, int, hipStream_t);
+
+template <typename T>
+hipError_t graph_add_march(hipGraph_t g, hipGraphNode_t* node, hipGraphNode_t dep, const StepArgs<T>& a,
+                           int ty, int batch)
+{
+    switch (ty) {
+    case 4: return node_march_ty<T, 4>(g, node, dep, a, batch);
+    case 8: return node_march_ty<T, 8>(g, node, dep, a, batch);
+    case 16: return node_march_ty<T, 16>(g, node, dep, a, batch);
+    case 32: return node_march_ty<T, 32>(g, node, dep, a, batch);
+    default: return hipErrorInvalidValue;
+    }
+}
+template hipError_t graph_add_march<float>(hipGraph_t, hipGraphNode_t*, hipGraphNode_t, const StepArgs<float>&,
+                                           int, int);
+template hipError_t graph_add_march<double>(hipGraph_t, hipGraphNode_t*, hipGraphNode_t, const StepArgs<double>&,
+                                            int, int);
+
+}  // namespace pfk

@@ -23,85 +23,12 @@
 // evaluated by the same two inline functions with a fixed expression order
 // (contraction off, explicit fma), so all variants give bitwise-identical
 // states.
-#include "pf_kernels.h"
-
-#include <math.h>
+#include "pf_cell.h"
 
 namespace pfk {
 namespace {
 
-__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
-
-// exp(-phi^2/sigma^2): float uses the hardware base-2 exponential with
-// log2(e)/sigma^2 folded on the host; double uses the device math library.
-__device__ __forceinline__ float surf_exp(float ph2, float e) { return __builtin_amdgcn_exp2f(-(ph2 * e)); }
-__device__ __forceinline__ double surf_exp(double ph2, double e) { return exp(-(ph2 * e)); }
-
-template <typename T>
-__device__ __forceinline__ T clampT(T x, T lo, T hi)
-{
-    return x < lo ? lo : (x > hi ? hi : x);
-}
-
-// Stage 1 at one cell: chemical potentials and composition mobility.
-//   mu_c   = W_c p(phi) g'(c) - kappa_c Lap c
-//   mu_phi = W_c p'(phi) g(c) - W_phi phi (1 - phi^2) - kappa_phi Lap phi
-//   M_c    = p(phi~)(MB + H dM)_bulk + exp(-(phi~/sigma)^2)(MB + H dM)_surf
-// Neighbour sums are (E + W) + (N + S): mirrored ghost rows then reproduce
-// the interior values exactly.
-template <typename T>
-__device__ __forceinline__ void potentials(const Coef<T>& k, T c, T cE, T cW, T cN, T cS,
-                                           T p, T pE, T pW, T pN, T pS,
-                                           T& mu_c, T& mu_p, T& M)
-{
-    const T lapc = fmaT(T(-4), c, (cE + cW) + (cN + cS));
-    const T lapp = fmaT(T(-4), p, (pE + pW) + (pN + pS));
-    const T q1 = T(1) + p;
-    const T pf = (T(0.25) * (T(2) - p)) * (q1 * q1);
-    const T w = fmaT(-p, p, T(1));
-    const T dpf = T(0.75) * w;
-    const T cg = c * (T(1) - c);
-    const T g = cg * cg;
-    const T dg = cg * fmaT(T(-4), c, T(2));
-    mu_c = fmaT(k.Wc * pf, dg, -(k.kc * lapc));
-    mu_p = fmaT(k.Wc * dpf, g, fmaT(-(k.Wphi * p), w, -(k.kp * lapp)));
-    const T x = clampT(c, T(0), T(1));
-    const T H = ((x * x) * x) * fmaT(fmaT(T(6), x, T(-15)), x, T(10));
-    const T ph = clampT(p, T(-1), T(1));
-    const T r1 = T(1) + ph;
-    const T pb = (T(0.25) * (T(2) - ph)) * (r1 * r1);
-    const T e = surf_exp(ph * ph, k.esurf);
-    M = fmaT(pb, fmaT(H, k.dMb, k.MBb), e * fmaT(H, k.dMs, k.MBs));
-}
-
-// Stage 2 at one cell: Euler update of (c, phi, rho).
-//   c'   = c   + dt * div(M_c grad mu_c)              (face-averaged M_c)
-//   phi' = phi + dt * (M_phi Lap mu_phi + S),  S = rho v . grad phi
-//   rho' = rho + dt * (D Lap rho - div(rho v) - S)    (central face fluxes)
-// `bottom`: the substrate row, whose south advective face flux is zero.
-template <typename T>
-__device__ __forceinline__ void update(const Coef<T>& k, T vx2h, T vy2h, bool bottom,
-                                       T c0, T p0, T pE, T pW, T pN, T pS,
-                                       T r0, T rE, T rW, T rN, T rS,
-                                       T M0, T ME, T MW, T MN, T MS,
-                                       T m0, T mE, T mW, T mN, T mS,
-                                       T q0, T qE, T qW, T qN, T qS,
-                                       T& nc, T& np, T& nr)
-{
-    const T fx = (ME + M0) * (mE - m0) + (MW + M0) * (mW - m0);
-    const T fy = (MN + M0) * (mN - m0) + (MS + M0) * (mS - m0);
-    const T divc = k.half_ih2 * (fx + fy);
-    const T divp = k.mphi_h2 * fmaT(T(-4), q0, (qE + qW) + (qN + qS));
-    const T src = r0 * fmaT(vx2h, pE - pW, vy2h * (pN - pS));
-    const T lapr = fmaT(T(-4), r0, (rE + rW) + (rN + rS));
-    const T rSa = bottom ? -r0 : rS;
-    const T adv = fmaT(vx2h, rE - rW, vy2h * (rN - rSa));
-    const T Tr = fmaT(k.D_h2, lapr, -adv);
-    nc = fmaT(k.dt, divc, c0);
-    np = fmaT(k.dt, divp + src, p0);
-    nr = fmaT(k.dt, Tr - src, r0);
-}
+using namespace cell;
 
 // 16-byte vectors as native clang vector types (kept in registers)
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -156,6 +83,7 @@ struct Stepper {
     int b, x0, y0, tid, lane, wv;
     T vx2h, vy2h;
     double qa, qb;
+    RhoCoef<T> rc;
 
     // ------------------------------------------------------------ load
     __device__ __forceinline__ void load()
@@ -282,11 +210,12 @@ struct Stepper {
     // ------------------------------------------------------- stage 2
     __device__ __forceinline__ void upd_cell(int l, bool bottom, T& nc, T& np, T& nr)
     {
-        update(a.k, vx2h, vy2h, bottom, t.c[l],
+        const T M0 = t.M[l], m0 = t.mc[l];
+        update(a.k, rc, vx2h, vy2h, bottom, t.c[l],
                t.p[l], t.p[l + 1], t.p[l - 1], t.p[l + P], t.p[l - P],
                t.r[l], t.r[l + 1], t.r[l - 1], t.r[l + P], t.r[l - P],
-               t.M[l], t.M[l + 1], t.M[l - 1], t.M[l + P], t.M[l - P],
-               t.mc[l], t.mc[l + 1], t.mc[l - 1], t.mc[l + P], t.mc[l - P],
+               cflux(M0, m0, t.M[l + 1], t.mc[l + 1]), cflux(t.M[l - 1], t.mc[l - 1], M0, m0),
+               cflux(M0, m0, t.M[l + P], t.mc[l + P]), cflux(t.M[l - P], t.mc[l - P], M0, m0),
                t.mp[l], t.mp[l + 1], t.mp[l - 1], t.mp[l + P], t.mp[l - P], nc, np, nr);
     }
 
@@ -328,11 +257,11 @@ struct Stepper {
                     const int l = r * P + lx;
                     const T pN = t.p[l + P], rN = t.r[l + P], MN = t.M[l + P], mN = t.mc[l + P], qN = t.mp[l + P];
                     const bool bottom = a.pvd && (y0 - R + r) == 0;
-                    update(a.k, vx2h, vy2h, bottom, t.c[l],
+                    update(a.k, rc, vx2h, vy2h, bottom, t.c[l],
                            pC, t.p[l + 1], t.p[l - 1], pN, pS,
                            rC, t.r[l + 1], t.r[l - 1], rN, rS,
-                           MC, t.M[l + 1], t.M[l - 1], MN, MS,
-                           mC, t.mc[l + 1], t.mc[l - 1], mN, mS,
+                           cflux(MC, mC, t.M[l + 1], t.mc[l + 1]), cflux(t.M[l - 1], t.mc[l - 1], MC, mC),
+                           cflux(MC, mC, MN, mN), cflux(MS, mS, MC, mC),
                            qC, t.mp[l + 1], t.mp[l - 1], qN, qS, mc_[i], mp_[i], mr_[i]);
                     inflow(r, lx, rC);
                     pS = pC; pC = pN;
@@ -483,7 +412,9 @@ __global__ __launch_bounds__(256) void step_kernel(StepArgs<T> a)
     const int y0 = (tileid / a.tiles_x) * TY;
 
     const Real rl = a.real[b];
-    Stepper<T, K, TY> st{a, t, s_q, b, x0, y0, tid, tid & 63, tid >> 6, (T)rl.vx2h, (T)rl.vy2h, rl.qa, rl.qb};
+    const T vx2h = (T)rl.vx2h, vy2h = (T)rl.vy2h;
+    Stepper<T, K, TY> st{a,    t,   s_q,  b,     x0,    y0,    tid,  tid & 63, tid >> 6,
+                         vx2h, vy2h, rl.qa, rl.qb, rho_coef(a.k, vx2h, vy2h)};
     st.load();
     const bool top = a.pvd && y0 <= ny - 1 && ny - 1 < y0 + TY;
     if (top && tid < 64 && x0 + tid < nx) s_q[tid] = a.Qcol[(size_t)b * nx + x0 + tid];
@@ -514,7 +445,45 @@ hipError_t launch_k(StepArgs<T> a, int batch, hipStream_t s)
     return hipGetLastError();
 }
 
+template <typename T, int K>
+hipError_t node_k(hipGraph_t g, hipGraphNode_t* node, hipGraphNode_t dep, StepArgs<T> a, int batch)
+{
+    using G = Geo<T, K, Shape<T, K>::TY>;
+    a.fast = (a.nx % G::V == 0) && (a.nx >= 64 + G::A) ? 1 : 0;
+    void* args[] = {&a};
+    hipKernelNodeParams kp{};
+    kp.func = (void*)step_kernel<T, K, Shape<T, K>::TY>;
+    kp.gridDim = dim3(a.tiles_x * a.tiles_y, batch);
+    kp.blockDim = dim3(256);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    return hipGraphAddKernelNode(node, g, dep ? &dep : nullptr, dep ? 1 : 0, &kp);
+}
+
 }  // namespace
+
+template <>
+hipError_t graph_add_step<float>(hipGraph_t g, hipGraphNode_t* node, hipGraphNode_t dep,
+                                 const StepArgs<float>& a, int k, int batch)
+{
+    switch (k) {
+    case 2: return node_k<float, 2>(g, node, dep, a, batch);
+    case 3: return node_k<float, 3>(g, node, dep, a, batch);
+    case 4: return node_k<float, 4>(g, node, dep, a, batch);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <>
+hipError_t graph_add_step<double>(hipGraph_t g, hipGraphNode_t* node, hipGraphNode_t dep,
+                                  const StepArgs<double>& a, int k, int batch)
+{
+    switch (k) {
+    case 2: return node_k<double, 2>(g, node, dep, a, batch);
+    default: return hipErrorInvalidValue;
+    }
+}
 
 template <>
 TileCfg tile_cfg<float>(int k)
@@ -542,7 +511,6 @@ template <>
 hipError_t launch_step<float>(const StepArgs<float>& a, int k, int batch, hipStream_t s)
 {
     switch (k) {
-    case 1: return launch_k<float, 1>(a, batch, s);
     case 2: return launch_k<float, 2>(a, batch, s);
     case 3: return launch_k<float, 3>(a, batch, s);
     case 4: return launch_k<float, 4>(a, batch, s);
@@ -554,7 +522,6 @@ template <>
 hipError_t launch_step<double>(const StepArgs<double>& a, int k, int batch, hipStream_t s)
 {
     switch (k) {
-    case 1: return launch_k<double, 1>(a, batch, s);
     case 2: return launch_k<double, 2>(a, batch, s);
     default: return hipErrorInvalidValue;
     }

@@ -1,0 +1,122 @@
+"""Summaries of rocprofv3 output for the stepper kernels.
+
+    python -m paper_2312_05410_amd.rocprof_summary stats DIR [--kernel SUBSTR]
+    python -m paper_2312_05410_amd.rocprof_summary traffic FETCH_DIR WRITE_DIR --kernel SUBSTR \
+        [--ref-bytes N] [--out FILE] [--command TEXT]
+
+`stats` prints the per-kernel summary of a `--kernel-trace --stats` run.
+`traffic` reads two `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs of the same
+program, whose first large device copy (--ref-bytes bytes, read once and
+written once) calibrates the counters: each counter is scaled by
+ref_bytes / (its reading for that copy).  It prints (or writes) the scaled
+HBM bytes per launch of the kernels whose name contains SUBSTR, tagged with
+a hash of the stepper sources so that a stale summary can be recognised.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import os
+import statistics
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+STEPPER_SOURCES = ("csrc/pf_cell.h", "csrc/pf_march.hip", "csrc/pf_step.hip", "csrc/pf_kernels.h")
+
+
+def stepper_hash() -> str:
+    h = hashlib.sha256()
+    for rel in STEPPER_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def _one(pattern: str) -> str:
+    files = sorted(glob.glob(pattern, recursive=True))
+    if not files:
+        raise SystemExit(f"no file matches {pattern}")
+    return files[0]
+
+
+def stats(d: str, kernel: str | None = None):
+    rows = list(csv.DictReader(open(_one(os.path.join(d, "**", "*kernel_stats.csv")))))
+    out = []
+    for r in rows:
+        if kernel and kernel not in r["Name"]:
+            continue
+        out.append((r["Name"], int(r["Calls"]), float(r["AverageNs"]), float(r["MinNs"]), float(r["MaxNs"]),
+                    float(r["Percentage"])))
+    return out
+
+
+def _counter(d: str, name: str):
+    rows = list(csv.DictReader(open(_one(os.path.join(d, "**", "*counter_collection.csv")))))
+    return [(int(r["Dispatch_Id"]), r["Kernel_Name"], int(r["Grid_Size"]), float(r["Counter_Value"]))
+            for r in rows if r["Counter_Name"] == name]
+
+
+def traffic(fetch_dir: str, write_dir: str, kernel: str, ref_bytes: int):
+    f = _counter(fetch_dir, "FETCH_SIZE")
+    w = _counter(write_dir, "WRITE_SIZE")
+    # reference: the largest copy kernel dispatch
+    ref_f = max((v for _, n, _, v in f if "copyBuffer" in n or "copy" in n.lower()), default=None)
+    ref_w = max((v for _, n, _, v in w if "copyBuffer" in n or "copy" in n.lower()), default=None)
+    if not ref_f or not ref_w:
+        raise SystemExit("no reference copy kernel in the counter runs")
+    sf = ref_bytes / (ref_f * 1024.0)
+    sw = ref_bytes / (ref_w * 1024.0)
+    kf = [v for _, n, _, v in f if kernel in n]
+    kw = [v for _, n, _, v in w if kernel in n]
+    if not kf or not kw:
+        raise SystemExit(f"no dispatch of a kernel matching {kernel!r}")
+    return dict(fetch_kib_raw=statistics.median(kf), write_kib_raw=statistics.median(kw),
+                fetch_scale=sf, write_scale=sw,
+                fetch_bytes=statistics.median(kf) * 1024.0 * sf,
+                write_bytes=statistics.median(kw) * 1024.0 * sw,
+                launches=min(len(kf), len(kw)))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("dir")
+    s.add_argument("--kernel")
+    t = sub.add_parser("traffic")
+    t.add_argument("fetch_dir")
+    t.add_argument("write_dir")
+    t.add_argument("--kernel", required=True)
+    t.add_argument("--ref-bytes", type=int, default=512 * 1024 * 1024)
+    t.add_argument("--out")
+    t.add_argument("--command", default="")
+    a = ap.parse_args(argv)
+    if a.cmd == "stats":
+        for name, calls, avg, mn, mx, pct in stats(a.dir, a.kernel):
+            print(f"{name}\n    calls {calls}  avg {avg / 1e3:.3f} us  min {mn / 1e3:.3f}  max {mx / 1e3:.3f}  "
+                  f"share {pct:.2f} %")
+        return
+    r = traffic(a.fetch_dir, a.write_dir, a.kernel, a.ref_bytes)
+    lines = [f"kernel: {a.kernel}",
+             f"stepper_source_sha256_16: {stepper_hash()}",
+             f"launches_measured: {r['launches']}",
+             f"FETCH_SIZE_KiB_per_launch_raw: {r['fetch_kib_raw']:.1f}",
+             f"WRITE_SIZE_KiB_per_launch_raw: {r['write_kib_raw']:.1f}",
+             f"fetch_scale_from_reference_copy: {r['fetch_scale']:.4f}",
+             f"write_scale_from_reference_copy: {r['write_scale']:.4f}",
+             f"hbm_read_bytes_per_launch: {r['fetch_bytes']:.0f}",
+             f"hbm_write_bytes_per_launch: {r['write_bytes']:.0f}",
+             f"hbm_bytes_per_launch: {r['fetch_bytes'] + r['write_bytes']:.0f}"]
+    if a.command:
+        lines.insert(0, f"command: {a.command}")
+    text = "\n".join(lines) + "\n"
+    if a.out:
+        with open(a.out, "w") as fh:
+            fh.write(text)
+    sys.stdout.write(text)
+
+
+if __name__ == "__main__":
+    main()

@@ -5,6 +5,8 @@
 * dns_1024_f32: 1024 x 1024, FP32 fields with FP64 diagnostics, 50,000
   steps; deposition rate and composition drawn per seed (rate in [0.5, 2] x
   nominal, composition in [0.3, 0.7]).  The throughput workload.
+* dns_8192_f32: the production model on 8192 x 8192 (805 MB of state, 1.6 GB
+  with the ping-pong copy), 500 steps: the size for the HBM-bandwidth claim.
 * batched_32x512_f32: 32 independent 512 x 512 FP32 realisations with seeded
   (rate, composition) pairs, 10,000 steps each.
 
@@ -18,9 +20,10 @@ from .inputs import PFParams, realisation_draws
 
 V0_NOM = 0.5
 
-# fused sub-steps per launch used by the throughput measurement (and by the
-# full-size parity test, which runs the same launch configuration)
-BENCH_TEMPORAL_BLOCK = {"f32": 1, "f64": 1}
+# fused sub-steps per launch used by the throughput measurement and by the
+# full-size parity tests, which run the same launch configuration: 0 means
+# the library's own choice for the grid
+BENCH_TEMPORAL_BLOCK = {"f32": 0, "f64": 0}
 
 
 def dns_small(seed: int = 0, precision: str = "f64") -> PFParams:
@@ -38,4 +41,6 @@ def batched(seed: int = 0, batch: int = 32, n: int = 512, precision: str = "f32"
                     v0_per=v0, c0_per=c0)
 
 
-STEPS = {"dns_small_128_f64": 1000, "dns_1024_f32": 50_000, "batched_32x512_f32": 10_000}
+STEPS = {"dns_small_128_f64": 1000, "dns_1024_f32": 50_000, "batched_32x512_f32": 10_000,
+         # the production model at a size far above the 256 MB Infinity Cache
+         "dns_8192_f32": 500}

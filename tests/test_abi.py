@@ -33,11 +33,11 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_params_struct_layout():
-    # int32 x 10, uint64 seed at 40, 21 doubles, 2 pointers
-    assert _lib.PFParamsC.seed.offset == 40
-    assert _lib.PFParamsC.h.offset == 48
-    assert _lib.PFParamsC.v0_per.offset == 48 + 21 * 8
-    assert ctypes.sizeof(_lib.PFParamsC) == 48 + 21 * 8 + 16
+    # int32 x 12, uint64 seed at 48, 21 doubles, 2 pointers
+    assert _lib.PFParamsC.seed.offset == 48
+    assert _lib.PFParamsC.h.offset == 56
+    assert _lib.PFParamsC.v0_per.offset == 56 + 21 * 8
+    assert ctypes.sizeof(_lib.PFParamsC) == 56 + 21 * 8 + 16
 
 
 def test_strerror():
@@ -101,6 +101,7 @@ def test_init_rejects_bad_pointers_and_workspace():
     assert _init(p, ws=4096 + 64)[0] == _lib.PF_EINVAL                   # workspace not 256-aligned
     assert _init(p, wsize=1024)[0] == _lib.PF_EINVAL                      # workspace too small
     assert _init(p, temporal_block=5)[0] == _lib.PF_EINVAL
+    assert _init(p, tile_rows=12)[0] == _lib.PF_EINVAL
     assert _init(p.replace(precision="f64"), temporal_block=3)[0] == _lib.PF_EINVAL
     L = _lib.load()
     assert L.pf_step_n(None, 3) == _lib.PF_EINVAL

@@ -211,6 +211,46 @@ def test_temporal_blocking_is_bitwise(prec, Ks):
     ref.close()
 
 
+@pytest.mark.parametrize("prec,K", [("f32", 1), ("f32", 2), ("f64", 1)])
+def test_graph_replay_is_bitwise(prec, K):
+    """Long runs replay a HIP graph of launches; it must equal plain launches."""
+    announce(f"graph replay {prec} K={K}")
+    p = PFParams(nx=192, ny=80, precision=prec, theta_deg=66.0, v0=0.7)
+    state = random_state(26, 1, 80, 192)
+    n = 64 * 3 * K + 5
+    out = []
+    for mode in (0, 1):
+        sim = Sim(p, state=state, temporal_block=K, graph_mode=mode)
+        sim.step(n)
+        sim.step(n + 1)
+        out.append((sim.state(), sim.inflow()))
+        sim.close()
+    for u, v in zip(out[0][0], out[1][0]):
+        assert np.array_equal(u, v)
+    assert np.array_equal(out[0][1], out[1][1])
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_march_chunk_heights_are_bitwise(prec):
+    """The single-step kernel at every chunk height equals the LDS-tiled
+    two-step kernel bit for bit (same per-cell arithmetic)."""
+    announce(f"march chunk heights {prec}")
+    p = PFParams(nx=150, ny=100, precision=prec, theta_deg=58.0, v0=0.9)
+    state = random_state(27, 1, 100, 150)
+    ref = Sim(p, state=state, temporal_block=2)
+    ref.step(37)
+    base = ref.state()
+    qb = ref.inflow()
+    ref.close()
+    for rows in (4, 8, 16, 32):
+        sim = Sim(p, state=state, temporal_block=1, tile_rows=rows)
+        sim.step(37)
+        for u, v in zip(sim.state(), base):
+            assert np.array_equal(u, v), f"rows={rows}"
+        assert np.array_equal(sim.inflow(), qb), f"rows={rows}"
+        sim.close()
+
+
 def test_runs_are_deterministic():
     announce("determinism")
     p = workloads.dns_small(1, "f32").replace(nx=256, ny=192)
