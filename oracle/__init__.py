@@ -70,7 +70,11 @@ def lib():
         L.or_step_n.argtypes = [P, ctypes.c_void_p, ctypes.c_int64, dp, dp, dp, dp]
         L.or_mass.argtypes = [P, dp, dp, dp, dp, dp]
         L.or_energy.argtypes = [P, dp, dp, dp]
-        for f in (L.or_init, L.or_potentials, L.or_step_n, L.or_mass, L.or_energy):
+        L.or_adjoint_step.argtypes = [P, ctypes.c_double, dp, dp, dp, dp, dp, dp, dp]
+        L.or_loss_grad.argtypes = [P, ctypes.c_double, ctypes.c_int64, ctypes.c_int64,
+                                   dp, dp, dp, dp, dp, dp, dp]
+        for f in (L.or_init, L.or_potentials, L.or_step_n, L.or_mass, L.or_energy,
+                  L.or_adjoint_step, L.or_loss_grad):
             f.restype = None
         _lib = L
     return _lib
@@ -173,3 +177,46 @@ class State:
         out = np.empty(self.p.batch)
         lib().or_energy(ctypes.byref(to_c(self.p, self.dt)), _ptr(self.c), _ptr(self.phi), _ptr(out))
         return out
+
+
+# ------------------------------------------------------------------ adjoint
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def adjoint_step(p, v0: float, dt: float, state, lam):
+    """(lambda_prev, g) for one step of one realisation from `state` =
+    (c, phi, rho) [ny, nx], given lam = dL/du' as three [ny, nx] arrays.
+    g = (dL/dM_scale, dL/dv0) contributions of this step (fixed dt)."""
+    c, phi, rho = (_f64(u) for u in state)
+    lc, lp, lr = (np.array(u, dtype=np.float64) for u in lam)
+    g = np.zeros(2)
+    cp = to_c(p.replace(batch=1) if hasattr(p, "replace") else p, dt)
+    lib().or_adjoint_step(ctypes.byref(cp), float(v0), _ptr(c), _ptr(phi), _ptr(rho),
+                          _ptr(lc), _ptr(lp), _ptr(lr), _ptr(g))
+    return (lc, lp, lr), g
+
+
+def loss_grad(p, v0: float, dt: float, n: int, every: int, state, target):
+    """(L, dL/dM_scale, dL/dv0) of L = h^2/2 sum (u_n - u*)^2 after n steps of
+    one realisation from `state`, by the checkpointed adjoint."""
+    c, phi, rho = (_f64(u) for u in state)
+    ct, pt, rt = (_f64(u) for u in target)
+    out = np.zeros(3)
+    cp = to_c(p.replace(batch=1) if hasattr(p, "replace") else p, dt)
+    lib().or_loss_grad(ctypes.byref(cp), float(v0), int(n), int(every), _ptr(c), _ptr(phi), _ptr(rho),
+                       _ptr(ct), _ptr(pt), _ptr(rt), _ptr(out))
+    return out
+
+
+def run(p, v0: float, dt: float, n: int, state):
+    """Final (c, phi, rho) [ny, nx] after n steps of one realisation."""
+    q = p.replace(batch=1, v0=float(v0), v0_per=None, c0_per=None)
+    s = State(q, *(np.asarray(u)[None] for u in state), dt=dt).step(n)
+    return s.c[0], s.phi[0], s.rho[0]
+
+
+def loss(p, v0, dt, n, state, target):
+    u = run(p, v0, dt, n, state)
+    return 0.5 * p.h ** 2 * sum(float(np.sum((a - b) ** 2)) for a, b in zip(u, target))

@@ -339,3 +339,213 @@ void or_energy(const or_params* p, const double* c, const double* phi,
         out[b] = h2 * bulk + 0.5 * p->kappa_c * grad_c + 0.5 * p->kappa_phi * grad_p;
     }
 }
+
+/* ============================================================== adjoint
+ * Reverse mode of one step, written as a scatter: for every cell, each term
+ * of its right-hand side R_i sends its partial derivatives (times the
+ * incoming cotangent dt lambda'_i) to the cells whose values it read.  The
+ * chain through mu_c, mu_phi and M_c is taken in a second pass.  Mirror
+ * ghosts map to the cell itself and the rho inlet ghost is a constant, so
+ * the same neighbour rules as the forward step give the transpose.
+ */
+
+static int cell(const or_params* p, int i, int j)
+{
+    return yrow(p, j) * p->nx + imod(i, p->nx);
+}
+
+/* index of rho's neighbour, or -1 for the constant inlet value */
+static int rho_cell(const or_params* p, int i, int j)
+{
+    if (p->bc_mode == OR_BC_PVD && j >= p->ny) return -1;
+    return cell(p, i, j);
+}
+
+static double d2gfun(double c) { return 2.0 * (1.0 - 6.0 * c + 6.0 * c * c); }
+static double d2pfun(double phi) { return -1.5 * phi; }
+
+/* m(c, phi) = M_c / M_scale and its partial derivatives (zero where the
+ * clamps are active) */
+static void mobility_partials(const or_params* p, double c, double phi,
+                              double* m, double* dm_dc, double* dm_dphi)
+{
+    double x = clampd(c, 0.0, 1.0), ph = clampd(phi, -1.0, 1.0);
+    double H = hswitch(c);
+    double dH = 30.0 * x * x * (1.0 - x) * (1.0 - x);
+    double bulk = H * p->MA_bulk + (1.0 - H) * p->MB_bulk;
+    double surf = H * p->MA_surf + (1.0 - H) * p->MB_surf;
+    double q = ph / p->sigma_surf;
+    double e = exp(-q * q);
+    double de = -2.0 * ph / (p->sigma_surf * p->sigma_surf) * e;
+    *m = pfun(ph) * bulk + e * surf;
+    *dm_dc = (c > 0.0 && c < 1.0)
+                 ? (pfun(ph) * (p->MA_bulk - p->MB_bulk) + e * (p->MA_surf - p->MB_surf)) * dH : 0.0;
+    *dm_dphi = (phi > -1.0 && phi < 1.0) ? dpfun(ph) * bulk + de * surf : 0.0;
+}
+
+void or_adjoint_step(const or_params* p, double v0, const double* c, const double* phi,
+                     const double* rho, double* lc, double* lphi, double* lrho, double* g)
+{
+    int nx = p->nx, ny = p->ny;
+    size_t n = (size_t)nx * ny;
+    double h = p->h, h2 = h * h, dt = p->dt;
+    int pvd = p->bc_mode == OR_BC_PVD;
+    double vx, vy, dvx = 0.0, dvy = 0.0;
+    velocity(p, v0, &vx, &vy);
+    if (p->flux_on) {
+        double th = p->theta_deg * (3.14159265358979323846 / 180.0);
+        dvx = cos(th);
+        dvy = -sin(th);
+    }
+    double* buf = (double*)calloc(9 * n, sizeof(double));
+    if (!buf) abort();
+    double *mu = buf, *nu = buf + n, *M = buf + 2 * n;
+    double *gc = buf + 3 * n, *gp = buf + 4 * n, *gr = buf + 5 * n;
+    double *mub = buf + 6 * n, *nub = buf + 7 * n, *Mb = buf + 8 * n;
+    or_potentials(p, c, phi, mu, nu, M);
+
+    const int di[4] = {1, -1, 0, 0}, dj[4] = {0, 0, 1, -1};
+    for (int j = 0; j < ny; ++j) {
+        for (int i = 0; i < nx; ++i) {
+            int k = j * nx + i;
+            double wc = dt * lc[k], wp = dt * lphi[k], wr = dt * lrho[k];
+            /* composition: face terms (M_k + M_n)(mu_n - mu_k) / (2 h^2) */
+            for (int q = 0; q < 4; ++q) {
+                int kn = cell(p, i + di[q], j + dj[q]);
+                double a = wc * 0.5 / h2;
+                double dmu = mu[kn] - mu[k], sm = M[k] + M[kn];
+                Mb[k] += a * dmu;
+                Mb[kn] += a * dmu;
+                mub[kn] += a * sm;
+                mub[k] -= a * sm;
+            }
+            /* order parameter: M_phi (nu_n - nu_k) / h^2 */
+            for (int q = 0; q < 4; ++q) {
+                int kn = cell(p, i + di[q], j + dj[q]);
+                nub[kn] += wp * p->M_phi / h2;
+                nub[k] -= wp * p->M_phi / h2;
+            }
+            /* deposition S = rho (vx (phiE - phiW) + vy (phiN - phiS)) / 2h,
+             * added to phi and subtracted from rho */
+            int kE = cell(p, i + 1, j), kW = cell(p, i - 1, j);
+            int kN = cell(p, i, j + 1), kS = cell(p, i, j - 1);
+            double sb = wp - wr;
+            double gx = phi[kE] - phi[kW], gy = phi[kN] - phi[kS];
+            gr[k] += sb * (vx * gx + vy * gy) / (2.0 * h);
+            gp[kE] += sb * rho[k] * vx / (2.0 * h);
+            gp[kW] -= sb * rho[k] * vx / (2.0 * h);
+            gp[kN] += sb * rho[k] * vy / (2.0 * h);
+            gp[kS] -= sb * rho[k] * vy / (2.0 * h);
+            g[1] += sb * rho[k] * (dvx * gx + dvy * gy) / (2.0 * h);
+            /* vapour: D Lap rho - ((Fe - Fw) + (Gn - Gs)) / h */
+            int rE = rho_cell(p, i + 1, j), rW = rho_cell(p, i - 1, j);
+            int rN = rho_cell(p, i, j + 1), rS = rho_cell(p, i, j - 1);
+            int bottom = pvd && j == 0;
+            double r0 = rho[k];
+            double vE = rE >= 0 ? rho[rE] : p->rho_in, vW = rW >= 0 ? rho[rW] : p->rho_in;
+            double vN = rN >= 0 ? rho[rN] : p->rho_in, vS = rS >= 0 ? rho[rS] : p->rho_in;
+            double dD = p->D_rho / h2;
+            double cE = dD - vx / (2.0 * h), cW = dD + vx / (2.0 * h);
+            double cN = dD - vy / (2.0 * h), cS = bottom ? dD : dD + vy / (2.0 * h);
+            double c0 = -4.0 * dD + (bottom ? -vy / (2.0 * h) : 0.0);
+            if (rE >= 0) gr[rE] += wr * cE;
+            if (rW >= 0) gr[rW] += wr * cW;
+            if (rN >= 0) gr[rN] += wr * cN;
+            if (rS >= 0) gr[rS] += wr * cS;
+            gr[k] += wr * c0;
+            double dT = -((dvx * 0.5 * (r0 + vE) - dvx * 0.5 * (vW + r0))
+                          + (dvy * 0.5 * (r0 + vN) - (bottom ? 0.0 : dvy * 0.5 * (vS + r0)))) / h;
+            g[1] += wr * dT;
+        }
+    }
+    /* chain through mu_c, mu_phi and M_c */
+    for (int j = 0; j < ny; ++j) {
+        for (int i = 0; i < nx; ++i) {
+            int k = j * nx + i;
+            double cc = c[k], pp = phi[k];
+            /* mu_c = W_c p g' - kappa_c Lap c */
+            gc[k] += mub[k] * p->W_c * pfun(pp) * d2gfun(cc);
+            gp[k] += mub[k] * p->W_c * dpfun(pp) * dgfun(cc);
+            /* mu_phi = W_c p' g - W_phi phi (1 - phi^2) - kappa_phi Lap phi */
+            gp[k] += nub[k] * (p->W_c * d2pfun(pp) * gfun(cc) - p->W_phi * (1.0 - 3.0 * pp * pp));
+            gc[k] += nub[k] * p->W_c * dpfun(pp) * dgfun(cc);
+            for (int q = 0; q < 4; ++q) {
+                int kn = cell(p, i + di[q], j + dj[q]);
+                gc[kn] -= p->kappa_c / h2 * mub[k];
+                gc[k] += p->kappa_c / h2 * mub[k];
+                gp[kn] -= p->kappa_phi / h2 * nub[k];
+                gp[k] += p->kappa_phi / h2 * nub[k];
+            }
+            /* M_c = M_scale m(c, phi) */
+            double m, dmc, dmp;
+            mobility_partials(p, cc, pp, &m, &dmc, &dmp);
+            gc[k] += Mb[k] * p->M_scale * dmc;
+            gp[k] += Mb[k] * p->M_scale * dmp;
+            g[0] += Mb[k] * m;
+        }
+    }
+    for (size_t k = 0; k < n; ++k) {
+        lc[k] += gc[k];
+        lphi[k] += gp[k];
+        lrho[k] += gr[k];
+    }
+    free(buf);
+}
+
+void or_loss_grad(const or_params* p, double v0, int64_t n, int64_t every,
+                  const double* c, const double* phi, const double* rho,
+                  const double* ct, const double* phit, const double* rhot, double* out)
+{
+    size_t cells = (size_t)p->nx * p->ny;
+    if (every < 1) every = 1;
+    int64_t nseg = (n + every - 1) / every;
+    if (nseg < 1) nseg = 1;
+    double* ck = (double*)malloc((size_t)nseg * 3 * cells * sizeof(double));
+    double* seg = (double*)malloc((size_t)every * 3 * cells * sizeof(double));
+    double* w = (double*)malloc(9 * cells * sizeof(double));
+    double* u = (double*)malloc(3 * cells * sizeof(double));
+    double* lam = (double*)malloc(3 * cells * sizeof(double));
+    if (!ck || !seg || !w || !u || !lam) abort();
+    memcpy(u, c, cells * sizeof(double));
+    memcpy(u + cells, phi, cells * sizeof(double));
+    memcpy(u + 2 * cells, rho, cells * sizeof(double));
+    double Q = 0.0;
+    /* forward, keeping the state at the start of every segment */
+    for (int64_t s = 0; s < n; ++s) {
+        if (s % every == 0) memcpy(ck + (size_t)(s / every) * 3 * cells, u, 3 * cells * sizeof(double));
+        step_one(p, v0, u, u + cells, u + 2 * cells, &Q, w, w + cells, w + 2 * cells,
+                 w + 3 * cells, w + 4 * cells, w + 5 * cells);
+    }
+    double L = 0.0, h2 = p->h * p->h;
+    const double* tgt[3] = {ct, phit, rhot};
+    for (int f = 0; f < 3; ++f)
+        for (size_t k = 0; k < cells; ++k) {
+            double d = u[f * cells + k] - tgt[f][k];
+            L += 0.5 * h2 * d * d;
+            lam[f * cells + k] = h2 * d;
+        }
+    double g[2] = {0.0, 0.0};
+    /* reverse: recompute each segment's states from its checkpoint */
+    for (int64_t sg = nseg - 1; sg >= 0; --sg) {
+        int64_t s0 = sg * every, s1 = s0 + every < n ? s0 + every : n;
+        memcpy(seg, ck + (size_t)sg * 3 * cells, 3 * cells * sizeof(double));
+        for (int64_t t = 1; t < s1 - s0; ++t) {
+            double* dst = seg + (size_t)t * 3 * cells;
+            memcpy(dst, dst - 3 * cells, 3 * cells * sizeof(double));
+            step_one(p, v0, dst, dst + cells, dst + 2 * cells, &Q, w, w + cells, w + 2 * cells,
+                     w + 3 * cells, w + 4 * cells, w + 5 * cells);
+        }
+        for (int64_t t = s1 - s0 - 1; t >= 0; --t) {
+            const double* st = seg + (size_t)t * 3 * cells;
+            or_adjoint_step(p, v0, st, st + cells, st + 2 * cells, lam, lam + cells, lam + 2 * cells, g);
+        }
+    }
+    out[0] = L;
+    out[1] = g[0];
+    out[2] = g[1];
+    free(ck);
+    free(seg);
+    free(w);
+    free(u);
+    free(lam);
+}

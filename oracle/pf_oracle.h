@@ -70,6 +70,24 @@ void or_mass(const or_params* p, const double* c, const double* phi,
 void or_energy(const or_params* p, const double* c, const double* phi,
                double* out);
 
+/* ------------------------------------------------------------- adjoint
+ * Discrete adjoint of one explicit Euler step u' = u + dt R(u; M_scale, v0)
+ * of one realisation.  On entry (lc, lphi, lrho) hold lambda' = dL/du'; on
+ * exit they hold dL/du = lambda' + (dR/du)^T (dt lambda').  g[0] and g[1]
+ * receive += dt lambda'.(dR/dM_scale) and += dt lambda'.(dR/dv0), at fixed
+ * dt.  (c, phi, rho) is the state u the step started from. */
+void or_adjoint_step(const or_params* p, double v0, const double* c, const double* phi,
+                     const double* rho, double* lc, double* lphi, double* lrho, double* g);
+
+/* Loss L = h^2/2 sum over c, phi, rho of (u_n - u*)^2 after n steps of one
+ * realisation from (c, phi, rho), and its gradient with respect to M_scale
+ * and v0 (fixed dt) by the adjoint with checkpoints every `every` steps and
+ * recomputation.  out = {L, dL/dM_scale, dL/dv0}.  The inputs are not
+ * modified. */
+void or_loss_grad(const or_params* p, double v0, int64_t n, int64_t every,
+                  const double* c, const double* phi, const double* rho,
+                  const double* ct, const double* phit, const double* rhot, double* out);
+
 #ifdef __cplusplus
 }
 #endif
