@@ -39,7 +39,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="dns_1024_f32",
-                    choices=["dns_1024_f32", "dns_8192_f32", "batched_32x512_f32", "dns_small_128_f64"])
+                    choices=["dns_1024_f32", "dns_8192_f32", "batched_32x512_f32", "dns_small_128_f64",
+                             "adjoint_256_f32"])
     ap.add_argument("--temporal-block", type=int, default=None)
     ap.add_argument("--graph-mode", type=int, default=0, help="0: replay HIP graphs of launches; 1: plain launches")
     ap.add_argument("--no-sweep", action="store_true")
@@ -185,8 +186,52 @@ def cpu_leg(p, seconds: float):
                        f"({el:.1f} s, OpenMP over rows)")
 
 
+def adjoint_leg(args):
+    """Forward with checkpoints plus the reverse sweep (recompute + adjoint)
+    of the adjoint workload; GLUPS counts forward steps of the whole job."""
+    import torch
+
+    from paper_2312_05410_amd import workloads
+    from paper_2312_05410_amd.adjoint import final_state, l2_mismatch
+    from paper_2312_05410_amd.inputs import initial_state
+
+    p = workloads.adjoint_case(precision="f32")
+    n, every = workloads.ADJOINT_STEPS, workloads.ADJOINT_EVERY
+    c, phi, rho = initial_state(p)
+    dev = lambda a: torch.as_tensor(a, dtype=torch.float32, device="cuda").contiguous()
+    u0 = (dev(c), dev(phi), dev(rho))
+    # target: the same seed with the target parameters, run by the stepper
+    tp = p.replace(M_scale=workloads.ADJOINT_TARGET[0], v0=workloads.ADJOINT_TARGET[1] * p.v0)
+    from paper_2312_05410_amd._lib import Simulator
+
+    ts = Simulator(tp, tensors=[t.clone() for t in u0])
+    ts.step(n)
+    target = (ts.c, ts.phi, ts.rho)
+    times = []
+    for rep in range(2):
+        Ms = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+        v0 = torch.tensor(p.v0, dtype=torch.float64, requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L = l2_mismatch(final_state(Ms, v0, p, u0, n, every), target, p.h)
+        L.backward()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    el = times[-1]
+    cells = p.nx * p.ny
+    return {"metric": "adjoint forward+reverse time", "value": round(el * 1e3, 2), "unit": "ms",
+            "n_gpus": 1, "steps": n, "warmup": 1, "higher_is_better": False, "dtype": "f32",
+            "data": "synthetic (seeded)", "vs_baseline": None,
+            "config": {"workload": "adjoint_256_f32", "nx": p.nx, "ny": p.ny, "checkpoint_every": every,
+                       "loss": float(L), "dL_dMscale": float(Ms.grad), "dL_dv0": float(v0.grad)},
+            "glups_equiv": round(cells * n / el / 1e9, 3)}
+
+
 def main():
     args = parse()
+    if args.workload == "adjoint_256_f32":
+        print(json.dumps(adjoint_leg(args)), flush=True)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                                    "(multi-GPU sharding is a design note, not implemented)"}))

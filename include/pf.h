@@ -155,6 +155,30 @@ void pf_destroy(pf_handle* h);
  * strip-march kernel; 2..4: LDS-tiled kernel) and rows per wave / tile. */
 int pf_get_launch(const pf_handle* h, int32_t* temporal_block, int32_t* tile_rows);
 
+/* ------------------------------------------------------------------ adjoint
+ * Discrete adjoint of the explicit step, for gradients of a loss of the
+ * final state with respect to the mobility scale M_scale and the deposition
+ * rate v0 at fixed dt (the inverse-design use the paper's Discussion names).
+ * For one step u' = u + dt R(u; M_scale, v0) started from the state
+ * (c, phi, rho), pf_adjoint_step writes lambda = lambda' + (dR/du)^T
+ * (dt lambda') into out_* given lambda' = dL/du' in lam_*, and adds
+ * dt lambda'.dR/dM_scale and dt lambda'.dR/dv0 per cell into FP64
+ * accumulators in the adjoint workspace.  All arrays are device buffers with
+ * the state's layout and precision; out_* must not alias lam_*.  The handle
+ * supplies the model, dt and the stream (enqueued, returns at once).
+ * M_scale must be positive.  A checkpointed reverse sweep calls it once per
+ * step, from the last step to the first, on recomputed states. */
+size_t pf_adjoint_workspace_bytes(const pf_params* p);
+int pf_adjoint_step(pf_handle* h, const void* c, const void* phi, const void* rho,
+                    const void* lam_c, const void* lam_phi, const void* lam_rho,
+                    void* out_c, void* out_phi, void* out_rho,
+                    void* adj_workspace, size_t adj_bytes);
+/* Zero the parameter-gradient accumulators (enqueued). */
+int pf_adjoint_reset(pf_handle* h, void* adj_workspace, size_t adj_bytes);
+/* Wait for the stream and write out[2*b] = dL/dM_scale, out[2*b+1] = dL/dv0
+ * of realisation b, summed in FP64 in a fixed order. */
+int pf_adjoint_grad(pf_handle* h, void* adj_workspace, size_t adj_bytes, double* out);
+
 /* Text of a pf_status code. */
 const char* pf_strerror(int code);
 

@@ -27,6 +27,7 @@ EXPORTS = (
     "pf_workspace_bytes", "pf_dt_limit", "pf_init", "pf_step_n", "pf_mass", "pf_energy",
     "pf_get_step", "pf_set_step", "pf_get_dt", "pf_get_inflow", "pf_set_inflow",
     "pf_destroy", "pf_strerror", "pf_last_hip_error", "pf_get_launch",
+    "pf_adjoint_workspace_bytes", "pf_adjoint_step", "pf_adjoint_reset", "pf_adjoint_grad",
 )
 
 
@@ -101,6 +102,14 @@ def load():
         L.pf_last_hip_error.restype = ctypes.c_int
         L.pf_get_launch.argtypes = [H, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]
         L.pf_get_launch.restype = ctypes.c_int
+        L.pf_adjoint_workspace_bytes.argtypes = [P]
+        L.pf_adjoint_workspace_bytes.restype = ctypes.c_size_t
+        L.pf_adjoint_step.argtypes = [H] * 11 + [ctypes.c_size_t]
+        L.pf_adjoint_step.restype = ctypes.c_int
+        L.pf_adjoint_reset.argtypes = [H, H, ctypes.c_size_t]
+        L.pf_adjoint_reset.restype = ctypes.c_int
+        L.pf_adjoint_grad.argtypes = [H, H, ctypes.c_size_t, dp]
+        L.pf_adjoint_grad.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -166,7 +175,10 @@ class Simulator:
     pf_handle that steps them on the current stream of `device`."""
 
     def __init__(self, p: PFParams, state=None, temporal_block: int = 0, device: str = "cuda",
-                 allow_unstable: bool = False, graph_mode: int = 0, tile_rows: int = 0):
+                 allow_unstable: bool = False, graph_mode: int = 0, tile_rows: int = 0, tensors=None):
+        """state: host arrays copied to the device as the initial condition;
+        tensors: (c, phi, rho) device tensors stepped in place (no copy);
+        neither: the seeded initial condition."""
         import torch
 
         L = load()
@@ -174,7 +186,15 @@ class Simulator:
         self.device = torch.device(device)
         dtype = torch.float64 if p.precision == "f64" else torch.float32
         shape = (p.batch, p.ny, p.nx)
-        if state is None:
+        if tensors is not None:
+            for u in tensors:
+                if u.dtype != dtype or tuple(u.shape) != shape or not u.is_contiguous() or u.device.type != "cuda":
+                    raise ValueError("tensors must be contiguous device tensors of shape (batch, ny, nx) "
+                                     "and the handle's precision")
+            self.c, self.phi, self.rho = tensors
+            self.device = tensors[0].device
+            mode = PF_INIT_KEEP
+        elif state is None:
             self.c, self.phi, self.rho = (torch.empty(shape, dtype=dtype, device=self.device) for _ in range(3))
             mode = PF_INIT_SEEDED
         else:
@@ -245,6 +265,31 @@ class Simulator:
         out = ctypes.c_int64()
         self._check(load().pf_get_step(self._h, ctypes.byref(out)), "pf_get_step")
         return out.value
+
+    # -- adjoint -------------------------------------------------------------------
+    def adjoint_workspace(self):
+        """A zeroed device workspace for the adjoint calls of this handle."""
+        import torch
+
+        s, _keep = to_c(self.p)
+        n = load().pf_adjoint_workspace_bytes(ctypes.byref(s))
+        if n == 0:
+            raise PFError(PF_EINVAL, "pf_adjoint_workspace_bytes")
+        ws = torch.empty(n, dtype=torch.uint8, device=self.device)
+        self._check(load().pf_adjoint_reset(self._h, ws.data_ptr(), n), "pf_adjoint_reset")
+        return ws
+
+    def adjoint_step(self, state, lam, out, ws) -> None:
+        """out = lam + (dR/du)^T dt lam at `state`; (c, phi, rho) tensors each."""
+        args = [u.data_ptr() for u in (*state, *lam, *out)]
+        self._check(load().pf_adjoint_step(self._h, *args, ws.data_ptr(), ws.numel()), "pf_adjoint_step")
+
+    def adjoint_grad(self, ws) -> np.ndarray:
+        """[batch, 2] accumulated (dL/dM_scale, dL/dv0)."""
+        out = np.empty((self.p.batch, 2))
+        self._check(load().pf_adjoint_grad(self._h, ws.data_ptr(), ws.numel(),
+                                           out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))), "pf_adjoint_grad")
+        return out
 
     def state(self):
         """Host float64 copies of (c, phi, rho), after the stream finishes."""

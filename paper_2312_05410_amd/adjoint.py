@@ -1,0 +1,83 @@
+"""Gradients of a final-state loss with respect to the mobility scale and
+the deposition rate, through the library's discrete adjoint.
+
+`final_state(M_scale, v0, p, u0, n, every)` runs n explicit steps of the
+stepper from u0 = (c, phi, rho) and returns the final fields; as a
+torch.autograd.Function its backward sweeps the steps in reverse with the
+hand-written adjoint kernels (pf_adjoint_step), recomputing each segment of
+`every` steps from a stored checkpoint, so memory holds n/every checkpoints
+plus one segment instead of all n states.  Gradients are taken at fixed dt
+(p.dt must be set) and are summed over the realisations of the batch.
+Every step, forward and reverse, runs in the HIP library; torch only holds
+the buffers and copies checkpoints.
+"""
+from __future__ import annotations
+
+import torch
+
+from .inputs import PFParams
+
+
+class _FinalState(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, Ms, v0, p: PFParams, c0, phi0, rho0, n: int, every: int, temporal_block: int):
+        from ._lib import Simulator
+
+        if not (p.dt > 0):
+            raise ValueError("final_state needs a fixed dt (p.dt > 0)")
+        q = p.replace(M_scale=float(Ms), v0=float(v0), v0_per=None)
+        u = [t.detach().clone().contiguous() for t in (c0, phi0, rho0)]
+        sim = Simulator(q, tensors=u, temporal_block=temporal_block)
+        ckpts = []
+        for s in range(0, n, every):
+            ckpts.append([t.clone() for t in u])
+            sim.step(min(every, n - s))
+        ctx.q, ctx.n, ctx.every, ctx.ckpts = q, n, every, ckpts
+        ctx.temporal_block = temporal_block
+        out = tuple(t.clone() for t in u)
+        sim.close()
+        return out
+
+    @staticmethod
+    def backward(ctx, gc, gphi, grho):
+        from ._lib import Simulator
+
+        q, n, every = ctx.q, ctx.n, ctx.every
+        dtype = ctx.ckpts[0][0].dtype
+        lam = [g.detach().to(dtype).contiguous() if g is not None else torch.zeros_like(ctx.ckpts[0][i])
+               for i, g in enumerate((gc, gphi, grho))]
+        nxt = [torch.empty_like(t) for t in lam]
+        work = [torch.empty_like(t) for t in ctx.ckpts[0]]
+        rec = Simulator(q, tensors=work, temporal_block=ctx.temporal_block)
+        ws = rec.adjoint_workspace()
+        nseg = len(ctx.ckpts)
+        for sg in range(nseg - 1, -1, -1):
+            s0 = sg * every
+            length = min(every, n - s0)
+            for w, ck in zip(work, ctx.ckpts[sg]):
+                w.copy_(ck)
+            states = [[t.clone() for t in work]]
+            for _ in range(1, length):
+                rec.step(1)
+                states.append([t.clone() for t in work])
+            for t in range(length - 1, -1, -1):
+                rec.adjoint_step(states[t], lam, nxt, ws)
+                lam, nxt = nxt, lam
+        g = rec.adjoint_grad(ws).sum(axis=0)
+        rec.close()
+        ctx.ckpts = None
+        dMs = torch.tensor(g[0], dtype=torch.float64)
+        dv0 = torch.tensor(g[1], dtype=torch.float64)
+        return dMs, dv0, None, lam[0], lam[1], lam[2], None, None, None
+
+
+def final_state(Ms, v0, p: PFParams, u0, n: int, every: int = 50, temporal_block: int = 0):
+    """Final (c, phi, rho) after n steps; differentiable in Ms, v0 and u0."""
+    Ms = torch.as_tensor(Ms, dtype=torch.float64)
+    v0 = torch.as_tensor(v0, dtype=torch.float64)
+    return _FinalState.apply(Ms, v0, p, u0[0], u0[1], u0[2], n, every, temporal_block)
+
+
+def l2_mismatch(u, target, h: float = 1.0):
+    """h^2/2 sum over the three fields of (u - u*)^2, in FP64."""
+    return 0.5 * h * h * sum(((a.double() - b.double()) ** 2).sum() for a, b in zip(u, target))

@@ -1,0 +1,324 @@
+// gfx950 discrete adjoint of the explicit PVD phase-field step.
+//
+// For u' = u + dt R(u; M_scale, v0) and a cotangent lambda' = dL/du', one
+// adjoint step produces lambda = lambda' + (dR/du)^T w with w = dt lambda',
+// and accumulates w . dR/dM_scale and w . dR/dv0 per cell in FP64.  The
+// transpose is taken as a gather (each thread owns one output cell, no
+// atomics) in three passes over the grid:
+//   pass 0  forward potentials mu_c, mu_phi, M_c (the shared per-cell code of
+//           the stepper) and the mobility partials dM/dc, dM/dphi;
+//   pass A  cotangents of the intermediates at every cell:
+//             mubar = sum_n (M + M_n)(w_c,n - w_c) / 2h^2   (CH operator on w_c)
+//             Mbar  = sum_n (mu_n - mu)(w_c - w_c,n) / 2h^2
+//             nubar = M_phi Lap w_phi,  Sbar = w_phi - w_rho;
+//   pass B  chain rule back to (c, phi, rho): the pointwise derivatives of
+//           mu_c, mu_phi and M_c, the symmetric Laplacians of mubar and
+//           nubar, the transposed deposition stencil (an anti-mirrored
+//           ghost in y for Sbar rho) and the transposed vapour
+//           transport (inlet ghost is a constant; the substrate row keeps
+//           its own mirror coefficient).
+// The boundary rules are the transposes of the forward step's.
+#include "pf_cell.h"
+
+namespace pfk {
+namespace {
+
+using namespace cell;
+
+template <typename T>
+struct AdjArgs {
+    const T* c;
+    const T* phi;
+    const T* rho;
+    const T* lc;       // lambda' (in)
+    const T* lp;
+    const T* lr;
+    T* oc;             // lambda (out)
+    T* op;
+    T* orr;
+    // scratch [B][ny][nx]: forward intermediates and cotangents
+    T* mu;
+    T* nu;
+    T* M;
+    T* dMc;
+    T* dMp;
+    T* mbar;
+    T* nbar;
+    T* Mbar;
+    T* sig;            // Sbar rho
+    double* gacc;      // [2][B][ny][nx] accumulated parameter gradients
+    const Real* real;
+    Coef<T> k;
+    T Mscale_inv;      // 1 / M_scale (0 if M_scale == 0)
+    T cosx, siny;      // d vx/d v0 = cos(theta), d vy/d v0 = -sin(theta) (0 if flux off)
+    T inv2h;
+    int nx, ny, pvd, batch;
+};
+
+__device__ __forceinline__ int wrapi(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
+
+// neighbour row under the forward rule for c and phi: mirror (PVD) or wrap
+__device__ __forceinline__ int nrow(int j, int n, int pvd)
+{
+    if (pvd) return j < 0 ? 0 : (j >= n ? n - 1 : j);
+    return wrapi(j, n);
+}
+
+template <typename T>
+__device__ __forceinline__ T ld(const T* a, int i, int j, int nx) { return a[(size_t)j * nx + i]; }
+
+// dM_c/dc and dM_c/dphi (the coefficients in Coef are already scaled by
+// M_scale), zero where the clamps are active
+template <typename T>
+__device__ __forceinline__ void mobility_grad(const Coef<T>& k, T c, T p, T& dmc, T& dmp)
+{
+    const T x = clampT(c, T(0), T(1));
+    const T ph = clampT(p, T(-1), T(1));
+    const T H = ((x * x) * x) * fmaT(fmaT(T(6), x, T(-15)), x, T(10));
+    const T om = T(1) - x;
+    const T dH = T(30) * (x * x) * (om * om);
+    const T r1 = T(1) + ph;
+    const T pb = (T(0.25) * (T(2) - ph)) * (r1 * r1);
+    const T dpb = T(0.75) * (T(1) - ph * ph);
+    const T e = surf_exp(ph * ph, k.esurf);
+    // d e / d phi = -2 phi / sigma^2 e; esurf holds 1/sigma^2 (double) or
+    // log2(e)/sigma^2 (float)
+    const T inv_s2 = sizeof(T) == 4 ? k.esurf * T(0.6931471805599453) : k.esurf;
+    const T de = T(-2) * ph * inv_s2 * e;
+    const T bulk = fmaT(H, k.dMb, k.MBb), surf = fmaT(H, k.dMs, k.MBs);
+    dmc = (c > T(0) && c < T(1)) ? (pb * k.dMb + e * k.dMs) * dH : T(0);
+    dmp = (p > T(-1) && p < T(1)) ? fmaT(dpb, bulk, de * surf) : T(0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void adj_pass0(AdjArgs<T> a)
+{
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int b = blockIdx.z;
+    const int nx = a.nx, ny = a.ny;
+    if (i >= nx || j >= ny) return;
+    const size_t o = (size_t)b * nx * ny;
+    const T* c = a.c + o;
+    const T* p = a.phi + o;
+    const int iE = wrapi(i + 1, nx), iW = wrapi(i - 1, nx);
+    const int jN = nrow(j + 1, ny, a.pvd), jS = nrow(j - 1, ny, a.pvd);
+    const T cc = ld(c, i, j, nx), pp = ld(p, i, j, nx);
+    T mu, nu, M;
+    potentials(a.k, cc, ld(c, iE, j, nx), ld(c, iW, j, nx), ld(c, i, jN, nx), ld(c, i, jS, nx),
+               pp, ld(p, iE, j, nx), ld(p, iW, j, nx), ld(p, i, jN, nx), ld(p, i, jS, nx), mu, nu, M);
+    T dmc, dmp;
+    mobility_grad(a.k, cc, pp, dmc, dmp);
+    const size_t g = o + (size_t)j * nx + i;
+    a.mu[g] = mu;
+    a.nu[g] = nu;
+    a.M[g] = M;
+    a.dMc[g] = dmc;
+    a.dMp[g] = dmp;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void adj_passA(AdjArgs<T> a)
+{
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int b = blockIdx.z;
+    const int nx = a.nx, ny = a.ny;
+    if (i >= nx || j >= ny) return;
+    const size_t o = (size_t)b * nx * ny;
+    const T dt = a.k.dt;
+    const int iE = wrapi(i + 1, nx), iW = wrapi(i - 1, nx);
+    const int jN = nrow(j + 1, ny, a.pvd), jS = nrow(j - 1, ny, a.pvd);
+    const int ni[4] = {iE, iW, i, i}, nj[4] = {j, j, jN, jS};
+    const T* lc = a.lc + o;
+    const T* lp = a.lp + o;
+    const T* M = a.M + o;
+    const T* mu = a.mu + o;
+    const T wc = dt * ld(lc, i, j, nx), wp = dt * ld(lp, i, j, nx), wr = dt * ld(a.lr + o, i, j, nx);
+    const T M0 = ld(M, i, j, nx), m0 = ld(mu, i, j, nx);
+    T mb = 0, Mb = 0, lapw = 0;
+    for (int q = 0; q < 4; ++q) {
+        const T wn = dt * ld(lc, ni[q], nj[q], nx);
+        mb += (M0 + ld(M, ni[q], nj[q], nx)) * (wn - wc);
+        Mb += (ld(mu, ni[q], nj[q], nx) - m0) * (wc - wn);
+        lapw += dt * ld(lp, ni[q], nj[q], nx) - wp;
+    }
+    const size_t g = o + (size_t)j * nx + i;
+    a.mbar[g] = a.k.half_ih2 * mb;
+    a.Mbar[g] = a.k.half_ih2 * Mb;
+    a.nbar[g] = a.k.mphi_h2 * lapw;
+    a.sig[g] = (wp - wr) * ld(a.rho + o, i, j, nx);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void adj_passB(AdjArgs<T> a)
+{
+    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int b = blockIdx.z;
+    const int nx = a.nx, ny = a.ny, pvd = a.pvd;
+    if (i >= nx || j >= ny) return;
+    const size_t o = (size_t)b * nx * ny;
+    const Coef<T>& k = a.k;
+    const Real rl = a.real[b];
+    const T vx2h = (T)rl.vx2h, vy2h = (T)rl.vy2h;
+    const int iE = wrapi(i + 1, nx), iW = wrapi(i - 1, nx);
+    const bool top = pvd && j == ny - 1, bottom = pvd && j == 0;
+    const int jN = nrow(j + 1, ny, pvd), jS = nrow(j - 1, ny, pvd);
+    const size_t g = o + (size_t)j * nx + i;
+    const T* mbar = a.mbar + o;
+    const T* nbar = a.nbar + o;
+    const T* sig = a.sig + o;
+    const T* phi = a.phi + o;
+    const T* rho = a.rho + o;
+    const T* lr = a.lr + o;
+    const T cc = a.c[g], pp = a.phi[g], rr = a.rho[g];
+    const T mb = a.mbar[g], nb = a.nbar[g], Mb = a.Mbar[g];
+
+    // pointwise derivatives of mu_c = W_c p g' - ... and mu_phi = W_c p' g - W_phi phi (1-phi^2) - ...
+    const T cg = cc * (T(1) - cc);
+    const T g0 = cg * cg;
+    const T g1 = cg * fmaT(T(-4), cc, T(2));
+    const T g2 = T(2) * fmaT(T(6) * cc, cc, fmaT(T(-6), cc, T(1)));
+    const T q1 = T(1) + pp;
+    const T p0 = (T(0.25) * (T(2) - pp)) * (q1 * q1);
+    const T p1 = T(0.75) * (T(1) - pp * pp);
+    const T p2 = T(-1.5) * pp;
+    T gc = mb * k.Wc * p0 * g2 + nb * k.Wc * p1 * g1;
+    T gp = mb * k.Wc * p1 * g1 + nb * (k.Wc * p2 * g0 - k.Wphi * (T(1) - T(3) * pp * pp));
+    // the Laplacians inside mu_c and mu_phi are symmetric (mirror rule)
+    const T mE = ld(mbar, iE, j, nx), mW = ld(mbar, iW, j, nx), mN = ld(mbar, i, jN, nx), mS = ld(mbar, i, jS, nx);
+    const T nE = ld(nbar, iE, j, nx), nW = ld(nbar, iW, j, nx), nN = ld(nbar, i, jN, nx), nS = ld(nbar, i, jS, nx);
+    gc += k.kc * (T(4) * mb - ((mE + mW) + (mN + mS)));
+    gp += k.kp * (T(4) * nb - ((nE + nW) + (nN + nS)));
+    // mobility M_c (its host-scaled coefficients make dMc, dMp derivatives of M_c)
+    gc += Mb * a.dMc[g];
+    gp += Mb * a.dMp[g];
+    // deposition: sig = Sbar rho of every cell whose stencil reads phi here;
+    // the mirror ghost row in y turns into an anti-mirrored sig
+    const T s0 = ld(sig, i, j, nx);
+    const T sE = ld(sig, iE, j, nx), sW = ld(sig, iW, j, nx);
+    const T sN = top ? -s0 : ld(sig, i, jN, nx);
+    const T sS = bottom ? -s0 : ld(sig, i, jS, nx);
+    gp += fmaT(vx2h, sW - sE, vy2h * (sS - sN));
+    // rho: deposition, then the transposed transport stencil
+    const T wp = k.dt * a.lp[g], wr = k.dt * a.lr[g];
+    const T dphx = ld(phi, iE, j, nx) - ld(phi, iW, j, nx), dphy = ld(phi, i, jN, nx) - ld(phi, i, jS, nx);
+    T gr = (wp - wr) * fmaT(vx2h, dphx, vy2h * dphy);
+    const T D = k.D_h2;
+    gr += (D - vx2h) * (k.dt * ld(lr, iW, j, nx)) + (D + vx2h) * (k.dt * ld(lr, iE, j, nx));
+    if (!pvd) {
+        gr += (D - vy2h) * (k.dt * ld(lr, i, jS, nx)) + (D + vy2h) * (k.dt * ld(lr, i, jN, nx));
+    } else {
+        if (j > 0) gr += (D - vy2h) * (k.dt * ld(lr, i, j - 1, nx));       // north coefficient of the cell below
+        if (j < ny - 1) gr += (D + vy2h) * (k.dt * ld(lr, i, j + 1, nx));  // south coefficient of the cell above
+        if (bottom) gr += (D - vy2h) * wr;                               // own mirror ghost, no advective flux
+    }
+    gr += T(-4) * D * wr;
+    // parameter gradients (FP64 per cell): w . dR/dM_scale and w . dR/dv0
+    const T rN = top ? k.rho_in : ld(rho, i, jN, nx);
+    const T rSa = bottom ? -rr : ld(rho, i, jS, nx);
+    const T dTv = -(a.cosx * (ld(rho, iE, j, nx) - ld(rho, iW, j, nx)) + a.siny * (rN - rSa)) * a.inv2h;
+    const T dSv = rr * (a.cosx * dphx + a.siny * dphy) * a.inv2h;
+    const size_t cells = (size_t)a.batch * nx * ny;
+    a.gacc[g] += (double)Mb * (double)(a.M[g] * a.Mscale_inv);
+    a.gacc[cells + g] += (double)(wp - wr) * (double)dSv + (double)wr * (double)dTv;
+    a.oc[g] = a.lc[g] + gc;
+    a.op[g] = a.lp[g] + gp;
+    a.orr[g] = a.lr[g] + gr;
+}
+
+__global__ __launch_bounds__(256) void fill_kernel(double* x, size_t n)
+{
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) x[i] = 0.0;
+}
+
+__device__ __forceinline__ double wave_sum64(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// out[b*2 + comp] = sum over the cells of realisation b of gacc[comp] (fixed order)
+__global__ __launch_bounds__(256) void gsum_kernel(const double* gacc, double* out, size_t cells_per, int batch)
+{
+    const int b = blockIdx.x, comp = blockIdx.y;
+    const double* x = gacc + (size_t)comp * batch * cells_per + (size_t)b * cells_per;
+    double s = 0.0;
+    for (size_t i = threadIdx.x; i < cells_per; i += 256) s += x[i];
+    __shared__ double red[4];
+    s = wave_sum64(s);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) out[b * 2 + comp] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+template <typename T>
+hipError_t adjoint_launch(AdjArgs<T> a, hipStream_t s)
+{
+    dim3 grid((a.nx + 63) / 64, (a.ny + 3) / 4, a.batch);
+    hipLaunchKernelGGL(adj_pass0<T>, grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL(adj_passA<T>, grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL(adj_passB<T>, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_adjoint(const AdjointIO<T>& io, const StepArgs<T>& st, double Mscale, double cos_th,
+                          double msin_th, double h, int batch, hipStream_t s)
+{
+    AdjArgs<T> a{};
+    a.c = io.c;
+    a.phi = io.phi;
+    a.rho = io.rho;
+    a.lc = io.lc;
+    a.lp = io.lp;
+    a.lr = io.lr;
+    a.oc = io.oc;
+    a.op = io.op;
+    a.orr = io.orr;
+    const size_t n = (size_t)batch * st.nx * st.ny;
+    T* w = io.scratch;
+    a.mu = w;
+    a.nu = w + n;
+    a.M = w + 2 * n;
+    a.dMc = w + 3 * n;
+    a.dMp = w + 4 * n;
+    a.mbar = w + 5 * n;
+    a.nbar = w + 6 * n;
+    a.Mbar = w + 7 * n;
+    a.sig = w + 8 * n;
+    a.gacc = io.gacc;
+    a.real = st.real;
+    a.k = st.k;
+    a.Mscale_inv = (T)(1.0 / Mscale);
+    a.cosx = (T)cos_th;
+    a.siny = (T)msin_th;
+    a.inv2h = (T)(0.5 / h);
+    a.nx = st.nx;
+    a.ny = st.ny;
+    a.pvd = st.pvd;
+    a.batch = batch;
+    return adjoint_launch<T>(a, s);
+}
+template hipError_t launch_adjoint<float>(const AdjointIO<float>&, const StepArgs<float>&, double, double, double,
+                                          double, int, hipStream_t);
+template hipError_t launch_adjoint<double>(const AdjointIO<double>&, const StepArgs<double>&, double, double,
+                                           double, double, int, hipStream_t);
+
+hipError_t launch_gacc_zero(double* gacc, size_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(fill_kernel, dim3(256), dim3(256), 0, s, gacc, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_gacc_sum(const double* gacc, double* out, size_t cells_per, int batch, hipStream_t s)
+{
+    hipLaunchKernelGGL(gsum_kernel, dim3(batch, 2), dim3(256), 0, s, gacc, out, cells_per, batch);
+    return hipGetLastError();
+}
+
+}  // namespace pfk

@@ -536,7 +536,119 @@ const char* pf_strerror(int code)
 
 int pf_last_hip_error(const pf_handle* h) { return h ? h->last_hip : 0; }
 
-int pf_get_launch(const pf_handle* h, int32_t* temporal_block, int32_t* tile_rows)
+}  // extern "C"
+
+namespace {
+
+struct AdjLayout {
+    size_t scratch, gacc, out, total;
+};
+
+AdjLayout adj_layout(const pf_params* p)
+{
+    AdjLayout L{};
+    const size_t cells = (size_t)p->batch * p->nx * p->ny;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        const size_t o = off;
+        off += round_up(bytes);
+        return o;
+    };
+    L.scratch = take(9 * cells * esize(p));
+    L.gacc = take(2 * cells * sizeof(double));
+    L.out = take(2 * (size_t)p->batch * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+template <typename T>
+int adjoint_step_t(pf_handle* h, const void* c, const void* phi, const void* rho, const void* lc,
+                   const void* lp, const void* lr, void* oc, void* op, void* orr, char* ws)
+{
+    const pf_params* p = &h->p;
+    const AdjLayout L = adj_layout(p);
+    pfk::AdjointIO<T> io{};
+    io.c = (const T*)c;
+    io.phi = (const T*)phi;
+    io.rho = (const T*)rho;
+    io.lc = (const T*)lc;
+    io.lp = (const T*)lp;
+    io.lr = (const T*)lr;
+    io.oc = (T*)oc;
+    io.op = (T*)op;
+    io.orr = (T*)orr;
+    io.scratch = (T*)(ws + L.scratch);
+    io.gacc = (double*)(ws + L.gacc);
+    const pfk::StepArgs<T> st = step_args<T>(h);
+    const double th = p->theta_deg * (3.14159265358979323846 / 180.0);
+    const double cx = p->flux_on ? std::cos(th) : 0.0, sy = p->flux_on ? -std::sin(th) : 0.0;
+    return hip_fail(h, pfk::launch_adjoint<T>(io, st, p->M_scale, cx, sy, p->h, p->batch, h->stream));
+}
+
+bool adj_ws_ok(const pf_handle* h, const void* ws, size_t bytes)
+{
+    return ws && aligned(ws, kAlign) && bytes >= adj_layout(&h->p).total;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pf_adjoint_workspace_bytes(const pf_params* p)
+{
+    if (validate(p) != PF_OK) return 0;
+    return adj_layout(p).total;
+}
+
+int pf_adjoint_step(pf_handle* h, const void* c, const void* phi, const void* rho, const void* lam_c,
+                    const void* lam_phi, const void* lam_rho, void* out_c, void* out_phi, void* out_rho,
+                    void* adj_workspace, size_t adj_bytes)
+{
+    if (!h || !adj_ws_ok(h, adj_workspace, adj_bytes)) return PF_EINVAL;
+    const void* in[9] = {c, phi, rho, lam_c, lam_phi, lam_rho, out_c, out_phi, out_rho};
+    for (const void* q : in)
+        if (!q || !aligned(q, 16)) return PF_EINVAL;
+    if (out_c == lam_c || out_phi == lam_phi || out_rho == lam_rho) return PF_EINVAL;
+    if (!(h->p.M_scale > 0)) return PF_EINVAL;
+    char* ws = (char*)adj_workspace;
+    return h->p.precision == PF_F64
+               ? adjoint_step_t<double>(h, c, phi, rho, lam_c, lam_phi, lam_rho, out_c, out_phi, out_rho, ws)
+               : adjoint_step_t<float>(h, c, phi, rho, lam_c, lam_phi, lam_rho, out_c, out_phi, out_rho, ws);
+}
+
+int pf_adjoint_reset(pf_handle* h, void* adj_workspace, size_t adj_bytes)
+{
+    if (!h || !adj_ws_ok(h, adj_workspace, adj_bytes)) return PF_EINVAL;
+    const AdjLayout L = adj_layout(&h->p);
+    const size_t cells = (size_t)h->p.batch * h->p.nx * h->p.ny;
+    return hip_fail(h, pfk::launch_gacc_zero((double*)((char*)adj_workspace + L.gacc), 2 * cells, h->stream));
+}
+
+int pf_adjoint_grad(pf_handle* h, void* adj_workspace, size_t adj_bytes, double* out)
+{
+    if (!h || !out || !adj_ws_ok(h, adj_workspace, adj_bytes)) return PF_EINVAL;
+    const AdjLayout L = adj_layout(&h->p);
+    char* ws = (char*)adj_workspace;
+    const size_t per = (size_t)h->p.nx * h->p.ny;
+    hipError_t e = pfk::launch_gacc_sum((const double*)(ws + L.gacc), (double*)(ws + L.out), per, h->p.batch,
+                                        h->stream);
+    h->host_out.resize(2 * (size_t)h->p.batch);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h->host_out.data(), ws + L.out, 2 * h->p.batch * sizeof(double),
+                           hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e);
+    bool ok = true;
+    for (int i = 0; i < 2 * h->p.batch; ++i) {
+        out[i] = h->host_out[i];
+        ok = ok && std::isfinite(out[i]);
+    }
+    return ok ? PF_OK : PF_ENONFINITE;
+}
+
+}  // extern "C"
+
+extern "C" int pf_get_launch(const pf_handle* h, int32_t* temporal_block, int32_t* tile_rows)
 {
     if (!h || !temporal_block || !tile_rows) return PF_EINVAL;
     *temporal_block = h->K;
@@ -544,5 +656,3 @@ int pf_get_launch(const pf_handle* h, int32_t* temporal_block, int32_t* tile_row
     if (h->p.precision == PF_F64 && h->K > 1) *tile_rows = pfk::tile_cfg<double>(h->K).ty;
     return PF_OK;
 }
-
-}  // extern "C"

@@ -99,4 +99,27 @@ hipError_t launch_reduce(const T* c, const T* phi, const T* rho, const double* Q
 
 constexpr int kRedBlocks = 128;   // partial-sum blocks per realisation
 
+// Discrete adjoint of one step: lambda_out = lambda_in + (dR/du)^T dt lambda_in
+// at the state (c, phi, rho); per-cell FP64 parameter gradients accumulate in
+// gacc[2][B][ny][nx] (dM_scale, dv0).  scratch holds 9 [B][ny][nx] arrays.
+template <typename T>
+struct AdjointIO {
+    const T* c;
+    const T* phi;
+    const T* rho;
+    const T* lc;
+    const T* lp;
+    const T* lr;
+    T* oc;
+    T* op;
+    T* orr;
+    T* scratch;
+    double* gacc;
+};
+template <typename T>
+hipError_t launch_adjoint(const AdjointIO<T>& io, const StepArgs<T>& st, double Mscale, double cos_th,
+                          double msin_th, double h, int batch, hipStream_t s);
+hipError_t launch_gacc_zero(double* gacc, size_t n, hipStream_t s);
+hipError_t launch_gacc_sum(const double* gacc, double* out, size_t cells_per, int batch, hipStream_t s);
+
 }  // namespace pfk

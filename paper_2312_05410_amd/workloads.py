@@ -41,6 +41,22 @@ def batched(seed: int = 0, batch: int = 32, n: int = 512, precision: str = "f32"
                     v0_per=v0, c0_per=c0)
 
 
+# Adjoint workload: 256 x 256, 2000 steps with a checkpoint every 50; the
+# loss is the L2 mismatch of the final fields to a target run of the same
+# seed with (M_scale, v0) = (1.1, 0.9 v0_nom); gradients in (M_scale, v0) at
+# a fixed dt chosen below the stability limit of both runs (the P0 limit is
+# 4.17e-3 at M_scale = 1 and 3.79e-3 at M_scale = 1.1).
+ADJOINT_STEPS = 2000
+ADJOINT_EVERY = 50
+ADJOINT_TARGET = (1.1, 0.9)
+ADJOINT_DT = 7.5e-4
+
+
+def adjoint_case(seed: int = 0, precision: str = "f32") -> PFParams:
+    return PFParams(nx=256, ny=256, batch=1, precision=precision, seed=seed, v0=V0_NOM, c0=0.5,
+                    c_noise=0.05, dt=ADJOINT_DT)
+
+
 STEPS = {"dns_small_128_f64": 1000, "dns_1024_f32": 50_000, "batched_32x512_f32": 10_000,
          # the production model at a size far above the 256 MB Infinity Cache
          "dns_8192_f32": 500}

@@ -1,0 +1,125 @@
+"""GPU discrete adjoint (pf_adjoint_step through the C ABI, and the
+checkpointed torch.autograd.Function) against the oracle's adjoint, which
+test_oracle_adjoint.py pins to central finite differences."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2312_05410_amd.inputs import PFParams, initial_state, random_state, uniform01
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2312_05410_amd import _lib
+
+    _lib.load()
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def announce(msg):
+    print(f"\n[case] {msg}", flush=True)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("bc,theta,shape", [("pvd", 60.0, (100, 77)), ("pvd", 90.0, (64, 33)),
+                                            ("periodic", 40.0, (70, 36))])
+def test_adjoint_step_matches_oracle(prec, bc, theta, shape):
+    import torch
+
+    from paper_2312_05410_amd._lib import Simulator
+
+    nx, ny = shape
+    announce(f"adjoint step {prec} {bc} {theta} {nx}x{ny}")
+    p = PFParams(nx=nx, ny=ny, bc_mode=bc, theta_deg=theta, v0=0.8, M_scale=1.2, precision=prec)
+    dt = 0.2 * oracle.dt_limit(p)
+    p = p.replace(dt=dt)
+    c, phi, rho = random_state(51, 1, ny, nx)
+    lam = uniform01(52, np.arange(3 * nx * ny)).reshape(3, ny, nx) - 0.5
+    ref, gref = oracle.adjoint_step(p, p.v0, dt, (c[0], phi[0], rho[0]), lam)
+    dtype = torch.float64 if prec == "f64" else torch.float32
+    sim = Simulator(p, state=(c, phi, rho))
+    st = [t.clone() for t in (sim.c, sim.phi, sim.rho)]
+    lin = [torch.as_tensor(l[None], dtype=dtype, device="cuda").contiguous() for l in lam]
+    lout = [torch.empty_like(t) for t in lin]
+    ws = sim.adjoint_workspace()
+    sim.adjoint_step(st, lin, lout, ws)
+    g = sim.adjoint_grad(ws)[0]
+    tol = 1e-11 if prec == "f64" else 2e-5
+    for name, o, i, r, l0 in zip(("c", "phi", "rho"), lout, lin, ref, lam):
+        inc = (o - i).double().cpu().numpy()[0]
+        e = rel_l2(inc, r - l0)
+        assert e <= tol, f"{name}: increment rel L2 {e:.2e}"
+    np.testing.assert_allclose(g, gref, rtol=1e-10 if prec == "f64" else 1e-4, atol=1e-14)
+    sim.close()
+
+
+def test_loss_gradient_f64_matches_oracle():
+    """Checkpointed autograd gradient (GPU FP64) equals the oracle's."""
+    import torch
+
+    from paper_2312_05410_amd.adjoint import final_state, l2_mismatch
+
+    announce("loss gradient f64 96x64")
+    p = PFParams(nx=96, ny=64, precision="f64", theta_deg=70.0, c_noise=0.05)
+    dt = 0.2 * oracle.dt_limit(p.replace(M_scale=1.1))
+    p = p.replace(dt=dt)
+    c, phi, rho = initial_state(p)
+    u0n = (c[0], phi[0], rho[0])
+    n, every = 300, 50
+    tgt = oracle.run(p.replace(M_scale=1.1), 0.9 * p.v0, dt, n, u0n)
+    L_ref, gM_ref, gv_ref = oracle.loss_grad(p, p.v0, dt, n, every, u0n, tgt)
+    dev = lambda a: torch.as_tensor(np.asarray(a)[None], dtype=torch.float64, device="cuda").contiguous()
+    u0 = tuple(dev(a) for a in u0n)
+    target = tuple(dev(a) for a in tgt)
+    Ms = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+    v0 = torch.tensor(p.v0, dtype=torch.float64, requires_grad=True)
+    L = l2_mismatch(final_state(Ms, v0, p, u0, n, every), target, p.h)
+    L.backward()
+    assert float(L) == pytest.approx(L_ref, rel=1e-11)
+    assert float(Ms.grad) == pytest.approx(gM_ref, rel=1e-9)
+    assert float(v0.grad) == pytest.approx(gv_ref, rel=1e-9)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_adjoint_workload_256(prec):
+    """The adjoint workload: 256^2, 2000 steps, checkpoints every 50, loss =
+    L2 mismatch of the final fields to a target run with (M_scale, v0) =
+    (1.1, 0.9 v0); gradients in (M_scale, v0) against the FP64 oracle."""
+    import torch
+
+    from paper_2312_05410_amd import workloads
+    from paper_2312_05410_amd.adjoint import final_state, l2_mismatch
+
+    announce(f"adjoint workload 256 {prec}")
+    p = workloads.adjoint_case(precision=prec)
+    n, every = workloads.ADJOINT_STEPS, workloads.ADJOINT_EVERY
+    c, phi, rho = initial_state(p)
+    u0n = (c[0], phi[0], rho[0])
+    tgt = oracle.run(p.replace(M_scale=workloads.ADJOINT_TARGET[0]), workloads.ADJOINT_TARGET[1] * p.v0, p.dt, n,
+                     u0n)
+    L_ref, gM_ref, gv_ref = oracle.loss_grad(p, p.v0, p.dt, n, every, u0n, tgt)
+    dtype = torch.float64 if prec == "f64" else torch.float32
+    dev = lambda a: torch.as_tensor(np.asarray(a)[None], dtype=dtype, device="cuda").contiguous()
+    u0 = tuple(dev(a) for a in u0n)
+    target = tuple(dev(a) for a in tgt)
+    Ms = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+    v0 = torch.tensor(p.v0, dtype=torch.float64, requires_grad=True)
+    L = l2_mismatch(final_state(Ms, v0, p, u0, n, every), target, p.h)
+    L.backward()
+    rtol = 1e-9 if prec == "f64" else 1e-3
+    print(f"L {float(L):.10e} ref {L_ref:.10e}; dMs {float(Ms.grad):.10e} ref {gM_ref:.10e}; "
+          f"dv0 {float(v0.grad):.10e} ref {gv_ref:.10e}", flush=True)
+    assert float(L) == pytest.approx(L_ref, rel=rtol)
+    assert float(Ms.grad) == pytest.approx(gM_ref, rel=rtol)
+    assert float(v0.grad) == pytest.approx(gv_ref, rel=rtol)
