@@ -229,13 +229,13 @@ def adjoint_leg(args):
 
 def main():
     args = parse()
-    if args.workload == "adjoint_256_f32":
-        print(json.dumps(adjoint_leg(args)), flush=True)
-        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                                    "(multi-GPU sharding is a design note, not implemented)"}))
         sys.exit(2)
+    if args.workload == "adjoint_256_f32":
+        print(json.dumps(adjoint_leg(args)), flush=True)
+        return
     import torch
 
     from paper_2312_05410_amd import workloads
