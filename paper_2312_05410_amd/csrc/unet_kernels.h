@@ -1,0 +1,138 @@
+// Device kernels of the time-conditioned U-Net (Materials and Methods, "U-Net
+// with temporal conditioning" and "Training of the network").  Internal to
+// the library; the C ABI is in include/unet.h.
+//
+// Tensors are NHWC (channels fastest).  MFMA operands are BF16 (stored as
+// uint16_t bit patterns), accumulation and every statistic is FP32 or FP64.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace pfu {
+
+constexpr int kMaxLevels = 6;
+
+// Implicit GEMM out[p][o] = sum_k A[p][k] B[o][k]; see unet_conv.hip for
+// the four gather/scatter modes.
+enum ConvMode { kConvFwd = 0, kConvDgrad = 1, kUpFwd = 2, kUpDgrad = 3 };
+
+struct ConvArgs {
+    const uint16_t* in1;   // first input (NHWC, C1 channels)
+    const uint16_t* in2;   // concatenated second input (C2 channels) or null
+    const uint16_t* Wt;    // BF16 operand weights [taps][ldo][ldk], zero padded
+    float* out_f32;        // first output, FP32 (or null)
+    uint16_t* out_bf16;    // first output, BF16 (or null)
+    float* out2_f32;       // channels [O1, Nout) when the output is split
+    uint16_t* out2_bf16;
+    int N, H, W;           // pixel grid the GEMM rows run over
+    int C1, C2;            // input channels (K per tap = C1 + C2)
+    int Nout, O1;          // output channels, split point (O1 = Nout: no split)
+    int ldk;               // row stride of Wt (K rounded up to 16)
+    int ldo;               // rows per tap of Wt (Nout rounded up to 64)
+};
+
+struct WgradArgs {
+    const uint16_t* dy;    // output gradient (NHWC, Nout channels; 2H x 2W for up)
+    const uint16_t* x1;    // forward input (C1 channels) at H x W
+    const uint16_t* x2;    // concatenated second input or null
+    float* partial;        // [chunks][taps][Nout][C1+C2]
+    int N, H, W, C1, C2, Nout;
+    int chunk;             // pixels per partial product (multiple of 16)
+};
+
+hipError_t conv_gemm(const ConvArgs& a, int mode, hipStream_t s);
+// dW[taps][Nout][C1+C2] = (accumulate ? dW : 0) + sum over pixels; mode
+// kConvFwd (3x3) or kUpFwd (2x2 stride 2).  a.partial must hold
+// wgrad_partial_floats() floats.
+hipError_t conv_wgrad(const WgradArgs& a, int mode, float* dW, int accumulate, hipStream_t s);
+size_t wgrad_partial_floats(const WgradArgs& a, int mode);
+// BF16 operand copies of an FP32 weight [taps][R][Kc]: fwd[t][o][k] = W[t][o][k]
+// (ldo_f x ldk_f, zero padded) and tr[t][o][k] = W[t][k][o] (ldo_t x ldk_t);
+// either may be null.
+hipError_t weight_prep(const float* W, int taps, int R, int Kc, uint16_t* fwd, int ldo_f, int ldk_f, uint16_t* tr,
+                       int ldo_t, int ldk_t, hipStream_t s);
+
+// ---------------------------------------------------------------- elementwise
+// Per-channel partial sums over pixel chunks, then finished per sample.
+struct GNArgs {
+    const float* y;        // pre-normalisation input [N][P][C] (FP32)
+    const float* gamma;    // [C]
+    const float* beta;     // [C]
+    const float* scale;    // FiLM scale [N][C] or null
+    float* stats;          // [N][G][2]: mean, 1/sqrt(var + eps)
+    float* csum;           // per-(N, chunk, C, 3) partial sums (workspace)
+    double* cacc;          // [N][C][3] finished per-channel sums (workspace)
+    // forward outputs (any may be null): z = act(GN(y)), zs = z * scale
+    float* z_f32;
+    uint16_t* z_bf16;
+    float* zs_f32;
+    uint16_t* zs_bf16;
+    // backward: dz = dA + dB * scale (dA, dB may be null), outputs dy
+    const float* dA;
+    const float* dB;
+    float* dy_f32;
+    uint16_t* dy_bf16;
+    float* dgamma;         // [C] (=, summed over samples)
+    float* dbeta;          // [C] (=)
+    float* dscale;         // [N][C] (=), when scale and dB are given
+    int N, P, C, G;
+    int gelu;
+    float eps;
+    int chunks;            // pixel chunks per sample
+};
+hipError_t gn_forward(const GNArgs& a, hipStream_t s);
+hipError_t gn_backward(const GNArgs& a, hipStream_t s);
+size_t gn_csum_floats(int N, int P, int C);
+int gn_chunks(int P);
+
+// 2x2 stride-2 max pool of BF16 NHWC; backward writes the full-resolution
+// FP32 gradient (the first maximum in (0,0), (0,1), (1,0), (1,1) order
+// receives it, the others zero).
+hipError_t maxpool_fwd(const uint16_t* x, uint16_t* y, int N, int H, int W, int C, hipStream_t s);
+hipError_t maxpool_bwd(const uint16_t* x, const float* dy, float* dx, int N, int H, int W, int C, hipStream_t s);
+
+// Network input: x[n][p][0..3] = (c, phi, rho, jump[n]) as BF16.
+hipError_t assemble_input(const float* c, const float* phi, const float* rho, const float* jump, uint16_t* x, int N,
+                          int P, hipStream_t s);
+// out_f[n][p] = in_f[n][p] + head[n][p][f] for the three fields.
+hipError_t residual_out(const float* head, const float* c, const float* phi, const float* rho, float* oc, float* ophi,
+                        float* orho, int N, int P, hipStream_t s);
+
+// Time basis f(jump) (two sin layers of width Hd) and the per-level FiLM
+// scales s_l = w_l f; one block per sample.
+struct MLPArgs {
+    const float* jump;     // [N]
+    const float* W0;       // [Hd]
+    const float* b0;       // [Hd]
+    const float* W1;       // [Hd][Hd]
+    const float* b1;
+    const float* W2;       // [F][Hd]
+    const float* b2;       // [F]
+    const float* Wl[kMaxLevels];    // [C_l][F]
+    float* h0;             // [N][Hd] pre-activations (saved)
+    float* h1;             // [N][Hd]
+    float* f;              // [N][F]
+    float* sc[kMaxLevels];          // [N][C_l]
+    const float* dsc[kMaxLevels];   // backward: [N][C_l]
+    float* gW0; float* gb0; float* gW1; float* gb1; float* gW2; float* gb2;
+    float* gWl[kMaxLevels];
+    int N, Hd, F, L;
+    int C[kMaxLevels];
+};
+hipError_t mlp_forward(const MLPArgs& a, hipStream_t s);
+hipError_t mlp_backward(const MLPArgs& a, hipStream_t s);
+
+// Relative MSE per field: L = sum_f sum (pred - tgt)^2 / sum tgt^2.
+// Writes dL/dpred as [N][P][3] (NHWC, the head's layout) and L (FP64).
+hipError_t rel_mse(const float* pc, const float* pphi, const float* prho, const float* tc, const float* tphi,
+                   const float* trho, float* grad, double* part, double* loss, int N, int P, hipStream_t s);
+size_t rel_mse_partial_doubles();
+
+// Adam on FP32 master parameters.
+hipError_t adam_update(float* w, const float* g, float* m, float* v, size_t n, float lr, float b1, float b2,
+                       float eps, float bc1, float bc2, hipStream_t s);
+
+hipError_t fill_f32(float* p, size_t n, float v, hipStream_t s);
+
+}  // namespace pfu

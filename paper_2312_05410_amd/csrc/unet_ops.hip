@@ -1,0 +1,589 @@
+// Non-GEMM kernels of the time-conditioned U-Net (Materials and Methods,
+// "U-Net with temporal conditioning"): group normalisation with the tanh
+// form of GELU and the per-channel time conditioning fused in, max pooling,
+// the sin-basis MLP of the time step with its per-level projections, the
+// relative mean-squared error ("Error metrics") and Adam ("Training of the
+// network").  NHWC layout; statistics in FP32 per thread and FP64 across
+// threads, summed in a fixed order.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "unet_kernels.h"
+
+namespace pfu {
+namespace {
+
+__device__ __forceinline__ float bf2f(uint16_t v) { return __builtin_bit_cast(float, (uint32_t)v << 16); }
+
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// GELU, tanh form: 0.5 a (1 + tanh(sqrt(2/pi) (a + 0.044715 a^3)))
+constexpr float kGeluS = 0.7978845608028654f;
+constexpr float kGeluA = 0.044715f;
+__device__ __forceinline__ float gelu(float a)
+{
+    const float t = tanhf(kGeluS * (a + kGeluA * a * a * a));
+    return 0.5f * a * (1.f + t);
+}
+__device__ __forceinline__ float gelu_grad(float a)
+{
+    const float t = tanhf(kGeluS * (a + kGeluA * a * a * a));
+    return 0.5f * (1.f + t) + 0.5f * a * (1.f - t * t) * kGeluS * (1.f + 3.f * kGeluA * a * a);
+}
+
+// Threads of a reduction block: the largest multiple of C not above 256, so
+// every thread keeps one channel.
+__device__ __forceinline__ int red_threads(int C) { return (256 / C) * C; }
+
+// pixels per reduction chunk: a multiple of 64, at most 256 chunks per sample
+int chunk_px(int P)
+{
+    const int c = ((P + 255) / 256 + 63) / 64 * 64;
+    return c < 64 ? 64 : c;
+}
+
+// ------------------------------------------------------------ group norm
+// Per-(sample, chunk, channel) sums of y and y^2.
+__global__ __launch_bounds__(256) void gn_stats_kernel(GNArgs a, int CH)
+{
+    __shared__ float sh[2][256];
+    const int chunk = blockIdx.x, n = blockIdx.y, tid = threadIdx.x;
+    const int T = red_threads(a.C), c = tid % a.C, pl = tid / a.C, PL = T / a.C;
+    float s0 = 0.f, s1 = 0.f;
+    if (tid < T) {
+        const int pe = min(a.P, (chunk + 1) * CH);
+        for (int p = chunk * CH + pl; p < pe; p += PL) {
+            const float v = a.y[((size_t)n * a.P + p) * a.C + c];
+            s0 += v;
+            s1 += v * v;
+        }
+    }
+    sh[0][tid] = s0;
+    sh[1][tid] = s1;
+    __syncthreads();
+    if (tid < a.C) {
+        float t0 = 0.f, t1 = 0.f;
+        for (int k = 0; k < PL; ++k) {
+            t0 += sh[0][k * a.C + tid];
+            t1 += sh[1][k * a.C + tid];
+        }
+        float* o = a.csum + (((size_t)n * a.chunks + chunk) * a.C + tid) * 3;
+        o[0] = t0;
+        o[1] = t1;
+    }
+}
+
+// mean and 1/sqrt(var + eps) per (sample, group); one block
+__global__ __launch_bounds__(256) void gn_stats_finish(GNArgs a)
+{
+    const int Cg = a.C / a.G;
+    const double M = (double)Cg * a.P;
+    for (int i = threadIdx.x; i < a.N * a.G; i += blockDim.x) {
+        const int n = i / a.G, g = i % a.G;
+        double s0 = 0.0, s1 = 0.0;
+        for (int c = g * Cg; c < (g + 1) * Cg; ++c)
+            for (int k = 0; k < a.chunks; ++k) {
+                const float* o = a.csum + (((size_t)n * a.chunks + k) * a.C + c) * 3;
+                s0 += o[0];
+                s1 += o[1];
+            }
+        const double mean = s0 / M;
+        const double var = fmax(s1 / M - mean * mean, 0.0);
+        a.stats[2 * i] = (float)mean;
+        a.stats[2 * i + 1] = (float)(1.0 / sqrt(var + (double)a.eps));
+    }
+}
+
+__global__ __launch_bounds__(256) void gn_apply_kernel(GNArgs a)
+{
+    const size_t total = (size_t)a.N * a.P * a.C;
+    const int Cg = a.C / a.G;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (size_t)gridDim.x * 256) {
+        const int c = (int)(i % a.C);
+        const int n = (int)(i / ((size_t)a.P * a.C));
+        const float* st = a.stats + 2 * (n * a.G + c / Cg);
+        const float xh = (a.y[i] - st[0]) * st[1];
+        const float av = fmaf(a.gamma[c], xh, a.beta[c]);
+        const float z = a.gelu ? gelu(av) : av;
+        if (a.z_f32) a.z_f32[i] = z;
+        if (a.z_bf16) a.z_bf16[i] = f2bf(z);
+        if (a.scale) {
+            const float zs = z * a.scale[n * a.C + c];
+            if (a.zs_f32) a.zs_f32[i] = zs;
+            if (a.zs_bf16) a.zs_bf16[i] = f2bf(zs);
+        }
+    }
+}
+
+// Backward pass 1: per-(sample, chunk, channel) sums of g, g * xhat and
+// dB * z, where g = dL/da (a = gamma xhat + beta).
+struct BwdElem {
+    float g, xh, z, dB;
+};
+__device__ __forceinline__ BwdElem bwd_elem(const GNArgs& a, size_t i, int n, int c)
+{
+    BwdElem e;
+    const float* st = a.stats + 2 * (n * a.G + c / (a.C / a.G));
+    e.xh = (a.y[i] - st[0]) * st[1];
+    const float av = fmaf(a.gamma[c], e.xh, a.beta[c]);
+    e.z = a.gelu ? gelu(av) : av;
+    e.dB = a.dB ? a.dB[i] : 0.f;
+    float dz = a.dA ? a.dA[i] : 0.f;
+    if (a.dB) dz = fmaf(e.dB, a.scale ? a.scale[n * a.C + c] : 1.f, dz);
+    e.g = a.gelu ? dz * gelu_grad(av) : dz;
+    return e;
+}
+
+__global__ __launch_bounds__(256) void gn_bwd_reduce_kernel(GNArgs a, int CH)
+{
+    __shared__ float sh[3][256];
+    const int chunk = blockIdx.x, n = blockIdx.y, tid = threadIdx.x;
+    const int T = red_threads(a.C), c = tid % a.C, pl = tid / a.C, PL = T / a.C;
+    float s0 = 0.f, s1 = 0.f, s2 = 0.f;
+    if (tid < T) {
+        const int pe = min(a.P, (chunk + 1) * CH);
+        for (int p = chunk * CH + pl; p < pe; p += PL) {
+            const size_t i = ((size_t)n * a.P + p) * a.C + c;
+            const BwdElem e = bwd_elem(a, i, n, c);
+            s0 += e.g;
+            s1 += e.g * e.xh;
+            s2 += e.dB * e.z;
+        }
+    }
+    sh[0][tid] = s0;
+    sh[1][tid] = s1;
+    sh[2][tid] = s2;
+    __syncthreads();
+    if (tid < a.C) {
+        float t0 = 0.f, t1 = 0.f, t2 = 0.f;
+        for (int k = 0; k < PL; ++k) {
+            t0 += sh[0][k * a.C + tid];
+            t1 += sh[1][k * a.C + tid];
+            t2 += sh[2][k * a.C + tid];
+        }
+        float* o = a.csum + (((size_t)n * a.chunks + chunk) * a.C + tid) * 3;
+        o[0] = t0;
+        o[1] = t1;
+        o[2] = t2;
+    }
+}
+
+// cacc[n][c][3] = chunk sums; then dgamma, dbeta, dscale and the group sums
+// S1 = sum gamma g, S2 = sum gamma g xhat (stored after cacc); one block
+__global__ __launch_bounds__(256) void gn_bwd_finish(GNArgs a)
+{
+    const int NC = a.N * a.C;
+    for (int i = threadIdx.x; i < NC; i += blockDim.x) {
+        const int n = i / a.C, c = i % a.C;
+        double t[3] = {0.0, 0.0, 0.0};
+        for (int k = 0; k < a.chunks; ++k) {
+            const float* o = a.csum + (((size_t)n * a.chunks + k) * a.C + c) * 3;
+            t[0] += o[0];
+            t[1] += o[1];
+            t[2] += o[2];
+        }
+        for (int q = 0; q < 3; ++q) a.cacc[3 * i + q] = t[q];
+    }
+    __syncthreads();
+    double* grp = a.cacc + 3 * (size_t)NC;
+    const int Cg = a.C / a.G;
+    for (int i = threadIdx.x; i < a.N * a.G; i += blockDim.x) {
+        const int n = i / a.G, g = i % a.G;
+        double s1 = 0.0, s2 = 0.0;
+        for (int c = g * Cg; c < (g + 1) * Cg; ++c) {
+            s1 += (double)a.gamma[c] * a.cacc[3 * (n * a.C + c)];
+            s2 += (double)a.gamma[c] * a.cacc[3 * (n * a.C + c) + 1];
+        }
+        grp[2 * i] = s1;
+        grp[2 * i + 1] = s2;
+    }
+    for (int c = threadIdx.x; c < a.C; c += blockDim.x) {
+        double gb = 0.0, gg = 0.0;
+        for (int n = 0; n < a.N; ++n) {
+            gb += a.cacc[3 * (n * a.C + c)];
+            gg += a.cacc[3 * (n * a.C + c) + 1];
+        }
+        if (a.dbeta) a.dbeta[c] = (float)gb;
+        if (a.dgamma) a.dgamma[c] = (float)gg;
+    }
+    if (a.dscale)
+        for (int i = threadIdx.x; i < NC; i += blockDim.x) a.dscale[i] = (float)a.cacc[3 * i + 2];
+}
+
+// dy = rstd (gamma g - (S1 + xhat S2) / M), M = elements per group
+__global__ __launch_bounds__(256) void gn_bwd_apply_kernel(GNArgs a)
+{
+    const size_t total = (size_t)a.N * a.P * a.C;
+    const int Cg = a.C / a.G;
+    const float invM = (float)(1.0 / ((double)Cg * a.P));
+    const double* grp = a.cacc + 3 * (size_t)a.N * a.C;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (size_t)gridDim.x * 256) {
+        const int c = (int)(i % a.C);
+        const int n = (int)(i / ((size_t)a.P * a.C));
+        const int gi = n * a.G + c / Cg;
+        const BwdElem e = bwd_elem(a, i, n, c);
+        const float S1 = (float)grp[2 * gi], S2 = (float)grp[2 * gi + 1];
+        const float v = a.stats[2 * gi + 1] * (a.gamma[c] * e.g - fmaf(e.xh, S2, S1) * invM);
+        if (a.dy_f32) a.dy_f32[i] = v;
+        if (a.dy_bf16) a.dy_bf16[i] = f2bf(v);
+    }
+}
+
+// --------------------------------------------------------------- pooling
+__global__ __launch_bounds__(256) void pool_fwd_kernel(const uint16_t* x, uint16_t* y, int N, int H, int W, int C)
+{
+    const int Ho = H / 2, Wo = W / 2;
+    const size_t total = (size_t)N * Ho * Wo * C;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (size_t)gridDim.x * 256) {
+        const int c = (int)(i % C);
+        const size_t q = i / C;
+        const int xo = (int)(q % Wo), yo = (int)((q / Wo) % Ho), n = (int)(q / ((size_t)Wo * Ho));
+        const uint16_t* b = x + (((size_t)n * H + 2 * yo) * W + 2 * xo) * C + c;
+        uint16_t best = b[0];
+        float bv = bf2f(best);
+        const uint16_t cand[3] = {b[C], b[(size_t)W * C], b[(size_t)W * C + C]};
+        for (int k = 0; k < 3; ++k)
+            if (bf2f(cand[k]) > bv) {
+                bv = bf2f(cand[k]);
+                best = cand[k];
+            }
+        y[i] = best;
+    }
+}
+
+__global__ __launch_bounds__(256) void pool_bwd_kernel(const uint16_t* x, const float* dy, float* dx, int N, int H,
+                                                       int W, int C)
+{
+    const int Ho = H / 2, Wo = W / 2;
+    const size_t total = (size_t)N * Ho * Wo * C;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (size_t)gridDim.x * 256) {
+        const int c = (int)(i % C);
+        const size_t q = i / C;
+        const int xo = (int)(q % Wo), yo = (int)((q / Wo) % Ho), n = (int)(q / ((size_t)Wo * Ho));
+        const size_t base = (((size_t)n * H + 2 * yo) * W + 2 * xo) * C + c;
+        const size_t off[4] = {0, (size_t)C, (size_t)W * C, (size_t)W * C + C};
+        int best = 0;
+        float bv = bf2f(x[base]);
+        for (int k = 1; k < 4; ++k)
+            if (bf2f(x[base + off[k]]) > bv) {
+                bv = bf2f(x[base + off[k]]);
+                best = k;
+            }
+        const float g = dy[i];
+        for (int k = 0; k < 4; ++k) dx[base + off[k]] = k == best ? g : 0.f;
+    }
+}
+
+// ------------------------------------------------------- input / output
+__global__ __launch_bounds__(256) void assemble_kernel(const float* c, const float* phi, const float* rho,
+                                                       const float* jump, uint16_t* x, int N, int P)
+{
+    const size_t total = (size_t)N * P;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (size_t)gridDim.x * 256) {
+        const int n = (int)(i / P);
+        ushort4 v;
+        v.x = f2bf(c[i]);
+        v.y = f2bf(phi[i]);
+        v.z = f2bf(rho[i]);
+        v.w = f2bf(jump[n]);
+        *(ushort4*)(x + 4 * i) = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void residual_kernel(const float* head, const float* c, const float* phi,
+                                                       const float* rho, float* oc, float* ophi, float* orho,
+                                                       size_t total)
+{
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (size_t)gridDim.x * 256) {
+        const float h0 = head[3 * i], h1 = head[3 * i + 1], h2 = head[3 * i + 2];
+        oc[i] = c[i] + h0;
+        ophi[i] = phi[i] + h1;
+        orho[i] = rho[i] + h2;
+    }
+}
+
+// -------------------------------------------------------------------- MLP
+// f = W2 sin(W1 sin(W0 t + b0) + b1) + b2; s_l = Wl f.  One block per sample.
+__global__ __launch_bounds__(256) void mlp_fwd_kernel(MLPArgs a)
+{
+    __shared__ float a0[256], a1[256], fv[256];
+    const int n = blockIdx.x, tid = threadIdx.x;
+    const float t = a.jump[n];
+    for (int j = tid; j < a.Hd; j += blockDim.x) {
+        const float h = fmaf(a.W0[j], t, a.b0[j]);
+        a.h0[n * a.Hd + j] = h;
+        a0[j] = sinf(h);
+    }
+    __syncthreads();
+    for (int j = tid; j < a.Hd; j += blockDim.x) {
+        float h = a.b1[j];
+        for (int k = 0; k < a.Hd; ++k) h = fmaf(a.W1[j * a.Hd + k], a0[k], h);
+        a.h1[n * a.Hd + j] = h;
+        a1[j] = sinf(h);
+    }
+    __syncthreads();
+    for (int i = tid; i < a.F; i += blockDim.x) {
+        float v = a.b2[i];
+        for (int k = 0; k < a.Hd; ++k) v = fmaf(a.W2[i * a.Hd + k], a1[k], v);
+        a.f[n * a.F + i] = v;
+        fv[i] = v;
+    }
+    __syncthreads();
+    for (int l = 0; l < a.L; ++l)
+        for (int c = tid; c < a.C[l]; c += blockDim.x) {
+            float v = 0.f;
+            for (int i = 0; i < a.F; ++i) v = fmaf(a.Wl[l][c * a.F + i], fv[i], v);
+            a.sc[l][n * a.C[l] + c] = v;
+        }
+}
+
+// Gradients of every MLP and projection parameter, summed over the samples
+// in order; one block.
+__global__ __launch_bounds__(256) void mlp_bwd_kernel(MLPArgs a)
+{
+    __shared__ float df[256], dh1[256], dh0[256];
+    const int tid = threadIdx.x;
+    for (int n = 0; n < a.N; ++n) {
+        const float t = a.jump[n];
+        const float* f = a.f + n * a.F;
+        const float* h0 = a.h0 + n * a.Hd;
+        const float* h1 = a.h1 + n * a.Hd;
+        for (int i = tid; i < a.F; i += blockDim.x) {
+            float v = 0.f;
+            for (int l = 0; l < a.L; ++l)
+                for (int c = 0; c < a.C[l]; ++c) v = fmaf(a.Wl[l][c * a.F + i], a.dsc[l][n * a.C[l] + c], v);
+            df[i] = v;
+        }
+        for (int l = 0; l < a.L; ++l)
+            for (int e = tid; e < a.C[l] * a.F; e += blockDim.x) {
+                const int c = e / a.F, i = e % a.F;
+                const float v = a.dsc[l][n * a.C[l] + c] * f[i];
+                a.gWl[l][e] = n ? a.gWl[l][e] + v : v;
+            }
+        __syncthreads();
+        for (int e = tid; e < a.F * a.Hd; e += blockDim.x) {
+            const int i = e / a.Hd, k = e % a.Hd;
+            const float v = df[i] * sinf(h1[k]);
+            a.gW2[e] = n ? a.gW2[e] + v : v;
+        }
+        for (int i = tid; i < a.F; i += blockDim.x) a.gb2[i] = n ? a.gb2[i] + df[i] : df[i];
+        for (int k = tid; k < a.Hd; k += blockDim.x) {
+            float v = 0.f;
+            for (int i = 0; i < a.F; ++i) v = fmaf(a.W2[i * a.Hd + k], df[i], v);
+            dh1[k] = v * cosf(h1[k]);
+        }
+        __syncthreads();
+        for (int e = tid; e < a.Hd * a.Hd; e += blockDim.x) {
+            const int j = e / a.Hd, k = e % a.Hd;
+            const float v = dh1[j] * sinf(h0[k]);
+            a.gW1[e] = n ? a.gW1[e] + v : v;
+        }
+        for (int j = tid; j < a.Hd; j += blockDim.x) a.gb1[j] = n ? a.gb1[j] + dh1[j] : dh1[j];
+        for (int k = tid; k < a.Hd; k += blockDim.x) {
+            float v = 0.f;
+            for (int j = 0; j < a.Hd; ++j) v = fmaf(a.W1[j * a.Hd + k], dh1[j], v);
+            dh0[k] = v * cosf(h0[k]);
+        }
+        __syncthreads();
+        for (int j = tid; j < a.Hd; j += blockDim.x) {
+            a.gW0[j] = n ? a.gW0[j] + dh0[j] * t : dh0[j] * t;
+            a.gb0[j] = n ? a.gb0[j] + dh0[j] : dh0[j];
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------- loss
+constexpr int kLossBlocks = 256;
+
+__global__ __launch_bounds__(256) void mse_part_kernel(const float* p0, const float* p1, const float* p2,
+                                                       const float* t0, const float* t1, const float* t2, double* part,
+                                                       size_t total)
+{
+    __shared__ double sh[6][256];
+    double s[6] = {0, 0, 0, 0, 0, 0};
+    const float* P[3] = {p0, p1, p2};
+    const float* T[3] = {t0, t1, t2};
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (size_t)gridDim.x * 256)
+        for (int f = 0; f < 3; ++f) {
+            const double d = (double)P[f][i] - (double)T[f][i];
+            s[2 * f] += d * d;
+            s[2 * f + 1] += (double)T[f][i] * T[f][i];
+        }
+    for (int q = 0; q < 6; ++q) sh[q][threadIdx.x] = s[q];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int q = 0; q < 6; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = sh[threadIdx.x][0];
+}
+
+// part[kLossBlocks][6] -> loss[0] = L, loss[1..3] = 2 / sum tgt^2 per field
+__global__ void mse_finish_kernel(const double* part, double* loss)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s[6] = {0, 0, 0, 0, 0, 0};
+    for (int b = 0; b < kLossBlocks; ++b)
+        for (int q = 0; q < 6; ++q) s[q] += part[b * 6 + q];
+    double L = 0.0;
+    for (int f = 0; f < 3; ++f) {
+        const double den = s[2 * f + 1] > 0.0 ? s[2 * f + 1] : 1.0;
+        L += s[2 * f] / den;
+        loss[1 + f] = 2.0 / den;
+    }
+    loss[0] = L;
+}
+
+__global__ __launch_bounds__(256) void mse_grad_kernel(const float* p0, const float* p1, const float* p2,
+                                                       const float* t0, const float* t1, const float* t2,
+                                                       const double* loss, float* grad, size_t total)
+{
+    const float k0 = (float)loss[1], k1 = (float)loss[2], k2 = (float)loss[3];
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (size_t)gridDim.x * 256) {
+        grad[3 * i] = k0 * (p0[i] - t0[i]);
+        grad[3 * i + 1] = k1 * (p1[i] - t1[i]);
+        grad[3 * i + 2] = k2 * (p2[i] - t2[i]);
+    }
+}
+
+// ------------------------------------------------------------------- Adam
+__global__ __launch_bounds__(256) void adam_kernel(float* w, const float* g, float* m, float* v, size_t n, float lr,
+                                                   float b1, float b2, float eps, float bc1, float bc2)
+{
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+        const float gi = g[i];
+        const float mi = fmaf(b1, m[i], (1.f - b1) * gi);
+        const float vi = fmaf(b2, v[i], (1.f - b2) * gi * gi);
+        m[i] = mi;
+        v[i] = vi;
+        w[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    }
+}
+
+__global__ __launch_bounds__(256) void fill_kernel(float* p, size_t n, float v)
+{
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) p[i] = v;
+}
+
+unsigned grid_for(size_t n)
+{
+    const size_t b = (n + 255) / 256;
+    return (unsigned)(b < 8192 ? (b ? b : 1) : 8192);
+}
+
+}  // namespace
+
+int gn_chunks(int P) { return (P + chunk_px(P) - 1) / chunk_px(P); }
+
+size_t gn_csum_floats(int N, int P, int C) { return (size_t)N * gn_chunks(P) * C * 3; }
+
+hipError_t gn_forward(const GNArgs& a_in, hipStream_t s)
+{
+    if (a_in.N <= 0 || a_in.P <= 0) return hipSuccess;
+    GNArgs a = a_in;
+    a.chunks = gn_chunks(a.P);
+    const int CH = chunk_px(a.P);
+    hipLaunchKernelGGL(gn_stats_kernel, dim3(a.chunks, a.N), dim3(256), 0, s, a, CH);
+    hipLaunchKernelGGL(gn_stats_finish, dim3(1), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(gn_apply_kernel, dim3(grid_for((size_t)a.N * a.P * a.C)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t gn_backward(const GNArgs& a_in, hipStream_t s)
+{
+    if (a_in.N <= 0 || a_in.P <= 0) return hipSuccess;
+    GNArgs a = a_in;
+    a.chunks = gn_chunks(a.P);
+    const int CH = chunk_px(a.P);
+    hipLaunchKernelGGL(gn_bwd_reduce_kernel, dim3(a.chunks, a.N), dim3(256), 0, s, a, CH);
+    hipLaunchKernelGGL(gn_bwd_finish, dim3(1), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(gn_bwd_apply_kernel, dim3(grid_for((size_t)a.N * a.P * a.C)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t maxpool_fwd(const uint16_t* x, uint16_t* y, int N, int H, int W, int C, hipStream_t s)
+{
+    const size_t n = (size_t)N * (H / 2) * (W / 2) * C;
+    if (!n) return hipSuccess;
+    hipLaunchKernelGGL(pool_fwd_kernel, dim3(grid_for(n)), dim3(256), 0, s, x, y, N, H, W, C);
+    return hipGetLastError();
+}
+
+hipError_t maxpool_bwd(const uint16_t* x, const float* dy, float* dx, int N, int H, int W, int C, hipStream_t s)
+{
+    const size_t n = (size_t)N * (H / 2) * (W / 2) * C;
+    if (!n) return hipSuccess;
+    hipLaunchKernelGGL(pool_bwd_kernel, dim3(grid_for(n)), dim3(256), 0, s, x, dy, dx, N, H, W, C);
+    return hipGetLastError();
+}
+
+hipError_t assemble_input(const float* c, const float* phi, const float* rho, const float* jump, uint16_t* x, int N,
+                          int P, hipStream_t s)
+{
+    const size_t n = (size_t)N * P;
+    if (!n) return hipSuccess;
+    hipLaunchKernelGGL(assemble_kernel, dim3(grid_for(n)), dim3(256), 0, s, c, phi, rho, jump, x, N, P);
+    return hipGetLastError();
+}
+
+hipError_t residual_out(const float* head, const float* c, const float* phi, const float* rho, float* oc, float* ophi,
+                        float* orho, int N, int P, hipStream_t s)
+{
+    const size_t n = (size_t)N * P;
+    if (!n) return hipSuccess;
+    hipLaunchKernelGGL(residual_kernel, dim3(grid_for(n)), dim3(256), 0, s, head, c, phi, rho, oc, ophi, orho, n);
+    return hipGetLastError();
+}
+
+hipError_t mlp_forward(const MLPArgs& a, hipStream_t s)
+{
+    if (a.N <= 0) return hipSuccess;
+    hipLaunchKernelGGL(mlp_fwd_kernel, dim3(a.N), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t mlp_backward(const MLPArgs& a, hipStream_t s)
+{
+    hipLaunchKernelGGL(mlp_bwd_kernel, dim3(1), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+size_t rel_mse_partial_doubles() { return (size_t)kLossBlocks * 6; }
+
+hipError_t rel_mse(const float* pc, const float* pphi, const float* prho, const float* tc, const float* tphi,
+                   const float* trho, float* grad, double* part, double* loss, int N, int P, hipStream_t s)
+{
+    const size_t n = (size_t)N * P;
+    hipLaunchKernelGGL(mse_part_kernel, dim3(kLossBlocks), dim3(256), 0, s, pc, pphi, prho, tc, tphi, trho, part, n);
+    hipLaunchKernelGGL(mse_finish_kernel, dim3(1), dim3(64), 0, s, part, loss);
+    if (grad && n)
+        hipLaunchKernelGGL(mse_grad_kernel, dim3(grid_for(n)), dim3(256), 0, s, pc, pphi, prho, tc, tphi, trho, loss,
+                           grad, n);
+    return hipGetLastError();
+}
+
+hipError_t adam_update(float* w, const float* g, float* m, float* v, size_t n, float lr, float b1, float b2,
+                       float eps, float bc1, float bc2, hipStream_t s)
+{
+    if (!n) return hipSuccess;
+    hipLaunchKernelGGL(adam_kernel, dim3(grid_for(n)), dim3(256), 0, s, w, g, m, v, n, lr, b1, b2, eps, bc1, bc2);
+    return hipGetLastError();
+}
+
+hipError_t fill_f32(float* p, size_t n, float v, hipStream_t s)
+{
+    if (!n) return hipSuccess;
+    hipLaunchKernelGGL(fill_kernel, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+}  // namespace pfu

@@ -123,3 +123,64 @@ def test_product_path_has_no_oracle_import():
             if f.endswith((".py", ".hip", ".cpp", ".h")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "pf_oracle" not in text, f
+
+
+# ------------------------------------------------------------------ U-Net
+def test_unet_library_exports_every_declared_symbol():
+    from paper_2312_05410_amd import unet
+
+    text = open(os.path.join(ROOT, "include", "unet.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = sorted(set(re.findall(r"\b(unet_[a-z0-9_]+)\s*\(", text)))
+    L = unet.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(unet.UNET_EXPORTS)
+
+
+def test_unet_struct_layouts():
+    from paper_2312_05410_amd import unet
+
+    assert ctypes.sizeof(unet.UNetConfigC) == 12 * 4
+    assert unet.ParamDescC.offset.offset == 32 and ctypes.sizeof(unet.ParamDescC) == 32 + 8 + 8 + 4 + 16 + 4
+
+
+def test_unet_param_layout_and_validation():
+    from paper_2312_05410_amd import unet
+
+    cfg = unet.UNetConfig()
+    e = unet.param_entries(cfg)
+    names = [x[0] for x in e]
+    assert names[:3] == ["enc0.w", "enc0.gamma", "enc0.beta"] and names[-1] == "film3.w"
+    d = dict((x[0], x[2]) for x in e)
+    assert d["enc0.w"] == (9, 32, 4) and d["mid.w"] == (9, 256, 256) and d["up3.w"] == (4, 128, 256)
+    assert d["dec0.w"] == (9, 32, 64) and d["head.w"] == (9, 3, 32) and d["film2.w"] == (128, 128)
+    offs = [x[1] for x in e]
+    assert offs == sorted(offs) and offs[0] == 0
+    L = unet.lib()
+    for bad in (dict(in_ch=3), dict(out_ch=4), dict(levels=1), dict(height=100), dict(base=6), dict(groups=5),
+                dict(mlp_hidden=300), dict(head_groups=2), dict(gn_eps=0.0), dict(max_batch=0), dict(base=128)):
+        c = unet.UNetConfig(**{**cfg.__dict__, **bad})
+        assert L.unet_param_count(ctypes.byref(c.c())) == -1, bad
+        assert L.unet_workspace_bytes(ctypes.byref(c.c())) == 0, bad
+    h = ctypes.c_void_p()
+    rc = L.unet_create(ctypes.byref(h), ctypes.byref(cfg.c()), None, None, None, 0, None)
+    assert rc == _lib.PF_EINVAL and not h.value
+
+
+def test_unet_ops_reject_bad_arguments():
+    """Shape and pointer errors are caught before any device work."""
+    from paper_2312_05410_amd import unet
+
+    L = unet.lib()
+    fake = 4096  # aligned non-null value: never dereferenced, every call below fails validation first
+    assert L.unet_conv3x3_fwd(0, 4, 4, fake, 4, None, 0, fake, 8, fake, fake, 1 << 20, None) == _lib.PF_EINVAL
+    assert L.unet_conv3x3_fwd(1, 4, 4, fake, 6, fake, 4, fake, 8, fake, fake, 1 << 20, None) == _lib.PF_EINVAL
+    assert L.unet_conv3x3_fwd(1, 4, 4, fake + 2, 4, None, 0, fake, 8, fake, fake, 1 << 20, None) == _lib.PF_EINVAL
+    assert L.unet_conv3x3_fwd(1, 4, 4, fake, 4, None, 0, fake, 8, fake, fake, 16, None) == _lib.PF_EINVAL
+    assert L.unet_up_dgrad(1, 4, 4, fake, 6, fake, 8, fake, fake, 1 << 20, None) == _lib.PF_EINVAL
+    assert L.unet_groupnorm_fwd(1, 16, 10, 3, 1e-5, 1, fake, fake, fake, None, fake, None, fake, fake, 1 << 20,
+                                None) == _lib.PF_EINVAL
+    assert L.unet_groupnorm_fwd(1, 16, 300, 3, 1e-5, 1, fake, fake, fake, None, fake, None, fake, fake, 1 << 20,
+                                None) == _lib.PF_EINVAL
+    assert L.unet_maxpool_fwd(1, 5, 4, 8, fake, fake, None) == _lib.PF_EINVAL

@@ -1,0 +1,369 @@
+"""U-Net kernels through the C ABI against the FP64 PyTorch-CPU oracle.
+
+Single ops take BF16-exact inputs and weights on both sides, so products
+are exact and the only GPU error is FP32 accumulation: |gpu - ref| is
+bounded by a few units of 2^-24 times the same sum over absolute values.
+The whole network is compared with the oracle's BF16-rounding forward
+(same storage roundings, FP64 arithmetic)."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+from oracle import unet_oracle as uo
+from paper_2312_05410_amd.inputs import uniform01
+from paper_2312_05410_amd.unet_inputs import bf16_exact, init_params
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2312_05410_amd import unet
+
+    unet.lib()
+
+
+def announce(msg):
+    print(f"\n[case] {msg}", flush=True)
+
+
+def dev_bf16(a):
+    import torch
+
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32).to(torch.bfloat16).cuda()
+
+
+def dev_f32(a):
+    import torch
+
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float32).cuda()
+
+
+def t64(a):
+    import torch
+
+    return torch.as_tensor(np.asarray(a), dtype=torch.float64)
+
+
+def nchw(a):
+    return t64(a).permute(0, 3, 1, 2)
+
+
+def nhwc(t):
+    return t.permute(0, 2, 3, 1)
+
+
+def check_bound(gpu, ref, bound, k, what):
+    err = np.abs(gpu.double().cpu().numpy() - ref)
+    lim = k * 2.0 ** -24 * bound + 1e-30
+    bad = err > lim
+    assert not bad.any(), f"{what}: {bad.sum()} of {bad.size} beyond bound, worst {float((err / lim).max()):.2f}x"
+
+
+# ------------------------------------------------------------------ conv3x3
+@pytest.mark.parametrize("n,H,W,C1,C2,Cout", [(2, 10, 13, 8, 12, 40), (1, 9, 7, 4, 0, 32), (2, 6, 11, 32, 32, 3),
+                                              (1, 16, 16, 64, 0, 70)])
+def test_conv3x3_fwd_dgrad_wgrad(n, H, W, C1, C2, Cout):
+    import torch
+
+    from paper_2312_05410_amd import unet as U
+
+    announce(f"conv3x3 n{n} {H}x{W} C1={C1} C2={C2} Cout={Cout}")
+    x1 = bf16_exact(1, (n, H, W, C1))
+    x2 = bf16_exact(2, (n, H, W, C2)) if C2 else None
+    w = bf16_exact(3, (9, Cout, C1 + C2), exp=9)
+    dy = bf16_exact(4, (n, H, W, Cout), exp=8)
+    xcat = np.concatenate([x1, x2], axis=3) if C2 else x1
+    # forward
+    y = U.conv3x3_fwd(dev_bf16(x1), dev_f32(w), dev_bf16(x2) if C2 else None)
+    torch.cuda.synchronize()
+    ref = nhwc(uo.conv3x3(nchw(xcat), t64(w))).numpy()
+    bound = nhwc(uo.conv3x3(nchw(np.abs(xcat)), t64(np.abs(w)))).numpy()
+    check_bound(y, ref, bound, 9 * (C1 + C2) + 4, "fwd")
+    # gradients by autograd of the oracle
+    xt = nchw(xcat).clone().requires_grad_(True)
+    wt = t64(w).clone().requires_grad_(True)
+    out = uo.conv3x3(xt, wt)
+    gx, gw = torch.autograd.grad(out, (xt, wt), nchw(dy))
+    dx1, dx2 = U.conv3x3_dgrad(dev_bf16(dy), dev_f32(w), C1, C2)
+    dwg = U.conv3x3_wgrad(dev_bf16(dy), dev_bf16(x1), dev_bf16(x2) if C2 else None)
+    torch.cuda.synchronize()
+    xb = nchw(np.abs(xcat)).clone().requires_grad_(True)
+    wb = t64(np.abs(w)).clone().requires_grad_(True)
+    bx, bw = torch.autograd.grad(uo.conv3x3(xb, wb), (xb, wb), nchw(np.abs(dy)))
+    gx, bx = nhwc(gx).numpy(), nhwc(bx).numpy()
+    check_bound(dx1, gx[..., :C1], bx[..., :C1], 9 * Cout + 4, "dgrad x1")
+    if C2:
+        check_bound(dx2, gx[..., C1:], bx[..., C1:], 9 * Cout + 4, "dgrad x2")
+    check_bound(dwg, gw.numpy(), bw.numpy(), 2 * n * H * W + 16, "wgrad")
+
+
+@pytest.mark.parametrize("n,H,W,Cin,Cout", [(2, 5, 7, 12, 8), (1, 8, 8, 64, 32), (3, 3, 5, 256, 128)])
+def test_up_fwd_dgrad_wgrad(n, H, W, Cin, Cout):
+    import torch
+
+    from paper_2312_05410_amd import unet as U
+
+    announce(f"up n{n} {H}x{W} Cin={Cin} Cout={Cout}")
+    x = bf16_exact(5, (n, H, W, Cin))
+    w = bf16_exact(6, (4, Cout, Cin), exp=9)
+    dy = bf16_exact(7, (n, 2 * H, 2 * W, Cout), exp=8)
+    y = U.up_fwd(dev_bf16(x), dev_f32(w))
+    dx = U.up_dgrad(dev_bf16(dy), dev_f32(w))
+    dw = U.up_wgrad(dev_bf16(dy), dev_bf16(x))
+    torch.cuda.synchronize()
+    xt = nchw(x).clone().requires_grad_(True)
+    wt = t64(w).clone().requires_grad_(True)
+    out = uo.up(xt, wt)
+    gx, gw = torch.autograd.grad(out, (xt, wt), nchw(dy))
+    xb = nchw(np.abs(x)).clone().requires_grad_(True)
+    wb = t64(np.abs(w)).clone().requires_grad_(True)
+    ob = uo.up(xb, wb)
+    bx, bw = torch.autograd.grad(ob, (xb, wb), nchw(np.abs(dy)))
+    check_bound(y, nhwc(out.detach()).numpy(), nhwc(ob.detach()).numpy(), Cin + 4, "up fwd")
+    check_bound(dx, nhwc(gx).numpy(), nhwc(bx).numpy(), 4 * Cout + 4, "up dgrad")
+    check_bound(dw, gw.numpy(), bw.numpy(), n * H * W + 16, "up wgrad")
+
+
+# ------------------------------------------------------------------ GN
+@pytest.mark.parametrize("n,P,C,G,gelu,film", [(2, 300, 40, 8, True, True), (1, 4096, 32, 8, True, False),
+                                               (3, 77, 3, 1, False, False), (2, 1000, 256, 8, True, True)])
+def test_groupnorm_fwd_bwd(n, P, C, G, gelu, film):
+    import torch
+
+    from paper_2312_05410_amd import unet as U
+
+    announce(f"groupnorm n{n} P{P} C{C} G{G} gelu={gelu} film={film}")
+    y = (2.0 * uniform01(11, np.arange(n * P * C)) - 1.0 + 0.3).reshape(n, P, C).astype(np.float32)
+    gam = (0.5 + uniform01(12, np.arange(C))).astype(np.float32)
+    bet = (uniform01(13, np.arange(C)) - 0.5).astype(np.float32)
+    sc = (uniform01(14, np.arange(n * C)) + 0.5).reshape(n, C).astype(np.float32) if film else None
+    dA = (uniform01(15, np.arange(n * P * C)) - 0.5).reshape(n, P, C).astype(np.float32)
+    dB = (uniform01(16, np.arange(n * P * C)) - 0.5).reshape(n, P, C).astype(np.float32) if film else None
+    z, zs, st = U.groupnorm_fwd(dev_f32(y), G, dev_f32(gam), dev_f32(bet), 1e-5, gelu, dev_f32(sc) if film else None)
+    dy, dg, db, ds = U.groupnorm_bwd(dev_f32(y), G, dev_f32(gam), dev_f32(bet), st, dev_f32(dA),
+                                     dev_f32(dB) if film else None, 1e-5, gelu, dev_f32(sc) if film else None)
+    torch.cuda.synchronize()
+    # oracle: [n][P][C] viewed as NCHW with H = P, W = 1
+    yt = t64(y).permute(0, 2, 1)[..., None].clone().requires_grad_(True)
+    gt = t64(gam).clone().requires_grad_(True)
+    bt = t64(bet).clone().requires_grad_(True)
+    a = uo.group_norm(yt, G, gt, bt, 1e-5)
+    zr = uo.gelu(a) if gelu else a
+    outs = [zr]
+    if film:
+        st_ = t64(sc).clone().requires_grad_(True)
+        zsr = zr * st_[:, :, None, None]
+        outs.append(zsr)
+    lin = (zr * t64(dA).permute(0, 2, 1)[..., None]).sum()
+    if film:
+        lin = lin + (zsr * t64(dB).permute(0, 2, 1)[..., None]).sum()
+    inputs = (yt, gt, bt) + ((st_,) if film else ())
+    grads = torch.autograd.grad(lin, inputs)
+    tocpu = lambda t: t.double().cpu().numpy()
+    zref = zr.detach()[..., 0].permute(0, 2, 1).numpy()
+    np.testing.assert_allclose(tocpu(z), zref, rtol=2e-5, atol=2e-5)
+    if film:
+        np.testing.assert_allclose(tocpu(zs), zsr.detach()[..., 0].permute(0, 2, 1).numpy(), rtol=2e-5, atol=2e-5)
+    g4 = yt.detach().reshape(n, G, C // G, P)
+    np.testing.assert_allclose(tocpu(st)[..., 0], g4.mean(dim=(2, 3)).numpy(), rtol=1e-5, atol=1e-6)
+    gy = grads[0][..., 0].permute(0, 2, 1).numpy()
+    scale = np.abs(gy).max()
+    np.testing.assert_allclose(tocpu(dy), gy, rtol=1e-3, atol=2e-4 * scale)
+    np.testing.assert_allclose(tocpu(dg), grads[1].numpy(), rtol=1e-4, atol=1e-4 * np.abs(grads[1].numpy()).max())
+    np.testing.assert_allclose(tocpu(db), grads[2].numpy(), rtol=1e-4, atol=1e-4 * np.abs(grads[2].numpy()).max())
+    if film:
+        np.testing.assert_allclose(tocpu(ds), grads[3].numpy(), rtol=1e-4,
+                                   atol=1e-4 * np.abs(grads[3].numpy()).max())
+
+
+def test_maxpool_first_maximum_rule():
+    import torch
+
+    from paper_2312_05410_amd import unet as U
+
+    announce("maxpool n2 10x14 C20 with ties")
+    n, H, W, C = 2, 10, 14, 20
+    x = bf16_exact(21, (n, H, W, C), kmax=3)          # few values: many ties
+    dy = (uniform01(22, np.arange(n * H * W * C // 4)) - 0.5).reshape(n, H // 2, W // 2, C).astype(np.float32)
+    y = U.maxpool_fwd(dev_bf16(x))
+    dx = U.maxpool_bwd(dev_bf16(x), dev_f32(dy))
+    torch.cuda.synchronize()
+    ref = nhwc(uo.down(nchw(x))).numpy()
+    assert np.array_equal(y.float().cpu().numpy(), ref)
+    dref = np.zeros_like(x)
+    for m in range(2):
+        for q in range(2):
+            win = x[:, m::2, q::2, :]
+            first = np.ones_like(win, dtype=bool)
+            for (m2, q2) in [(0, 0), (0, 1), (1, 0), (1, 1)]:
+                if (m2, q2) == (m, q):
+                    break
+                first &= ~(x[:, m2::2, q2::2, :] == ref)
+            dref[:, m::2, q::2, :] = np.where((win == ref) & first, dy, 0.0)
+    assert np.array_equal(dx.cpu().numpy(), dref)
+
+
+# ------------------------------------------------------------------ network
+def _cfg(H, W, levels, base, groups, n, hid=16, basis=16):
+    from paper_2312_05410_amd.unet import UNetConfig
+
+    return UNetConfig(height=H, width=W, base=base, levels=levels, groups=groups, mlp_hidden=hid, basis=basis,
+                      max_batch=n)
+
+
+def _state(seed, n, H, W):
+    c = (0.3 + 0.4 * uniform01(seed, np.arange(n * H * W))).reshape(n, H, W)
+    phi = (2 * uniform01(seed + 1, np.arange(n * H * W)) - 1).reshape(n, H, W)
+    rho = uniform01(seed + 2, np.arange(n * H * W)).reshape(n, H, W)
+    return [a.astype(np.float32) for a in (c, phi, rho)]
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def check_forward(cfg, params, st, jump, out):
+    """Increments (prediction - input) against the BF16-rounding oracle in
+    FP64.  A BF16 rounding point turns accumulation error into a jump of one
+    BF16 step wherever a value sits near a rounding boundary, and later
+    layers amplify such jumps; the same oracle evaluated in FP32 measures
+    that amplification (sens).  The limit is 3 sens, and never below 5e-3."""
+    import torch
+
+    ref = uo.Net(cfg, params).forward(*st, jump, bf16=True)
+    ref32 = uo.Net(cfg, params, dtype=torch.float32).forward(*st, jump, bf16=True)
+    for name, o, r, r32, s in zip(("c", "phi", "rho"), out, ref, ref32, st):
+        rinc = r.detach().numpy() - s
+        e = rel_l2(o.double().cpu().numpy() - s, rinc)
+        sens = rel_l2(r32.detach().double().numpy() - s, rinc)
+        print(f"{name}: increment rel L2 {e:.2e} (oracle FP32 vs FP64 {sens:.2e})", flush=True)
+        assert e < max(5e-3, 3 * sens), f"{name}: increment rel L2 {e:.2e}, sensitivity {sens:.2e}"
+
+
+@pytest.mark.parametrize("H,W,levels,base,groups,n", [(32, 32, 3, 8, 4, 2), (24, 40, 4, 8, 2, 3)])
+def test_network_forward_matches_oracle(H, W, levels, base, groups, n):
+    import torch
+
+    from paper_2312_05410_amd.unet import UNet
+
+    announce(f"network forward {H}x{W} L{levels} base{base} n{n}")
+    cfg = _cfg(H, W, levels, base, groups, n)
+    net = UNet(cfg, seed=7)
+    params = net.param_dict()
+    st = _state(31, n, H, W)
+    jump = np.array([1.0, 2.0, 0.5][:n], dtype=np.float32)
+    out = net.forward(*(dev_f32(a) for a in st), dev_f32(jump))
+    torch.cuda.synchronize()
+    check_forward(cfg, params, st, jump, out)
+    net.close()
+
+
+@pytest.mark.parametrize("H,W,levels,base,groups,n", [(32, 32, 3, 8, 4, 2), (16, 24, 2, 16, 8, 3)])
+def test_network_gradients_match_oracle(H, W, levels, base, groups, n):
+    import torch
+
+    from paper_2312_05410_amd.unet import UNet
+
+    announce(f"network gradients {H}x{W} L{levels} base{base} n{n}")
+    cfg = _cfg(H, W, levels, base, groups, n)
+    p0 = None
+    net = UNet(cfg, seed=8)
+    p0 = net.param_dict()
+    p0["head.gamma"][:] = 0.3
+    net.set_params(p0)
+    st = _state(41, n, H, W)
+    tgt = _state(51, n, H, W)
+    jump = np.array([1.0, 3.0, 2.0][:n], dtype=np.float32)
+    pred = net.forward(*(dev_f32(a) for a in st), dev_f32(jump))
+    L = net.backward(pred, [dev_f32(a) for a in tgt])
+    g = net.grad_dict()
+    Lr, gr = uo.Net(cfg, p0).loss_and_grads(st, jump, tgt, bf16=True)
+    print(f"loss {L:.8e} ref {Lr:.8e}", flush=True)
+    assert L == pytest.approx(Lr, rel=1e-3)
+    # Limits: the GPU stores every activation gradient in BF16 (relative
+    # rounding 2^-9) and passes at most 2 levels + 2 of them before a weight
+    # gradient, so 2e-2 per tensor.  The first layer's weight gradient is a
+    # sum of dy x where GN makes dy zero-mean per group and the inputs hold a
+    # constant channel (the jump) and a nearly constant one (c): the exact sum
+    # cancels, the BF16 copy of dy does not, so its limit is 8e-2.
+    num = den = 0.0
+    errs = {}
+    for name in gr:
+        errs[name] = rel_l2(g[name], gr[name])
+        num += float(np.sum((g[name] - gr[name]) ** 2))
+        den += float(np.sum(gr[name] ** 2))
+    print("grad rel L2: " + ", ".join(f"{k} {v:.1e}" for k, v in errs.items()), flush=True)
+    for name, e in errs.items():
+        assert e < (8e-2 if name == "enc0.w" else 2e-2), f"{name}: grad rel L2 {e:.2e}"
+    assert (num / den) ** 0.5 < 1e-2
+    net.close()
+
+
+def test_network_full_size_forward():
+    """The production shape (512^2, 4 levels of 32..256 channels, batch 1)
+    against the oracle's full BF16-rounding forward."""
+    import torch
+
+    from paper_2312_05410_amd.unet import UNet, UNetConfig
+
+    announce("network forward 512x512 L4 base32 n1")
+    cfg = UNetConfig(max_batch=1)
+    net = UNet(cfg, seed=9)
+    st = _state(61, 1, 512, 512)
+    jump = np.array([1.0], dtype=np.float32)
+    out = net.forward(*(dev_f32(a) for a in st), dev_f32(jump))
+    torch.cuda.synchronize()
+    check_forward(cfg, net.param_dict(), st, jump, out)
+    net.close()
+
+
+def test_adam_matches_oracle():
+    import torch
+
+    from paper_2312_05410_amd.unet import UNet
+
+    announce("adam two steps")
+    net = UNet(_cfg(16, 16, 2, 8, 4, 1), seed=10)
+    n = net.params.numel()
+    w0 = net.params.double().cpu().numpy()
+    g1 = (uniform01(71, np.arange(n)) - 0.5).astype(np.float32)
+    g2 = (uniform01(72, np.arange(n)) - 0.5).astype(np.float32)
+    net.grads.copy_(torch.from_numpy(g1))
+    net.adam_step(lr=1e-3)
+    net.grads.copy_(torch.from_numpy(g2))
+    net.adam_step(lr=1e-3)
+    torch.cuda.synchronize()
+    w, m, v = uo.adam(w0, g1, np.zeros(n), np.zeros(n), 1, 1e-3, 0.9, 0.999, 1e-8)
+    w, m, v = uo.adam(w, g2, m, v, 2, 1e-3, 0.9, 0.999, 1e-8)
+    np.testing.assert_allclose(net.params.double().cpu().numpy(), w, rtol=0, atol=1e-6)
+    # m = b1 m + (1 - b1) g in FP32, where b1 = 0.9 and 1 - b1 are themselves
+    # off by up to 2.4e-7 relative; |m| <= 0.05 here
+    np.testing.assert_allclose(net.m.double().cpu().numpy(), m, rtol=0, atol=1e-7)
+    net.close()
+
+
+def test_training_reduces_loss():
+    import torch
+
+    from paper_2312_05410_amd.unet import UNet
+
+    announce("training 40 Adam steps on one batch")
+    cfg = _cfg(32, 32, 3, 8, 4, 2)
+    net = UNet(cfg, seed=11)
+    st = [dev_f32(a) for a in _state(81, 2, 32, 32)]
+    tgt = [a + off for a, off in zip(st, (0.01, -0.02, 0.015))]
+    jump = dev_f32(np.array([1.0, 1.0], dtype=np.float32))
+    losses = []
+    for _ in range(40):
+        pred = net.forward(*st, jump)
+        losses.append(net.backward(pred, tgt))
+        net.adam_step(lr=2e-3)
+    print("losses", losses[0], losses[-1], flush=True)
+    assert losses[-1] < 0.3 * losses[0]
+    net.close()
