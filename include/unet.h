@@ -55,7 +55,7 @@ typedef struct unet_config {
     int32_t height, width;  /* grid (ny, nx); divisible by 2^(levels-1) */
     int32_t in_ch;          /* must be 4: c, phi, rho, jump-length map */
     int32_t out_ch;         /* must be 3: increments of c, phi, rho */
-    int32_t base;           /* channels of the first level; level l has base*2^l */
+    int32_t base;           /* channels of the first level, a multiple of 8; level l has base*2^l */
     int32_t levels;         /* encoder levels, 2..6 */
     int32_t groups;         /* GN groups of the convolution blocks */
     int32_t head_groups;    /* GN groups of the output head (divides out_ch) */
@@ -98,6 +98,11 @@ int unet_prepare(unet_handle* h);
  * inputs).  Activations are kept for unet_backward. */
 int unet_forward(unet_handle* h, int n, const float* jump, const float* c, const float* phi, const float* rho,
                  float* oc, float* ophi, float* orho);
+
+/* The same prediction without keeping what unet_backward needs (inference:
+ * less memory traffic); a following unet_backward returns PF_EINVAL. */
+int unet_forward_infer(unet_handle* h, int n, const float* jump, const float* c, const float* phi, const float* rho,
+                       float* oc, float* ophi, float* orho);
 
 /* Loss of the last forward's prediction (pc, pphi, prho) against the truth
  * (tc, tphi, trho), and its gradient with respect to every parameter,

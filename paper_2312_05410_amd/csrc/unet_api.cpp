@@ -21,15 +21,17 @@ namespace {
 
 using namespace pfu;
 
-size_t r16(size_t v) { return (v + 15) / 16 * 16; }
-size_t r64(size_t v) { return (v + 63) / 64 * 64; }
+// operand weight padding: K to a multiple of 32 (one wide MFMA step), output
+// rows to a multiple of 128 (the widest block tile)
+size_t r32(size_t v) { return (v + 31) / 32 * 32; }
+size_t r128(size_t v) { return (v + 127) / 128 * 128; }
 size_t r256(size_t v) { return (v + 255) / 256 * 256; }
 
 bool cfg_ok(const unet_config* c)
 {
     if (!c) return false;
     if (c->in_ch != 4 || c->out_ch != 3) return false;
-    if (c->levels < 2 || c->levels > kMaxLevels || c->base < 4 || c->base % 4) return false;
+    if (c->levels < 2 || c->levels > kMaxLevels || c->base < 8 || c->base % 8) return false;
     if (c->height <= 0 || c->width <= 0 || c->max_batch <= 0) return false;
     const int f = 1 << (c->levels - 1);
     if (c->height % f || c->width % f) return false;
@@ -64,6 +66,7 @@ size_t wgrad_floats(long P, int taps, int Nout, int K)
 struct Conv {
     int pw = -1, pg = -1, pb = -1;  // parameter indices (weight, gamma, beta)
     int taps = 9, cin1 = 0, cin2 = 0, cout = 0, groups = 1, gelu = 1;
+    bool folded = false;             // 4-channel input: forward operand [1][ldo_f][64], k = 4 tap + c
     uint16_t* wf = nullptr;          // BF16 forward operand [taps][ldo_f][ldk_f]
     uint16_t* wt = nullptr;          // BF16 transposed operand (input gradient)
     int ldo_f = 0, ldk_f = 0, ldo_t = 0, ldk_t = 0;
@@ -117,6 +120,7 @@ struct Net {
             snprintf(nm, sizeof nm, "enc%d", l);
             add_conv(enc[l], nm, l ? w[l - 1] : c.in_ch, 0, w[l], c.groups, 1);
         }
+        enc[0].folded = true;
         add_conv(mid, "mid", w[L - 1], 0, w[L - 1], c.groups, 1);
         for (int l = L - 1; l >= 1; --l) {
             snprintf(nm, sizeof nm, "up%d.w", l);
@@ -160,6 +164,7 @@ struct Bufs {
     float* std_[kMaxLevels];
     float *yh, *sth, *hout;
     float *jump, *h0, *h1, *f, *sc[kMaxLevels];
+    float *mdf, *mdh1, *mdh0;
     // backward
     float* gout;
     uint16_t* dyh;
@@ -200,7 +205,8 @@ void carve(Net& net, char* base, Bufs& b)
     size_t part = 0, csum = 0;
     int cmax = 0, gmax = 0;
     auto note_gn = [&](long P1, int C, int G) {
-        csum = std::max(csum, gn_csum_floats(n, (int)P1, C));
+        // partials: the normalisation's own chunks, or one per conv tile (>= 64 pixels)
+        csum = std::max(csum, std::max(gn_csum_floats(n, (int)P1, C), (size_t)n * ((P1 + 63) / 64) * C * 3));
         cmax = std::max(cmax, C);
         gmax = std::max(gmax, G);
     };
@@ -256,6 +262,9 @@ void carve(Net& net, char* base, Bufs& b)
     b.h0 = m.take<float>((size_t)n * Hd);
     b.h1 = m.take<float>((size_t)n * Hd);
     b.f = m.take<float>((size_t)n * F);
+    b.mdf = m.take<float>((size_t)n * F);
+    b.mdh1 = m.take<float>((size_t)n * Hd);
+    b.mdh0 = m.take<float>((size_t)n * Hd);
     b.lpart = m.take<double>(rel_mse_partial_doubles());
     b.loss = m.take<double>(4);
     b.wpart = m.take<float>(part);
@@ -263,13 +272,19 @@ void carve(Net& net, char* base, Bufs& b)
     b.cacc = m.take<double>((size_t)n * (3 * cmax + 2 * gmax));
     // BF16 operand copies of every weight
     auto wcopies = [&](Conv& k, bool tr) {
+        if (k.folded) {
+            k.ldo_f = (int)r128(k.cout);
+            k.ldk_f = 64;
+            k.wf = m.take<uint16_t>((size_t)k.ldo_f * 64);
+            return;
+        }
         const int R = k.taps == 9 ? k.cout : 4 * k.cout, Kc = k.cin1 + k.cin2;
-        k.ldo_f = (int)r64(R);
-        k.ldk_f = (int)r16(Kc);
+        k.ldo_f = (int)r128(R);
+        k.ldk_f = (int)r32(Kc);
         k.wf = m.take<uint16_t>((size_t)k.taps * k.ldo_f * k.ldk_f);
         if (tr) {
-            k.ldo_t = (int)r64(Kc);
-            k.ldk_t = (int)r16(R);
+            k.ldo_t = (int)r128(Kc);
+            k.ldk_t = (int)r32(R);
             k.wt = m.take<uint16_t>((size_t)k.taps * k.ldo_t * k.ldk_t);
         }
     };
@@ -309,6 +324,7 @@ float* grd(unet_handle* h, int idx) { return h->grads + h->net.params[idx].offse
 
 int prep(unet_handle* h, Conv& k)
 {
+    if (k.folded) return dev_err(weight_prep_folded(par(h, k.pw), k.cout, k.wf, k.ldo_f, h->stream));
     const int R = k.taps == 9 ? k.cout : 4 * k.cout, Kc = k.cin1 + k.cin2;
     return dev_err(weight_prep(par(h, k.pw), k.taps, R, Kc, k.wf, k.ldo_f, k.ldk_f, k.wt, k.ldo_t, k.ldk_t, h->stream));
 }
@@ -417,6 +433,9 @@ MLPArgs mlp_args(unet_handle* h, int n, const float* jump)
     a.h0 = h->b.h0;
     a.h1 = h->b.h1;
     a.f = h->b.f;
+    a.df = h->b.mdf;
+    a.dh1 = h->b.mdh1;
+    a.dh0 = h->b.mdh0;
     a.N = n;
     a.Hd = net.c.mlp_hidden;
     a.F = net.c.basis;
@@ -431,14 +450,38 @@ MLPArgs mlp_args(unet_handle* h, int n, const float* jump)
     return a;
 }
 
+// Convolution whose output feeds a group normalisation: the wide kernel's
+// epilogue writes the normalisation's partial sums when a sample's pixels
+// split evenly into its blocks.
+int conv_gn(unet_handle* h, ConvArgs a, int mode, GNArgs g)
+{
+    const int rows = conv_stat_rows(a, mode);
+    const long Ps = (long)a.H * a.W;
+    if (rows > 0 && Ps % rows == 0) {
+        a.gsum = h->b.csum;
+        g.sums_ready = 1;
+        g.chunks = (int)(Ps / rows);
+    }
+    UCHECK(conv_gemm(a, mode, h->stream));
+    UCHECK(gn_forward(g, h->stream));
+    return PF_OK;
+}
+
+#define RCHECK(x)                      \
+    do {                               \
+        const int r_ = (x);            \
+        if (r_ != PF_OK) return r_;    \
+    } while (0)
+
+// train: also keep what the backward pass reads (the unconditioned encoder
+// latents z_l behind the pooling)
 int forward(unet_handle* h, int n, const float* jump, const float* c, const float* phi, const float* rho, float* oc,
-            float* ophi, float* orho)
+            float* ophi, float* orho, bool train)
 {
     Net& net = h->net;
     Bufs& b = h->b;
     hipStream_t s = h->stream;
     const int L = net.L;
-    const int* w = net.w;
     auto Hl = [&](int l) { return net.c.height >> l; };
     auto Wl = [&](int l) { return net.c.width >> l; };
     const long P0 = net.P(0, 1);
@@ -446,27 +489,28 @@ int forward(unet_handle* h, int n, const float* jump, const float* c, const floa
     UCHECK(hipMemcpyAsync(b.jump, jump, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
     UCHECK(assemble_input(c, phi, rho, b.jump, b.xin, n, (int)P0, s));
     UCHECK(mlp_forward(mlp_args(h, n, b.jump), s));
-    // encoder: z_l = block(down(z_{l-1})), zs_l = z_l * (w_l f(dt))
+    // encoder: z_l = block(down(z_{l-1})), zs_l = z_l * (w_l f(dt)); the
+    // normalisation kernel also pools z_l for the next level
     for (int l = 0; l < L; ++l) {
         const Conv& k = net.enc[l];
         ConvArgs a = conv_args(k, n, Hl(l), Wl(l), l ? b.q[l - 1] : b.xin, nullptr);
         a.out_f32 = b.y[l];
-        UCHECK(conv_gemm(a, kConvFwd, s));
         GNArgs g = gn_args(h, k, n, net.P(l, 1), b.y[l], b.st[l]);
         g.scale = b.sc[l];
-        g.z_bf16 = b.z[l];
+        g.z_bf16 = train ? b.z[l] : nullptr;
         g.zs_bf16 = b.zs[l];
-        UCHECK(gn_forward(g, s));
-        if (l < L - 1) UCHECK(maxpool_fwd(b.z[l], b.q[l], n, Hl(l), Wl(l), w[l], s));
+        g.pool_bf16 = l < L - 1 ? b.q[l] : nullptr;
+        g.H = Hl(l);
+        g.W = Wl(l);
+        RCHECK(conv_gn(h, a, l ? kConvFwd : kFirst, g));
     }
-    // bottom block and the first up-sampling
+    // bottom block
     {
         ConvArgs a = conv_args(net.mid, n, Hl(L - 1), Wl(L - 1), b.zs[L - 1], nullptr);
         a.out_f32 = b.ym;
-        UCHECK(conv_gemm(a, kConvFwd, s));
         GNArgs g = gn_args(h, net.mid, n, net.P(L - 1, 1), b.ym, b.stm);
         g.z_bf16 = b.am;
-        UCHECK(gn_forward(g, s));
+        RCHECK(conv_gn(h, a, kConvFwd, g));
     }
     for (int l = L - 2; l >= 0; --l) {
         // d_l = up(a_{l+1}); block(zs_l (+) d_l)
@@ -476,22 +520,20 @@ int forward(unet_handle* h, int n, const float* jump, const float* c, const floa
         UCHECK(conv_gemm(u, kUpFwd, s));
         ConvArgs a = conv_args(net.dec[l], n, Hl(l), Wl(l), b.zs[l], b.d[l]);
         a.out_f32 = b.yd[l];
-        UCHECK(conv_gemm(a, kConvFwd, s));
         GNArgs g = gn_args(h, net.dec[l], n, net.P(l, 1), b.yd[l], b.std_[l]);
         g.z_bf16 = b.ad[l];
-        UCHECK(gn_forward(g, s));
+        RCHECK(conv_gn(h, a, kConvFwd, g));
     }
     // head: GN(conv(a_0)), added to the input state
     {
         ConvArgs a = conv_args(net.head, n, Hl(0), Wl(0), b.ad[0], nullptr);
         a.out_f32 = b.yh;
-        UCHECK(conv_gemm(a, kConvFwd, s));
         GNArgs g = gn_args(h, net.head, n, P0, b.yh, b.sth);
         g.z_f32 = b.hout;
-        UCHECK(gn_forward(g, s));
+        RCHECK(conv_gn(h, a, kConvFwd, g));
         UCHECK(residual_out(b.hout, c, phi, rho, oc, ophi, orho, n, (int)P0, s));
     }
-    h->last_n = n;
+    h->last_n = train ? n : 0;
     return PF_OK;
 }
 
@@ -678,7 +720,16 @@ int unet_forward(unet_handle* h, int n, const float* jump, const float* c, const
     if (!h || n <= 0 || n > h->net.c.max_batch) return PF_EINVAL;
     if (!al(jump, 4) || !al(c, 4) || !al(phi, 4) || !al(rho, 4) || !al(oc, 4) || !al(ophi, 4) || !al(orho, 4))
         return PF_EINVAL;
-    return forward(h, n, jump, c, phi, rho, oc, ophi, orho);
+    return forward(h, n, jump, c, phi, rho, oc, ophi, orho, true);
+}
+
+int unet_forward_infer(unet_handle* h, int n, const float* jump, const float* c, const float* phi, const float* rho,
+                       float* oc, float* ophi, float* orho)
+{
+    if (!h || n <= 0 || n > h->net.c.max_batch) return PF_EINVAL;
+    if (!al(jump, 4) || !al(c, 4) || !al(phi, 4) || !al(rho, 4) || !al(oc, 4) || !al(ophi, 4) || !al(orho, 4))
+        return PF_EINVAL;
+    return forward(h, n, jump, c, phi, rho, oc, ophi, orho, false);
 }
 
 int unet_backward(unet_handle* h, const float* pc, const float* pphi, const float* prho, const float* tc,
@@ -736,8 +787,8 @@ size_t unet_op_workspace_bytes(int n, int H, int W, int Cmax)
 {
     if (!dims_ok(n, H, W) || Cmax <= 0) return 0;
     const size_t C = (size_t)Cmax;
-    const size_t wconv = 9 * r64(C) * r16(C), wup = r64(4 * C) * r16(C) + r64(C) * r16(4 * C);
-    const size_t wbytes = r256(2 * std::max(wconv, wup)) + r256(2 * 9 * r64(C) * r16(C));
+    const size_t wconv = 9 * r128(C) * r32(C), wup = r128(4 * C) * r32(C) + r128(C) * r32(4 * C);
+    const size_t wbytes = r256(2 * std::max(wconv, wup)) + r256(2 * 9 * r128(C) * r32(C));
     const size_t part = (size_t)4194304 + 9 * C * 4 * C;
     const size_t P = (size_t)H * W;
     const size_t csum = gn_csum_floats(n, (int)std::min(P, (size_t)1 << 30), Cmax);
@@ -753,10 +804,10 @@ int unet_conv3x3_fwd(int n, int H, int W, const uint16_t* x1, int C1, const uint
     if (C2 > 0 && (!al(x2, 8) || C1 % 4)) return PF_EINVAL;
     const int K = C1 + C2;
     OpWs ws{(char*)workspace, workspace_bytes};
-    uint16_t* wf = ws.take<uint16_t>(9 * r64(Cout) * r16(K));
+    uint16_t* wf = ws.take<uint16_t>(9 * r128(Cout) * r32(K));
     if (!ws.ok) return PF_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    UCHECK(weight_prep(w, 9, Cout, K, wf, (int)r64(Cout), (int)r16(K), nullptr, 0, 0, s));
+    UCHECK(weight_prep(w, 9, Cout, K, wf, (int)r128(Cout), (int)r32(K), nullptr, 0, 0, s));
     ConvArgs a{};
     a.in1 = x1;
     a.in2 = C2 ? x2 : nullptr;
@@ -768,8 +819,8 @@ int unet_conv3x3_fwd(int n, int H, int W, const uint16_t* x1, int C1, const uint
     a.C1 = C1;
     a.C2 = C2;
     a.Nout = a.O1 = Cout;
-    a.ldk = (int)r16(K);
-    a.ldo = (int)r64(Cout);
+    a.ldk = (int)r32(K);
+    a.ldo = (int)r128(Cout);
     UCHECK(conv_gemm(a, kConvFwd, s));
     return PF_OK;
 }
@@ -783,10 +834,10 @@ int unet_conv3x3_dgrad(int n, int H, int W, const uint16_t* dy, int Cout, const 
     if (C2 > 0 && !al(dx2, 4)) return PF_EINVAL;
     const int K = C1 + C2;
     OpWs ws{(char*)workspace, workspace_bytes};
-    uint16_t* wt = ws.take<uint16_t>(9 * r64(K) * r16(Cout));
+    uint16_t* wt = ws.take<uint16_t>(9 * r128(K) * r32(Cout));
     if (!ws.ok) return PF_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    UCHECK(weight_prep(w, 9, Cout, K, nullptr, 0, 0, wt, (int)r64(K), (int)r16(Cout), s));
+    UCHECK(weight_prep(w, 9, Cout, K, nullptr, 0, 0, wt, (int)r128(K), (int)r32(Cout), s));
     ConvArgs a{};
     a.in1 = dy;
     a.Wt = wt;
@@ -798,8 +849,8 @@ int unet_conv3x3_dgrad(int n, int H, int W, const uint16_t* dy, int Cout, const 
     a.C1 = Cout;
     a.Nout = K;
     a.O1 = C1;
-    a.ldk = (int)r16(Cout);
-    a.ldo = (int)r64(K);
+    a.ldk = (int)r32(Cout);
+    a.ldo = (int)r128(K);
     UCHECK(conv_gemm(a, kConvDgrad, s));
     return PF_OK;
 }
@@ -837,10 +888,10 @@ int unet_up_fwd(int n, int H, int W, const uint16_t* x, int Cin, const float* w,
         !al(workspace, 256))
         return PF_EINVAL;
     OpWs ws{(char*)workspace, workspace_bytes};
-    uint16_t* wf = ws.take<uint16_t>(r64(4 * Cout) * r16(Cin));
+    uint16_t* wf = ws.take<uint16_t>(r128(4 * Cout) * r32(Cin));
     if (!ws.ok) return PF_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    UCHECK(weight_prep(w, 1, 4 * Cout, Cin, wf, (int)r64(4 * Cout), (int)r16(Cin), nullptr, 0, 0, s));
+    UCHECK(weight_prep(w, 1, 4 * Cout, Cin, wf, (int)r128(4 * Cout), (int)r32(Cin), nullptr, 0, 0, s));
     ConvArgs a{};
     a.in1 = x;
     a.Wt = wf;
@@ -850,8 +901,8 @@ int unet_up_fwd(int n, int H, int W, const uint16_t* x, int Cin, const float* w,
     a.W = W;
     a.C1 = Cin;
     a.Nout = a.O1 = 4 * Cout;
-    a.ldk = (int)r16(Cin);
-    a.ldo = (int)r64(4 * Cout);
+    a.ldk = (int)r32(Cin);
+    a.ldo = (int)r128(4 * Cout);
     UCHECK(conv_gemm(a, kUpFwd, s));
     return PF_OK;
 }
@@ -863,10 +914,10 @@ int unet_up_dgrad(int n, int H, int W, const uint16_t* dy, int Cout, const float
         !al(workspace, 256))
         return PF_EINVAL;
     OpWs ws{(char*)workspace, workspace_bytes};
-    uint16_t* wt = ws.take<uint16_t>(r64(Cin) * r16(4 * Cout));
+    uint16_t* wt = ws.take<uint16_t>(r128(Cin) * r32(4 * Cout));
     if (!ws.ok) return PF_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    UCHECK(weight_prep(w, 1, 4 * Cout, Cin, nullptr, 0, 0, wt, (int)r64(Cin), (int)r16(4 * Cout), s));
+    UCHECK(weight_prep(w, 1, 4 * Cout, Cin, nullptr, 0, 0, wt, (int)r128(Cin), (int)r32(4 * Cout), s));
     ConvArgs a{};
     a.in1 = dy;
     a.Wt = wt;
@@ -876,8 +927,8 @@ int unet_up_dgrad(int n, int H, int W, const uint16_t* dy, int Cout, const float
     a.W = W;
     a.C1 = 4 * Cout;
     a.Nout = a.O1 = Cin;
-    a.ldk = (int)r16(4 * Cout);
-    a.ldo = (int)r64(Cin);
+    a.ldk = (int)r32(4 * Cout);
+    a.ldo = (int)r128(Cin);
     UCHECK(conv_gemm(a, kUpDgrad, s));
     return PF_OK;
 }

@@ -15,7 +15,9 @@ constexpr int kMaxLevels = 6;
 
 // Implicit GEMM out[p][o] = sum_k A[p][k] B[o][k]; see unet_conv.hip for
 // the four gather/scatter modes.
-enum ConvMode { kConvFwd = 0, kConvDgrad = 1, kUpFwd = 2, kUpDgrad = 3 };
+// kFirst: 3x3 convolution of a 4-channel input with the taps folded into K
+// (k = 4 tap + c, weights [1][ldo][64]); forward only.
+enum ConvMode { kConvFwd = 0, kConvDgrad = 1, kUpFwd = 2, kUpDgrad = 3, kFirst = 4 };
 
 struct ConvArgs {
     const uint16_t* in1;   // first input (NHWC, C1 channels)
@@ -28,8 +30,12 @@ struct ConvArgs {
     int N, H, W;           // pixel grid the GEMM rows run over
     int C1, C2;            // input channels (K per tap = C1 + C2)
     int Nout, O1;          // output channels, split point (O1 = Nout: no split)
-    int ldk;               // row stride of Wt (K rounded up to 16)
-    int ldo;               // rows per tap of Wt (Nout rounded up to 64)
+    int ldk;               // row stride of Wt (K rounded up to 32)
+    int ldo;               // rows per tap of Wt (Nout rounded up to 128)
+    // optional per-tile channel sums of the FP32 output for group
+    // normalisation, [N][Nout][P_sample / rows per block][2] = (sum, sum of
+    // squares); only with conv_stat_rows() > 0
+    float* gsum;
 };
 
 struct WgradArgs {
@@ -42,6 +48,14 @@ struct WgradArgs {
 };
 
 hipError_t conv_gemm(const ConvArgs& a, int mode, hipStream_t s);
+// True when conv_gemm takes the wide 16x16x32 kernel: channel counts
+// multiples of 32 (128 for the up-sampling gradient's 4 sub-pixels),
+// ldk % 32 == 0, ldo % 128 == 0 and 16-byte aligned operands.
+bool conv_wide_ok(const ConvArgs& a, int mode);
+// Pixel rows per block of the kernel conv_gemm picks for (a, mode) when it
+// can also write a.gsum (wide kernel, forward modes), else 0.  a.gsum is
+// usable when the pixels of one sample are a multiple of it.
+int conv_stat_rows(const ConvArgs& a, int mode);
 // dW[taps][Nout][C1+C2] = (accumulate ? dW : 0) + sum over pixels; mode
 // kConvFwd (3x3) or kUpFwd (2x2 stride 2).  a.partial must hold
 // wgrad_partial_floats() floats.
@@ -52,6 +66,9 @@ size_t wgrad_partial_floats(const WgradArgs& a, int mode);
 // either may be null.
 hipError_t weight_prep(const float* W, int taps, int R, int Kc, uint16_t* fwd, int ldo_f, int ldk_f, uint16_t* tr,
                        int ldo_t, int ldk_t, hipStream_t s);
+// kFirst operand of a [9][R][4] weight: out[o][4 t + c] = W[t][o][c],
+// [ldo][64] zero padded.
+hipError_t weight_prep_folded(const float* W, int R, uint16_t* out, int ldo, hipStream_t s);
 
 // ---------------------------------------------------------------- elementwise
 // Per-channel partial sums over pixel chunks, then finished per sample.
@@ -61,7 +78,8 @@ struct GNArgs {
     const float* beta;     // [C]
     const float* scale;    // FiLM scale [N][C] or null
     float* stats;          // [N][G][2]: mean, 1/sqrt(var + eps)
-    float* csum;           // per-(N, chunk, C, 3) partial sums (workspace)
+    float* csum;           // partial sums (workspace): forward [N][C][chunks][2],
+                           // backward [N][chunks][C][3]
     double* cacc;          // [N][C][3] finished per-channel sums (workspace)
     // forward outputs (any may be null): z = act(GN(y)), zs = z * scale
     float* z_f32;
@@ -76,10 +94,13 @@ struct GNArgs {
     float* dgamma;         // [C] (=, summed over samples)
     float* dbeta;          // [C] (=)
     float* dscale;         // [N][C] (=), when scale and dB are given
+    uint16_t* pool_bf16;   // forward: 2x2 max pool of z (BF16) or null
+    int H, W;              // pixel grid of one sample when pooling (H W = P)
     int N, P, C, G;
     int gelu;
     float eps;
-    int chunks;            // pixel chunks per sample
+    int chunks;            // partial sums per sample
+    int sums_ready;        // forward: csum already holds `chunks` partials
 };
 hipError_t gn_forward(const GNArgs& a, hipStream_t s);
 hipError_t gn_backward(const GNArgs& a, hipStream_t s);
@@ -100,7 +121,7 @@ hipError_t residual_out(const float* head, const float* c, const float* phi, con
                         float* orho, int N, int P, hipStream_t s);
 
 // Time basis f(jump) (two sin layers of width Hd) and the per-level FiLM
-// scales s_l = w_l f; one block per sample.
+// scales s_l = w_l f.
 struct MLPArgs {
     const float* jump;     // [N]
     const float* W0;       // [Hd]
@@ -115,6 +136,9 @@ struct MLPArgs {
     float* f;              // [N][F]
     float* sc[kMaxLevels];          // [N][C_l]
     const float* dsc[kMaxLevels];   // backward: [N][C_l]
+    float* df;             // backward workspace [N][F]
+    float* dh1;            // [N][Hd]
+    float* dh0;            // [N][Hd]
     float* gW0; float* gb0; float* gW1; float* gb1; float* gW2; float* gb2;
     float* gWl[kMaxLevels];
     int N, Hd, F, L;

@@ -74,28 +74,45 @@ __global__ __launch_bounds__(256) void gn_stats_kernel(GNArgs a, int CH)
             t0 += sh[0][k * a.C + tid];
             t1 += sh[1][k * a.C + tid];
         }
-        float* o = a.csum + (((size_t)n * a.chunks + chunk) * a.C + tid) * 3;
+        float* o = a.csum + (((size_t)n * a.C + tid) * a.chunks + chunk) * 2;
         o[0] = t0;
         o[1] = t1;
     }
 }
 
-// mean and 1/sqrt(var + eps) per (sample, group); one block
+// Fixed-order tree sum of per-thread values over a 256-thread block.
+template <int Q>
+__device__ __forceinline__ void block_sum(double (*sh)[256], double* v)
+{
+    const int tid = threadIdx.x;
+    for (int q = 0; q < Q; ++q) sh[q][tid] = v[q];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (tid < w)
+            for (int q = 0; q < Q; ++q) sh[q][tid] += sh[q][tid + w];
+        __syncthreads();
+    }
+    for (int q = 0; q < Q; ++q) v[q] = sh[q][0];
+}
+
+// mean and 1/sqrt(var + eps) of one (sample, group) per block
 __global__ __launch_bounds__(256) void gn_stats_finish(GNArgs a)
 {
-    const int Cg = a.C / a.G;
-    const double M = (double)Cg * a.P;
-    for (int i = threadIdx.x; i < a.N * a.G; i += blockDim.x) {
-        const int n = i / a.G, g = i % a.G;
-        double s0 = 0.0, s1 = 0.0;
-        for (int c = g * Cg; c < (g + 1) * Cg; ++c)
-            for (int k = 0; k < a.chunks; ++k) {
-                const float* o = a.csum + (((size_t)n * a.chunks + k) * a.C + c) * 3;
-                s0 += o[0];
-                s1 += o[1];
-            }
-        const double mean = s0 / M;
-        const double var = fmax(s1 / M - mean * mean, 0.0);
+    __shared__ double sh[2][256];
+    const int i = blockIdx.x, n = i / a.G, g = i % a.G, Cg = a.C / a.G;
+    double v[2] = {0.0, 0.0};
+    // the group's channels are contiguous: [n][g Cg .. (g+1) Cg)[chunks][2]
+    const float2* o = (const float2*)a.csum + ((size_t)n * a.C + g * Cg) * a.chunks;
+    for (int e = threadIdx.x; e < Cg * a.chunks; e += 256) {
+        const float2 q = o[e];
+        v[0] += q.x;
+        v[1] += q.y;
+    }
+    block_sum<2>(sh, v);
+    if (threadIdx.x == 0) {
+        const double M = (double)Cg * a.P;
+        const double mean = v[0] / M;
+        const double var = fmax(v[1] / M - mean * mean, 0.0);
         a.stats[2 * i] = (float)mean;
         a.stats[2 * i + 1] = (float)(1.0 / sqrt(var + (double)a.eps));
     }
@@ -119,6 +136,91 @@ __global__ __launch_bounds__(256) void gn_apply_kernel(GNArgs a)
             if (a.zs_f32) a.zs_f32[i] = zs;
             if (a.zs_bf16) a.zs_bf16[i] = f2bf(zs);
         }
+    }
+}
+
+// Eight channels per thread (C % 8 == 0): 16-byte FP32 loads and BF16
+// stores; with pool_bf16 each thread takes the 2x2 window of one pooled pixel
+// and also writes the window's maximum of BF16(z).
+__device__ __forceinline__ void gn8(const GNArgs& a, int n, int c0, const float* y, float* z)
+{
+    const float4 v0 = *(const float4*)y, v1 = *(const float4*)(y + 4);
+    const float yv[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+    const int Cg = a.C / a.G;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int c = c0 + u;
+        const float* st = a.stats + 2 * (n * a.G + c / Cg);
+        const float av = fmaf(a.gamma[c], (yv[u] - st[0]) * st[1], a.beta[c]);
+        z[u] = a.gelu ? gelu(av) : av;
+    }
+}
+
+__device__ __forceinline__ uint4 pack8(const float* v)
+{
+    uint32_t w[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) w[u] = (uint32_t)f2bf(v[2 * u]) | ((uint32_t)f2bf(v[2 * u + 1]) << 16);
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+__device__ __forceinline__ void store8(const GNArgs& a, size_t i, int n, int c0, const float* z)
+{
+    if (a.z_f32) {
+        *(float4*)(a.z_f32 + i) = make_float4(z[0], z[1], z[2], z[3]);
+        *(float4*)(a.z_f32 + i + 4) = make_float4(z[4], z[5], z[6], z[7]);
+    }
+    if (a.z_bf16) *(uint4*)(a.z_bf16 + i) = pack8(z);
+    if (a.scale) {
+        float zs[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) zs[u] = z[u] * a.scale[n * a.C + c0 + u];
+        if (a.zs_f32) {
+            *(float4*)(a.zs_f32 + i) = make_float4(zs[0], zs[1], zs[2], zs[3]);
+            *(float4*)(a.zs_f32 + i + 4) = make_float4(zs[4], zs[5], zs[6], zs[7]);
+        }
+        if (a.zs_bf16) *(uint4*)(a.zs_bf16 + i) = pack8(zs);
+    }
+}
+
+__global__ __launch_bounds__(256) void gn_apply8_kernel(GNArgs a)
+{
+    const int C8 = a.C / 8;
+    if (!a.pool_bf16) {
+        const size_t total = (size_t)a.N * a.P * C8;
+        for (size_t it = (size_t)blockIdx.x * 256 + threadIdx.x; it < total; it += (size_t)gridDim.x * 256) {
+            const int c0 = (int)(it % C8) * 8;
+            const size_t px = it / C8;
+            const int n = (int)(px / a.P);
+            const size_t i = px * a.C + c0;
+            float z[8];
+            gn8(a, n, c0, a.y + i, z);
+            store8(a, i, n, c0, z);
+        }
+        return;
+    }
+    const int Ho = a.H / 2, Wo = a.W / 2;
+    const size_t total = (size_t)a.N * Ho * Wo * C8;
+    for (size_t it = (size_t)blockIdx.x * 256 + threadIdx.x; it < total; it += (size_t)gridDim.x * 256) {
+        const int c0 = (int)(it % C8) * 8;
+        size_t q = it / C8;
+        const int xo = (int)(q % Wo);
+        q /= Wo;
+        const int yo = (int)(q % Ho), n = (int)(q / Ho);
+        float m[8];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const size_t i = (((size_t)n * a.H + 2 * yo + (w >> 1)) * a.W + 2 * xo + (w & 1)) * a.C + c0;
+            float z[8];
+            gn8(a, n, c0, a.y + i, z);
+            store8(a, i, n, c0, z);
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const float r = bf2f(f2bf(z[u]));
+                m[u] = w ? fmaxf(m[u], r) : r;
+            }
+        }
+        *(uint4*)(a.pool_bf16 + (((size_t)n * Ho + yo) * Wo + xo) * a.C + c0) = pack8(m);
     }
 }
 
@@ -175,23 +277,28 @@ __global__ __launch_bounds__(256) void gn_bwd_reduce_kernel(GNArgs a, int CH)
     }
 }
 
-// cacc[n][c][3] = chunk sums; then dgamma, dbeta, dscale and the group sums
-// S1 = sum gamma g, S2 = sum gamma g xhat (stored after cacc); one block
+// cacc[n][c][3]: the chunk sums of one (sample, channel) per block
+__global__ __launch_bounds__(256) void gn_bwd_chan_kernel(GNArgs a)
+{
+    __shared__ double sh[3][256];
+    const int i = blockIdx.x, n = i / a.C, c = i % a.C;
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int k = threadIdx.x; k < a.chunks; k += 256) {
+        const float* o = a.csum + (((size_t)n * a.chunks + k) * a.C + c) * 3;
+        v[0] += o[0];
+        v[1] += o[1];
+        v[2] += o[2];
+    }
+    block_sum<3>(sh, v);
+    if (threadIdx.x == 0)
+        for (int q = 0; q < 3; ++q) a.cacc[3 * i + q] = v[q];
+}
+
+// dgamma, dbeta, dscale and the group sums S1 = sum gamma g,
+// S2 = sum gamma g xhat (stored after cacc); one block
 __global__ __launch_bounds__(256) void gn_bwd_finish(GNArgs a)
 {
     const int NC = a.N * a.C;
-    for (int i = threadIdx.x; i < NC; i += blockDim.x) {
-        const int n = i / a.C, c = i % a.C;
-        double t[3] = {0.0, 0.0, 0.0};
-        for (int k = 0; k < a.chunks; ++k) {
-            const float* o = a.csum + (((size_t)n * a.chunks + k) * a.C + c) * 3;
-            t[0] += o[0];
-            t[1] += o[1];
-            t[2] += o[2];
-        }
-        for (int q = 0; q < 3; ++q) a.cacc[3 * i + q] = t[q];
-    }
-    __syncthreads();
     double* grp = a.cacc + 3 * (size_t)NC;
     const int Cg = a.C / a.G;
     for (int i = threadIdx.x; i < a.N * a.G; i += blockDim.x) {
@@ -310,94 +417,154 @@ __global__ __launch_bounds__(256) void residual_kernel(const float* head, const 
 }
 
 // -------------------------------------------------------------------- MLP
-// f = W2 sin(W1 sin(W0 t + b0) + b1) + b2; s_l = Wl f.  One block per sample.
-__global__ __launch_bounds__(256) void mlp_fwd_kernel(MLPArgs a)
+constexpr int kMlpThreads = 1024;
+
+// y[j] = b[j] + sum_k W[j][k] x[k] for j < R, by groups of G lanes per row
+// (lane-strided partial sums, then a fixed butterfly inside the group).
+template <int G>
+__device__ __forceinline__ float row_dot(const float* W, const float* x, int len, int j, int k)
 {
-    __shared__ float a0[256], a1[256], fv[256];
-    const int n = blockIdx.x, tid = threadIdx.x;
-    const float t = a.jump[n];
-    for (int j = tid; j < a.Hd; j += blockDim.x) {
-        const float h = fmaf(a.W0[j], t, a.b0[j]);
-        a.h0[n * a.Hd + j] = h;
-        a0[j] = sinf(h);
-    }
-    __syncthreads();
-    for (int j = tid; j < a.Hd; j += blockDim.x) {
-        float h = a.b1[j];
-        for (int k = 0; k < a.Hd; ++k) h = fmaf(a.W1[j * a.Hd + k], a0[k], h);
-        a.h1[n * a.Hd + j] = h;
-        a1[j] = sinf(h);
-    }
-    __syncthreads();
-    for (int i = tid; i < a.F; i += blockDim.x) {
-        float v = a.b2[i];
-        for (int k = 0; k < a.Hd; ++k) v = fmaf(a.W2[i * a.Hd + k], a1[k], v);
-        a.f[n * a.F + i] = v;
-        fv[i] = v;
-    }
-    __syncthreads();
-    for (int l = 0; l < a.L; ++l)
-        for (int c = tid; c < a.C[l]; c += blockDim.x) {
-            float v = 0.f;
-            for (int i = 0; i < a.F; ++i) v = fmaf(a.Wl[l][c * a.F + i], fv[i], v);
-            a.sc[l][n * a.C[l] + c] = v;
-        }
+    float s = 0.f;
+    for (int i = k; i < len; i += G) s = fmaf(W[(size_t)j * len + i], x[i], s);
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    return s;
 }
 
-// Gradients of every MLP and projection parameter, summed over the samples
-// in order; one block.
-__global__ __launch_bounds__(256) void mlp_bwd_kernel(MLPArgs a)
+// f = W2 sin(W1 sin(W0 t + b0) + b1) + b2; one block per sample, 4 lanes
+// per output row (rows <= 256).
+__global__ __launch_bounds__(kMlpThreads) void mlp_fwd_kernel(MLPArgs a)
 {
-    __shared__ float df[256], dh1[256], dh0[256];
-    const int tid = threadIdx.x;
-    for (int n = 0; n < a.N; ++n) {
-        const float t = a.jump[n];
-        const float* f = a.f + n * a.F;
-        const float* h0 = a.h0 + n * a.Hd;
-        const float* h1 = a.h1 + n * a.Hd;
-        for (int i = tid; i < a.F; i += blockDim.x) {
-            float v = 0.f;
-            for (int l = 0; l < a.L; ++l)
-                for (int c = 0; c < a.C[l]; ++c) v = fmaf(a.Wl[l][c * a.F + i], a.dsc[l][n * a.C[l] + c], v);
-            df[i] = v;
-        }
-        for (int l = 0; l < a.L; ++l)
-            for (int e = tid; e < a.C[l] * a.F; e += blockDim.x) {
-                const int c = e / a.F, i = e % a.F;
-                const float v = a.dsc[l][n * a.C[l] + c] * f[i];
-                a.gWl[l][e] = n ? a.gWl[l][e] + v : v;
-            }
-        __syncthreads();
-        for (int e = tid; e < a.F * a.Hd; e += blockDim.x) {
-            const int i = e / a.Hd, k = e % a.Hd;
-            const float v = df[i] * sinf(h1[k]);
-            a.gW2[e] = n ? a.gW2[e] + v : v;
-        }
-        for (int i = tid; i < a.F; i += blockDim.x) a.gb2[i] = n ? a.gb2[i] + df[i] : df[i];
-        for (int k = tid; k < a.Hd; k += blockDim.x) {
-            float v = 0.f;
-            for (int i = 0; i < a.F; ++i) v = fmaf(a.W2[i * a.Hd + k], df[i], v);
-            dh1[k] = v * cosf(h1[k]);
-        }
-        __syncthreads();
-        for (int e = tid; e < a.Hd * a.Hd; e += blockDim.x) {
-            const int j = e / a.Hd, k = e % a.Hd;
-            const float v = dh1[j] * sinf(h0[k]);
-            a.gW1[e] = n ? a.gW1[e] + v : v;
-        }
-        for (int j = tid; j < a.Hd; j += blockDim.x) a.gb1[j] = n ? a.gb1[j] + dh1[j] : dh1[j];
-        for (int k = tid; k < a.Hd; k += blockDim.x) {
-            float v = 0.f;
-            for (int j = 0; j < a.Hd; ++j) v = fmaf(a.W1[j * a.Hd + k], dh1[j], v);
-            dh0[k] = v * cosf(h0[k]);
-        }
-        __syncthreads();
-        for (int j = tid; j < a.Hd; j += blockDim.x) {
-            a.gW0[j] = n ? a.gW0[j] + dh0[j] * t : dh0[j] * t;
-            a.gb0[j] = n ? a.gb0[j] + dh0[j] : dh0[j];
-        }
-        __syncthreads();
+    __shared__ float a0[256], a1[256];
+    const int n = blockIdx.x, tid = threadIdx.x, j = tid >> 2, k = tid & 3;
+    const float t = a.jump[n];
+    for (int q = tid; q < a.Hd; q += blockDim.x) {
+        const float h = fmaf(a.W0[q], t, a.b0[q]);
+        a.h0[n * a.Hd + q] = h;
+        a0[q] = sinf(h);
     }
+    __syncthreads();
+    {
+        const float h = row_dot<4>(a.W1, a0, a.Hd, j < a.Hd ? j : 0, k) + (j < a.Hd ? a.b1[j] : 0.f);
+        if (j < a.Hd && k == 0) {
+            a.h1[n * a.Hd + j] = h;
+            a1[j] = sinf(h);
+        }
+    }
+    __syncthreads();
+    {
+        const float v = row_dot<4>(a.W2, a1, a.Hd, j < a.F ? j : 0, k) + (j < a.F ? a.b2[j] : 0.f);
+        if (j < a.F && k == 0) a.f[n * a.F + j] = v;
+    }
+}
+
+// s_l[n][c] = sum_i Wl[c][i] f[n][i] for every level; rows of all levels
+// numbered consecutively, 8 lanes per row; grid (rows / 32, N).
+__global__ __launch_bounds__(256) void film_kernel(MLPArgs a)
+{
+    const int n = blockIdx.y, row = blockIdx.x * 32 + (threadIdx.x >> 3), k = threadIdx.x & 7;
+    int l = 0, c = row;
+    while (l < a.L && c >= a.C[l]) c -= a.C[l++];
+    const bool ok = l < a.L;
+    const float v = row_dot<8>(ok ? a.Wl[l] : a.Wl[0], a.f + (size_t)n * a.F, a.F, ok ? c : 0, k);
+    if (ok && k == 0) a.sc[l][n * a.C[l] + c] = v;
+}
+
+// Backward, per sample: df = sum_l Wl^T ds_l, dh1 = cos(h1) W2^T df,
+// dh0 = cos(h0) W1^T dh1 (saved for the parameter pass).
+__global__ __launch_bounds__(256) void mlp_bwd_sample_kernel(MLPArgs a)
+{
+    __shared__ float df[256], dh1[256];
+    const int n = blockIdx.x, tid = threadIdx.x;
+    for (int i = tid; i < a.F; i += blockDim.x) {
+        float v = 0.f;
+        for (int l = 0; l < a.L; ++l)
+            for (int c = 0; c < a.C[l]; ++c) v = fmaf(a.Wl[l][(size_t)c * a.F + i], a.dsc[l][n * a.C[l] + c], v);
+        df[i] = v;
+        a.df[n * a.F + i] = v;
+    }
+    __syncthreads();
+    for (int k = tid; k < a.Hd; k += blockDim.x) {
+        float v = 0.f;
+        for (int i = 0; i < a.F; ++i) v = fmaf(a.W2[(size_t)i * a.Hd + k], df[i], v);
+        v *= cosf(a.h1[n * a.Hd + k]);
+        dh1[k] = v;
+        a.dh1[n * a.Hd + k] = v;
+    }
+    __syncthreads();
+    for (int k = tid; k < a.Hd; k += blockDim.x) {
+        float v = 0.f;
+        for (int j = 0; j < a.Hd; ++j) v = fmaf(a.W1[(size_t)j * a.Hd + k], dh1[j], v);
+        a.dh0[n * a.Hd + k] = v * cosf(a.h0[n * a.Hd + k]);
+    }
+}
+
+// Every parameter gradient, one element per thread, summed over the
+// samples in order.
+__global__ __launch_bounds__(256) void mlp_bwd_param_kernel(MLPArgs a)
+{
+    const int Hd = a.Hd, F = a.F;
+    size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    // W0, b0
+    if (e < (size_t)Hd) {
+        float gw = 0.f, gb = 0.f;
+        for (int n = 0; n < a.N; ++n) {
+            gw = fmaf(a.dh0[n * Hd + e], a.jump[n], gw);
+            gb += a.dh0[n * Hd + e];
+        }
+        a.gW0[e] = gw;
+        a.gb0[e] = gb;
+        return;
+    }
+    e -= Hd;
+    if (e < (size_t)Hd * Hd) {  // W1[j][k]
+        const int j = (int)(e / Hd), k = (int)(e % Hd);
+        float g = 0.f;
+        for (int n = 0; n < a.N; ++n) g = fmaf(a.dh1[n * Hd + j], sinf(a.h0[n * Hd + k]), g);
+        a.gW1[e] = g;
+        return;
+    }
+    e -= (size_t)Hd * Hd;
+    if (e < (size_t)Hd) {
+        float g = 0.f;
+        for (int n = 0; n < a.N; ++n) g += a.dh1[n * Hd + e];
+        a.gb1[e] = g;
+        return;
+    }
+    e -= Hd;
+    if (e < (size_t)F * Hd) {  // W2[i][k]
+        const int i = (int)(e / Hd), k = (int)(e % Hd);
+        float g = 0.f;
+        for (int n = 0; n < a.N; ++n) g = fmaf(a.df[n * F + i], sinf(a.h1[n * Hd + k]), g);
+        a.gW2[e] = g;
+        return;
+    }
+    e -= (size_t)F * Hd;
+    if (e < (size_t)F) {
+        float g = 0.f;
+        for (int n = 0; n < a.N; ++n) g += a.df[n * F + e];
+        a.gb2[e] = g;
+        return;
+    }
+    e -= F;
+    for (int l = 0; l < a.L; ++l) {
+        const size_t cnt = (size_t)a.C[l] * F;
+        if (e < cnt) {  // Wl[c][i]
+            const int c = (int)(e / F), i = (int)(e % F);
+            float g = 0.f;
+            for (int n = 0; n < a.N; ++n) g = fmaf(a.dsc[l][n * a.C[l] + c], a.f[n * F + i], g);
+            a.gWl[l][e] = g;
+            return;
+        }
+        e -= cnt;
+    }
+}
+
+size_t mlp_param_count(const MLPArgs& a)
+{
+    size_t n = (size_t)3 * a.Hd + (size_t)a.Hd * a.Hd + (size_t)a.F * a.Hd + a.F;
+    for (int l = 0; l < a.L; ++l) n += (size_t)a.C[l] * a.F;
+    return n;
 }
 
 // ------------------------------------------------------------------- loss
@@ -490,11 +657,19 @@ hipError_t gn_forward(const GNArgs& a_in, hipStream_t s)
 {
     if (a_in.N <= 0 || a_in.P <= 0) return hipSuccess;
     GNArgs a = a_in;
-    a.chunks = gn_chunks(a.P);
-    const int CH = chunk_px(a.P);
-    hipLaunchKernelGGL(gn_stats_kernel, dim3(a.chunks, a.N), dim3(256), 0, s, a, CH);
-    hipLaunchKernelGGL(gn_stats_finish, dim3(1), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(gn_apply_kernel, dim3(grid_for((size_t)a.N * a.P * a.C)), dim3(256), 0, s, a);
+    const bool vec = a.C % 8 == 0 && ((uintptr_t)a.y & 15) == 0;
+    if (a.pool_bf16 && (!vec || a.H % 2 || a.W % 2 || (long)a.H * a.W != a.P)) return hipErrorInvalidValue;
+    if (!a.sums_ready) {
+        a.chunks = gn_chunks(a.P);
+        hipLaunchKernelGGL(gn_stats_kernel, dim3(a.chunks, a.N), dim3(256), 0, s, a, chunk_px(a.P));
+    }
+    hipLaunchKernelGGL(gn_stats_finish, dim3(a.N * a.G), dim3(256), 0, s, a);
+    if (vec) {
+        const size_t items = (size_t)a.N * a.P * (a.C / 8) / (a.pool_bf16 ? 4 : 1);
+        hipLaunchKernelGGL(gn_apply8_kernel, dim3(grid_for(items)), dim3(256), 0, s, a);
+    } else {
+        hipLaunchKernelGGL(gn_apply_kernel, dim3(grid_for((size_t)a.N * a.P * a.C)), dim3(256), 0, s, a);
+    }
     return hipGetLastError();
 }
 
@@ -505,6 +680,7 @@ hipError_t gn_backward(const GNArgs& a_in, hipStream_t s)
     a.chunks = gn_chunks(a.P);
     const int CH = chunk_px(a.P);
     hipLaunchKernelGGL(gn_bwd_reduce_kernel, dim3(a.chunks, a.N), dim3(256), 0, s, a, CH);
+    hipLaunchKernelGGL(gn_bwd_chan_kernel, dim3(a.N * a.C), dim3(256), 0, s, a);
     hipLaunchKernelGGL(gn_bwd_finish, dim3(1), dim3(256), 0, s, a);
     hipLaunchKernelGGL(gn_bwd_apply_kernel, dim3(grid_for((size_t)a.N * a.P * a.C)), dim3(256), 0, s, a);
     return hipGetLastError();
@@ -547,13 +723,19 @@ hipError_t residual_out(const float* head, const float* c, const float* phi, con
 hipError_t mlp_forward(const MLPArgs& a, hipStream_t s)
 {
     if (a.N <= 0) return hipSuccess;
-    hipLaunchKernelGGL(mlp_fwd_kernel, dim3(a.N), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(mlp_fwd_kernel, dim3(a.N), dim3(kMlpThreads), 0, s, a);
+    int rows = 0;
+    for (int l = 0; l < a.L; ++l) rows += a.C[l];
+    hipLaunchKernelGGL(film_kernel, dim3((rows + 31) / 32, a.N), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t mlp_backward(const MLPArgs& a, hipStream_t s)
 {
-    hipLaunchKernelGGL(mlp_bwd_kernel, dim3(1), dim3(256), 0, s, a);
+    if (a.N <= 0) return hipSuccess;
+    hipLaunchKernelGGL(mlp_bwd_sample_kernel, dim3(a.N), dim3(256), 0, s, a);
+    const size_t n = mlp_param_count(a);
+    hipLaunchKernelGGL(mlp_bwd_param_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

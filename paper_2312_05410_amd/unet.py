@@ -20,7 +20,7 @@ _I = ctypes.c_int
 
 UNET_EXPORTS = (
     "unet_param_count", "unet_param_entry", "unet_workspace_bytes", "unet_create", "unet_prepare",
-    "unet_forward", "unet_backward", "unet_adam", "unet_destroy", "unet_op_workspace_bytes",
+    "unet_forward", "unet_forward_infer", "unet_backward", "unet_adam", "unet_destroy", "unet_op_workspace_bytes",
     "unet_conv3x3_fwd", "unet_conv3x3_dgrad", "unet_conv3x3_wgrad", "unet_up_fwd", "unet_up_dgrad",
     "unet_up_wgrad", "unet_groupnorm_fwd", "unet_groupnorm_bwd", "unet_maxpool_fwd", "unet_maxpool_bwd",
 )
@@ -81,6 +81,7 @@ def lib():
         L.unet_create.argtypes = [ctypes.POINTER(_H), C, _H, _H, _H, sz, _H]
         L.unet_prepare.argtypes = [_H]
         L.unet_forward.argtypes = [_H, _I] + [_H] * 7
+        L.unet_forward_infer.argtypes = [_H, _I] + [_H] * 7
         L.unet_backward.argtypes = [_H] * 7 + [ctypes.POINTER(ctypes.c_double)]
         L.unet_adam.argtypes = [_H, _H, _H, i64, f32, f32, f32, f32]
         L.unet_destroy.argtypes = [_H]
@@ -186,8 +187,9 @@ class UNet:
         return self._split(self.grads)
 
     # -- passes
-    def forward(self, c, phi, rho, jump, out=None):
-        """Prediction for states [n][H][W] (float32, device) and jumps [n]."""
+    def forward(self, c, phi, rho, jump, out=None, train: bool = True):
+        """Prediction for states [n][H][W] (float32, device) and jumps [n];
+        train=False skips what the backward pass needs."""
         import torch
 
         n = c.shape[0]
@@ -195,8 +197,9 @@ class UNet:
             out = tuple(torch.empty_like(c) for _ in range(3))
         jump = torch.as_tensor(jump, dtype=torch.float32, device=c.device).reshape(n).contiguous()
         self._jump = jump  # the library copies it, but keep the tensor alive until enqueued
-        _check(lib().unet_forward(self._h, n, jump.data_ptr(), c.data_ptr(), phi.data_ptr(), rho.data_ptr(),
-                                  *(o.data_ptr() for o in out)), "unet_forward")
+        fn = lib().unet_forward if train else lib().unet_forward_infer
+        _check(fn(self._h, n, jump.data_ptr(), c.data_ptr(), phi.data_ptr(), rho.data_ptr(),
+                  *(o.data_ptr() for o in out)), "unet_forward")
         return out
 
     def backward(self, pred, target, want_loss: bool = True) -> Optional[float]:

@@ -159,7 +159,8 @@ def test_unet_param_layout_and_validation():
     assert offs == sorted(offs) and offs[0] == 0
     L = unet.lib()
     for bad in (dict(in_ch=3), dict(out_ch=4), dict(levels=1), dict(height=100), dict(base=6), dict(groups=5),
-                dict(mlp_hidden=300), dict(head_groups=2), dict(gn_eps=0.0), dict(max_batch=0), dict(base=128)):
+                dict(mlp_hidden=300), dict(head_groups=2), dict(gn_eps=0.0), dict(max_batch=0), dict(base=128),
+                dict(base=4), dict(base=12)):
         c = unet.UNetConfig(**{**cfg.__dict__, **bad})
         assert L.unet_param_count(ctypes.byref(c.c())) == -1, bad
         assert L.unet_workspace_bytes(ctypes.byref(c.c())) == 0, bad

@@ -66,8 +66,13 @@ def check_bound(gpu, ref, bound, k, what):
 
 
 # ------------------------------------------------------------------ conv3x3
+# shapes reach both kernels (channel counts off and on multiples of 32) and
+# every block tile (pixels x channels) of the wide one: 64x64, 128x32,
+# 256x16, 256x32, 256x64 (second to last) and 128x128 (last), with ragged
+# pixel and channel tails
 @pytest.mark.parametrize("n,H,W,C1,C2,Cout", [(2, 10, 13, 8, 12, 40), (1, 9, 7, 4, 0, 32), (2, 6, 11, 32, 32, 3),
-                                              (1, 16, 16, 64, 0, 70)])
+                                              (1, 16, 16, 64, 0, 70), (1, 40, 36, 32, 32, 32),
+                                              (2, 250, 262, 32, 0, 64), (1, 130, 254, 32, 0, 256)])
 def test_conv3x3_fwd_dgrad_wgrad(n, H, W, C1, C2, Cout):
     import torch
 
@@ -259,8 +264,11 @@ def test_network_forward_matches_oracle(H, W, levels, base, groups, n):
     st = _state(31, n, H, W)
     jump = np.array([1.0, 2.0, 0.5][:n], dtype=np.float32)
     out = net.forward(*(dev_f32(a) for a in st), dev_f32(jump))
+    inf = net.forward(*(dev_f32(a) for a in st), dev_f32(jump), train=False)
     torch.cuda.synchronize()
     check_forward(cfg, params, st, jump, out)
+    for a, b in zip(out, inf):  # the inference entry point runs the same arithmetic
+        assert torch.equal(a, b)
     net.close()
 
 
