@@ -370,13 +370,15 @@ int pf_init(pf_handle** out, const pf_params* p, void* c, void* phi, void* rho, 
     h->stream = (hipStream_t)stream;
     h->dt = dt;
     // Launch shape.  Fused steps per launch K: as requested, else (measured
-    // on MI355X) two steps through the LDS-tiled kernel for FP32 grids of up
-    // to ~3M cells per launch, where one step does not fill the GPU, and the
-    // single-step strip-march kernel otherwise and for FP64.  The mirror
-    // ghosts of a launch must be real rows, so 2K <= ny.
+    // on MI355X) two steps through the LDS-tiled kernel for FP32 grids of
+    // ~0.75M to ~3M cells per launch, where one step does not fill the GPU,
+    // and the single-step strip-march kernel otherwise (below ~0.75M cells
+    // the tiled kernel has too few tiles and its longer launches cost more)
+    // and for FP64.  The mirror ghosts of a launch must be real rows, so
+    // 2K <= ny.
     const long cells = (long)p->nx * p->ny * p->batch;
     int K = p->temporal_block;
-    if (K == 0) K = (p->precision == PF_F32 && cells < 3000000L) ? 2 : 1;
+    if (K == 0) K = (p->precision == PF_F32 && cells >= 786432L && cells < 3000000L) ? 2 : 1;
     while (K > 1 && 2 * K > p->ny) --K;
     h->K = K;
     if (p->tile_rows > 0) {
