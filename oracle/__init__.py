@@ -20,12 +20,13 @@ _SRC = os.path.join(_HERE, "pf_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 _BC = {"pvd": 0, "periodic": 1}
+_INTEGRATOR = {"euler": 0, "midpoint": 1}
 
 
 class _OrParams(ctypes.Structure):
     _fields_ = [
         ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("batch", ctypes.c_int32),
-        ("bc_mode", ctypes.c_int32), ("flux_on", ctypes.c_int32), ("pad0", ctypes.c_int32),
+        ("bc_mode", ctypes.c_int32), ("flux_on", ctypes.c_int32), ("integrator", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
         ("h", ctypes.c_double), ("dt", ctypes.c_double),
         ("W_c", ctypes.c_double), ("W_phi", ctypes.c_double),
@@ -37,6 +38,7 @@ class _OrParams(ctypes.Structure):
         ("D_rho", ctypes.c_double), ("v0", ctypes.c_double),
         ("theta_deg", ctypes.c_double), ("rho_in", ctypes.c_double),
         ("c0", ctypes.c_double), ("c_noise", ctypes.c_double), ("film_h", ctypes.c_double),
+        ("interface_noise", ctypes.c_double),
     ]
 
 
@@ -67,7 +69,10 @@ def lib():
         L.or_splitmix64.restype = ctypes.c_uint64
         L.or_init.argtypes = [P, ctypes.c_void_p, dp, dp, dp]
         L.or_potentials.argtypes = [P, dp, dp, dp, dp, dp]
-        L.or_step_n.argtypes = [P, ctypes.c_void_p, ctypes.c_int64, dp, dp, dp, dp]
+        L.or_step_n.argtypes = [P, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64,
+                                dp, dp, dp, dp]
+        L.or_trunc_gauss.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double, ctypes.c_double]
+        L.or_trunc_gauss.restype = ctypes.c_double
         L.or_mass.argtypes = [P, dp, dp, dp, dp, dp]
         L.or_energy.argtypes = [P, dp, dp, dp]
         L.or_adjoint_step.argtypes = [P, ctypes.c_double, dp, dp, dp, dp, dp, dp, dp]
@@ -96,13 +101,14 @@ def to_c(p, dt: float | None = None) -> _OrParams:
     """Convert a parameter object (attributes as in PFParams) to the C struct."""
     return _OrParams(
         nx=p.nx, ny=p.ny, batch=p.batch, bc_mode=_BC[p.bc_mode], flux_on=int(bool(p.flux_on)),
-        pad0=0, seed=p.seed & 0xFFFFFFFFFFFFFFFF,
+        integrator=_INTEGRATOR[getattr(p, "integrator", "euler")], seed=p.seed & 0xFFFFFFFFFFFFFFFF,
         h=p.h, dt=p.dt if dt is None else dt,
         W_c=p.W_c, W_phi=p.W_phi, kappa_c=p.kappa_c, kappa_phi=p.kappa_phi,
         MA_bulk=p.MA_bulk, MB_bulk=p.MB_bulk, MA_surf=p.MA_surf, MB_surf=p.MB_surf,
         sigma_surf=p.sigma_surf, M_phi=p.M_phi, M_scale=p.M_scale,
         D_rho=p.D_rho, v0=p.v0, theta_deg=p.theta_deg, rho_in=p.rho_in,
-        c0=p.c0, c_noise=p.c_noise, film_h=p.film_h)
+        c0=p.c0, c_noise=p.c_noise, film_h=p.film_h,
+        interface_noise=float(getattr(p, "interface_noise", 0.0)))
 
 
 def _vmax(p) -> float:
@@ -144,10 +150,16 @@ def potentials(p, c, phi):
     return mc, mp, M
 
 
-class State:
-    """Oracle state: c, phi, rho [batch, ny, nx] and cumulative inflow Q[batch]."""
+def trunc_gauss(seed: int, counter0: int, mean: float, sigma: float) -> float:
+    """The interface composition draw (see pf_oracle.c)."""
+    return float(lib().or_trunc_gauss(seed & 0xFFFFFFFFFFFFFFFF, counter0, mean, sigma))
 
-    def __init__(self, p, c, phi, rho, Q=None, dt: float | None = None):
+
+class State:
+    """Oracle state: c, phi, rho [batch, ny, nx], cumulative inflow Q[batch]
+    and the global step count (it keys the interface composition draws)."""
+
+    def __init__(self, p, c, phi, rho, Q=None, dt: float | None = None, nstep: int = 0):
         self.p = p
         self.dt = resolve_dt(p) if dt is None else dt
         shape = (p.batch, p.ny, p.nx)
@@ -156,6 +168,8 @@ class State:
         self.rho = np.array(rho, dtype=np.float64).reshape(shape)
         self.Q = np.zeros(p.batch) if Q is None else np.array(Q, dtype=np.float64)
         self._v0 = _opt(getattr(p, "v0_per", None))
+        self._c0 = _opt(getattr(p, "c0_per", None))
+        self.nstep = int(nstep)
 
     @classmethod
     def seeded(cls, p, dt: float | None = None):
@@ -163,8 +177,10 @@ class State:
 
     def step(self, n: int):
         cp = to_c(self.p, self.dt)
-        lib().or_step_n(ctypes.byref(cp), None if self._v0 is None else self._v0.ctypes.data, int(n),
+        lib().or_step_n(ctypes.byref(cp), None if self._v0 is None else self._v0.ctypes.data,
+                        None if self._c0 is None else self._c0.ctypes.data, self.nstep, int(n),
                         _ptr(self.c), _ptr(self.phi), _ptr(self.rho), _ptr(self.Q))
+        self.nstep += int(n)
         return self
 
     def mass(self) -> np.ndarray:

@@ -20,7 +20,14 @@
  *   - switching function h(c) = c^3 (6c^2 - 15c + 10) on c clamped to [0,1];
  *   - the surface mobility drops the self-referential trailing term;
  *   - M(phi) = M_phi constant; face mobilities are arithmetic means;
- *   - explicit Euler in time (every right-hand side uses the old state);
+ *   - time integration: explicit Euler (every right-hand side uses the old
+ *     state), or the explicit midpoint method the paper's solver uses
+ *     (u' = u + dt R(u + dt/2 R(u)));
+ *   - random interface composition (the paper's truncated-Gaussian
+ *     boundary condition at the interface), when interface_noise > 0:
+ *     after every step each cell on the vapour side (phi' < 0) takes a
+ *     fresh composition drawn from N(c0, interface_noise^2) truncated to
+ *     [0, 1] (Box-Muller on SplitMix64 uniforms, rejection);
  *   - boundaries: x periodic; at y = 0 and y = top, mirror ghosts for c,
  *     phi and the potentials (no diffusive flux); rho has no flux through
  *     the substrate and a fixed inlet density rho_in as its top ghost;
@@ -197,13 +204,14 @@ void or_potentials(const or_params* p, const double* c, const double* phi,
     }
 }
 
-/* One explicit Euler step of one realisation. */
-static void step_one(const or_params* p, double v0, double* c, double* phi,
-                     double* rho, double* Q, double* mu_c, double* mu_phi,
-                     double* Mc, double* cn, double* pn, double* rn)
+/* Right-hand side R(u) of one realisation: (Rc, Rp, Rr) per cell and the
+ * inflow rate through the top face (per unit time). */
+static void rhs(const or_params* p, double v0, const double* c, const double* phi,
+                const double* rho, double* mu_c, double* mu_phi, double* Mc,
+                double* Rc, double* Rp, double* Rr, double* inflow_rate)
 {
     int nx = p->nx, ny = p->ny;
-    double h = p->h, h2 = h * h, dt = p->dt;
+    double h = p->h, h2 = h * h;
     double vx, vy;
     velocity(p, v0, &vx, &vy);
     int pvd = p->bc_mode == OR_BC_PVD;
@@ -243,14 +251,15 @@ static void step_one(const or_params* p, double v0, double* c, double* phi,
             double Gs = (pvd && j == 0) ? 0.0 : vy * 0.5 * (rS + r0);
             double T = p->D_rho * lap_r - ((Fe - Fw) + (Gn - Gs)) / h;
 
-            cn[k] = c[k] + dt * div_c;
-            pn[k] = phi[k] + dt * (div_p + S);
-            rn[k] = r0 + dt * (T - S);
+            Rc[k] = div_c;
+            Rp[k] = div_p + S;
+            Rr[k] = T - S;
         }
     }
 
-    /* inflow through the top face during this step: advective plus
-     * diffusive flux of rho, per unit length, times the face length h */
+    /* inflow through the top face: advective plus diffusive flux of rho
+     * per unit length, summed over the top cells (times h: per unit time) */
+    *inflow_rate = 0.0;
     if (pvd) {
         int j = ny - 1;
         double acc = 0.0;
@@ -259,29 +268,83 @@ static void step_one(const or_params* p, double v0, double* c, double* phi,
             double Gn = vy * 0.5 * (r0 + p->rho_in);
             acc += -Gn + p->D_rho * (p->rho_in - r0) / h;
         }
-        *Q += dt * h * acc;
+        *inflow_rate = acc;
     }
-
-    size_t n = (size_t)nx * ny;
-    memcpy(c, cn, n * sizeof(double));
-    memcpy(phi, pn, n * sizeof(double));
-    memcpy(rho, rn, n * sizeof(double));
 }
 
-void or_step_n(const or_params* p, const double* v0_per, int64_t n,
-               double* c, double* phi, double* rho, double* Q)
+/* key of the interface-composition stream (first digits of e) */
+#define OR_NOISE_KEY 0x2B7E151628AED2A6ull
+
+/* Composition drawn from N(mean, sigma^2) truncated to [0, 1]: Box-Muller
+ * on pairs of SplitMix64 uniforms (53 bits; the first in (0, 1], the second
+ * in [0, 1)) of the stream `seed`, counters 2a and 2a + 1 of attempt a from
+ * `counter0`, the first draw inside [0, 1] taken; after 8 misses, mean. */
+double or_trunc_gauss(uint64_t seed, uint64_t counter0, double mean, double sigma)
+{
+    for (int a = 0; a < 8; ++a) {
+        uint64_t x1 = or_splitmix64(seed, counter0 + 2u * (uint64_t)a);
+        uint64_t x2 = or_splitmix64(seed, counter0 + 2u * (uint64_t)a + 1u);
+        double u1 = (double)((x1 >> 11) + 1u) * 0x1.0p-53;
+        double u2 = (double)(x2 >> 11) * 0x1.0p-53;
+        double z = sqrt(-2.0 * log(u1)) * cos(2.0 * 3.14159265358979323846 * u2);
+        double v = mean + sigma * z;
+        if (v >= 0.0 && v <= 1.0) return v;
+    }
+    return mean;
+}
+
+/* One step of one realisation (integrator as p->integrator), then the
+ * interface composition draw for global step index `step`. */
+static void step_one(const or_params* p, double v0, double c0, int b, int64_t step,
+                     double* c, double* phi, double* rho, double* Q, double* w)
+{
+    int nx = p->nx, ny = p->ny;
+    size_t n = (size_t)nx * ny;
+    double dt = p->dt;
+    double *mu_c = w, *mu_phi = w + n, *Mc = w + 2 * n;
+    double *Rc = w + 3 * n, *Rp = w + 4 * n, *Rr = w + 5 * n;
+    double *ch = w + 6 * n, *ph = w + 7 * n, *rh = w + 8 * n;
+    double rate;
+
+    rhs(p, v0, c, phi, rho, mu_c, mu_phi, Mc, Rc, Rp, Rr, &rate);
+    if (p->integrator == OR_MIDPOINT) {
+        /* half step to t + dt/2, then the full step with the rates there */
+        for (size_t k = 0; k < n; ++k) {
+            ch[k] = c[k] + 0.5 * dt * Rc[k];
+            ph[k] = phi[k] + 0.5 * dt * Rp[k];
+            rh[k] = rho[k] + 0.5 * dt * Rr[k];
+        }
+        rhs(p, v0, ch, ph, rh, mu_c, mu_phi, Mc, Rc, Rp, Rr, &rate);
+    }
+    for (size_t k = 0; k < n; ++k) {
+        c[k] = c[k] + dt * Rc[k];
+        phi[k] = phi[k] + dt * Rp[k];
+        rho[k] = rho[k] + dt * Rr[k];
+    }
+    *Q += dt * p->h * rate;
+
+    if (p->interface_noise > 0.0) {
+        uint64_t seed = (p->seed + (uint64_t)b) ^ OR_NOISE_KEY;
+        for (size_t k = 0; k < n; ++k)
+            if (phi[k] < 0.0)
+                c[k] = or_trunc_gauss(seed, ((uint64_t)step * n + k) * 16u, c0, p->interface_noise);
+    }
+}
+
+void or_step_n(const or_params* p, const double* v0_per, const double* c0_per, int64_t step0,
+               int64_t n, double* c, double* phi, double* rho, double* Q)
 {
     size_t cells = (size_t)p->nx * p->ny;
-    double* buf = (double*)malloc(6 * cells * sizeof(double));
+    double* buf = (double*)malloc(9 * cells * sizeof(double));
     if (!buf) abort();
     for (int b = 0; b < p->batch; ++b) {
         double v0 = v0_per ? v0_per[b] : p->v0;
+        double c0 = c0_per ? c0_per[b] : p->c0;
         double* cb = c + (size_t)b * cells;
         double* pb = phi + (size_t)b * cells;
         double* rb = rho + (size_t)b * cells;
         for (int64_t s = 0; s < n; ++s)
-            step_one(p, v0, cb, pb, rb, &Q[b], buf, buf + cells, buf + 2 * cells,
-                     buf + 3 * cells, buf + 4 * cells, buf + 5 * cells);
+            step_one(p, v0, c0, b, step0 + s, cb, pb, rb, &Q[b], buf);
     }
     free(buf);
 }
@@ -497,6 +560,11 @@ void or_loss_grad(const or_params* p, double v0, int64_t n, int64_t every,
                   const double* ct, const double* phit, const double* rhot, double* out)
 {
     size_t cells = (size_t)p->nx * p->ny;
+    if (p->integrator != OR_EULER || p->interface_noise > 0.0) {
+        /* the adjoint is that of the explicit Euler step without draws */
+        out[0] = out[1] = out[2] = NAN;
+        return;
+    }
     if (every < 1) every = 1;
     int64_t nseg = (n + every - 1) / every;
     if (nseg < 1) nseg = 1;
@@ -513,8 +581,7 @@ void or_loss_grad(const or_params* p, double v0, int64_t n, int64_t every,
     /* forward, keeping the state at the start of every segment */
     for (int64_t s = 0; s < n; ++s) {
         if (s % every == 0) memcpy(ck + (size_t)(s / every) * 3 * cells, u, 3 * cells * sizeof(double));
-        step_one(p, v0, u, u + cells, u + 2 * cells, &Q, w, w + cells, w + 2 * cells,
-                 w + 3 * cells, w + 4 * cells, w + 5 * cells);
+        step_one(p, v0, p->c0, 0, s, u, u + cells, u + 2 * cells, &Q, w);
     }
     double L = 0.0, h2 = p->h * p->h;
     const double* tgt[3] = {ct, phit, rhot};
@@ -532,8 +599,7 @@ void or_loss_grad(const or_params* p, double v0, int64_t n, int64_t every,
         for (int64_t t = 1; t < s1 - s0; ++t) {
             double* dst = seg + (size_t)t * 3 * cells;
             memcpy(dst, dst - 3 * cells, 3 * cells * sizeof(double));
-            step_one(p, v0, dst, dst + cells, dst + 2 * cells, &Q, w, w + cells, w + 2 * cells,
-                     w + 3 * cells, w + 4 * cells, w + 5 * cells);
+            step_one(p, v0, p->c0, 0, s0 + t - 1, dst, dst + cells, dst + 2 * cells, &Q, w);
         }
         for (int64_t t = s1 - s0 - 1; t >= 0; --t) {
             const double* st = seg + (size_t)t * 3 * cells;

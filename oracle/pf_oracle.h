@@ -23,12 +23,13 @@ extern "C" {
 #endif
 
 enum { OR_BC_PVD = 0, OR_BC_PERIODIC = 1 };
+enum { OR_EULER = 0, OR_MIDPOINT = 1 };
 
 typedef struct or_params {
     int32_t nx, ny, batch;
     int32_t bc_mode;   /* OR_BC_PVD or OR_BC_PERIODIC */
     int32_t flux_on;   /* 0: incident vapour velocity v = 0 */
-    int32_t pad0;
+    int32_t integrator; /* OR_EULER or OR_MIDPOINT */
     uint64_t seed;
     double h, dt;
     /* free energy: double wells and gradient energies */
@@ -39,6 +40,8 @@ typedef struct or_params {
     double D_rho, v0, theta_deg, rho_in;
     /* initial condition */
     double c0, c_noise, film_h;
+    /* standard deviation of the interface composition draw (0: off) */
+    double interface_noise;
 } or_params;
 
 /* Frozen-coefficient explicit-Euler stability bound; vmax is the largest
@@ -57,10 +60,15 @@ void or_init(const or_params* p, const double* c0_per,
 void or_potentials(const or_params* p, const double* c, const double* phi,
                    double* mu_c, double* mu_phi, double* Mc);
 
-/* n explicit Euler steps of every realisation, in place.  v0_per: [batch]
- * incident speeds, or NULL for p->v0.  Q: [batch] cumulative inflow. */
-void or_step_n(const or_params* p, const double* v0_per, int64_t n,
-               double* c, double* phi, double* rho, double* Q);
+/* n steps of every realisation, in place.  v0_per, c0_per: [batch]
+ * incident speeds and mean compositions, or NULL for p->v0, p->c0.  step0:
+ * global index of the first step (keys the interface composition draws).
+ * Q: [batch] cumulative inflow. */
+void or_step_n(const or_params* p, const double* v0_per, const double* c0_per, int64_t step0,
+               int64_t n, double* c, double* phi, double* rho, double* Q);
+
+/* The interface composition draw (see pf_oracle.c). */
+double or_trunc_gauss(uint64_t seed, uint64_t counter0, double mean, double sigma);
 
 /* out[b][4] = h^2 sum c, h^2 sum phi, h^2 sum rho, Q[b]. */
 void or_mass(const or_params* p, const double* c, const double* phi,
@@ -83,7 +91,7 @@ void or_adjoint_step(const or_params* p, double v0, const double* c, const doubl
  * realisation from (c, phi, rho), and its gradient with respect to M_scale
  * and v0 (fixed dt) by the adjoint with checkpoints every `every` steps and
  * recomputation.  out = {L, dL/dM_scale, dL/dv0}.  The inputs are not
- * modified. */
+ * modified.  Explicit Euler without interface draws only (else NaN). */
 void or_loss_grad(const or_params* p, double v0, int64_t n, int64_t every,
                   const double* c, const double* phi, const double* rho,
                   const double* ct, const double* phit, const double* rhot, double* out);

@@ -62,6 +62,10 @@ class PFParams:
     c0: float = 0.5
     c_noise: float = 0.01
     film_h: float = 0.0           # <= 0: ny * h / 8
+    # model variants: "euler" or "midpoint" time integration; standard
+    # deviation of the per-step interface composition draw (0: off)
+    integrator: str = "euler"
+    interface_noise: float = 0.0
     # optional per-realisation incident speed and mean composition
     v0_per: Optional[np.ndarray] = field(default=None, repr=False)
     c0_per: Optional[np.ndarray] = field(default=None, repr=False)
