@@ -25,6 +25,7 @@ import time
 
 import numpy as np
 
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -40,7 +41,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="dns_1024_f32",
                     choices=["dns_1024_f32", "dns_8192_f32", "batched_32x512_f32", "dns_small_128_f64",
-                             "adjoint_256_f32"])
+                             "adjoint_256_f32", "unet_512_bf16", "blended_512_f32"])
     ap.add_argument("--temporal-block", type=int, default=None)
     ap.add_argument("--graph-mode", type=int, default=0, help="0: replay HIP graphs of launches; 1: plain launches")
     ap.add_argument("--no-sweep", action="store_true")
@@ -227,6 +228,153 @@ def adjoint_leg(args):
             "glups_equiv": round(cells * n / el / 1e9, 3)}
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def unet_forward_flops(cfg) -> float:
+    """Multiply-adds x 2 of one forward pass of one sample (convolutions and
+    up-samplings; the normalisations and the MLP are negligible)."""
+    H, W, L, w = cfg.height, cfg.width, cfg.levels, [cfg.base << l for l in range(cfg.levels)]
+    P = lambda l: (H >> l) * (W >> l)
+    f = 0.0
+    for l in range(L):
+        f += 2 * 9 * P(l) * w[l] * (w[l - 1] if l else cfg.in_ch)      # encoder blocks
+    f += 2 * 9 * P(L - 1) * w[L - 1] * w[L - 1]                        # bottom block
+    for l in range(L - 2, -1, -1):
+        f += 2 * P(l + 1) * w[l + 1] * 4 * w[l]                         # up-sampling
+        f += 2 * 9 * P(l) * w[l] * 2 * w[l]                             # decoder blocks
+    f += 2 * 9 * P(0) * cfg.out_ch * w[0]                              # head
+    return f
+
+
+def unet_leg(args):
+    """Training steps (forward, backward, Adam) at the paper's batch of 5 and
+    inference at batch 1 on 512^2; the roofline is that of the largest
+    convolution (the top decoder block, 64 -> 32 channels at 512^2) timed
+    alone with HIP events on its stream."""
+    import torch
+
+    from paper_2312_05410_amd import unet as U
+
+    cfg = U.UNetConfig(max_batch=5)
+    net = U.UNet(cfg, seed=0)
+    n = 5
+    st = [torch.rand(n, cfg.height, cfg.width, device="cuda") for _ in range(3)]
+    tg = [u + 1e-3 for u in st]
+    jump = torch.ones(n, device="cuda")
+    steps = args.steps if args.steps is not None else 100
+    warmup = args.warmup if args.warmup is not None else 10
+    out = net.forward(*st, jump)
+    for _ in range(warmup):
+        net.forward(*st, jump, out=out)
+        net.backward(out, tg, want_loss=False)
+        net.adam_step()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        net.forward(*st, jump, out=out)
+        net.backward(out, tg, want_loss=False)
+        net.adam_step()
+    e1.record()
+    torch.cuda.synchronize()
+    train_ms = e0.elapsed_time(e1) / steps
+    fwd = unet_forward_flops(cfg)
+    # inference, batch 1
+    one = [u[:1].contiguous() for u in st]
+    o1 = net.forward(*one, jump[:1], train=False)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        net.forward(*one, jump[:1], out=o1, train=False)
+    e1.record()
+    torch.cuda.synchronize()
+    infer_ms = e0.elapsed_time(e1) / steps
+    net.close()
+    # dominant convolution alone
+    x1 = torch.rand(n, cfg.height, cfg.width, 32, device="cuda").to(torch.bfloat16)
+    x2 = torch.rand(n, cfg.height, cfg.width, 32, device="cuda").to(torch.bfloat16)
+    w = torch.rand(9, 32, 64, device="cuda") - 0.5
+    U.conv3x3_fwd(x1, w, x2)
+    torch.cuda.synchronize()
+    reps = 50
+    e0.record()
+    for _ in range(reps):
+        U.conv3x3_fwd(x1, w, x2)
+    e1.record()
+    torch.cuda.synchronize()
+    conv_s = e0.elapsed_time(e1) / reps / 1e3
+    conv_flops = 2.0 * 9 * n * cfg.height * cfg.width * 32 * 64
+    achieved = conv_flops / conv_s / 1e12
+    res = {"metric": "U-Net training throughput", "value": round(n / (train_ms / 1e3), 2), "unit": "samples/s",
+           "n_gpus": 1, "steps": steps, "warmup": warmup, "ms_per_step": round(train_ms, 4),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+           "data": "synthetic (uniform random fields)",
+           "config": {"workload": "unet_512_bf16", "height": cfg.height, "width": cfg.width, "batch": n,
+                      "levels": cfg.levels, "base": cfg.base,
+                      "forward_gflop_per_sample": round(fwd / 1e9, 2),
+                      "train_tflops": round(3 * fwd * n / (train_ms / 1e3) / 1e12, 1),
+                      "inference_ms_batch1": round(infer_ms, 4),
+                      "inference_tflops_batch1": round(fwd / (infer_ms / 1e3) / 1e12, 1)},
+           "roofline": {"bound": "mfma", "achieved": round(achieved, 1), "peak": MFMA_BF16_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(achieved / MFMA_BF16_PEAK_TFLOPS, 4), "traffic": None,
+                        "kernel": "gemm32_kernel<0, 4, 2, 4, 1> (conv3x3 64->32, 5 x 512^2)",
+                        "avg_launch_us": round(conv_s * 1e6, 2), "flops_per_launch": conv_flops}}
+    if not args.no_cpu:
+        res["cpu_baseline"] = unet_cpu_leg(cfg, args.cpu_seconds)
+    return res
+
+
+def unet_cpu_leg(cfg, seconds):
+    """The FP64 PyTorch-CPU oracle's forward pass on one 512^2 sample."""
+    import numpy as np
+    import torch
+
+    from oracle import unet_oracle as uo
+    from paper_2312_05410_amd import unet as U
+    from paper_2312_05410_amd.unet_inputs import init_params
+
+    params = init_params([(e[0], e[2]) for e in U.param_entries(cfg)], 0)
+    net = uo.Net(cfg, params)
+    st = [np.full((1, cfg.height, cfg.width), 0.5) for _ in range(3)]
+    n, t0 = 0, time.perf_counter()
+    with torch.no_grad():
+        while True:
+            net.forward(*st, np.ones(1))
+            n += 1
+            if time.perf_counter() - t0 > seconds:
+                break
+    el = time.perf_counter() - t0
+    return {"value": round(n / el, 4), "unit": "samples/s (forward)", "cores": torch.get_num_threads(),
+            "kind": "oracle", "sample": f"{n} FP64 forward passes of one 512^2 sample ({el:.1f} s)"}
+
+
+def blended_leg(args):
+    """The blended run (200 DNS steps, then one U-Net leap of 4 x 100 steps,
+    repeated to 50,000 steps on 512^2) against plain DNS at 0.2 of the
+    stability limit, and plain DNS at larger time steps."""
+    import numpy as np
+
+    from paper_2312_05410_amd import surrogate as S
+    from paper_2312_05410_amd import unet as U
+
+    path = os.path.join(ROOT, "paper_2312_05410_amd", "weights", "unet_blend_512.npz")
+    with np.load(path, allow_pickle=False) as z:
+        params = {k: z[k] for k in z.files}
+    net = U.UNet(U.UNetConfig(max_batch=1), params=params)
+    r = S.compare(net, log=lambda m: print("# " + m, file=sys.stderr, flush=True))
+    net.close()
+    b = r["runs"]["blend_leap"]
+    return {"metric": "blended vs DNS time-to-solution at fixed error", "value": r["speedup_fixed_error"],
+            "unit": "x (DNS time / blended time)", "n_gpus": 1, "steps": r["steps"], "warmup": 0,
+            "ms_per_step": round(b["ms"] / r["steps"], 6), "higher_is_better": True, "scaling": "strong",
+            "vs_baseline": None, "dtype": "f32 (DNS) + bf16 (U-Net)",
+            "data": "synthetic (seeded; U-Net trained on stepper snapshots only)",
+            "config": {"workload": "blended_512_f32", "n": r["n"], "seed": r["seed"],
+                       "schedule": f"{S.BLEND_DNS} DNS steps + 1 leap of {S.BLEND_JUMPS} x {S.JUMP} steps",
+                       "speedup_same_dt": r["speedup_same_dt"], "dns_ms": r["dns_ms"], "runs": r["runs"]}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -235,6 +383,12 @@ def main():
         sys.exit(2)
     if args.workload == "adjoint_256_f32":
         print(json.dumps(adjoint_leg(args)), flush=True)
+        return
+    if args.workload == "unet_512_bf16":
+        print(json.dumps(unet_leg(args)), flush=True)
+        return
+    if args.workload == "blended_512_f32":
+        print(json.dumps(blended_leg(args)), flush=True)
         return
     import torch
 

@@ -54,6 +54,7 @@ enum pf_status {
 enum pf_precision { PF_F32 = 0, PF_F64 = 1 };
 enum pf_bc { PF_BC_PVD = 0, PF_BC_PERIODIC = 1 };
 enum pf_init_mode { PF_INIT_SEEDED = 0, PF_INIT_KEEP = 1 };
+enum pf_integrator { PF_EULER = 0, PF_MIDPOINT = 1 };
 
 /*
  * Problem definition.  Units are dimensionless, as in the paper's dataset.
@@ -72,6 +73,20 @@ enum pf_init_mode { PF_INIT_SEEDED = 0, PF_INIT_KEEP = 1 };
  *     (j = 0) and the top (j = ny-1); rho has no flux through the substrate
  *     and the fixed value rho_in above the top row (vapour inlet);
  *   PF_BC_PERIODIC: periodic in x and y, no inlet (a test mode).
+ *
+ * Model variants (Materials and Methods, "Dataset"; Introduction):
+ *   integrator PF_MIDPOINT: the explicit midpoint method of the paper's
+ *     solver, u' = u + dt R(u + dt/2 R(u)) (two launches per step, the
+ *     first into the workspace, the second in place); same stability limit;
+ *   interface_noise > 0: the paper's random interface composition, read as:
+ *     after every step each cell on the vapour side (phi' < 0) takes a
+ *     fresh composition drawn from N(c0_b, interface_noise^2) truncated to
+ *     [0, 1].  The draw is FP64 Box-Muller on SplitMix64 uniforms of the
+ *     stream (seed + b) ^ 0x2B7E151628AED2A6, counters 16 (s nx ny + j nx + i)
+ *     + 2a, + 2a + 1 for attempt a = 0..7 at global step s (pf_get_step),
+ *     first draw inside [0, 1] kept, else c0_b.
+ *   Both variants run the single-step kernel (temporal_block 0 or 1);
+ *   interface_noise also runs plain launches (no graph replay).
  */
 typedef struct pf_params {
     int32_t nx, ny, batch;        /* grid cells and independent realisations */
@@ -85,7 +100,7 @@ typedef struct pf_params {
     int32_t graph_mode;           /* 0: long runs replay a HIP graph of launches; 1: plain launches */
     int32_t tile_rows;            /* single-step kernel: rows per wave (4, 8, 16, 32); 0: library's
                                      choice by grid size */
-    int32_t reserved0;            /* must be 0 */
+    int32_t integrator;           /* pf_integrator */
     uint64_t seed;                /* seeded initial condition: realisation b uses seed + b */
     double h;                     /* grid spacing */
     double dt;                    /* time step; <= 0 means dt_factor * stability limit */
@@ -96,6 +111,7 @@ typedef struct pf_params {
     double c0, c_noise, film_h;   /* initial condition; film_h <= 0 means ny h / 8 */
     const double* v0_per;         /* host [batch] incident speeds, or NULL for v0 */
     const double* c0_per;         /* host [batch] mean compositions, or NULL for c0 */
+    double interface_noise;       /* standard deviation of the interface draw, 0..1; 0: off */
 } pf_params;
 
 /* Bytes of device workspace a handle for *p needs (ping-pong copy of the

@@ -9,8 +9,10 @@
  * two-layer sin MLP of the time step.  The output head is GN(conv(block)).
  * Training follows "Training of the network" (Adam) with the relative
  * squared error of "Error metrics".  Readings where the paper is silent:
- *   - input channels (c, phi, rho, jump length) and output = the three
- *     fields' increments over the jump (u(t+dt) = u(t) + head);
+ *   - input channels (c, phi, rho, jump length dt); the head gives the three
+ *     fields' mean rate over the leap: u(t+dt) = u(t) + dt head (the
+ *     head's normalisation fixes its overall scale, the increment grows
+ *     with dt);
  *   - 3x3 convolutions with zero "same" padding and no bias; transposed
  *     convolutions without bias; GN with `groups` groups (eps gn_eps) in the
  *     blocks and `head_groups` in the head;

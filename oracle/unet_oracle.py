@@ -9,7 +9,8 @@ Every function follows one passage of the paper's Materials and Methods
 plain tensor operations on NCHW float64 tensors.  Gradients are those of
 torch.autograd on this forward.  Readings where the paper is silent (they
 match the GPU library's documented interface):
-  * input channels (c, phi, rho, jump map); output = the fields' increments;
+  * input channels (c, phi, rho, jump map); the head gives the fields' mean
+    rate over the leap: prediction = state + jump * head;
   * 3x3 convolutions, zero padding, no bias; transposed convolutions
     without bias;
   * decoder widths: the bottom block keeps the deepest width, each
@@ -146,7 +147,8 @@ class Net:
             d = R(up(a, self.W(f"up{l + 1}.w")))
             a = R(self.block(torch.cat([zs[l], d], dim=1), f"dec{l}"))
         head = self.block(a, "head", G=self.Gh, act=False)
-        return c + head[:, 0], phi + head[:, 1], rho + head[:, 2]
+        dt = jump.view(n, 1, 1)
+        return c + dt * head[:, 0], phi + dt * head[:, 1], rho + dt * head[:, 2]
 
     def loss_and_grads(self, state, jump, target, bf16: bool = False):
         """Loss of the prediction from `state` against `target` and its

@@ -22,6 +22,7 @@ PF_OK, PF_EINVAL, PF_EUNSTABLE, PF_ENONFINITE, PF_EDEVICE = 0, -1, -2, -3, -4
 PF_F32, PF_F64 = 0, 1
 PF_BC_PVD, PF_BC_PERIODIC = 0, 1
 PF_INIT_SEEDED, PF_INIT_KEEP = 0, 1
+PF_INTEGRATOR = {"euler": 0, "midpoint": 1}
 
 EXPORTS = (
     "pf_workspace_bytes", "pf_dt_limit", "pf_init", "pf_step_n", "pf_mass", "pf_energy",
@@ -39,7 +40,7 @@ class PFParamsC(ctypes.Structure):
         ("precision", ctypes.c_int32), ("bc_mode", ctypes.c_int32), ("flux_on", ctypes.c_int32),
         ("init_mode", ctypes.c_int32), ("allow_unstable", ctypes.c_int32),
         ("temporal_block", ctypes.c_int32), ("graph_mode", ctypes.c_int32),
-        ("tile_rows", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+        ("tile_rows", ctypes.c_int32), ("integrator", ctypes.c_int32),
         ("seed", ctypes.c_uint64),
         ("h", ctypes.c_double), ("dt", ctypes.c_double), ("dt_factor", ctypes.c_double),
         ("W_c", ctypes.c_double), ("W_phi", ctypes.c_double),
@@ -51,6 +52,7 @@ class PFParamsC(ctypes.Structure):
         ("rho_in", ctypes.c_double),
         ("c0", ctypes.c_double), ("c_noise", ctypes.c_double), ("film_h", ctypes.c_double),
         ("v0_per", ctypes.c_void_p), ("c0_per", ctypes.c_void_p),
+        ("interface_noise", ctypes.c_double),
     ]
 
 
@@ -142,14 +144,15 @@ def to_c(p: PFParams, init_mode: int = PF_INIT_SEEDED, temporal_block: int = 0,
     s = PFParamsC(
         nx=p.nx, ny=p.ny, batch=p.batch, precision=_PREC[p.precision], bc_mode=_BC[p.bc_mode],
         flux_on=int(bool(p.flux_on)), init_mode=init_mode, allow_unstable=int(bool(allow_unstable)),
-        temporal_block=temporal_block, graph_mode=graph_mode, tile_rows=tile_rows, reserved0=0, seed=p.seed & 0xFFFFFFFFFFFFFFFF,
+        temporal_block=temporal_block, graph_mode=graph_mode, tile_rows=tile_rows,
+        integrator=PF_INTEGRATOR[p.integrator], seed=p.seed & 0xFFFFFFFFFFFFFFFF,
         h=p.h, dt=p.dt, dt_factor=p.dt_factor,
         W_c=p.W_c, W_phi=p.W_phi, kappa_c=p.kappa_c, kappa_phi=p.kappa_phi,
         MA_bulk=p.MA_bulk, MB_bulk=p.MB_bulk, MA_surf=p.MA_surf, MB_surf=p.MB_surf,
         sigma_surf=p.sigma_surf, M_phi=p.M_phi, M_scale=p.M_scale,
         D_rho=p.D_rho, v0=p.v0, theta_deg=p.theta_deg, rho_in=p.rho_in,
         c0=p.c0, c_noise=p.c_noise, film_h=p.film_h,
-        v0_per=arr(p.v0_per), c0_per=arr(p.c0_per))
+        v0_per=arr(p.v0_per), c0_per=arr(p.c0_per), interface_noise=float(p.interface_noise))
     return s, keep
 
 

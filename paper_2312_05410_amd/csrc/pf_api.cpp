@@ -70,7 +70,10 @@ int validate(const pf_params* p)
     if (p->graph_mode < 0 || p->graph_mode > 1) return PF_EINVAL;
     if (p->tile_rows != 0 && p->tile_rows != 4 && p->tile_rows != 8 && p->tile_rows != 16 && p->tile_rows != 32)
         return PF_EINVAL;
-    if (p->reserved0 != 0) return PF_EINVAL;
+    if (p->integrator != PF_EULER && p->integrator != PF_MIDPOINT) return PF_EINVAL;
+    if (!std::isfinite(p->interface_noise) || p->interface_noise < 0 || p->interface_noise > 1) return PF_EINVAL;
+    // the variants run on the single-step kernel
+    if ((p->integrator != PF_EULER || p->interface_noise > 0) && p->temporal_block > 1) return PF_EINVAL;
     if (!finite_all({p->h, p->dt, p->dt_factor, p->W_c, p->W_phi, p->kappa_c, p->kappa_phi, p->MA_bulk,
                      p->MB_bulk, p->MA_surf, p->MB_surf, p->sigma_surf, p->M_phi, p->M_scale, p->D_rho,
                      p->v0, p->theta_deg, p->rho_in, p->c0, p->c_noise, p->film_h}))
@@ -223,19 +226,51 @@ void set_parity(pf_handle* h, pfk::StepArgs<T>& a, int parity)
     a.rho_out = (T*)dst[2];
 }
 
-// A graph of kGraphLen full-K launches (caller -> workspace -> caller ...),
-// built once per handle and replayed for long runs.
+// Arguments of the two launches of one midpoint step: A advances the
+// caller's state by dt/2 into the workspace (no inflow), B evaluates the
+// rates there and adds dt times them to the caller's state in place.
+template <typename T>
+void midpoint_args(pf_handle* h, pfk::StepArgs<T>& A, pfk::StepArgs<T>& B)
+{
+    A = step_args<T>(h);
+    B = A;
+    set_parity<T>(h, A, 0);
+    A.k = make_coef<T>(&h->p, 0.5 * h->dt);
+    A.Qcol = nullptr;
+    A.noise = 0;
+    A.nsub = 1;
+    B.c = (const T*)h->w[0];
+    B.phi = (const T*)h->w[1];
+    B.rho = (const T*)h->w[2];
+    B.cb = (const T*)h->f[0];
+    B.pb = (const T*)h->f[1];
+    B.rb = (const T*)h->f[2];
+    B.c_out = (T*)h->f[0];
+    B.phi_out = (T*)h->f[1];
+    B.rho_out = (T*)h->f[2];
+    B.nsub = 1;
+}
+
+// A graph of kGraphLen launches (caller -> workspace -> caller ..., or
+// kGraphLen / 2 midpoint steps), built once per handle and replayed for
+// long runs.  Not used with interface draws (their launches differ).
 template <typename T>
 int ensure_graph(pf_handle* h)
 {
     if (h->gexec) return PF_OK;
-    pfk::StepArgs<T> a = step_args<T>(h);
+    pfk::StepArgs<T> a = step_args<T>(h), A, B;
+    const bool mid = h->p.integrator == PF_MIDPOINT;
+    if (mid) midpoint_args<T>(h, A, B);
     hipGraph_t g = nullptr;
     hipError_t e = hipGraphCreate(&g, 0);
     hipGraphNode_t prev = nullptr;
     for (int i = 0; i < kGraphLen && e == hipSuccess; ++i) {
-        set_parity<T>(h, a, i & 1);
-        a.nsub = h->K;
+        if (mid) {
+            a = (i & 1) ? B : A;
+        } else {
+            set_parity<T>(h, a, i & 1);
+            a.nsub = h->K;
+        }
         hipGraphNode_t node = nullptr;
         e = h->K == 1 ? pfk::graph_add_march<T>(g, &node, prev, a, h->march_ty, h->p.batch)
                       : pfk::graph_add_step<T>(g, &node, prev, a, h->K, h->p.batch);
@@ -253,17 +288,42 @@ int ensure_graph(pf_handle* h)
 }
 
 template <typename T>
+int enqueue_midpoint(pf_handle* h, int64_t n)
+{
+    pfk::StepArgs<T> A, B;
+    midpoint_args<T>(h, A, B);
+    const bool noise = h->p.interface_noise > 0;
+    B.noise = h->p.interface_noise;
+    int64_t s = 0;
+    int rc;
+    if (!noise && h->p.graph_mode == 0 && n >= kGraphLen / 2) {
+        if ((rc = ensure_graph<T>(h))) return rc;
+        for (; s + kGraphLen / 2 <= n; s += kGraphLen / 2)
+            if ((rc = hip_fail(h, hipGraphLaunch(h->gexec, h->stream)))) return rc;
+    }
+    for (; s < n; ++s) {
+        B.step = h->step + s;
+        if ((rc = hip_fail(h, pfk::launch_march<T>(A, h->march_ty, h->p.batch, h->stream)))) return rc;
+        if ((rc = hip_fail(h, pfk::launch_march<T>(B, h->march_ty, h->p.batch, h->stream)))) return rc;
+    }
+    return PF_OK;
+}
+
+template <typename T>
 int enqueue_steps(pf_handle* h, int64_t n)
 {
     const pf_params* p = &h->p;
+    if (p->integrator == PF_MIDPOINT) return enqueue_midpoint<T>(h, n);
     const int K = h->K;
+    const bool noise = p->interface_noise > 0;
     pfk::StepArgs<T> a = step_args<T>(h);
+    a.noise = p->interface_noise;
     const std::vector<int> plan = launch_plan(n, K);
     size_t full = 0;
     while (full < plan.size() && plan[full] == K) ++full;
     size_t l = 0;
     int rc;
-    if (p->graph_mode == 0 && full >= (size_t)kGraphLen) {
+    if (!noise && p->graph_mode == 0 && full >= (size_t)kGraphLen) {
         if ((rc = ensure_graph<T>(h))) return rc;
         for (; l + kGraphLen <= full; l += kGraphLen)
             if ((rc = hip_fail(h, hipGraphLaunch(h->gexec, h->stream)))) return rc;
@@ -272,6 +332,7 @@ int enqueue_steps(pf_handle* h, int64_t n)
     for (; l < plan.size(); ++l) {
         set_parity<T>(h, a, parity);
         a.nsub = plan[l];
+        a.step = h->step + (int64_t)l;  // one step per launch whenever draws are on (K = 1)
         const hipError_t e = K == 1 ? pfk::launch_march<T>(a, h->march_ty, p->batch, h->stream)
                                     : pfk::launch_step<T>(a, K, p->batch, h->stream);
         if ((rc = hip_fail(h, e))) return rc;
@@ -379,6 +440,7 @@ int pf_init(pf_handle** out, const pf_params* p, void* c, void* phi, void* rho, 
     const long cells = (long)p->nx * p->ny * p->batch;
     int K = p->temporal_block;
     if (K == 0) K = (p->precision == PF_F32 && cells >= 786432L && cells < 3000000L) ? 2 : 1;
+    if (p->integrator != PF_EULER || p->interface_noise > 0) K = 1;
     while (K > 1 && 2 * K > p->ny) --K;
     h->K = K;
     if (p->tile_rows > 0) {
@@ -400,6 +462,8 @@ int pf_init(pf_handle** out, const pf_params* p, void* c, void* phi, void* rho, 
         h->real[b].vy2h = vy / (2.0 * p->h);
         h->real[b].qa = dt * p->h * (-0.5 * vy);
         h->real[b].qb = dt * p->D_rho;
+        h->real[b].c0 = c0_of(p, b);
+        h->real[b].nseed = (p->seed + (uint64_t)b) ^ 0x2B7E151628AED2A6ull;  // interface-draw stream
         h->c0[b] = c0_of(p, b);
     }
     // pf_params says the per-realisation arrays are read during the call

@@ -1,9 +1,10 @@
 // Per-cell arithmetic of the explicit PVD phase-field step, shared by every
 // stepper kernel (Materials and Methods, "Phase-field modeling of physical
 // vapor deposition"; second-order central differences as stated in
-// "Dataset"; explicit Euler).  Each kernel evaluates every cell through these
-// two functions with a fixed expression order (contraction off, explicit
-// fma), so all kernels and launch shapes give bitwise-identical states.
+// "Dataset"; explicit Euler or the midpoint method).  Each kernel evaluates
+// every cell through these functions with a fixed expression order
+// (contraction off, explicit fma), so all kernels and launch shapes give
+// bitwise-identical states.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -83,12 +84,49 @@ __device__ __forceinline__ RhoCoef<T> rho_coef(const Coef<T>& k, T vx2h, T vy2h)
     return {k.D_h2 - vx2h, k.D_h2 + vx2h, k.D_h2 - vy2h, k.D_h2 + vy2h, k.D_h2 - vy2h, T(-4) * k.D_h2};
 }
 
-// Stage 2 at one cell: Euler update of (c, phi, rho) from the four face
-// fluxes of c (east, west, north, south as defined by cflux), mu_phi at the
-// cell and its neighbours, phi's neighbours and rho's 5-point stencil.
-//   c'   = c   + dt * (1/2h^2)((FE - FW) + (FN - FS))
-//   phi' = phi + dt * (M_phi Lap mu_phi + S),  S = rho v . grad phi
-//   rho' = rho + dt * (D Lap rho - div(rho v) - S)
+// Stage 2 at one cell: the rates of (c, phi, rho) from the four face fluxes
+// of c (east, west, north, south as defined by cflux), mu_phi at the cell
+// and its neighbours, phi's neighbours and rho's 5-point stencil.
+//   Rc = (1/2h^2)((FE - FW) + (FN - FS))
+//   Rp = M_phi Lap mu_phi + S,  S = rho v . grad phi
+//   Rr = D Lap rho - div(rho v) - S
+template <typename T>
+__device__ __forceinline__ void rates(const Coef<T>& k, const RhoCoef<T>& rc, T vx2h, T vy2h, bool bottom,
+                                      T pE, T pW, T pN, T pS,
+                                      T r0, T rE, T rW, T rN, T rS,
+                                      T FE, T FW, T FN, T FS,
+                                      T q0, T qE, T qW, T qN, T qS,
+                                      T& Rc, T& Rp, T& Rr)
+{
+    const T divc = k.half_ih2 * ((FE - FW) + (FN - FS));
+    const T divp = k.mphi_h2 * fmaT(T(-4), q0, (qE + qW) + (qN + qS));
+    const T src = r0 * fmaT(vx2h, pE - pW, vy2h * (pN - pS));
+    const T aS = bottom ? rc.aS_bottom : rc.aS;
+    const T Tr = fmaT(rc.aE, rE, fmaT(rc.aW, rW, fmaT(rc.aN, rN, fmaT(aS, rS, rc.a0 * r0))));
+    Rc = divc;
+    Rp = divp + src;
+    Rr = Tr - src;
+}
+
+// Euler update from base values (c0, p0, r0): u' = u + dt R.  For explicit
+// Euler the base is the cell's own state; the midpoint method's second stage
+// passes the state at the start of the step.
+template <typename T>
+__device__ __forceinline__ void update(const Coef<T>& k, const RhoCoef<T>& rc, T vx2h, T vy2h, bool bottom,
+                                       T c0, T p0, T pE, T pW, T pN, T pS,
+                                       T r0, T rE, T rW, T rN, T rS,
+                                       T FE, T FW, T FN, T FS,
+                                       T q0, T qE, T qW, T qN, T qS,
+                                       T& nc, T& np, T& nr, T cb, T pb, T rb)
+{
+    T Rc, Rp, Rr;
+    rates(k, rc, vx2h, vy2h, bottom, pE, pW, pN, pS, r0, rE, rW, rN, rS, FE, FW, FN, FS, q0, qE, qW, qN, qS,
+          Rc, Rp, Rr);
+    nc = fmaT(k.dt, Rc, cb);
+    np = fmaT(k.dt, Rp, pb);
+    nr = fmaT(k.dt, Rr, rb);
+}
+
 template <typename T>
 __device__ __forceinline__ void update(const Coef<T>& k, const RhoCoef<T>& rc, T vx2h, T vy2h, bool bottom,
                                        T c0, T p0, T pE, T pW, T pN, T pS,
@@ -97,14 +135,34 @@ __device__ __forceinline__ void update(const Coef<T>& k, const RhoCoef<T>& rc, T
                                        T q0, T qE, T qW, T qN, T qS,
                                        T& nc, T& np, T& nr)
 {
-    const T divc = k.half_ih2 * ((FE - FW) + (FN - FS));
-    const T divp = k.mphi_h2 * fmaT(T(-4), q0, (qE + qW) + (qN + qS));
-    const T src = r0 * fmaT(vx2h, pE - pW, vy2h * (pN - pS));
-    const T aS = bottom ? rc.aS_bottom : rc.aS;
-    const T Tr = fmaT(rc.aE, rE, fmaT(rc.aW, rW, fmaT(rc.aN, rN, fmaT(aS, rS, rc.a0 * r0))));
-    nc = fmaT(k.dt, divc, c0);
-    np = fmaT(k.dt, divp + src, p0);
-    nr = fmaT(k.dt, Tr - src, r0);
+    update(k, rc, vx2h, vy2h, bottom, c0, p0, pE, pW, pN, pS, r0, rE, rW, rN, rS, FE, FW, FN, FS, q0, qE, qW, qN,
+           qS, nc, np, nr, c0, p0, r0);
+}
+
+// SplitMix64 (Steele, Lea & Flood 2014): output n of the stream `seed`.
+__device__ __forceinline__ uint64_t mix64(uint64_t seed, uint64_t n)
+{
+    uint64_t z = seed + (n + 1ull) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Interface composition: N(mean, sigma^2) truncated to [0, 1] by rejection,
+// Box-Muller in FP64 on the uniforms (53 bits; first in (0, 1], second in
+// [0, 1)) of counters counter0 + 2a and + 2a + 1, attempts a = 0..7, then
+// the mean.
+__device__ __noinline__ double trunc_gauss(uint64_t seed, uint64_t counter0, double mean, double sigma)
+{
+    for (int a = 0; a < 8; ++a) {
+        const uint64_t x1 = mix64(seed, counter0 + 2ull * a), x2 = mix64(seed, counter0 + 2ull * a + 1ull);
+        const double u1 = (double)((x1 >> 11) + 1ull) * 0x1.0p-53;
+        const double u2 = (double)(x2 >> 11) * 0x1.0p-53;
+        const double z = sqrt(-2.0 * log(u1)) * cos(2.0 * 3.14159265358979323846 * u2);
+        const double v = mean + sigma * z;
+        if (v >= 0.0 && v <= 1.0) return v;
+    }
+    return mean;
 }
 
 }  // namespace cell

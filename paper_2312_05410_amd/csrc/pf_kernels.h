@@ -25,9 +25,12 @@ struct Coef {
 };
 
 // Per-realisation constants (device array, double): vx/(2h), vy/(2h),
-// and the two inflow weights dt*h*(-vy/2) and dt*D.
+// the two inflow weights dt*h*(-vy/2) and dt*D, the mean composition and the
+// interface-draw stream.
 struct Real {
     double vx2h, vy2h, qa, qb;
+    double c0;
+    uint64_t nseed;
 };
 
 template <typename T>
@@ -38,8 +41,15 @@ struct StepArgs {
     T* c_out;
     T* phi_out;
     T* rho_out;
-    double* Qcol;        // [B][nx] cumulative inflow per column
+    double* Qcol;        // [B][nx] cumulative inflow per column (null: not accumulated)
     const Real* real;    // [B]
+    // midpoint second stage: the update adds dt R(c, phi, rho) to these
+    // (null: to c, phi, rho themselves)
+    const T* cb;
+    const T* pb;
+    const T* rb;
+    double noise;        // interface draw standard deviation (0: off)
+    long long step;      // global step index keying the draws
     Coef<T> k;
     int nx, ny;
     int tiles_x, tiles_y;

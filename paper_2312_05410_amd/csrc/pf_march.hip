@@ -80,7 +80,10 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const T* base, size
 
 // One wave per (strip, chunk).  TY output rows; input rows t = 0..TY+3 are
 // global rows y0-2+t; stage 1 runs on t = 1..TY+2, stage 2 on t = 2..TY+1.
-template <typename T, int TY, int D>
+// BASE: the update adds to the state at a.cb/pb/rb (the midpoint method's
+// second stage) instead of the evaluated state.  NOISE: cells that end on the
+// vapour side take the interface composition draw.
+template <typename T, int TY, int D, bool BASE, bool NOISE>
 __global__ __launch_bounds__(64) void march_kernel(StepArgs<T> a)
 {
     constexpr int NR = TY + 4;
@@ -111,6 +114,9 @@ __global__ __launch_bounds__(64) void march_kernel(StepArgs<T> a)
     const auto oc = plane_rsrc(a.c_out + (size_t)b * plane, plane);
     const auto op = plane_rsrc(a.phi_out + (size_t)b * plane, plane);
     const auto orr = plane_rsrc(a.rho_out + (size_t)b * plane, plane);
+    const auto bcb = plane_rsrc((BASE ? a.cb : a.c) + (size_t)b * plane, plane);
+    const auto bpb = plane_rsrc((BASE ? a.pb : a.phi) + (size_t)b * plane, plane);
+    const auto brb = plane_rsrc((BASE ? a.rb : a.rho) + (size_t)b * plane, plane);
     const int vo = gx * (int)sizeof(T);
     const int row_bytes = nx * (int)sizeof(T);
     const Coef<T> k = a.k;
@@ -163,11 +169,22 @@ __global__ __launch_bounds__(64) void march_kernel(StepArgs<T> a)
             const T FE = cflux(M[t], mc[t], east(M[t]), east(mc[t]));
             FN[t] = cflux(M[t], mc[t], M[t + 1], mc[t + 1]);
             T nc, np, nr;
+            T cb0 = c[t], pb0 = p[t], rb0 = r[t];
+            if (BASE && gj < ny) {
+                const int so = gj * row_bytes;
+                cb0 = Buf<T>::ld(bcb, vo, so);
+                pb0 = Buf<T>::ld(bpb, vo, so);
+                rb0 = Buf<T>::ld(brb, vo, so);
+            }
             update(k, rc, vx2h, vy2h, bottom, c[t],
                    p[t], pE[t], pW[t], p[t + 1], p[t - 1],
                    r[t], east(r[t]), west(r[t]), r[t + 1], r[t - 1],
                    FE, west(FE), FN[t], FN[t - 1],
-                   mp[t], east(mp[t]), west(mp[t]), mp[t + 1], mp[t - 1], nc, np, nr);
+                   mp[t], east(mp[t]), west(mp[t]), mp[t + 1], mp[t - 1], nc, np, nr, cb0, pb0, rb0);
+            if (NOISE && gj < ny && out_lane && np < T(0)) {
+                const uint64_t id = (uint64_t)a.step * plane + (uint64_t)gj * nx + ocol;
+                nc = (T)trunc_gauss(rl.nseed, id * 16ull, rl.c0, a.noise);
+            }
             if (gj < ny) {
                 if (out_lane) {
                     const int so = gj * row_bytes;
@@ -175,7 +192,7 @@ __global__ __launch_bounds__(64) void march_kernel(StepArgs<T> a)
                     Buf<T>::st(np, op, vo, so);
                     Buf<T>::st(nr, orr, vo, so);
                 }
-                if (pvd && gj == ny - 1 && out_lane) {
+                if (a.Qcol && pvd && gj == ny - 1 && out_lane) {
                     // inflow through the top face: advective + diffusive flux
                     double* q = a.Qcol + (size_t)b * nx + ocol;
                     const double rin = (double)k.rho_in, rr = (double)r[t];
@@ -190,14 +207,26 @@ __global__ __launch_bounds__(64) void march_kernel(StepArgs<T> a)
 // at once, long chunks keep a window of rows in flight
 template <int TY> constexpr int lookahead() { return TY <= 8 ? TY + 1 : 4; }
 
+// the kernel instantiation for the arguments' variant
+template <typename T, int TY>
+void* march_fn(const StepArgs<T>& a)
+{
+    constexpr int D = lookahead<TY>();
+    const bool base = a.cb != nullptr, noise = a.noise > 0;
+    if (base && noise) return (void*)march_kernel<T, TY, D, true, true>;
+    if (base) return (void*)march_kernel<T, TY, D, true, false>;
+    if (noise) return (void*)march_kernel<T, TY, D, false, true>;
+    return (void*)march_kernel<T, TY, D, false, false>;
+}
+
 template <typename T, int TY>
 hipError_t launch_march_ty(StepArgs<T> a, int batch, hipStream_t s)
 {
     a.tiles_x = (a.nx + kStripOut - 1) / kStripOut;
     a.tiles_y = (a.ny + TY - 1) / TY;
     dim3 grid(a.tiles_x * a.tiles_y, batch);
-    hipLaunchKernelGGL((march_kernel<T, TY, lookahead<TY>()>), grid, dim3(64), 0, s, a);
-    return hipGetLastError();
+    void* args[] = {&a};
+    return hipLaunchKernel(march_fn<T, TY>(a), grid, dim3(64), args, 0, s);
 }
 
 template <typename T, int TY>
@@ -207,7 +236,7 @@ hipError_t node_march_ty(hipGraph_t g, hipGraphNode_t* node, hipGraphNode_t dep,
     a.tiles_y = (a.ny + TY - 1) / TY;
     void* args[] = {&a};
     hipKernelNodeParams kp{};
-    kp.func = (void*)march_kernel<T, TY, lookahead<TY>()>;
+    kp.func = march_fn<T, TY>(a);
     kp.gridDim = dim3(a.tiles_x * a.tiles_y, batch);
     kp.blockDim = dim3(64);
     kp.sharedMemBytes = 0;

@@ -524,14 +524,14 @@ int forward(unet_handle* h, int n, const float* jump, const float* c, const floa
         g.z_bf16 = b.ad[l];
         RCHECK(conv_gn(h, a, kConvFwd, g));
     }
-    // head: GN(conv(a_0)), added to the input state
+    // head: GN(conv(a_0)) is the rate over the leap, u' = u + dt head
     {
         ConvArgs a = conv_args(net.head, n, Hl(0), Wl(0), b.ad[0], nullptr);
         a.out_f32 = b.yh;
         GNArgs g = gn_args(h, net.head, n, P0, b.yh, b.sth);
         g.z_f32 = b.hout;
         RCHECK(conv_gn(h, a, kConvFwd, g));
-        UCHECK(residual_out(b.hout, c, phi, rho, oc, ophi, orho, n, (int)P0, s));
+        UCHECK(residual_out(b.hout, b.jump, c, phi, rho, oc, ophi, orho, n, (int)P0, s));
     }
     h->last_n = train ? n : 0;
     return PF_OK;
@@ -548,7 +548,7 @@ int backward(unet_handle* h, const float* pc, const float* pphi, const float* pr
     auto Hl = [&](int l) { return net.c.height >> l; };
     auto Wl = [&](int l) { return net.c.width >> l; };
     const long P0 = net.P(0, 1);
-    UCHECK(rel_mse(pc, pphi, prho, tc, tphi, trho, b.gout, b.lpart, b.loss, n, (int)P0, s));
+    UCHECK(rel_mse(pc, pphi, prho, tc, tphi, trho, b.jump, b.gout, b.lpart, b.loss, n, (int)P0, s));
     // head
     {
         GNArgs g = gn_args(h, net.head, n, P0, b.yh, b.sth);

@@ -116,9 +116,9 @@ hipError_t maxpool_bwd(const uint16_t* x, const float* dy, float* dx, int N, int
 // Network input: x[n][p][0..3] = (c, phi, rho, jump[n]) as BF16.
 hipError_t assemble_input(const float* c, const float* phi, const float* rho, const float* jump, uint16_t* x, int N,
                           int P, hipStream_t s);
-// out_f[n][p] = in_f[n][p] + head[n][p][f] for the three fields.
-hipError_t residual_out(const float* head, const float* c, const float* phi, const float* rho, float* oc, float* ophi,
-                        float* orho, int N, int P, hipStream_t s);
+// out_f[n][p] = in_f[n][p] + jump[n] head[n][p][f] for the three fields.
+hipError_t residual_out(const float* head, const float* jump, const float* c, const float* phi, const float* rho,
+                        float* oc, float* ophi, float* orho, int N, int P, hipStream_t s);
 
 // Time basis f(jump) (two sin layers of width Hd) and the per-level FiLM
 // scales s_l = w_l f.
@@ -148,9 +148,11 @@ hipError_t mlp_forward(const MLPArgs& a, hipStream_t s);
 hipError_t mlp_backward(const MLPArgs& a, hipStream_t s);
 
 // Relative MSE per field: L = sum_f sum (pred - tgt)^2 / sum tgt^2.
-// Writes dL/dpred as [N][P][3] (NHWC, the head's layout) and L (FP64).
+// Writes dL/dhead = jump[n] dL/dpred as [N][P][3] (NHWC, the head's layout)
+// and L (FP64).
 hipError_t rel_mse(const float* pc, const float* pphi, const float* prho, const float* tc, const float* tphi,
-                   const float* trho, float* grad, double* part, double* loss, int N, int P, hipStream_t s);
+                   const float* trho, const float* jump, float* grad, double* part, double* loss, int N, int P,
+                   hipStream_t s);
 size_t rel_mse_partial_doubles();
 
 // Adam on FP32 master parameters.

@@ -404,15 +404,15 @@ __global__ __launch_bounds__(256) void assemble_kernel(const float* c, const flo
     }
 }
 
-__global__ __launch_bounds__(256) void residual_kernel(const float* head, const float* c, const float* phi,
-                                                       const float* rho, float* oc, float* ophi, float* orho,
-                                                       size_t total)
+__global__ __launch_bounds__(256) void residual_kernel(const float* head, const float* jump, const float* c,
+                                                       const float* phi, const float* rho, float* oc, float* ophi,
+                                                       float* orho, int P, size_t total)
 {
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (size_t)gridDim.x * 256) {
-        const float h0 = head[3 * i], h1 = head[3 * i + 1], h2 = head[3 * i + 2];
-        oc[i] = c[i] + h0;
-        ophi[i] = phi[i] + h1;
-        orho[i] = rho[i] + h2;
+        const float dt = jump[i / P];
+        oc[i] = fmaf(dt, head[3 * i], c[i]);
+        ophi[i] = fmaf(dt, head[3 * i + 1], phi[i]);
+        orho[i] = fmaf(dt, head[3 * i + 2], rho[i]);
     }
 }
 
@@ -610,15 +610,18 @@ __global__ void mse_finish_kernel(const double* part, double* loss)
     loss[0] = L;
 }
 
+// dL/dhead = jump[n] dL/dpred (the prediction is u + jump head)
 __global__ __launch_bounds__(256) void mse_grad_kernel(const float* p0, const float* p1, const float* p2,
                                                        const float* t0, const float* t1, const float* t2,
-                                                       const double* loss, float* grad, size_t total)
+                                                       const double* loss, const float* jump, int P, float* grad,
+                                                       size_t total)
 {
     const float k0 = (float)loss[1], k1 = (float)loss[2], k2 = (float)loss[3];
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (size_t)gridDim.x * 256) {
-        grad[3 * i] = k0 * (p0[i] - t0[i]);
-        grad[3 * i + 1] = k1 * (p1[i] - t1[i]);
-        grad[3 * i + 2] = k2 * (p2[i] - t2[i]);
+        const float dt = jump[i / P];
+        grad[3 * i] = dt * (k0 * (p0[i] - t0[i]));
+        grad[3 * i + 1] = dt * (k1 * (p1[i] - t1[i]));
+        grad[3 * i + 2] = dt * (k2 * (p2[i] - t2[i]));
     }
 }
 
@@ -711,12 +714,13 @@ hipError_t assemble_input(const float* c, const float* phi, const float* rho, co
     return hipGetLastError();
 }
 
-hipError_t residual_out(const float* head, const float* c, const float* phi, const float* rho, float* oc, float* ophi,
-                        float* orho, int N, int P, hipStream_t s)
+hipError_t residual_out(const float* head, const float* jump, const float* c, const float* phi, const float* rho,
+                        float* oc, float* ophi, float* orho, int N, int P, hipStream_t s)
 {
     const size_t n = (size_t)N * P;
     if (!n) return hipSuccess;
-    hipLaunchKernelGGL(residual_kernel, dim3(grid_for(n)), dim3(256), 0, s, head, c, phi, rho, oc, ophi, orho, n);
+    hipLaunchKernelGGL(residual_kernel, dim3(grid_for(n)), dim3(256), 0, s, head, jump, c, phi, rho, oc, ophi, orho,
+                       P, n);
     return hipGetLastError();
 }
 
@@ -742,14 +746,15 @@ hipError_t mlp_backward(const MLPArgs& a, hipStream_t s)
 size_t rel_mse_partial_doubles() { return (size_t)kLossBlocks * 6; }
 
 hipError_t rel_mse(const float* pc, const float* pphi, const float* prho, const float* tc, const float* tphi,
-                   const float* trho, float* grad, double* part, double* loss, int N, int P, hipStream_t s)
+                   const float* trho, const float* jump, float* grad, double* part, double* loss, int N, int P,
+                   hipStream_t s)
 {
     const size_t n = (size_t)N * P;
     hipLaunchKernelGGL(mse_part_kernel, dim3(kLossBlocks), dim3(256), 0, s, pc, pphi, prho, tc, tphi, trho, part, n);
     hipLaunchKernelGGL(mse_finish_kernel, dim3(1), dim3(64), 0, s, part, loss);
     if (grad && n)
         hipLaunchKernelGGL(mse_grad_kernel, dim3(grid_for(n)), dim3(256), 0, s, pc, pphi, prho, tc, tphi, trho, loss,
-                           grad, n);
+                           jump, P, grad, n);
     return hipGetLastError();
 }
 

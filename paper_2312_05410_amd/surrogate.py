@@ -166,8 +166,12 @@ def dns_run(seed: int = TEST_SEED, steps: int = BLEND_STEPS, dt_factor: float = 
 
     from ._lib import Simulator
 
-    sim = Simulator(blend_params(seed, n=n, dt_factor=dt_factor))
+    from ._lib import dt_limit
+
+    # the same physical time as `steps` steps at 0.2 of the limit, exactly
+    p = blend_params(seed, n=n)
     nsteps = int(round(steps * 0.2 / dt_factor))
+    sim = Simulator(p.replace(dt=steps * 0.2 * dt_limit(p) / nsteps))
     rec = {}
     e0, e1 = _events()
     e0.record()
@@ -224,3 +228,67 @@ def blended_run(net, seed: int = TEST_SEED, steps: int = BLEND_STEPS, dns_block:
     ms = e0.elapsed_time(e1)
     sim.close()
     return state, ms, rec
+
+
+def compare(net, seed: int = TEST_SEED, steps: int = BLEND_STEPS, dt_factors=(0.4, 0.6, 0.8, 0.95),
+            reps: int = 3, n: int = BLEND_N, log=print):
+    """The blended runs ("leap", "chain") and plain DNS at larger time steps,
+    all judged against plain DNS at 0.2 of the stability limit from the same
+    seeded initial condition: final-state relative L2 of each field, relative
+    L2 of the phase-A autocorrelation S2 and of its radial average, and the
+    best of `reps` timed runs.  "At fixed error": the fastest plain DNS whose
+    S2 error does not exceed the blended run's."""
+    from . import metrics as M
+
+    ref, ms_ref, _ = dns_run(seed, steps, 0.2, n)
+    ms_ref = min([ms_ref] + [dns_run(seed, steps, 0.2, n)[1] for _ in range(reps - 1)])
+    s2_ref = M.s2(M.phase_indicator(ref[0][0], ref[1][0]))
+    ra_ref = M.radial_average(s2_ref, n // 4)
+
+    def errors(st):
+        s2 = M.s2(M.phase_indicator(st[0][0], st[1][0]))
+        return {"c": M.rel_l2(st[0], ref[0]), "phi": M.rel_l2(st[1], ref[1]), "rho": M.rel_l2(st[2], ref[2]),
+                "S2": M.rel_l2(s2, s2_ref), "S2_radial": M.rel_l2(M.radial_average(s2, n // 4), ra_ref)}
+
+    out = {"steps": steps, "n": n, "seed": seed, "dns_ms": round(ms_ref, 3), "runs": {}}
+    for mode in ("leap", "chain"):
+        st, ms, _ = blended_run(net, seed, steps, mode=mode, n=n)
+        ms = min([ms] + [blended_run(net, seed, steps, mode=mode, n=n)[1] for _ in range(reps - 1)])
+        out["runs"][f"blend_{mode}"] = {"ms": round(ms, 3), "errors": errors(st)}
+        if log:
+            log(f"blended {mode}: {ms:.2f} ms {out['runs'][f'blend_{mode}']['errors']}")
+    for f in dt_factors:
+        st, ms, _ = dns_run(seed, steps, f, n)
+        ms = min([ms] + [dns_run(seed, steps, f, n)[1] for _ in range(reps - 1)])
+        out["runs"][f"dns_{f}"] = {"ms": round(ms, 3), "errors": errors(st)}
+        if log:
+            log(f"dns dt {f}: {ms:.2f} ms {out['runs'][f'dns_{f}']['errors']}")
+    b = out["runs"]["blend_leap"]
+    ok = [r for k, r in out["runs"].items() if k.startswith("dns_") and r["errors"]["S2"] <= b["errors"]["S2"]]
+    best = min([ms_ref] + [r["ms"] for r in ok])
+    out["speedup_same_dt"] = round(ms_ref / b["ms"], 3)
+    out["speedup_fixed_error"] = round(best / b["ms"], 3)
+    return out
+
+
+def error_curve(net, seed: int = TEST_SEED, steps: int = BLEND_STEPS, n: int = BLEND_N, mode: str = "leap",
+                dt_factor_dns: float = 0.8):
+    """S2 relative L2 error at every blended cycle boundary for the blended
+    run and for plain DNS at dt_factor_dns, against DNS at 0.2."""
+    from . import metrics as M
+
+    _, _, rec_b = blended_run(net, seed, steps, mode=mode, n=n, record=True)
+    ts = sorted(rec_b)
+    cyc = BLEND_DNS + BLEND_JUMPS * JUMP
+    _, _, rec_ref = dns_run(seed, steps, 0.2, n, record_every=cyc)
+    _, _, rec_d = dns_run(seed, steps, dt_factor_dns, n, record_every=cyc)
+    rows = []
+    for t in ts:
+        if t not in rec_ref:
+            continue
+        r = rec_ref[t]
+        s2r = M.s2(M.phase_indicator(r[0][0], r[1][0]))
+        e = lambda st: M.rel_l2(M.s2(M.phase_indicator(st[0][0], st[1][0])), s2r)
+        rows.append((t, e(rec_b[t]), e(rec_d[t]) if t in rec_d else float("nan"),
+                     M.rel_l2(rec_b[t][0], r[0])))
+    return rows

@@ -37,7 +37,9 @@ def test_params_struct_layout():
     assert _lib.PFParamsC.seed.offset == 48
     assert _lib.PFParamsC.h.offset == 56
     assert _lib.PFParamsC.v0_per.offset == 56 + 21 * 8
-    assert ctypes.sizeof(_lib.PFParamsC) == 56 + 21 * 8 + 16
+    assert _lib.PFParamsC.integrator.offset == 44
+    assert _lib.PFParamsC.interface_noise.offset == 56 + 21 * 8 + 16
+    assert ctypes.sizeof(_lib.PFParamsC) == 56 + 21 * 8 + 24
 
 
 def test_strerror():
@@ -185,3 +187,51 @@ def test_unet_ops_reject_bad_arguments():
     assert L.unet_groupnorm_fwd(1, 16, 300, 3, 1e-5, 1, fake, fake, fake, None, fake, None, fake, fake, 1 << 20,
                                 None) == _lib.PF_EINVAL
     assert L.unet_maxpool_fwd(1, 5, 4, 8, fake, fake, None) == _lib.PF_EINVAL
+
+
+def test_c_struct_layouts_match_the_bindings(tmp_path):
+    """Compile a probe against include/*.h with the host C compiler and
+    compare every field offset and struct size with the ctypes mirrors."""
+    import subprocess
+
+    from paper_2312_05410_amd import unet
+
+    probes = [("pf_params", "pf.h", _lib.PFParamsC), ("unet_config", "unet.h", unet.UNetConfigC),
+              ("unet_param_desc", "unet.h", unet.ParamDescC)]
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "pf.h"', '#include "unet.h"', "int main(void) {"]
+    for cname, _, cls in probes:
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _t in cls._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = {}
+    for line in subprocess.check_output([str(exe)], text=True).splitlines():
+        name, field, val = line.split()
+        got[(name, field)] = int(val)
+    for cname, _, cls in probes:
+        assert got[(cname, "size")] == ctypes.sizeof(cls), cname
+        for f, _t in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
+
+
+@pytest.mark.parametrize("bad", [dict(integrator=2), dict(interface_noise=-0.1), dict(interface_noise=2.0)])
+def test_variant_params_validated(bad):
+    L = _lib.load()
+    s, keep = _lib.to_c(PFParams(nx=16, ny=16))
+    for k, v in bad.items():
+        setattr(s, k, v)
+    assert L.pf_workspace_bytes(ctypes.byref(s)) == 0
+
+
+def test_variants_need_the_single_step_kernel():
+    L = _lib.load()
+    s, keep = _lib.to_c(PFParams(nx=16, ny=16, integrator="midpoint"), temporal_block=2)
+    assert L.pf_workspace_bytes(ctypes.byref(s)) == 0
+    s, keep = _lib.to_c(PFParams(nx=16, ny=16, interface_noise=0.1), temporal_block=3)
+    assert L.pf_workspace_bytes(ctypes.byref(s)) == 0
+    s, keep = _lib.to_c(PFParams(nx=16, ny=16, integrator="midpoint", interface_noise=0.1), temporal_block=1)
+    assert L.pf_workspace_bytes(ctypes.byref(s)) > 0
