@@ -32,6 +32,10 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published
 BYTES_PER_LUP = {"f32": 24, "f64": 48}   # read + write c, phi, rho
+# explicit midpoint: the first stage reads the state and writes the midpoint
+# (6 words per cell), the second reads the midpoint and the base state and
+# writes the new state in place (9 words per cell)
+MIDPOINT_WORDS = (6, 9)
 
 
 def parse():
@@ -41,6 +45,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=None)
     ap.add_argument("--workload", default="dns_1024_f32",
                     choices=["dns_1024_f32", "dns_8192_f32", "batched_32x512_f32", "dns_small_128_f64",
+                             "midpoint_1024_f32", "interface_1024_f32",
                              "adjoint_256_f32", "unet_512_bf16", "blended_512_f32"])
     ap.add_argument("--temporal-block", type=int, default=None)
     ap.add_argument("--graph-mode", type=int, default=0, help="0: replay HIP graphs of launches; 1: plain launches")
@@ -61,6 +66,11 @@ def make_params(name: str):
         return workloads.dns_production(0, n=8192), workloads.STEPS[name]
     if name == "batched_32x512_f32":
         return workloads.batched(0), workloads.STEPS[name]
+    if name == "midpoint_1024_f32":
+        return workloads.dns_production(0).replace(integrator="midpoint"), workloads.STEPS["dns_1024_f32"]
+    if name == "interface_1024_f32":
+        return (workloads.dns_production(0).replace(interface_noise=workloads.INTERFACE_SIGMA),
+                workloads.STEPS["dns_1024_f32"])
     return workloads.dns_small(0, "f64"), workloads.STEPS[name]
 
 
@@ -92,11 +102,13 @@ def launches_for(steps: int, K: int) -> int:
     return L
 
 
-def kernel_name(prec: str, K: int, rows: int) -> str:
+def kernel_name(prec: str, K: int, rows: int, base: bool = False, noise: bool = False) -> str:
     t = "float" if prec == "f32" else "double"
     if K == 1:
         ahead = rows + 1 if rows <= 8 else 4      # load look-ahead rows of the strip-march kernel
-        return f"march_kernel<{t}, {rows}, {ahead}>"
+        b = "true" if base else "false"           # second midpoint stage: update added to a base state
+        d = "true" if noise else "false"          # interface composition draws
+        return f"march_kernel<{t}, {rows}, {ahead}, {b}, {d}>"
     return f"step_kernel<{t}, {K}, {rows}>"
 
 
@@ -318,7 +330,7 @@ def unet_leg(args):
                       "inference_tflops_batch1": round(fwd / (infer_ms / 1e3) / 1e12, 1)},
            "roofline": {"bound": "mfma", "achieved": round(achieved, 1), "peak": MFMA_BF16_PEAK_TFLOPS,
                         "unit": "TFLOP/s", "frac": round(achieved / MFMA_BF16_PEAK_TFLOPS, 4), "traffic": None,
-                        "kernel": "gemm32_kernel<0, 4, 2, 4, 1> (conv3x3 64->32, 5 x 512^2)",
+                        "kernel": "conv3_lds_kernel<0, 2, 8, 32> (conv3x3 64->32, 5 x 512^2)",
                         "avg_launch_us": round(conv_s * 1e6, 2), "flops_per_launch": conv_flops}}
     if not args.no_cpu:
         res["cpu_baseline"] = unet_cpu_leg(cfg, args.cpu_seconds)
@@ -405,10 +417,19 @@ def main():
 
     g = gpu_leg(args, p, steps, warmup, K)
     cells = p.nx * p.ny * p.batch
+    noise = p.interface_noise > 0
+    if p.integrator == "midpoint":
+        # two launches per step; the roofline is that of the pair
+        word = BYTES_PER_LUP[prec] // 6
+        g["launches"] = 2 * steps
+        bytes_per_launch = sum(MIDPOINT_WORDS) * word * cells / 2
+        kname = (kernel_name(prec, 1, g["rows"]) + " + " +
+                 kernel_name(prec, 1, g["rows"], base=True, noise=noise))
+    else:
+        bytes_per_launch = BYTES_PER_LUP[prec] * cells * steps / g["launches"]
+        kname = kernel_name(prec, g["K"], g["rows"], noise=noise)
     launch_s = g["seconds"] / g["launches"]
-    bytes_per_launch = BYTES_PER_LUP[prec] * cells * steps / g["launches"]
     achieved = bytes_per_launch / launch_s / 1e9
-    kname = kernel_name(prec, g["K"], g["rows"])
     tb = measured_traffic(args.workload, kname)
     traffic = None if tb is None else round(tb / launch_s / 1e9, 1)
     result = {
@@ -428,7 +449,8 @@ def main():
                    "steps_total": total_steps, "temporal_block": g["K"], "tile_rows": g["rows"],
                    "launches": g["launches"],
                    "graph_mode": args.graph_mode,
-                   "seed": p.seed, "dt": None},
+                   "seed": p.seed, "dt": None, "integrator": p.integrator,
+                   "interface_noise": p.interface_noise},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": kname,
@@ -437,7 +459,7 @@ def main():
                      "traffic_bytes_per_launch": None if tb is None else int(tb)},
         "host_wall_s": round(g["wall"], 4),
     }
-    if not args.no_sweep and prec == "f32":
+    if not args.no_sweep and prec == "f32" and args.workload == "dns_1024_f32":
         result["size_sweep"] = sweep(K, args.graph_mode)
     if not args.no_cpu:
         result["cpu_baseline"] = cpu_leg(p, args.cpu_seconds)

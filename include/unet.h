@@ -9,7 +9,9 @@
  * two-layer sin MLP of the time step.  The output head is GN(conv(block)).
  * Training follows "Training of the network" (Adam) with the relative
  * squared error of "Error metrics".  Readings where the paper is silent:
- *   - input channels (c, phi, rho, jump length dt); the head gives the three
+ *   - input channels (c - 1/2, phi, rho - 1, jump length dt), centred so
+ *     that BF16 keeps the small composition and vapour-density fluctuations;
+ *     the head gives the three
  *     fields' mean rate over the leap: u(t+dt) = u(t) + dt head (the
  *     head's normalisation fixes its overall scale, the increment grows
  *     with dt);

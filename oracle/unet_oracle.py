@@ -9,7 +9,7 @@ Every function follows one passage of the paper's Materials and Methods
 plain tensor operations on NCHW float64 tensors.  Gradients are those of
 torch.autograd on this forward.  Readings where the paper is silent (they
 match the GPU library's documented interface):
-  * input channels (c, phi, rho, jump map); the head gives the fields' mean
+  * input channels (c - 1/2, phi, rho - 1, jump map); the head gives the fields' mean
     rate over the leap: prediction = state + jump * head;
   * 3x3 convolutions, zero padding, no bias; transposed convolutions
     without bias;
@@ -132,7 +132,7 @@ class Net:
         R = self.R
         c, phi, rho, jump = (_t(a, self.dtype) for a in (c, phi, rho, jump))
         n, H, W = c.shape
-        x = R(torch.stack([c, phi, rho, jump.view(n, 1, 1).expand(n, H, W)], dim=1))
+        x = R(torch.stack([c - 0.5, phi, rho - 1.0, jump.view(n, 1, 1).expand(n, H, W)], dim=1))
         f = time_basis(jump, self.p)
         zs = []
         h = x

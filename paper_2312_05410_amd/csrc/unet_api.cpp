@@ -45,21 +45,22 @@ bool cfg_ok(const unet_config* c)
     return true;
 }
 
-// Wgrad partial products: pixel chunks chosen for about 1024 blocks.
-int wgrad_chunk(long P, int taps, int Nout, int K)
+// Wgrad partial products: pixel chunks (multiples of 64, the staged
+// kernel's step) chosen for about 1024 blocks.
+int wgrad_chunk(long P, int taps, int Nout, int C1, int C2)
 {
-    const long tiles = (long)taps * ((Nout + 63) / 64) * ((K + 63) / 64);
+    const long tiles = wgrad_blocks_per_chunk(taps == 9 ? kConvFwd : kUpFwd, Nout, C1, C2);
     long chunks = std::max(1L, (1024 + tiles - 1) / tiles);
     chunks = std::min(chunks, std::max(1L, (P + 255) / 256));
     long ch = (P + chunks - 1) / chunks;
-    ch = (ch + 15) / 16 * 16;
-    return (int)std::max(16L, ch);
+    ch = (ch + 63) / 64 * 64;
+    return (int)std::max(64L, ch);
 }
-size_t wgrad_floats(long P, int taps, int Nout, int K)
+size_t wgrad_floats(long P, int taps, int Nout, int C1, int C2)
 {
-    const long ch = wgrad_chunk(P, taps, Nout, K);
+    const long ch = wgrad_chunk(P, taps, Nout, C1, C2);
     const long chunks = (P + ch - 1) / ch;
-    return (size_t)chunks * taps * Nout * K;
+    return (size_t)chunks * taps * Nout * (C1 + C2);
 }
 
 // ------------------------------------------------------------------ plan
@@ -225,7 +226,7 @@ void carve(Net& net, char* base, Bufs& b)
         b.dz[l] = l < L - 1 ? m.take<float>(Pl * w[l]) : nullptr;
         note_gn(net.P(l, 1), w[l], c.groups);
         const Conv& k = net.enc[l];
-        part = std::max(part, wgrad_floats(Pl, 9, k.cout, k.cin1));
+        part = std::max(part, wgrad_floats(Pl, 9, k.cout, k.cin1, 0));
     }
     {
         const long Pm = net.P(L - 1, n);
@@ -234,7 +235,7 @@ void carve(Net& net, char* base, Bufs& b)
         b.stm = m.take<float>((size_t)n * c.groups * 2);
         b.dym = m.take<uint16_t>(Pm * w[L - 1]);
         b.dad[L - 1] = m.take<float>(Pm * w[L - 1]);
-        part = std::max(part, wgrad_floats(Pm, 9, w[L - 1], w[L - 1]));
+        part = std::max(part, wgrad_floats(Pm, 9, w[L - 1], w[L - 1], 0));
     }
     for (int l = 0; l < L - 1; ++l) {
         const long Pl = net.P(l, n);
@@ -245,8 +246,8 @@ void carve(Net& net, char* base, Bufs& b)
         b.dad[l] = m.take<float>(Pl * w[l]);
         b.dyd[l] = m.take<uint16_t>(Pl * w[l]);
         b.dd[l] = m.take<uint16_t>(Pl * w[l]);
-        part = std::max(part, wgrad_floats(Pl, 9, w[l], 2 * w[l]));
-        part = std::max(part, wgrad_floats(net.P(l + 1, n), 1, 4 * w[l], w[l + 1]));
+        part = std::max(part, wgrad_floats(Pl, 9, w[l], w[l], w[l]));
+        part = std::max(part, wgrad_floats(net.P(l + 1, n), 1, 4 * w[l], w[l + 1], 0));
     }
     {
         const long P0 = net.P(0, n);
@@ -256,7 +257,7 @@ void carve(Net& net, char* base, Bufs& b)
         b.gout = m.take<float>(P0 * c.out_ch);
         b.dyh = m.take<uint16_t>(P0 * c.out_ch);
         note_gn(net.P(0, 1), c.out_ch, c.head_groups);
-        part = std::max(part, wgrad_floats(P0, 9, c.out_ch, w[0]));
+        part = std::max(part, wgrad_floats(P0, 9, c.out_ch, w[0], 0));
     }
     b.jump = m.take<float>((size_t)n);
     b.h0 = m.take<float>((size_t)n * Hd);
@@ -409,7 +410,7 @@ WgradArgs wgrad_args(unet_handle* h, int n, int H, int W, const uint16_t* dy, in
     a.C1 = C1;
     a.C2 = C2;
     a.Nout = Nout;
-    a.chunk = wgrad_chunk((long)n * H * W, taps, Nout, C1 + C2);
+    a.chunk = wgrad_chunk((long)n * H * W, taps, Nout, C1, C2);
     return a;
 }
 
@@ -455,12 +456,11 @@ MLPArgs mlp_args(unet_handle* h, int n, const float* jump)
 // split evenly into its blocks.
 int conv_gn(unet_handle* h, ConvArgs a, int mode, GNArgs g)
 {
-    const int rows = conv_stat_rows(a, mode);
-    const long Ps = (long)a.H * a.W;
-    if (rows > 0 && Ps % rows == 0) {
+    const int chunks = conv_stat_chunks(a, mode);
+    if (chunks > 0) {
         a.gsum = h->b.csum;
         g.sums_ready = 1;
-        g.chunks = (int)(Ps / rows);
+        g.chunks = chunks;
     }
     UCHECK(conv_gemm(a, mode, h->stream));
     UCHECK(gn_forward(g, h->stream));
@@ -874,8 +874,8 @@ int unet_conv3x3_wgrad(int n, int H, int W, const uint16_t* dy, int Cout, const 
     a.C1 = C1;
     a.C2 = C2;
     a.Nout = Cout;
-    a.chunk = wgrad_chunk(P, 9, Cout, C1 + C2);
-    a.partial = ws.take<float>(wgrad_floats(P, 9, Cout, C1 + C2));
+    a.chunk = wgrad_chunk(P, 9, Cout, C1, C2);
+    a.partial = ws.take<float>(wgrad_floats(P, 9, Cout, C1, C2));
     if (!ws.ok) return PF_EINVAL;
     UCHECK(conv_wgrad(a, kConvFwd, dw, 0, (hipStream_t)stream));
     return PF_OK;
@@ -949,8 +949,8 @@ int unet_up_wgrad(int n, int H, int W, const uint16_t* dy, int Cout, const uint1
     a.W = W;
     a.C1 = Cin;
     a.Nout = 4 * Cout;
-    a.chunk = wgrad_chunk(P, 1, 4 * Cout, Cin);
-    a.partial = ws.take<float>(wgrad_floats(P, 1, 4 * Cout, Cin));
+    a.chunk = wgrad_chunk(P, 1, 4 * Cout, Cin, 0);
+    a.partial = ws.take<float>(wgrad_floats(P, 1, 4 * Cout, Cin, 0));
     if (!ws.ok) return PF_EINVAL;
     UCHECK(conv_wgrad(a, kUpFwd, dw, 0, (hipStream_t)stream));
     return PF_OK;

@@ -19,9 +19,9 @@
 // NHWC pixel or of a weight row; the FP32 result of lane l holds rows
 // 4 (l / 16) .. +3 of column l % 16.
 //
-// Weight gradients reduce over pixels: wgrad_kernel forms partial products
-// over fixed pixel chunks with the same MFMA shape (k = 16 pixels) and
-// wsum_kernel adds the chunks in index order, so results are deterministic.
+// Weight gradients reduce over pixels: the wgrad kernels form partial
+// products over fixed pixel chunks and wsum_kernel adds the chunks in a fixed
+// order that depends only on the shapes, so results are deterministic.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -335,6 +335,170 @@ __global__ __launch_bounds__(256) void gemm32_kernel(ConvArgs a)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Halo-tile variant of the 3x3 convolution (forward and input gradient) for
+// channel counts that are multiples of 32.  A block owns a TH x TW pixel
+// tile of one sample and TN x 16 output channels; for every 32-channel chunk
+// of the input the (TH + 2) x (TW + 2) halo and the chunk's weights of all
+// nine taps are staged in LDS once (each 64-byte row padded to 80 so that
+// the MFMA-layout 16-byte reads of 8 consecutive rows fall in distinct
+// banks) and every tap reads its operands from there; the next chunk is
+// loaded into registers while the current one is used.  Wave w takes tile rows TH/4 w .. and their TW/16 16-pixel
+// segments (TM = TH/4 * TW/16 operand tiles).
+constexpr int kLdsPix = 40;  // BF16 elements per staged pixel (32 + 8 pad)
+
+template <int MODE, int TN, int TH, int TW>
+__global__ __launch_bounds__(256) void conv3_lds_kernel(ConvArgs a)
+{
+    constexpr int HP = TH + 2, WP = TW + 2, NPX = HP * WP;
+    constexpr int SEG = TW / 16, TM = (TH / 4) * SEG;
+    constexpr int NA = NPX * 4;             // 16-byte halo pieces per chunk
+    constexpr int NB = 9 * TN * 16 * 4;     // 16-byte weight pieces per chunk
+    constexpr int NLD = (NA + NB + 255) / 256;
+    // one chunk's halo [NPX][kLdsPix] and weights [9][TN 16][kLdsPix]
+    __shared__ __align__(16) uint16_t lds[(NPX + 9 * TN * 16) * kLdsPix];
+    uint16_t* const wl = lds + NPX * kLdsPix;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, tid = threadIdx.x;
+    const int r = lane & 15, kq = (lane >> 4) * 8;
+    const int tx = (a.W + TW - 1) / TW, ty = (a.H + TH - 1) / TH;
+    const int tpb = tx * ty;
+    const int n = blockIdx.x / tpb, t = blockIdx.x - n * tpb;
+    const int y0 = (t / tx) * TH, x0 = (t % tx) * TW;
+    const int on = blockIdx.y * (TN * 16);
+    const int K = a.C1 + a.C2, nk = K / 32;
+    // this lane's operand pixel in each of its TM tiles (tile coordinates)
+    int ry[TM], cx[TM];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+        ry[i] = wv * (TH / 4) + i / SEG;
+        cx[i] = (i % SEG) * 16 + r;
+    }
+    f32x4 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+
+    // piece e < NA: halo pixel e / 4, channels 8 (e % 4) ..; else weight row
+    // (tap, o) = (e - NA) / 4 of the chunk, k = 8 ((e - NA) % 4) ..
+    uint4 stage[NLD];
+    auto gload = [&](int kc) {
+        const int k0 = kc * 32;
+        const bool first = k0 < a.C1;
+        const uint16_t* src = first ? a.in1 : a.in2;
+        const int C = first ? a.C1 : a.C2, c0 = first ? k0 : k0 - a.C1;
+#pragma unroll
+        for (int u = 0; u < NLD; ++u) {
+            const int e = tid + 256 * u;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (e < NA) {
+                const int px = e >> 2, q = e & 3;
+                const int gy = y0 - 1 + px / WP, gx = x0 - 1 + px % WP;
+                if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W)
+                    v = *(const uint4*)(src + (((long)n * a.H + gy) * a.W + gx) * C + c0 + 8 * q);
+            } else if (e < NA + NB) {
+                const int row = (e - NA) >> 2, q = (e - NA) & 3;
+                const int tap = row / (TN * 16), o = row - tap * (TN * 16);
+                v = *(const uint4*)(a.Wt + ((size_t)tap * a.ldo + on + o) * a.ldk + k0 + 8 * q);
+            }
+            stage[u] = v;
+        }
+    };
+    auto lstore = [&]() {
+#pragma unroll
+        for (int u = 0; u < NLD; ++u) {
+            const int e = tid + 256 * u;
+            if (e < NA + NB) *(uint4*)(&lds[(e >> 2) * kLdsPix + 8 * (e & 3)]) = stage[u];
+        }
+    };
+    gload(0);
+    for (int kc = 0; kc < nk; ++kc) {
+        if (kc) __syncthreads();   // every wave is done with the previous chunk
+        lstore();
+        __syncthreads();
+        if (kc + 1 < nk) gload(kc + 1);
+#pragma unroll
+        for (int tap = 0; tap < 9; ++tap) {
+            int dy = tap / 3 - 1, dx = tap % 3 - 1;
+            if (MODE == kConvDgrad) {
+                dy = -dy;
+                dx = -dx;
+            }
+            bf16x8 B[TN], A[TM];
+#pragma unroll
+            for (int j = 0; j < TN; ++j) B[j] = *(const bf16x8*)(&wl[(tap * TN * 16 + 16 * j + r) * kLdsPix + kq]);
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+                A[i] = *(const bf16x8*)(&lds[((ry[i] + 1 + dy) * WP + cx[i] + 1 + dx) * kLdsPix + kq]);
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[i], B[j], acc[i][j], 0, 0, 0);
+        }
+    }
+    __syncthreads();   // LDS is reused by the epilogue's reduction
+    // acc[i][j][e]: pixel (ry[i], segment base + 4 (lane / 16) + e), channel on + 16 j + r
+    const int rq = (lane >> 4) * 4;
+    float s1[TN], s2[TN];
+#pragma unroll
+    for (int j = 0; j < TN; ++j) s1[j] = s2[j] = 0.f;
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+        const int o = on + 16 * j + r;
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int y = y0 + ry[i], x = x0 + (i % SEG) * 16 + rq + e;
+                if (o >= a.Nout || y >= a.H || x >= a.W) continue;
+                const float v = acc[i][j][e];
+                s1[j] += v;
+                s2[j] = fmaf(v, v, s2[j]);
+                const size_t p = ((size_t)n * a.H + y) * a.W + x;
+                if (o < a.O1) {
+                    const size_t idx = p * a.O1 + o;
+                    if (a.out_f32) a.out_f32[idx] = v;
+                    if (a.out_bf16) a.out_bf16[idx] = f2bf(v);
+                } else {
+                    const size_t idx = p * (a.Nout - a.O1) + (o - a.O1);
+                    if (a.out2_f32) a.out2_f32[idx] = v;
+                    if (a.out2_bf16) a.out2_bf16[idx] = f2bf(v);
+                }
+            }
+    }
+    if (MODE == kConvFwd && a.gsum) {
+        // per-channel sums over the tile: the 4 lane groups, then the 4 waves
+        // in order (LDS reused after the barrier that ended the main loop)
+        float* red = (float*)&lds[0];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            float u1 = s1[j], u2 = s2[j];
+            u1 += __shfl_xor(u1, 16);
+            u2 += __shfl_xor(u2, 16);
+            u1 += __shfl_xor(u1, 32);
+            u2 += __shfl_xor(u2, 32);
+            if (lane < 16) {
+                red[(wv * TN * 16 + 16 * j + r) * 2] = u1;
+                red[(wv * TN * 16 + 16 * j + r) * 2 + 1] = u2;
+            }
+        }
+        __syncthreads();
+        for (int c = tid; c < TN * 16; c += 256) {
+            const int o = on + c;
+            if (o >= a.Nout) continue;
+            float u1 = 0.f, u2 = 0.f;
+            for (int w = 0; w < 4; ++w) {
+                u1 += red[(w * TN * 16 + c) * 2];
+                u2 += red[(w * TN * 16 + c) * 2 + 1];
+            }
+            float* g = a.gsum + (((size_t)n * a.Nout + o) * tpb + t) * 2;
+            g[0] = u1;
+            g[1] = u2;
+        }
+    }
+}
+
 // Partial weight gradient over one pixel chunk: rows o (output channels),
 // columns k (input channels), k-dimension = 16 pixels per MFMA.
 // blockIdx.z = chunk * taps + tap.
@@ -398,14 +562,202 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a)
         }
 }
 
-__global__ __launch_bounds__(256) void wsum_kernel(const float* partial, float* dW, size_t n, int chunks,
-                                                   int accumulate)
+// Staged weight gradient: per 64-pixel step the block loads dy[64 pixels][64 o]
+// and x[64 pixels][64 k] (x at the tap's shifted pixel, zero outside) and
+// stores them transposed in LDS ([channel][pixel], rows padded by 8
+// elements), so each lane's MFMA operand (8 consecutive pixels of one
+// channel) is one 16-byte read; each wave forms a 32 x 32 sub-tile with
+// 2 x 2 v_mfma_f32_16x16x32_bf16 per 32 pixels.  A thread stages two
+// adjacent pixels of one 8-channel group and writes each channel's pair as
+// one 32-bit word: the 32 pairs of a wave land in 32 consecutive banks and
+// the wave's second channel group 32 banks further (row pitch 36 words), so
+// the transposition is free of bank conflicts.  The next step's operands are
+// loaded into registers while the current step is multiplied.  VEC: all
+// channel counts are multiples of 8 and rows 16-byte aligned (16-byte loads);
+// else 8 guarded 2-byte loads per piece.  FOLD (3x3 layers with fewer than
+// 8 channels on one side): 1 folds the nine taps into the input-channel
+// side (row k' = 9-tap index * K + c of x at the tap's shifted pixel), 2 into
+// the output side (row o' = tap * Nout + o of dy at the pixel shifted back,
+// which pairs the same products); one block then covers all taps.
+// blockIdx.z = chunk * taps + tap (taps = 9 unfolded 3x3, else 1).
+constexpr int kWgStep = 64;                // pixels per step
+constexpr int kWgRow = kWgStep + 8;        // LDS row length (elements)
+
+template <int MODE, bool VEC, int FOLD>
+__global__ __launch_bounds__(256) void wgrad32_kernel(WgradArgs a)
 {
-    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
-        float s = 0.f;
-        for (int c = 0; c < chunks; ++c) s += partial[(size_t)c * n + i];
-        dW[i] = accumulate ? dW[i] + s : s;
+    __shared__ __align__(16) uint16_t As[64 * kWgRow];
+    __shared__ __align__(16) uint16_t Bs[64 * kWgRow];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int o0 = blockIdx.x * 64, k0 = blockIdx.y * 64;
+    constexpr int ntaps = MODE == kConvFwd && FOLD == 0 ? 9 : 1;
+    const int tap = (int)(blockIdx.z % ntaps), chunk = (int)(blockIdx.z / ntaps);
+    const int dy = ntaps == 9 ? tap / 3 - 1 : 0, dx = ntaps == 9 ? tap % 3 - 1 : 0;
+    const int P = a.N * a.H * a.W, K = a.C1 + a.C2;
+    const int Ko = FOLD == 1 ? 9 * K : K, No = FOLD == 2 ? 9 * a.Nout : a.Nout;
+    const int pb = chunk * a.chunk, pe = min(P, pb + a.chunk);
+    // staging: pixels p0 + 2 pp + u (u = 0, 1), channels sg .. sg + 7
+    const int pp = tid & 31, sg = (tid >> 5) * 8;
+    const int wo = (wv & 1) * 32, wk = (wv >> 1) * 32;
+    const int r = lane & 15, kq = (lane >> 4) * 8;
+    f32x4 acc[2][2] = {};
+
+    auto piece = [&](const uint16_t* base, int C, int c, bool ok) {
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (!ok) return v;
+        if (VEC) return *(const uint4*)(base + c);
+        uint16_t* e = (uint16_t*)&v;
+        for (int j = 0; j < 8; ++j)
+            if (c + j < C) e[j] = base[c + j];
+        return v;
+    };
+    // folded rows: element j of the group is row g + j = t * C + c of the
+    // field at pixel (y + sy (t / 3 - 1), x + sy (t % 3 - 1)) of sample n
+    auto folded = [&](const uint16_t* f, int C, int g, const Pix& q, int sy) {
+        uint4 v = make_uint4(0, 0, 0, 0);
+        uint16_t* e = (uint16_t*)&v;
+        if (!q.ok) return v;
+        for (int j = 0; j < 8; ++j) {
+            const int row = g + j;
+            if (row >= 9 * C) break;
+            const int t = row / C, c = row - t * C;
+            const int yy = q.y + sy * (t / 3 - 1), xx = q.x + sy * (t % 3 - 1);
+            if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
+                e[j] = f[(((size_t)q.n * a.H + yy) * a.W + xx) * C + c];
+        }
+        return v;
+    };
+    uint4 va[2], vb[2];
+    auto gload = [&](int p0) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int p = p0 + 2 * pp + u;
+            const Pix q = pix(p, a.H, a.W, pe);
+            const int o = o0 + sg;
+            if (FOLD == 2) {
+                va[u] = folded(a.dy, a.Nout, o, q, -1);
+            } else if (MODE == kUpFwd) {
+                // o = (m, n, co): gradient pixel (2y + m, 2x + n); 8-runs stay in one m, n
+                const int Co = a.Nout >> 2, sub = o / Co, co = o - sub * Co;
+                const uint16_t* base =
+                    a.dy + (((size_t)q.n * 2 * a.H + 2 * q.y + (sub >> 1)) * 2 * a.W + 2 * q.x + (sub & 1)) * Co;
+                va[u] = piece(base, Co, co, q.ok && o < a.Nout);
+            } else {
+                va[u] = piece(a.dy + (size_t)p * a.Nout, a.Nout, o, q.ok && o < a.Nout);
+            }
+            const int k = k0 + sg;
+            if (FOLD == 1) {
+                vb[u] = folded(a.x1, a.C1, k, q, 1);
+            } else {
+                const int yy = q.y + dy, xx = q.x + dx;
+                const bool xin = q.ok && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W && k < K;
+                const size_t xo = ((size_t)q.n * a.H + yy) * a.W + xx;
+                if (k < a.C1) vb[u] = piece(a.x1 + xo * a.C1, a.C1, k, xin);
+                else vb[u] = piece(a.x2 + xo * a.C2, a.C2, k - a.C1, xin);
+            }
+        }
+    };
+    gload(pb);
+    for (int p0 = pb; p0 < pe; p0 += kWgStep) {
+        __syncthreads();  // the previous step's operands have been read
+        {
+            const uint32_t* a0 = (const uint32_t*)&va[0];
+            const uint32_t* a1 = (const uint32_t*)&va[1];
+            const uint32_t* b0 = (const uint32_t*)&vb[0];
+            const uint32_t* b1 = (const uint32_t*)&vb[1];
+            uint32_t* Aw = (uint32_t*)As;
+            uint32_t* Bw = (uint32_t*)Bs;
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                // channels sg + 2h (low halves) and sg + 2h + 1 (high halves) of both pixels
+                const int w0 = ((sg + 2 * h) * kWgRow) / 2 + pp, w1 = w0 + kWgRow / 2;
+                Aw[w0] = (a0[h] & 0xffffu) | (a1[h] << 16);
+                Aw[w1] = (a0[h] >> 16) | (a1[h] & 0xffff0000u);
+                Bw[w0] = (b0[h] & 0xffffu) | (b1[h] << 16);
+                Bw[w1] = (b0[h] >> 16) | (b1[h] & 0xffff0000u);
+            }
+        }
+        __syncthreads();
+        if (p0 + kWgStep < pe) gload(p0 + kWgStep);
+#pragma unroll
+        for (int s = 0; s < kWgStep; s += 32) {
+            bf16x8 A[2], B[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                A[h] = *(const bf16x8*)(&As[(wo + 16 * h + r) * kWgRow + s + kq]);
+                B[h] = *(const bf16x8*)(&Bs[(wk + 16 * h + r) * kWgRow + s + kq]);
+            }
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                for (int ni = 0; ni < 2; ++ni)
+                    acc[mi][ni] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mi], B[ni], acc[mi][ni], 0, 0, 0);
+        }
     }
+    // acc[mi][ni][e]: row o = o0 + wo + 16 mi + 4 (lane / 16) + e, column k = k0 + wk + 16 ni + r;
+    // partial layout per chunk [tap][Nout][K] (folded rows o' = t Nout + o map
+    // onto it directly; folded columns k' = t K + c are scattered)
+    constexpr int chunk_taps = MODE == kConvFwd ? 9 : 1;
+    float* part = a.partial + ((size_t)chunk * chunk_taps + tap) * a.Nout * K;
+    const int rq = (lane >> 4) * 4;
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int ni = 0; ni < 2; ++ni) {
+            const int kk = k0 + wk + 16 * ni + r;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int oo = o0 + wo + 16 * mi + rq + e;
+                if (oo >= No || kk >= Ko) continue;
+                if (FOLD == 1) {
+                    const int t = kk / K, c = kk - t * K;
+                    part[((size_t)t * a.Nout + oo) * K + c] = acc[mi][ni][e];
+                } else {
+                    part[(size_t)oo * K + kk] = acc[mi][ni][e];
+                }
+            }
+        }
+}
+
+// Sum of the per-chunk partials: a block owns 64 consecutive outputs
+// (coalesced rows) and splits the chunks over blockDim.y lanes (chunk c goes
+// to lane c mod blockDim.y), whose sums are combined by a fixed LDS tree, so
+// the result depends only on the shapes.
+__global__ __launch_bounds__(1024) void wsum_kernel(const float* partial, float* dW, size_t n, int chunks,
+                                                    int accumulate)
+{
+    __shared__ float red[16][64];
+    const int x = threadIdx.x, y = threadIdx.y, Y = blockDim.y;
+    const size_t i = (size_t)blockIdx.x * 64 + x;
+    float s = 0.f;
+    if (i < n) {
+        int c = y;
+        for (; c + 3 * Y < chunks; c += 4 * Y) {
+            const float v0 = partial[(size_t)c * n + i], v1 = partial[(size_t)(c + Y) * n + i];
+            const float v2 = partial[(size_t)(c + 2 * Y) * n + i], v3 = partial[(size_t)(c + 3 * Y) * n + i];
+            s += v0;
+            s += v1;
+            s += v2;
+            s += v3;
+        }
+        for (; c < chunks; c += Y) s += partial[(size_t)c * n + i];
+    }
+    red[y][x] = s;
+    __syncthreads();
+    for (int h = Y >> 1; h > 0; h >>= 1) {
+        if (y < h) red[y][x] += red[y + h][x];
+        __syncthreads();
+    }
+    if (y == 0 && i < n) dW[i] = accumulate ? dW[i] + red[0][x] : red[0][x];
+}
+
+// launch shape of wsum_kernel: lanes per output grow with the chunk count
+static void launch_wsum(const float* partial, float* dW, size_t n, int chunks, int accumulate, hipStream_t s)
+{
+    int Y = 1;
+    while (Y < 16 && Y * 16 < chunks) Y <<= 1;
+    hipLaunchKernelGGL(wsum_kernel, dim3((unsigned)((n + 63) / 64)), dim3(64, Y), 0, s, partial, dW, n, chunks,
+                       accumulate);
 }
 
 __global__ __launch_bounds__(256) void prep_kernel(const float* W, int taps, int R, int Kc, uint16_t* fwd, int ldo_f,
@@ -480,6 +832,31 @@ void dispatch32(const ConvArgs& a, long P, hipStream_t s)
     }
 }
 
+// Halo-tile kernel: 8 x 32 pixel tiles, 32 output channels per block (16
+// for narrower outputs; wider tiles keep one wave per SIMD for their staging
+// registers); used when it gives about two blocks per CU.
+constexpr int kLdsTH = 8, kLdsTW = 32;
+
+int lds_tn(const ConvArgs& a) { return a.Nout > 16 ? 2 : 1; }
+
+long lds_tiles(const ConvArgs& a) { return (long)((a.H + kLdsTH - 1) / kLdsTH) * ((a.W + kLdsTW - 1) / kLdsTW); }
+
+bool lds_ok(const ConvArgs& a, int mode)
+{
+    if (mode != kConvFwd && mode != kConvDgrad) return false;
+    const long blocks = lds_tiles(a) * a.N * ((a.Nout + 16 * lds_tn(a) - 1) / (16 * lds_tn(a)));
+    return blocks >= 512;
+}
+
+template <int MODE>
+void launch_lds(const ConvArgs& a, hipStream_t s)
+{
+    const int tn = lds_tn(a);
+    dim3 grid((unsigned)(lds_tiles(a) * a.N), (unsigned)((a.Nout + 16 * tn - 1) / (16 * tn)));
+    if (tn == 2) hipLaunchKernelGGL((conv3_lds_kernel<MODE, 2, kLdsTH, kLdsTW>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((conv3_lds_kernel<MODE, 1, kLdsTH, kLdsTW>), grid, dim3(256), 0, s, a);
+}
+
 }  // namespace
 
 bool conv_wide_ok(const ConvArgs& a, int mode)
@@ -492,10 +869,13 @@ bool conv_wide_ok(const ConvArgs& a, int mode)
            al(a.Wt, 16);
 }
 
-int conv_stat_rows(const ConvArgs& a, int mode)
+int conv_stat_chunks(const ConvArgs& a, int mode)
 {
     if ((mode != kConvFwd && mode != kFirst) || !conv_wide_ok(a, mode)) return 0;
-    return tile_rows(choose_tile(a, (long)a.N * a.H * a.W));
+    if (mode == kConvFwd && lds_ok(a, mode)) return (int)lds_tiles(a);
+    const long Ps = (long)a.H * a.W;
+    const int rows = tile_rows(choose_tile(a, (long)a.N * Ps));
+    return Ps % rows == 0 ? (int)(Ps / rows) : 0;
 }
 
 hipError_t conv_gemm(const ConvArgs& a, int mode, hipStream_t s)
@@ -503,9 +883,11 @@ hipError_t conv_gemm(const ConvArgs& a, int mode, hipStream_t s)
     const long P = (long)a.N * a.H * a.W;
     if (P <= 0 || a.Nout <= 0) return hipSuccess;
     if (mode < kConvFwd || mode > kFirst) return hipErrorInvalidValue;
-    if (a.gsum) {
-        const int rows = conv_stat_rows(a, mode);
-        if (rows == 0 || ((long)a.H * a.W) % rows != 0) return hipErrorInvalidValue;
+    if (a.gsum && conv_stat_chunks(a, mode) == 0) return hipErrorInvalidValue;
+    if (conv_wide_ok(a, mode) && lds_ok(a, mode)) {
+        if (mode == kConvFwd) launch_lds<kConvFwd>(a, s);
+        else launch_lds<kConvDgrad>(a, s);
+        return hipGetLastError();
     }
     if (conv_wide_ok(a, mode)) {
         switch (mode) {
@@ -535,6 +917,25 @@ size_t wgrad_partial_floats(const WgradArgs& a, int mode)
     return chunks * (mode == kConvFwd ? 9 : 1) * (size_t)a.Nout * (a.C1 + a.C2);
 }
 
+// Tap folding of the weight gradient (see wgrad32_kernel): 2 when the
+// output side has fewer than 8 channels, 1 when the input side has (single
+// input), else 0.
+static int wgrad_fold(int mode, int Nout, int C1, int C2)
+{
+    if (mode != kConvFwd) return 0;
+    if (Nout < 8) return 2;
+    if (C2 == 0 && C1 < 8) return 1;
+    return 0;
+}
+
+int wgrad_blocks_per_chunk(int mode, int Nout, int C1, int C2)
+{
+    const int K = C1 + C2, f = wgrad_fold(mode, Nout, C1, C2);
+    const int taps = mode == kConvFwd && f == 0 ? 9 : 1;
+    const int No = f == 2 ? 9 * Nout : Nout, Ko = f == 1 ? 9 * K : K;
+    return taps * ((No + 63) / 64) * ((Ko + 63) / 64);
+}
+
 hipError_t conv_wgrad(const WgradArgs& a, int mode, float* dW, int accumulate, hipStream_t s)
 {
     const long P = (long)a.N * a.H * a.W;
@@ -543,16 +944,36 @@ hipError_t conv_wgrad(const WgradArgs& a, int mode, float* dW, int accumulate, h
     const size_t n = (size_t)ntaps * a.Nout * K;
     if (mode != kConvFwd && mode != kUpFwd) return hipErrorInvalidValue;
     if (P <= 0) {
-        if (!accumulate) hipLaunchKernelGGL(wsum_kernel, dim3(grid_for(n)), dim3(256), 0, s, a.partial, dW, n, 0, 0);
+        if (!accumulate) launch_wsum(a.partial, dW, n, 0, 0, s);
         return hipGetLastError();
     }
     const int chunks = (int)((P + a.chunk - 1) / a.chunk);
-    dim3 grid((unsigned)((a.Nout + 63) / 64), (unsigned)((K + 63) / 64), (unsigned)(chunks * ntaps));
-    if (mode == kConvFwd) hipLaunchKernelGGL(wgrad_kernel<kConvFwd>, grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL(wgrad_kernel<kUpFwd>, grid, dim3(256), 0, s, a);
+    const int fold = wgrad_fold(mode, a.Nout, a.C1, a.C2);
+    const int No = fold == 2 ? 9 * a.Nout : a.Nout, Ko = fold == 1 ? 9 * K : K;
+    const int gz = chunks * (mode == kConvFwd && fold == 0 ? 9 : 1);
+    dim3 grid((unsigned)((No + 63) / 64), (unsigned)((Ko + 63) / 64), (unsigned)gz);
+    const auto al16 = [](const void* q) { return ((uintptr_t)q & 15) == 0; };
+    const bool vec = a.Nout % 8 == 0 && (mode == kConvFwd || (a.Nout / 4) % 8 == 0) && a.C1 % 8 == 0 &&
+                     a.C2 % 8 == 0 && al16(a.dy) && al16(a.x1) && (!a.x2 || al16(a.x2));
+    // 8-channel pieces must not cross a sub-pixel of the up-sampling's dy
+    // or the boundary of a concatenated input
+    if (fold == 2) {
+        hipLaunchKernelGGL((wgrad32_kernel<kConvFwd, false, 2>), grid, dim3(256), 0, s, a);
+    } else if (fold == 1) {
+        hipLaunchKernelGGL((wgrad32_kernel<kConvFwd, false, 1>), grid, dim3(256), 0, s, a);
+    } else if (!vec && ((mode == kUpFwd && (a.Nout / 4) % 8 != 0) || (a.C2 > 0 && a.C1 % 8 != 0))) {
+        if (mode == kConvFwd) hipLaunchKernelGGL(wgrad_kernel<kConvFwd>, grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL(wgrad_kernel<kUpFwd>, grid, dim3(256), 0, s, a);
+    } else if (mode == kConvFwd) {
+        if (vec) hipLaunchKernelGGL((wgrad32_kernel<kConvFwd, true, 0>), grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((wgrad32_kernel<kConvFwd, false, 0>), grid, dim3(256), 0, s, a);
+    } else {
+        if (vec) hipLaunchKernelGGL((wgrad32_kernel<kUpFwd, true, 0>), grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((wgrad32_kernel<kUpFwd, false, 0>), grid, dim3(256), 0, s, a);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(wsum_kernel, dim3(grid_for(n)), dim3(256), 0, s, a.partial, dW, n, chunks, accumulate);
+    launch_wsum(a.partial, dW, n, chunks, accumulate, s);
     return hipGetLastError();
 }
 

@@ -33,8 +33,8 @@ struct ConvArgs {
     int ldk;               // row stride of Wt (K rounded up to 32)
     int ldo;               // rows per tap of Wt (Nout rounded up to 128)
     // optional per-tile channel sums of the FP32 output for group
-    // normalisation, [N][Nout][P_sample / rows per block][2] = (sum, sum of
-    // squares); only with conv_stat_rows() > 0
+    // normalisation, [N][Nout][conv_stat_chunks()][2] = (sum, sum of
+    // squares); only when conv_stat_chunks() > 0
     float* gsum;
 };
 
@@ -44,7 +44,7 @@ struct WgradArgs {
     const uint16_t* x2;    // concatenated second input or null
     float* partial;        // [chunks][taps][Nout][C1+C2]
     int N, H, W, C1, C2, Nout;
-    int chunk;             // pixels per partial product (multiple of 16)
+    int chunk;             // pixels per partial product (multiple of 64)
 };
 
 hipError_t conv_gemm(const ConvArgs& a, int mode, hipStream_t s);
@@ -52,15 +52,17 @@ hipError_t conv_gemm(const ConvArgs& a, int mode, hipStream_t s);
 // multiples of 32 (128 for the up-sampling gradient's 4 sub-pixels),
 // ldk % 32 == 0, ldo % 128 == 0 and 16-byte aligned operands.
 bool conv_wide_ok(const ConvArgs& a, int mode);
-// Pixel rows per block of the kernel conv_gemm picks for (a, mode) when it
-// can also write a.gsum (wide kernel, forward modes), else 0.  a.gsum is
-// usable when the pixels of one sample are a multiple of it.
-int conv_stat_rows(const ConvArgs& a, int mode);
+// Number of per-sample partial sums the kernel conv_gemm picks for
+// (a, mode) writes to a.gsum (forward modes of the wide kernels, when its
+// pixel blocks do not straddle samples), else 0.
+int conv_stat_chunks(const ConvArgs& a, int mode);
 // dW[taps][Nout][C1+C2] = (accumulate ? dW : 0) + sum over pixels; mode
 // kConvFwd (3x3) or kUpFwd (2x2 stride 2).  a.partial must hold
 // wgrad_partial_floats() floats.
 hipError_t conv_wgrad(const WgradArgs& a, int mode, float* dW, int accumulate, hipStream_t s);
 size_t wgrad_partial_floats(const WgradArgs& a, int mode);
+// Blocks conv_wgrad launches per pixel chunk (taps and 64 x 64 output tiles).
+int wgrad_blocks_per_chunk(int mode, int Nout, int C1, int C2);
 // BF16 operand copies of an FP32 weight [taps][R][Kc]: fwd[t][o][k] = W[t][o][k]
 // (ldo_f x ldk_f, zero padded) and tr[t][o][k] = W[t][k][o] (ldo_t x ldk_t);
 // either may be null.
@@ -113,7 +115,7 @@ int gn_chunks(int P);
 hipError_t maxpool_fwd(const uint16_t* x, uint16_t* y, int N, int H, int W, int C, hipStream_t s);
 hipError_t maxpool_bwd(const uint16_t* x, const float* dy, float* dx, int N, int H, int W, int C, hipStream_t s);
 
-// Network input: x[n][p][0..3] = (c, phi, rho, jump[n]) as BF16.
+// Network input: x[n][p][0..3] = (c - 1/2, phi, rho - 1, jump[n]) as BF16.
 hipError_t assemble_input(const float* c, const float* phi, const float* rho, const float* jump, uint16_t* x, int N,
                           int P, hipStream_t s);
 // out_f[n][p] = in_f[n][p] + jump[n] head[n][p][f] for the three fields.

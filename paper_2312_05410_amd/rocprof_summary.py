@@ -4,7 +4,9 @@
     python -m paper_2312_05410_amd.rocprof_summary traffic FETCH_DIR WRITE_DIR --kernel SUBSTR \
         [--ref-bytes N] [--out FILE] [--command TEXT]
 
-`stats` prints the per-kernel summary of a `--kernel-trace --stats` run.
+`stats` prints the per-kernel summary of a `--kernel-trace --stats` run
+(CSV output); `dbstats` the same from the SQLite database rocprofv3 writes
+by default (`*_results.db`), grouped by kernel and grid.
 `traffic` reads two `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs of the same
 program, whose first large device copy (--ref-bytes bytes, read once and
 written once) calibrates the counters: each counter is scaled by
@@ -58,6 +60,24 @@ def _counter(d: str, name: str):
             for r in rows if r["Counter_Name"] == name]
 
 
+def dbstats(d: str, kernel: str | None = None, top: int = 40):
+    """(name, grid, calls, avg ns, min ns, max ns, share %) from a results
+    database, largest total time first."""
+    import sqlite3
+
+    db = sqlite3.connect(_one(os.path.join(d, "**", "*results.db")))
+    rows = db.execute("select name, grid_x, grid_y, grid_z, count(*), avg(end - start), min(end - start), "
+                      "max(end - start), sum(end - start) from kernels group by name, grid_x, grid_y, grid_z "
+                      "order by sum(end - start) desc").fetchall()
+    tot = sum(r[8] for r in rows) or 1
+    out = []
+    for name, gx, gy, gz, calls, avg, mn, mx, sm in rows:
+        if kernel and kernel not in name:
+            continue
+        out.append((name, f"{gx}x{gy}x{gz}", calls, avg, mn, mx, 100.0 * sm / tot))
+    return out[:top]
+
+
 def traffic(fetch_dir: str, write_dir: str, kernel: str, ref_bytes: int):
     f = _counter(fetch_dir, "FETCH_SIZE")
     w = _counter(write_dir, "WRITE_SIZE")
@@ -85,6 +105,10 @@ def main(argv=None):
     s = sub.add_parser("stats")
     s.add_argument("dir")
     s.add_argument("--kernel")
+    s2 = sub.add_parser("dbstats")
+    s2.add_argument("dir")
+    s2.add_argument("--kernel")
+    s2.add_argument("--top", type=int, default=40)
     t = sub.add_parser("traffic")
     t.add_argument("fetch_dir")
     t.add_argument("write_dir")
@@ -97,6 +121,11 @@ def main(argv=None):
         for name, calls, avg, mn, mx, pct in stats(a.dir, a.kernel):
             print(f"{name}\n    calls {calls}  avg {avg / 1e3:.3f} us  min {mn / 1e3:.3f}  max {mx / 1e3:.3f}  "
                   f"share {pct:.2f} %")
+        return
+    if a.cmd == "dbstats":
+        for name, grid, calls, avg, mn, mx, pct in dbstats(a.dir, a.kernel, a.top):
+            print(f"{name}\n    grid {grid}  calls {calls}  avg {avg / 1e3:.3f} us  min {mn / 1e3:.3f}  "
+                  f"max {mx / 1e3:.3f}  share {pct:.2f} %")
         return
     r = traffic(a.fetch_dir, a.write_dir, a.kernel, a.ref_bytes)
     lines = [f"kernel: {a.kernel}",

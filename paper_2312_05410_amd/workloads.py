@@ -7,6 +7,9 @@
   nominal, composition in [0.3, 0.7]).  The throughput workload.
 * dns_8192_f32: the production model on 8192 x 8192 (805 MB of state, 1.6 GB
   with the ping-pong copy), 500 steps: the size for the HBM-bandwidth claim.
+* midpoint_1024_f32 / interface_1024_f32: dns_1024_f32 with the explicit
+  midpoint integrator (two launches per step), or with truncated-Gaussian
+  interface composition draws (sigma 0.1) after every step.
 * batched_32x512_f32: 32 independent 512 x 512 FP32 realisations with seeded
   (rate, composition) pairs, 10,000 steps each.
 
@@ -56,6 +59,11 @@ def adjoint_case(seed: int = 0, precision: str = "f32") -> PFParams:
     return PFParams(nx=256, ny=256, batch=1, precision=precision, seed=seed, v0=V0_NOM, c0=0.5,
                     c_noise=0.05, dt=ADJOINT_DT)
 
+
+# Variant workloads of the throughput measurement: the 1024 x 1024 FP32
+# production run with the explicit midpoint integrator, and with interface
+# composition draws of width INTERFACE_SIGMA on the vapour side.
+INTERFACE_SIGMA = 0.1
 
 STEPS = {"dns_small_128_f64": 1000, "dns_1024_f32": 50_000, "batched_32x512_f32": 10_000,
          # the production model at a size far above the 256 MB Infinity Cache

@@ -72,7 +72,10 @@ def check_bound(gpu, ref, bound, k, what):
 # pixel and channel tails
 @pytest.mark.parametrize("n,H,W,C1,C2,Cout", [(2, 10, 13, 8, 12, 40), (1, 9, 7, 4, 0, 32), (2, 6, 11, 32, 32, 3),
                                               (1, 16, 16, 64, 0, 70), (1, 40, 36, 32, 32, 32),
-                                              (2, 250, 262, 32, 0, 64), (1, 130, 254, 32, 0, 256)])
+                                              (2, 250, 262, 32, 0, 64), (1, 130, 254, 32, 0, 256),
+                                              # weight gradients with the taps folded into the input side
+                                              # (4 channels) or the output side (3 and 7 channels), many chunks
+                                              (2, 70, 90, 4, 0, 32), (1, 100, 130, 32, 0, 3), (1, 33, 21, 5, 0, 7)])
 def test_conv3x3_fwd_dgrad_wgrad(n, H, W, C1, C2, Cout):
     import torch
 
