@@ -112,6 +112,8 @@ typedef struct pf_params {
     const double* v0_per;         /* host [batch] incident speeds, or NULL for v0 */
     const double* c0_per;         /* host [batch] mean compositions, or NULL for c0 */
     double interface_noise;       /* standard deviation of the interface draw, 0..1; 0: off */
+    int32_t lane_cols;            /* single-step FP32 kernel: grid columns per lane, 1 or 2 (2 needs
+                                     an even nx; else 1 is used); 0: library's choice */
 } pf_params;
 
 /* Bytes of device workspace a handle for *p needs (ping-pong copy of the
@@ -170,6 +172,10 @@ void pf_destroy(pf_handle* h);
 /* Launch shape a handle uses: steps fused per launch (1: single-step
  * strip-march kernel; 2..4: LDS-tiled kernel) and rows per wave / tile. */
 int pf_get_launch(const pf_handle* h, int32_t* temporal_block, int32_t* tile_rows);
+
+/* Grid columns per lane of the single-step kernel the handle launches (1 or
+ * 2; 1 whenever temporal_block > 1).  PF_EINVAL on a null argument. */
+int pf_get_lane_cols(const pf_handle* h, int32_t* lane_cols);
 
 /* ------------------------------------------------------------------ adjoint
  * Discrete adjoint of the explicit step, for gradients of a loss of the

@@ -71,12 +71,13 @@ hipError_t launch_step(const StepArgs<T>& a, int k, int batch, hipStream_t s);
 template <typename T>
 TileCfg tile_cfg(int k);
 
-// Single-step strip-march kernel (K = 1), chunks of ty in {4, 8, 16, 32} rows.
+// Single-step strip-march kernel (K = 1), chunks of ty in {4, 8, 16, 32} rows,
+// cols grid columns per lane (2: FP32 with even nx only, else 1 is used).
 template <typename T>
-hipError_t launch_march(const StepArgs<T>& a, int ty, int batch, hipStream_t s);
+hipError_t launch_march(const StepArgs<T>& a, int ty, int cols, int batch, hipStream_t s);
 template <typename T>
 hipError_t graph_add_march(hipGraph_t g, hipGraphNode_t* node, hipGraphNode_t dep, const StepArgs<T>& a,
-                           int ty, int batch);
+                           int ty, int cols, int batch);
 
 // Append one stepper launch as a kernel node of graph g after node dep
 // (dep == nullptr: no dependency).

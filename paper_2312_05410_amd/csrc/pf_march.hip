@@ -203,6 +203,165 @@ __global__ __launch_bounds__(64) void march_kernel(StepArgs<T> a)
     }
 }
 
+// Two columns per lane (FP32, even nx): lane i holds columns xs + 2i and
+// xs + 2i + 1 (xs = 124 s - 2) as one 8-byte load, so a wave covers 128
+// columns and writes 124.  Of each cell's east/west neighbours one is the
+// lane's other column and one comes from the adjacent lane (a single DPP
+// move per field per pair), which halves the neighbour exchanges and the
+// scalar work per cell and shrinks the strip overlap from 4/64 to 4/128.
+// Same per-cell functions in the same order: bitwise identical results.
+constexpr int kStripOut2 = 124;
+
+struct F2 {
+    float a, b;
+};
+__device__ __forceinline__ F2 ld2(__amdgpu_buffer_rsrc_t r, int vo, int so)
+{
+    // element access on the builtin's own vector type (a bit_cast of it to
+    // another two-element vector type compiled to a single-dword load)
+    const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, vo, so, 0);
+    return {__builtin_bit_cast(float, (unsigned)v[0]), __builtin_bit_cast(float, (unsigned)v[1])};
+}
+__device__ __forceinline__ void st2(F2 v, __amdgpu_buffer_rsrc_t r, int vo, int so)
+{
+    u32x2 w;
+    w.x = __builtin_bit_cast(unsigned, v.a);
+    w.y = __builtin_bit_cast(unsigned, v.b);
+    __builtin_amdgcn_raw_buffer_store_b64(w, r, vo, so, 0);
+}
+
+template <int TY, int D, bool BASE, bool NOISE>
+__global__ __launch_bounds__(64) void march2_kernel(StepArgs<float> a)
+{
+    using T = float;
+    constexpr int NR = TY + 4;
+    const int lane = threadIdx.x;
+    const int b = blockIdx.y;
+    const int nx = a.nx, ny = a.ny;
+    const int nstrip = a.tiles_x;
+
+    const int nblk = a.tiles_x * a.tiles_y;
+    const int bid = blockIdx.x;
+    const int xcd = bid & 7, slot = bid >> 3;
+    const int q8 = nblk >> 3, r8 = nblk & 7;
+    const int tileid = xcd * q8 + (xcd < r8 ? xcd : r8) + slot;
+    const int strip = tileid % nstrip;
+    const int y0 = (tileid / nstrip) * TY;
+
+    // nx is even, so the wrapped pair (gx, gx + 1) stays contiguous
+    int gx = strip * kStripOut2 - 2 + 2 * lane;
+    while (gx < 0) gx += nx;
+    while (gx >= nx) gx -= nx;
+    const int ocol = strip * kStripOut2 + 2 * lane - 2;  // output column of the pair's first cell
+    const bool out_lane = lane >= 1 && lane < 1 + kStripOut2 / 2 && ocol < nx;
+
+    const size_t plane = (size_t)nx * ny;
+    const auto bc = plane_rsrc(a.c + (size_t)b * plane, plane);
+    const auto bp = plane_rsrc(a.phi + (size_t)b * plane, plane);
+    const auto br = plane_rsrc(a.rho + (size_t)b * plane, plane);
+    const auto oc = plane_rsrc(a.c_out + (size_t)b * plane, plane);
+    const auto op = plane_rsrc(a.phi_out + (size_t)b * plane, plane);
+    const auto orr = plane_rsrc(a.rho_out + (size_t)b * plane, plane);
+    const auto bcb = plane_rsrc((BASE ? a.cb : a.c) + (size_t)b * plane, plane);
+    const auto bpb = plane_rsrc((BASE ? a.pb : a.phi) + (size_t)b * plane, plane);
+    const auto brb = plane_rsrc((BASE ? a.rb : a.rho) + (size_t)b * plane, plane);
+    const int vo = gx * (int)sizeof(T);
+    const int row_bytes = nx * (int)sizeof(T);
+    const Coef<T> k = a.k;
+    const Real rl = a.real[b];
+    const T vx2h = (T)rl.vx2h, vy2h = (T)rl.vy2h;
+    const int pvd = a.pvd;
+
+    F2 c[NR], p[NR], r[NR];
+    F2 mc[NR], mp[NR], M[NR], pE[NR], pW[NR], FN[NR];
+    const RhoCoef<T> rc = rho_coef(k, vx2h, vy2h);
+
+    auto load_row = [&](int t) {
+        const int gj = y0 - 2 + t;
+        int jj;
+        if (pvd) jj = gj < 0 ? -1 - gj : (gj >= ny ? 2 * ny - 1 - gj : gj);
+        else jj = gj < 0 ? gj + ny : (gj >= ny ? gj - ny : gj);
+        jj = jj < 0 ? 0 : (jj >= ny ? ny - 1 : jj);
+        const int so = jj * row_bytes;
+        c[t] = ld2(bc, vo, so);
+        p[t] = ld2(bp, vo, so);
+        const F2 rv = ld2(br, vo, so);
+        const bool inlet = pvd && gj >= ny;
+        r[t] = {inlet ? k.rho_in : rv.a, inlet ? k.rho_in : rv.b};
+    };
+
+#pragma unroll
+    for (int t = 0; t < NR; ++t)
+        if (t < 3 + D) load_row(t);
+
+#pragma unroll
+    for (int t1 = 1; t1 <= TY + 2; ++t1) {
+        if (t1 + 2 + D < NR) load_row(t1 + 2 + D);
+        // stage 1 at row t1: the first cell's west and the second cell's
+        // east neighbours come from the adjacent lanes
+        {
+            const T cW = west(c[t1].b), cE = east(c[t1].a);
+            const T pWv = west(p[t1].b), pEv = east(p[t1].a);
+            pE[t1] = {p[t1].b, pEv};
+            pW[t1] = {pWv, p[t1].a};
+            potentials(k, c[t1].a, c[t1].b, cW, c[t1 + 1].a, c[t1 - 1].a, p[t1].a, pE[t1].a, pW[t1].a,
+                       p[t1 + 1].a, p[t1 - 1].a, mc[t1].a, mp[t1].a, M[t1].a);
+            potentials(k, c[t1].b, cE, c[t1].a, c[t1 + 1].b, c[t1 - 1].b, p[t1].b, pE[t1].b, pW[t1].b,
+                       p[t1 + 1].b, p[t1 - 1].b, mc[t1].b, mp[t1].b, M[t1].b);
+        }
+        if (t1 >= 3) {
+            const int t = t1 - 1;
+            const int gj = y0 - 2 + t;
+            const bool bottom = pvd && gj == 0;
+            if (t == 2) {
+                FN[1].a = cflux(M[1].a, mc[1].a, M[2].a, mc[2].a);
+                FN[1].b = cflux(M[1].b, mc[1].b, M[2].b, mc[2].b);
+            }
+            const T FEa = cflux(M[t].a, mc[t].a, M[t].b, mc[t].b);
+            const T FEb = cflux(M[t].b, mc[t].b, east(M[t].a), east(mc[t].a));
+            const T FWa = west(FEb);
+            FN[t].a = cflux(M[t].a, mc[t].a, M[t + 1].a, mc[t + 1].a);
+            FN[t].b = cflux(M[t].b, mc[t].b, M[t + 1].b, mc[t + 1].b);
+            const T rW = west(r[t].b), rE = east(r[t].a);
+            const T qW = west(mp[t].b), qE = east(mp[t].a);
+            F2 cb0 = c[t], pb0 = p[t], rb0 = r[t];
+            if (BASE && gj < ny) {
+                const int so = gj * row_bytes;
+                cb0 = ld2(bcb, vo, so);
+                pb0 = ld2(bpb, vo, so);
+                rb0 = ld2(brb, vo, so);
+            }
+            F2 nc, np, nr;
+            update(k, rc, vx2h, vy2h, bottom, c[t].a, p[t].a, pE[t].a, pW[t].a, p[t + 1].a, p[t - 1].a,
+                   r[t].a, r[t].b, rW, r[t + 1].a, r[t - 1].a, FEa, FWa, FN[t].a, FN[t - 1].a,
+                   mp[t].a, mp[t].b, qW, mp[t + 1].a, mp[t - 1].a, nc.a, np.a, nr.a, cb0.a, pb0.a, rb0.a);
+            update(k, rc, vx2h, vy2h, bottom, c[t].b, p[t].b, pE[t].b, pW[t].b, p[t + 1].b, p[t - 1].b,
+                   r[t].b, rE, r[t].a, r[t + 1].b, r[t - 1].b, FEb, FEa, FN[t].b, FN[t - 1].b,
+                   mp[t].b, qE, mp[t].a, mp[t + 1].b, mp[t - 1].b, nc.b, np.b, nr.b, cb0.b, pb0.b, rb0.b);
+            if (NOISE && gj < ny && out_lane) {
+                const uint64_t id = (uint64_t)a.step * plane + (uint64_t)gj * nx + ocol;
+                if (np.a < T(0)) nc.a = (T)trunc_gauss(rl.nseed, id * 16ull, rl.c0, a.noise);
+                if (np.b < T(0)) nc.b = (T)trunc_gauss(rl.nseed, (id + 1ull) * 16ull, rl.c0, a.noise);
+            }
+            if (gj < ny) {
+                if (out_lane) {
+                    const int so = gj * row_bytes;
+                    st2(nc, oc, vo, so);
+                    st2(np, op, vo, so);
+                    st2(nr, orr, vo, so);
+                }
+                if (a.Qcol && pvd && gj == ny - 1 && out_lane) {
+                    double* q = a.Qcol + (size_t)b * nx + ocol;
+                    const double rin = (double)k.rho_in;
+                    const double ra = (double)r[t].a, rb = (double)r[t].b;
+                    q[0] = q[0] + (rl.qa * (ra + rin) + rl.qb * (rin - ra));
+                    q[1] = q[1] + (rl.qa * (rb + rin) + rl.qb * (rin - rb));
+                }
+            }
+        }
+    }
+}
+
 // rows of loads in flight ahead of use: short chunks issue all their loads
 // at once, long chunks keep a window of rows in flight
 template <int TY> constexpr int lookahead() { return TY <= 8 ? TY + 1 : 4; }
@@ -219,24 +378,51 @@ void* march_fn(const StepArgs<T>& a)
     return (void*)march_kernel<T, TY, D, false, false>;
 }
 
-template <typename T, int TY>
-hipError_t launch_march_ty(StepArgs<T> a, int batch, hipStream_t s)
+template <int TY>
+void* march2_fn(const StepArgs<float>& a)
 {
+    constexpr int D = lookahead<TY>();
+    const bool base = a.cb != nullptr, noise = a.noise > 0;
+    if (base && noise) return (void*)march2_kernel<TY, D, true, true>;
+    if (base) return (void*)march2_kernel<TY, D, true, false>;
+    if (noise) return (void*)march2_kernel<TY, D, false, true>;
+    return (void*)march2_kernel<TY, D, false, false>;
+}
+
+// the launch's kernel and strip width: two columns per lane when asked for
+// (FP32, even nx), else one
+template <typename T, int TY>
+void* pick_march(StepArgs<T>& a, int cols)
+{
+    if constexpr (sizeof(T) == 4) {
+        if (cols == 2 && a.nx % 2 == 0) {
+            a.tiles_x = (a.nx + kStripOut2 - 1) / kStripOut2;
+            a.tiles_y = (a.ny + TY - 1) / TY;
+            return march2_fn<TY>(a);
+        }
+    }
     a.tiles_x = (a.nx + kStripOut - 1) / kStripOut;
     a.tiles_y = (a.ny + TY - 1) / TY;
-    dim3 grid(a.tiles_x * a.tiles_y, batch);
-    void* args[] = {&a};
-    return hipLaunchKernel(march_fn<T, TY>(a), grid, dim3(64), args, 0, s);
+    return march_fn<T, TY>(a);
 }
 
 template <typename T, int TY>
-hipError_t node_march_ty(hipGraph_t g, hipGraphNode_t* node, hipGraphNode_t dep, StepArgs<T> a, int batch)
+hipError_t launch_march_ty(StepArgs<T> a, int cols, int batch, hipStream_t s)
 {
-    a.tiles_x = (a.nx + kStripOut - 1) / kStripOut;
-    a.tiles_y = (a.ny + TY - 1) / TY;
+    void* fn = pick_march<T, TY>(a, cols);
+    dim3 grid(a.tiles_x * a.tiles_y, batch);
+    void* args[] = {&a};
+    return hipLaunchKernel(fn, grid, dim3(64), args, 0, s);
+}
+
+template <typename T, int TY>
+hipError_t node_march_ty(hipGraph_t g, hipGraphNode_t* node, hipGraphNode_t dep, StepArgs<T> a, int cols,
+                         int batch)
+{
+    void* fn = pick_march<T, TY>(a, cols);
     void* args[] = {&a};
     hipKernelNodeParams kp{};
-    kp.func = march_fn<T, TY>(a);
+    kp.func = fn;
     kp.gridDim = dim3(a.tiles_x * a.tiles_y, batch);
     kp.blockDim = dim3(64);
     kp.sharedMemBytes = 0;
@@ -248,34 +434,34 @@ hipError_t node_march_ty(hipGraph_t g, hipGraphNode_t* node, hipGraphNode_t dep,
 }  // namespace
 
 template <typename T>
-hipError_t launch_march(const StepArgs<T>& a, int ty, int batch, hipStream_t s)
+hipError_t launch_march(const StepArgs<T>& a, int ty, int cols, int batch, hipStream_t s)
 {
     switch (ty) {
-    case 4: return launch_march_ty<T, 4>(a, batch, s);
-    case 8: return launch_march_ty<T, 8>(a, batch, s);
-    case 16: return launch_march_ty<T, 16>(a, batch, s);
-    case 32: return launch_march_ty<T, 32>(a, batch, s);
+    case 4: return launch_march_ty<T, 4>(a, cols, batch, s);
+    case 8: return launch_march_ty<T, 8>(a, cols, batch, s);
+    case 16: return launch_march_ty<T, 16>(a, cols, batch, s);
+    case 32: return launch_march_ty<T, 32>(a, cols, batch, s);
     default: return hipErrorInvalidValue;
     }
 }
-template hipError_t launch_march<float>(const StepArgs<float>&, int, int, hipStream_t);
-template hipError_t launch_march<double>(const StepArgs<double>&, int, int, hipStream_t);
+template hipError_t launch_march<float>(const StepArgs<float>&, int, int, int, hipStream_t);
+template hipError_t launch_march<double>(const StepArgs<double>&, int, int, int, hipStream_t);
 
 template <typename T>
 hipError_t graph_add_march(hipGraph_t g, hipGraphNode_t* node, hipGraphNode_t dep, const StepArgs<T>& a,
-                           int ty, int batch)
+                           int ty, int cols, int batch)
 {
     switch (ty) {
-    case 4: return node_march_ty<T, 4>(g, node, dep, a, batch);
-    case 8: return node_march_ty<T, 8>(g, node, dep, a, batch);
-    case 16: return node_march_ty<T, 16>(g, node, dep, a, batch);
-    case 32: return node_march_ty<T, 32>(g, node, dep, a, batch);
+    case 4: return node_march_ty<T, 4>(g, node, dep, a, cols, batch);
+    case 8: return node_march_ty<T, 8>(g, node, dep, a, cols, batch);
+    case 16: return node_march_ty<T, 16>(g, node, dep, a, cols, batch);
+    case 32: return node_march_ty<T, 32>(g, node, dep, a, cols, batch);
     default: return hipErrorInvalidValue;
     }
 }
 template hipError_t graph_add_march<float>(hipGraph_t, hipGraphNode_t*, hipGraphNode_t, const StepArgs<float>&,
-                                           int, int);
+                                           int, int, int);
 template hipError_t graph_add_march<double>(hipGraph_t, hipGraphNode_t*, hipGraphNode_t, const StepArgs<double>&,
-                                            int, int);
+                                            int, int, int);
 
 }  // namespace pfk

@@ -165,6 +165,7 @@ struct Bufs {
     float* std_[kMaxLevels];
     float *yh, *sth, *hout;
     float *jump, *h0, *h1, *f, *sc[kMaxLevels];
+    float* gcoef;                   // GN forward coefficients [2][n][C] (shared by every GN)
     float *mdf, *mdh1, *mdh0;
     // backward
     float* gout;
@@ -260,6 +261,7 @@ void carve(Net& net, char* base, Bufs& b)
         part = std::max(part, wgrad_floats(P0, 9, c.out_ch, w[0], 0));
     }
     b.jump = m.take<float>((size_t)n);
+    b.gcoef = m.take<float>((size_t)2 * n * std::max(w[L - 1], c.out_ch));
     b.h0 = m.take<float>((size_t)n * Hd);
     b.h1 = m.take<float>((size_t)n * Hd);
     b.f = m.take<float>((size_t)n * F);
@@ -393,6 +395,7 @@ GNArgs gn_args(unet_handle* h, const Conv& k, int n, long P1, const float* y, fl
     g.G = k.groups;
     g.gelu = k.gelu;
     g.eps = h->net.c.gn_eps;
+    g.coef = h->b.gcoef;
     return g;
 }
 

@@ -262,6 +262,50 @@ __global__ __launch_bounds__(256) void gemm32_kernel(ConvArgs a)
     }
     // acc[i][j][e]: pixel pm + 16 i + 4 (lane / 16) + e, channel on + 16 j + r
     const int rq = (lane >> 4) * 4;
+    if (MODE == kUpFwd) {
+        // sub-pixel scatter: one coordinate decomposition per 4 pixels (the
+        // next three step along the row, wrapping where W is not a multiple
+        // of 4) and the sub-pixel / channel split once per column tile
+        // (32-bit element offsets: the launcher checks the output size)
+        const unsigned Co = (unsigned)a.Nout >> 2, W2 = 2u * (unsigned)a.W;
+        unsigned offj[TN];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const unsigned o = (unsigned)(on + 16 * j + r), sub = o / Co;
+            offj[j] = ((sub >> 1) * W2 + (sub & 1)) * Co + (o - sub * Co);
+        }
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            const int p0 = pm + 16 * i + rq;
+            if (p0 >= P) continue;
+            const Pix t0 = pix(p0, a.H, a.W, P);
+            int n = t0.n, y = t0.y, x = t0.x;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                if (e) {
+                    ++x;
+                    while (x >= a.W) {
+                        x -= a.W;
+                        if (++y >= a.H) {
+                            y = 0;
+                            ++n;
+                        }
+                    }
+                }
+                if (p0 + e >= P) continue;
+                const unsigned row = (((unsigned)n * 2u * (unsigned)a.H + 2u * (unsigned)y) * W2 + 2u * (unsigned)x) * Co;
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    if (on + 16 * j + r >= a.Nout) continue;
+                    const unsigned idx = row + offj[j];
+                    const float v = acc[i][j][e];
+                    if (a.out_f32) a.out_f32[idx] = v;
+                    if (a.out_bf16) a.out_bf16[idx] = f2bf(v);
+                }
+            }
+        }
+        return;
+    }
 #pragma unroll
     for (int j = 0; j < TN; ++j) {
         const int o = on + 16 * j + r;
@@ -273,14 +317,7 @@ __global__ __launch_bounds__(256) void gemm32_kernel(ConvArgs a)
                 const int p = pm + 16 * i + rq + e;
                 if (p >= P) continue;
                 const float v = acc[i][j][e];
-                if (MODE == kUpFwd) {
-                    const Pix t = pix(p, a.H, a.W, P);
-                    const int Co = a.Nout >> 2, sub = o / Co, co = o - sub * Co;
-                    const size_t idx =
-                        (((size_t)t.n * 2 * a.H + 2 * t.y + (sub >> 1)) * 2 * a.W + 2 * t.x + (sub & 1)) * Co + co;
-                    if (a.out_f32) a.out_f32[idx] = v;
-                    if (a.out_bf16) a.out_bf16[idx] = f2bf(v);
-                } else if (o < a.O1) {
+                if (o < a.O1) {
                     const size_t idx = (size_t)p * a.O1 + o;
                     if (a.out_f32) a.out_f32[idx] = v;
                     if (a.out_bf16) a.out_bf16[idx] = f2bf(v);
@@ -837,15 +874,21 @@ void dispatch32(const ConvArgs& a, long P, hipStream_t s)
 // registers); used when it gives about two blocks per CU.
 constexpr int kLdsTH = 8, kLdsTW = 32;
 
-int lds_tn(const ConvArgs& a) { return a.Nout > 16 ? 2 : 1; }
-
 long lds_tiles(const ConvArgs& a) { return (long)((a.H + kLdsTH - 1) / kLdsTH) * ((a.W + kLdsTW - 1) / kLdsTW); }
+
+// 32 output channels per block while that still gives two blocks per CU,
+// else 16 (small grids: the deep levels of one sample)
+int lds_tn(const ConvArgs& a)
+{
+    if (a.Nout <= 16) return 1;
+    return lds_tiles(a) * a.N * ((a.Nout + 31) / 32) >= 512 ? 2 : 1;
+}
 
 bool lds_ok(const ConvArgs& a, int mode)
 {
     if (mode != kConvFwd && mode != kConvDgrad) return false;
     const long blocks = lds_tiles(a) * a.N * ((a.Nout + 16 * lds_tn(a) - 1) / (16 * lds_tn(a)));
-    return blocks >= 512;
+    return blocks >= 256;
 }
 
 template <int MODE>
@@ -883,6 +926,8 @@ hipError_t conv_gemm(const ConvArgs& a, int mode, hipStream_t s)
     const long P = (long)a.N * a.H * a.W;
     if (P <= 0 || a.Nout <= 0) return hipSuccess;
     if (mode < kConvFwd || mode > kFirst) return hipErrorInvalidValue;
+    // the up-sampling epilogue forms 32-bit element offsets
+    if (mode == kUpFwd && (size_t)P * a.Nout >= ((size_t)1 << 31)) return hipErrorInvalidValue;
     if (a.gsum && conv_stat_chunks(a, mode) == 0) return hipErrorInvalidValue;
     if (conv_wide_ok(a, mode) && lds_ok(a, mode)) {
         if (mode == kConvFwd) launch_lds<kConvFwd>(a, s);

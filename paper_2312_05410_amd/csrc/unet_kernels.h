@@ -103,6 +103,9 @@ struct GNArgs {
     float eps;
     int chunks;            // partial sums per sample
     int sums_ready;        // forward: csum already holds `chunks` partials
+    float* coef;           // forward workspace [2][N][C] (16-byte aligned) or null: the
+                           // normalisation as A y + B per channel, A = gamma rstd,
+                           // B = beta - A mean
 };
 hipError_t gn_forward(const GNArgs& a, hipStream_t s);
 hipError_t gn_backward(const GNArgs& a, hipStream_t s);

@@ -27,15 +27,19 @@ __device__ __forceinline__ uint16_t f2bf(float f)
 // GELU, tanh form: 0.5 a (1 + tanh(sqrt(2/pi) (a + 0.044715 a^3)))
 constexpr float kGeluS = 0.7978845608028654f;
 constexpr float kGeluA = 0.044715f;
-__device__ __forceinline__ float gelu(float a)
+// (1 + tanh u) / 2 = 1 / (1 + exp(-2u)): the logistic form, on the hardware
+// base-2 exponential and reciprocal (exp2 of +-inf gives 0 or inf, so both
+// tails saturate to 0 and 1)
+__device__ __forceinline__ float gelu_s(float a)
 {
-    const float t = tanhf(kGeluS * (a + kGeluA * a * a * a));
-    return 0.5f * a * (1.f + t);
+    const float u = kGeluS * fmaf(kGeluA * a, a * a, a);
+    return __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(-2.f * 1.4426950408889634f * u));
 }
+__device__ __forceinline__ float gelu(float a) { return a * gelu_s(a); }
 __device__ __forceinline__ float gelu_grad(float a)
 {
-    const float t = tanhf(kGeluS * (a + kGeluA * a * a * a));
-    return 0.5f * (1.f + t) + 0.5f * a * (1.f - t * t) * kGeluS * (1.f + 3.f * kGeluA * a * a);
+    const float s = gelu_s(a);
+    return s + 2.f * a * s * (1.f - s) * kGeluS * fmaf(3.f * kGeluA * a, a, 1.f);
 }
 
 // Threads of a reduction block: the largest multiple of C not above 256, so
@@ -109,12 +113,22 @@ __global__ __launch_bounds__(256) void gn_stats_finish(GNArgs a)
         v[1] += q.y;
     }
     block_sum<2>(sh, v);
+    __shared__ float ms[2];
     if (threadIdx.x == 0) {
         const double M = (double)Cg * a.P;
         const double mean = v[0] / M;
         const double var = fmax(v[1] / M - mean * mean, 0.0);
-        a.stats[2 * i] = (float)mean;
-        a.stats[2 * i + 1] = (float)(1.0 / sqrt(var + (double)a.eps));
+        ms[0] = (float)mean;
+        ms[1] = (float)(1.0 / sqrt(var + (double)a.eps));
+        a.stats[2 * i] = ms[0];
+        a.stats[2 * i + 1] = ms[1];
+    }
+    if (!a.coef) return;
+    __syncthreads();
+    for (int c = g * Cg + threadIdx.x; c < (g + 1) * Cg; c += 256) {
+        const float A = a.gamma[c] * ms[1];
+        a.coef[(size_t)n * a.C + c] = A;
+        a.coef[(size_t)(a.N + n) * a.C + c] = fmaf(-A, ms[0], a.beta[c]);
     }
 }
 
@@ -142,10 +156,26 @@ __global__ __launch_bounds__(256) void gn_apply_kernel(GNArgs a)
 // Eight channels per thread (C % 8 == 0): 16-byte FP32 loads and BF16
 // stores; with pool_bf16 each thread takes the 2x2 window of one pooled pixel
 // and also writes the window's maximum of BF16(z).
+__device__ __forceinline__ void ld8f(const float* p, float* v)
+{
+    const float4 v0 = *(const float4*)p, v1 = *(const float4*)(p + 4);
+    v[0] = v0.x, v[1] = v0.y, v[2] = v0.z, v[3] = v0.w, v[4] = v1.x, v[5] = v1.y, v[6] = v1.z, v[7] = v1.w;
+}
 __device__ __forceinline__ void gn8(const GNArgs& a, int n, int c0, const float* y, float* z)
 {
-    const float4 v0 = *(const float4*)y, v1 = *(const float4*)(y + 4);
-    const float yv[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+    float yv[8];
+    ld8f(y, yv);
+    if (a.coef) {
+        float A[8], B[8];
+        ld8f(a.coef + (size_t)n * a.C + c0, A);
+        ld8f(a.coef + (size_t)(a.N + n) * a.C + c0, B);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const float av = fmaf(A[u], yv[u], B[u]);
+            z[u] = a.gelu ? gelu(av) : av;
+        }
+        return;
+    }
     const int Cg = a.C / a.G;
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
@@ -172,9 +202,10 @@ __device__ __forceinline__ void store8(const GNArgs& a, size_t i, int n, int c0,
     }
     if (a.z_bf16) *(uint4*)(a.z_bf16 + i) = pack8(z);
     if (a.scale) {
-        float zs[8];
+        float zs[8], sc[8];
+        ld8f(a.scale + (size_t)n * a.C + c0, sc);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) zs[u] = z[u] * a.scale[n * a.C + c0 + u];
+        for (int u = 0; u < 8; ++u) zs[u] = z[u] * sc[u];
         if (a.zs_f32) {
             *(float4*)(a.zs_f32 + i) = make_float4(zs[0], zs[1], zs[2], zs[3]);
             *(float4*)(a.zs_f32 + i + 4) = make_float4(zs[4], zs[5], zs[6], zs[7]);
@@ -183,30 +214,31 @@ __device__ __forceinline__ void store8(const GNArgs& a, size_t i, int n, int c0,
     }
 }
 
+// 32-bit item indices (the launcher checks N P C / 8 < 2^31)
 __global__ __launch_bounds__(256) void gn_apply8_kernel(GNArgs a)
 {
-    const int C8 = a.C / 8;
+    const unsigned C8 = (unsigned)a.C / 8u;
     if (!a.pool_bf16) {
-        const size_t total = (size_t)a.N * a.P * C8;
-        for (size_t it = (size_t)blockIdx.x * 256 + threadIdx.x; it < total; it += (size_t)gridDim.x * 256) {
-            const int c0 = (int)(it % C8) * 8;
-            const size_t px = it / C8;
-            const int n = (int)(px / a.P);
-            const size_t i = px * a.C + c0;
+        const unsigned total = (unsigned)a.N * (unsigned)a.P * C8;
+        for (unsigned it = blockIdx.x * 256u + threadIdx.x; it < total; it += gridDim.x * 256u) {
+            const unsigned px = it / C8;
+            const int c0 = (int)(it - px * C8) * 8;
+            const int n = (int)(px / (unsigned)a.P);
+            const size_t i = (size_t)px * a.C + c0;
             float z[8];
             gn8(a, n, c0, a.y + i, z);
             store8(a, i, n, c0, z);
         }
         return;
     }
-    const int Ho = a.H / 2, Wo = a.W / 2;
-    const size_t total = (size_t)a.N * Ho * Wo * C8;
-    for (size_t it = (size_t)blockIdx.x * 256 + threadIdx.x; it < total; it += (size_t)gridDim.x * 256) {
-        const int c0 = (int)(it % C8) * 8;
-        size_t q = it / C8;
-        const int xo = (int)(q % Wo);
-        q /= Wo;
-        const int yo = (int)(q % Ho), n = (int)(q / Ho);
+    const unsigned Ho = (unsigned)a.H / 2u, Wo = (unsigned)a.W / 2u;
+    const unsigned total = (unsigned)a.N * Ho * Wo * C8;
+    for (unsigned it = blockIdx.x * 256u + threadIdx.x; it < total; it += gridDim.x * 256u) {
+        unsigned q = it / C8;
+        const int c0 = (int)(it - q * C8) * 8;
+        const unsigned q2 = q / Wo;
+        const int xo = (int)(q - q2 * Wo);
+        const int yo = (int)(q2 % Ho), n = (int)(q2 / Ho);
         float m[8];
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
@@ -665,6 +697,8 @@ hipError_t gn_forward(const GNArgs& a_in, hipStream_t s)
     GNArgs a = a_in;
     const bool vec = a.C % 8 == 0 && ((uintptr_t)a.y & 15) == 0;
     if (a.pool_bf16 && (!vec || a.H % 2 || a.W % 2 || (long)a.H * a.W != a.P)) return hipErrorInvalidValue;
+    if ((size_t)a.N * a.P * a.C >= ((size_t)1 << 31)) return hipErrorInvalidValue;
+    if (a.coef && ((uintptr_t)a.coef & 15)) return hipErrorInvalidValue;
     if (!a.sums_ready) {
         a.chunks = gn_chunks(a.P);
         hipLaunchKernelGGL(gn_stats_kernel, dim3(a.chunks, a.N), dim3(256), 0, s, a, chunk_px(a.P));

@@ -195,18 +195,24 @@ def dns_run(seed: int = TEST_SEED, steps: int = BLEND_STEPS, dt_factor: float = 
 
 
 def blended_run(net, seed: int = TEST_SEED, steps: int = BLEND_STEPS, dns_block: int = BLEND_DNS,
-                jumps: int = BLEND_JUMPS, mode: str = "leap", n: int = BLEND_N, record: bool = False):
+                jumps: int = BLEND_JUMPS, mode: str = "leap", n: int = BLEND_N, record: bool = False,
+                dns_factor: float = 0.2):
     """Alternate dns_block DNS steps with `jumps` U-Net units (one leap of
     `jumps`, or `jumps` chained single units), the U-Net writing its
     prediction straight into the stepper's state tensors, then DNS to
-    `steps`.  Returns (state, milliseconds, records {step: state copy})."""
+    `steps`; `steps`, dns_block and the jumps count steps at 0.2 of the
+    stability limit.  dns_factor > 0.2: each DNS segment covers the same
+    physical time in round(dns_block 0.2 / dns_factor) larger steps.
+    Returns (state, milliseconds, records {step: state copy})."""
     import torch
 
-    from ._lib import Simulator
+    from ._lib import Simulator, dt_limit
 
     if mode not in ("leap", "chain"):
         raise ValueError(mode)
-    sim = Simulator(blend_params(seed, n=n))
+    p = blend_params(seed, n=n)
+    seg = max(1, int(round(dns_block * 0.2 / dns_factor)))
+    sim = Simulator(p.replace(dt=dns_block * 0.2 * dt_limit(p) / seg))
     u = (sim.c, sim.phi, sim.rho)
     leap = torch.full((1,), float(jumps if mode == "leap" else 1), device=sim.c.device)
     rec = {}
@@ -214,14 +220,15 @@ def blended_run(net, seed: int = TEST_SEED, steps: int = BLEND_STEPS, dns_block:
     e0, e1 = _events()
     e0.record()
     while t + dns_block + jumps * JUMP <= steps:
-        sim.step(dns_block)
+        sim.step(seg)
         t += dns_block
         for _ in range(1 if mode == "leap" else jumps):
             net.forward(*u, leap, out=u, train=False)
         t += jumps * JUMP
         if record:
             rec[t] = tuple(x.clone() for x in u)
-    sim.step(steps - t)
+    # the tail in segment-sized steps (whole segments when dns_block divides it)
+    sim.step(int(round((steps - t) * seg / dns_block)))
     e1.record()
     torch.cuda.synchronize()
     state = tuple(x.clone() for x in u)
@@ -251,12 +258,14 @@ def compare(net, seed: int = TEST_SEED, steps: int = BLEND_STEPS, dt_factors=(0.
                 "S2": M.rel_l2(s2, s2_ref), "S2_radial": M.rel_l2(M.radial_average(s2, n // 4), ra_ref)}
 
     out = {"steps": steps, "n": n, "seed": seed, "dns_ms": round(ms_ref, 3), "runs": {}}
-    for mode in ("leap", "chain"):
-        st, ms, _ = blended_run(net, seed, steps, mode=mode, n=n)
-        ms = min([ms] + [blended_run(net, seed, steps, mode=mode, n=n)[1] for _ in range(reps - 1)])
-        out["runs"][f"blend_{mode}"] = {"ms": round(ms, 3), "errors": errors(st)}
+    fast = max(dt_factors)
+    for mode, f in (("leap", 0.2), ("chain", 0.2), ("leap", fast)):
+        key = f"blend_{mode}" if f == 0.2 else f"blend_{mode}_dns{f}"
+        st, ms, _ = blended_run(net, seed, steps, mode=mode, n=n, dns_factor=f)
+        ms = min([ms] + [blended_run(net, seed, steps, mode=mode, n=n, dns_factor=f)[1] for _ in range(reps - 1)])
+        out["runs"][key] = {"ms": round(ms, 3), "errors": errors(st)}
         if log:
-            log(f"blended {mode}: {ms:.2f} ms {out['runs'][f'blend_{mode}']['errors']}")
+            log(f"blended {key}: {ms:.2f} ms {out['runs'][key]['errors']}")
     for f in dt_factors:
         st, ms, _ = dns_run(seed, steps, f, n)
         ms = min([ms] + [dns_run(seed, steps, f, n)[1] for _ in range(reps - 1)])
@@ -264,10 +273,22 @@ def compare(net, seed: int = TEST_SEED, steps: int = BLEND_STEPS, dt_factors=(0.
         if log:
             log(f"dns dt {f}: {ms:.2f} ms {out['runs'][f'dns_{f}']['errors']}")
     b = out["runs"]["blend_leap"]
-    ok = [r for k, r in out["runs"].items() if k.startswith("dns_") and r["errors"]["S2"] <= b["errors"]["S2"]]
-    best = min([ms_ref] + [r["ms"] for r in ok])
     out["speedup_same_dt"] = round(ms_ref / b["ms"], 3)
-    out["speedup_fixed_error"] = round(best / b["ms"], 3)
+    # at fixed error: for each blended run, the fastest plain DNS whose S2
+    # error does not exceed the blended run's, over the blended run's time;
+    # the headline is the best blended configuration
+    best_key, best_ratio = None, 0.0
+    for key, r in out["runs"].items():
+        if not key.startswith("blend_"):
+            continue
+        ok = [d["ms"] for k, d in out["runs"].items()
+              if k.startswith("dns_") and d["errors"]["S2"] <= r["errors"]["S2"]]
+        r["dns_at_same_error_ms"] = min([ms_ref] + ok)
+        r["speedup_fixed_error"] = round(r["dns_at_same_error_ms"] / r["ms"], 3)
+        if r["speedup_fixed_error"] > best_ratio:
+            best_key, best_ratio = key, r["speedup_fixed_error"]
+    out["speedup_fixed_error"] = best_ratio
+    out["best_blend"] = best_key
     return out
 
 

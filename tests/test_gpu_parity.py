@@ -251,6 +251,52 @@ def test_march_chunk_heights_are_bitwise(prec):
         sim.close()
 
 
+@pytest.mark.parametrize("shape", [(150, 100), (250, 61), (6, 20), (124, 9)])
+def test_two_columns_per_lane_is_bitwise(shape):
+    """FP32 single-step kernel with two grid columns per lane (even nx:
+    ragged last strip, a strip wider than the grid, one exact strip) equals
+    the one-column kernel bit for bit (which equals the LDS-tiled kernel, see
+    above), at every chunk height, for Euler, the midpoint method and
+    interface draws."""
+    nx, ny = shape
+    announce(f"two columns per lane f32 {nx}x{ny}")
+    p = PFParams(nx=nx, ny=ny, precision="f32", theta_deg=58.0, v0=0.9)
+    state = random_state(28, 1, ny, nx)
+    ref = Sim(p, state=state, temporal_block=1, lane_cols=1)
+    ref.step(37)
+    base, qb = ref.state(), ref.inflow()
+    ref.close()
+    for rows in (4, 8, 16, 32):
+        sim = Sim(p, state=state, temporal_block=1, tile_rows=rows, lane_cols=2)
+        assert sim.lane_cols == 2
+        sim.step(37)
+        for u, v in zip(sim.state(), base):
+            assert np.array_equal(u, v), f"rows={rows}"
+        assert np.array_equal(sim.inflow(), qb), f"rows={rows}"
+        sim.close()
+    for variant in (dict(integrator="midpoint"), dict(interface_noise=0.1)):
+        q = p.replace(**variant)
+        out = []
+        for cols in (1, 2):
+            sim = Sim(q, state=state, lane_cols=cols)
+            assert sim.lane_cols == cols
+            sim.step(23)
+            sim.step(14)
+            out.append((sim.state(), sim.inflow()))
+            sim.close()
+        for u, v in zip(out[0][0], out[1][0]):
+            assert np.array_equal(u, v), str(variant)
+        assert np.array_equal(out[0][1], out[1][1]), str(variant)
+
+
+def test_two_columns_need_even_rows_and_fp32():
+    announce("two columns per lane fallback")
+    for q in (PFParams(nx=151, ny=40, precision="f32"), PFParams(nx=150, ny=40, precision="f64")):
+        sim = Sim(q, temporal_block=1, lane_cols=2)
+        assert sim.lane_cols == 1
+        sim.close()
+
+
 def test_runs_are_deterministic():
     announce("determinism")
     p = workloads.dns_small(1, "f32").replace(nx=256, ny=192)
