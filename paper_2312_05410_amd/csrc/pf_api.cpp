@@ -281,7 +281,7 @@ int ensure_graph(pf_handle* h)
     hipGraphExec_t ex = nullptr;
     if (e == hipSuccess) e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
     if (e != hipSuccess) {
-        if (g) hipGraphDestroy(g);
+        if (g) (void)hipGraphDestroy(g);  // the first error is the one reported
         return hip_fail(h, e);
     }
     h->graph = g;
@@ -448,17 +448,22 @@ int pf_init(pf_handle** out, const pf_params* p, void* c, void* phi, void* rho, 
     if (p->tile_rows > 0) {
         h->march_ty = p->tile_rows;
     } else {
-        // strip-march chunk height: 8 rows when that still gives about four
-        // waves per SIMD, else 4 (shorter chunks cost more row halo)
+        // strip-march chunk height: 8 rows for one large grid (when that still
+        // gives about four waves per SIMD), else 4 (shorter chunks cost more
+        // row halo; measured on MI355X, 32 x 512^2 runs at 251 GLUPS with 4
+        // rows against 237 with 8)
         const long strips = (p->nx + 59) / 60;
-        h->march_ty = strips * ((p->ny + 7) / 8) * (long)p->batch >= 4096 ? 8 : 4;
+        h->march_ty = p->batch == 1 && strips * ((p->ny + 7) / 8) >= 4096 ? 8 : 4;
     }
     // two grid columns per lane (FP32 with an even row length): on request,
     // and by default from ~8M cells per launch, where the step streams from
-    // HBM and the halved neighbour exchange pays (measured on MI355X: +4 % at
-    // 4096^2, +6 % at 8192^2; at 2048^2 and below one column is faster)
+    // HBM and the halved neighbour exchange pays (measured on MI355X: +2 % at
+    // 4096^2, +7 % at 8192^2; at 2048^2 and below one column is faster),
+    // unless the wider strips compute more columns in all (32 x 512^2: 640
+    // computed columns per row against 576)
     const bool two_ok = p->precision == PF_F32 && p->nx % 2 == 0;
-    const int cols = p->lane_cols ? p->lane_cols : (cells >= 8000000L ? 2 : 1);
+    const long w1 = (p->nx + 59) / 60 * 64L, w2 = (p->nx + 123) / 124 * 128L;
+    const int cols = p->lane_cols ? p->lane_cols : (cells >= 8000000L && w2 <= w1 ? 2 : 1);
     h->march_cols = cols == 2 && two_ok ? 2 : 1;
 
     const double th = p->theta_deg * (3.14159265358979323846 / 180.0);
@@ -592,8 +597,9 @@ int pf_set_inflow(pf_handle* h, const double* Q)
 void pf_destroy(pf_handle* h)
 {
     if (!h) return;
-    if (h->gexec) hipGraphExecDestroy(h->gexec);
-    if (h->graph) hipGraphDestroy(h->graph);
+    // teardown: nothing to report to a caller that is discarding the handle
+    if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
     delete h;
 }
 
