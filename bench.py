@@ -103,8 +103,11 @@ def launches_for(steps: int, K: int) -> int:
     return L
 
 
-def kernel_name(prec: str, K: int, rows: int, base: bool = False, noise: bool = False, cols: int = 1) -> str:
+def kernel_name(prec: str, K: int, rows: int, base: bool = False, noise: bool = False, cols: int = 1,
+                fused: int = 1) -> str:
     t = "float" if prec == "f32" else "double"
+    if K == 2 and fused == 2:                     # two steps in the register strip march
+        return f"march_k2_kernel<{t}, {rows}, {rows + 1 if rows <= 8 else 4}>"
     if K == 1:
         ahead = rows + 1 if rows <= 8 else 4      # load look-ahead rows of the strip-march kernel
         b = "true" if base else "false"           # second midpoint stage: update added to a base state
@@ -129,6 +132,7 @@ def gpu_leg(args, p, steps, warmup, K):
     sim = Simulator(p, temporal_block=K, graph_mode=args.graph_mode, lane_cols=args.lane_cols)
     Kr, rows = sim.launch
     cols = sim.lane_cols
+    fused = sim.fused_kernel
     dt_s, wall = time_steps(sim, steps, warmup)
     m = sim.mass()
     e = sim.energy()
@@ -136,7 +140,8 @@ def gpu_leg(args, p, steps, warmup, K):
     sim.close()
     cells = p.nx * p.ny * p.batch
     glups = cells * steps / dt_s / 1e9
-    return dict(seconds=dt_s, wall=wall, glups=glups, launches=launches_for(steps, Kr), K=Kr, rows=rows, cols=cols)
+    return dict(seconds=dt_s, wall=wall, glups=glups, launches=launches_for(steps, Kr), K=Kr, rows=rows, cols=cols,
+                fused=fused)
 
 
 def measured_traffic(workload: str, kernel: str):
@@ -170,13 +175,13 @@ def sweep(K, graph_mode, lane_cols=0, sizes=(1024, 2048, 4096, 8192)):
         steps = max(40, int(4e9 / (n * n)) // 2 * 2)
         sim = Simulator(p, temporal_block=K, graph_mode=graph_mode, lane_cols=lane_cols)
         Kr, rows = sim.launch
-        cols = sim.lane_cols
+        cols, fused = sim.lane_cols, sim.fused_kernel
         dt_s, _ = time_steps(sim, steps, 20)
         sim.close()
         glups = n * n * steps / dt_s / 1e9
         state_mb = 3 * n * n * 4 / 1e6
         out.append(dict(n=n, steps=steps, state_MB=round(state_mb, 1), glups=round(glups, 2),
-                        kernel=kernel_name("f32", Kr, rows, cols=cols),
+                        kernel=kernel_name("f32", Kr, rows, cols=cols, fused=fused),
                         effective_GBs=round(glups * BYTES_PER_LUP["f32"], 1),
                         frac_hbm=round(glups * BYTES_PER_LUP["f32"] / HBM_PEAK_GBS, 4)))
         print(f"# sweep {n}^2: {glups:.1f} GLUPS", file=sys.stderr, flush=True)
@@ -457,7 +462,7 @@ def main():
                  kernel_name(prec, 1, g["rows"], base=True, noise=noise, cols=g["cols"]))
     else:
         bytes_per_launch = BYTES_PER_LUP[prec] * cells * steps / g["launches"]
-        kname = kernel_name(prec, g["K"], g["rows"], noise=noise, cols=g["cols"])
+        kname = kernel_name(prec, g["K"], g["rows"], noise=noise, cols=g["cols"], fused=g["fused"])
     launch_s = g["seconds"] / g["launches"]
     achieved = bytes_per_launch / launch_s / 1e9
     tb = measured_traffic(args.workload, kname)
@@ -477,7 +482,7 @@ def main():
         "data": "synthetic (seeded; parameter ranges of the paper's dataset)",
         "config": {"workload": args.workload, "nx": p.nx, "ny": p.ny, "batch": p.batch,
                    "steps_total": total_steps, "temporal_block": g["K"], "tile_rows": g["rows"],
-                   "lane_cols": g["cols"],
+                   "lane_cols": g["cols"], "fused_kernel": g["fused"],
                    "launches": g["launches"],
                    "graph_mode": args.graph_mode,
                    "seed": p.seed, "dt": None, "integrator": p.integrator,

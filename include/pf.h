@@ -88,6 +88,11 @@ enum pf_integrator { PF_EULER = 0, PF_MIDPOINT = 1 };
  *   Both variants run the single-step kernel (temporal_block 0 or 1);
  *   interface_noise also runs plain launches (no graph replay).
  */
+/* Kernel of the launches that fuse several steps: a 64 x TY tile staged in
+ * LDS (any K), or the register strip march (K = 2: one wave per 64-column
+ * strip, radius-4 halo, the intermediate state kept in registers). */
+enum pf_fused { PF_FUSED_AUTO = 0, PF_FUSED_TILE = 1, PF_FUSED_MARCH = 2 };
+
 typedef struct pf_params {
     int32_t nx, ny, batch;        /* grid cells and independent realisations */
     int32_t precision;            /* pf_precision: storage and arithmetic type */
@@ -114,6 +119,9 @@ typedef struct pf_params {
     double interface_noise;       /* standard deviation of the interface draw, 0..1; 0: off */
     int32_t lane_cols;            /* single-step FP32 kernel: grid columns per lane, 1 or 2 (2 needs
                                      an even nx; else 1 is used); 0: library's choice */
+    int32_t fused_kernel;         /* pf_fused: kernel of launches that fuse steps (temporal_block
+                                     > 1); PF_FUSED_MARCH fuses exactly 2, with tile_rows (4, 8 or 16,
+                                     dividing ny; else 8 or 4) rows per wave; 0: library's choice */
 } pf_params;
 
 /* Bytes of device workspace a handle for *p needs (ping-pong copy of the
@@ -176,6 +184,11 @@ int pf_get_launch(const pf_handle* h, int32_t* temporal_block, int32_t* tile_row
 /* Grid columns per lane of the single-step kernel the handle launches (1 or
  * 2; 1 whenever temporal_block > 1).  PF_EINVAL on a null argument. */
 int pf_get_lane_cols(const pf_handle* h, int32_t* lane_cols);
+
+/* pf_fused kind of the handle's fused launches (PF_FUSED_TILE or
+ * PF_FUSED_MARCH; 0 when each launch is one step).  PF_EINVAL on a null
+ * argument. */
+int pf_get_fused_kernel(const pf_handle* h, int32_t* kind);
 
 /* ------------------------------------------------------------------ adjoint
  * Discrete adjoint of the explicit step, for gradients of a loss of the

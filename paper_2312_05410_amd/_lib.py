@@ -23,11 +23,12 @@ PF_F32, PF_F64 = 0, 1
 PF_BC_PVD, PF_BC_PERIODIC = 0, 1
 PF_INIT_SEEDED, PF_INIT_KEEP = 0, 1
 PF_INTEGRATOR = {"euler": 0, "midpoint": 1}
+PF_FUSED_TILE, PF_FUSED_MARCH = 1, 2
 
 EXPORTS = (
     "pf_workspace_bytes", "pf_dt_limit", "pf_init", "pf_step_n", "pf_mass", "pf_energy",
     "pf_get_step", "pf_set_step", "pf_get_dt", "pf_get_inflow", "pf_set_inflow",
-    "pf_destroy", "pf_strerror", "pf_last_hip_error", "pf_get_launch", "pf_get_lane_cols",
+    "pf_destroy", "pf_strerror", "pf_last_hip_error", "pf_get_launch", "pf_get_lane_cols", "pf_get_fused_kernel",
     "pf_adjoint_workspace_bytes", "pf_adjoint_step", "pf_adjoint_reset", "pf_adjoint_grad",
 )
 
@@ -53,7 +54,7 @@ class PFParamsC(ctypes.Structure):
         ("c0", ctypes.c_double), ("c_noise", ctypes.c_double), ("film_h", ctypes.c_double),
         ("v0_per", ctypes.c_void_p), ("c0_per", ctypes.c_void_p),
         ("interface_noise", ctypes.c_double),
-        ("lane_cols", ctypes.c_int32),
+        ("lane_cols", ctypes.c_int32), ("fused_kernel", ctypes.c_int32),
     ]
 
 
@@ -107,6 +108,8 @@ def load():
         L.pf_get_launch.restype = ctypes.c_int
         L.pf_get_lane_cols.argtypes = [H, ctypes.POINTER(ctypes.c_int32)]
         L.pf_get_lane_cols.restype = ctypes.c_int
+        L.pf_get_fused_kernel.argtypes = [H, ctypes.POINTER(ctypes.c_int32)]
+        L.pf_get_fused_kernel.restype = ctypes.c_int
         L.pf_adjoint_workspace_bytes.argtypes = [P]
         L.pf_adjoint_workspace_bytes.restype = ctypes.c_size_t
         L.pf_adjoint_step.argtypes = [H] * 11 + [ctypes.c_size_t]
@@ -131,7 +134,8 @@ _BC = {"pvd": PF_BC_PVD, "periodic": PF_BC_PERIODIC}
 
 
 def to_c(p: PFParams, init_mode: int = PF_INIT_SEEDED, temporal_block: int = 0,
-         allow_unstable: bool = False, graph_mode: int = 0, tile_rows: int = 0, lane_cols: int = 0):
+         allow_unstable: bool = False, graph_mode: int = 0, tile_rows: int = 0, lane_cols: int = 0,
+         fused_kernel: int = 0):
     """Build the C struct; returns (struct, keep-alive arrays)."""
     keep = []
 
@@ -156,7 +160,7 @@ def to_c(p: PFParams, init_mode: int = PF_INIT_SEEDED, temporal_block: int = 0,
         D_rho=p.D_rho, v0=p.v0, theta_deg=p.theta_deg, rho_in=p.rho_in,
         c0=p.c0, c_noise=p.c_noise, film_h=p.film_h,
         v0_per=arr(p.v0_per), c0_per=arr(p.c0_per), interface_noise=float(p.interface_noise),
-        lane_cols=lane_cols)
+        lane_cols=lane_cols, fused_kernel=fused_kernel)
     return s, keep
 
 
@@ -183,7 +187,7 @@ class Simulator:
 
     def __init__(self, p: PFParams, state=None, temporal_block: int = 0, device: str = "cuda",
                  allow_unstable: bool = False, graph_mode: int = 0, tile_rows: int = 0, tensors=None,
-                 lane_cols: int = 0):
+                 lane_cols: int = 0, fused_kernel: int = 0):
         """state: host arrays copied to the device as the initial condition;
         tensors: (c, phi, rho) device tensors stepped in place (no copy);
         neither: the seeded initial condition."""
@@ -211,7 +215,8 @@ class Simulator:
                 for u in state)
             mode = PF_INIT_KEEP
         s, keep = to_c(p, init_mode=mode, temporal_block=temporal_block, allow_unstable=allow_unstable,
-                       graph_mode=graph_mode, tile_rows=tile_rows, lane_cols=lane_cols)
+                       graph_mode=graph_mode, tile_rows=tile_rows, lane_cols=lane_cols,
+                       fused_kernel=fused_kernel)
         nbytes = L.pf_workspace_bytes(ctypes.byref(s))
         if nbytes == 0:
             raise PFError(PF_EINVAL, "pf_workspace_bytes")
@@ -273,6 +278,14 @@ class Simulator:
         """Grid columns per lane of the single-step kernel (1 or 2)."""
         c = ctypes.c_int32()
         self._check(load().pf_get_lane_cols(self._h, ctypes.byref(c)), "pf_get_lane_cols")
+        return c.value
+
+    @property
+    def fused_kernel(self) -> int:
+        """Kernel of the fused launches: 1 LDS tile, 2 register strip march,
+        0 when each launch is one step."""
+        c = ctypes.c_int32()
+        self._check(load().pf_get_fused_kernel(self._h, ctypes.byref(c)), "pf_get_fused_kernel")
         return c.value
 
     @property

@@ -72,6 +72,9 @@ int validate(const pf_params* p)
         return PF_EINVAL;
     if (p->integrator != PF_EULER && p->integrator != PF_MIDPOINT) return PF_EINVAL;
     if (p->lane_cols < 0 || p->lane_cols > 2) return PF_EINVAL;
+    if (p->fused_kernel < 0 || p->fused_kernel > PF_FUSED_MARCH) return PF_EINVAL;
+    // the register strip march fuses exactly two steps
+    if (p->fused_kernel == PF_FUSED_MARCH && p->temporal_block > 2) return PF_EINVAL;
     if (!std::isfinite(p->interface_noise) || p->interface_noise < 0 || p->interface_noise > 1) return PF_EINVAL;
     // the variants run on the single-step kernel
     if ((p->integrator != PF_EULER || p->interface_noise > 0) && p->temporal_block > 1) return PF_EINVAL;
@@ -130,6 +133,8 @@ struct pf_handle {
     int K = 1;
     int march_ty = 16;                   // K == 1: rows per wave of the strip-march kernel
     int march_cols = 1;                  // K == 1: grid columns per lane (2: FP32, even nx)
+    int fused = PF_FUSED_TILE;           // K >= 2: LDS tile or register strip march (K == 2)
+    int k2_ty = 8;                       // register strip march: rows per wave
     int last_hip = 0;
     hipGraph_t graph = nullptr;          // chain of kGraphLen full-K launches
     hipGraphExec_t gexec = nullptr;
@@ -274,8 +279,9 @@ int ensure_graph(pf_handle* h)
             a.nsub = h->K;
         }
         hipGraphNode_t node = nullptr;
-        e = h->K == 1 ? pfk::graph_add_march<T>(g, &node, prev, a, h->march_ty, h->march_cols, h->p.batch)
-                      : pfk::graph_add_step<T>(g, &node, prev, a, h->K, h->p.batch);
+        if (h->K == 1) e = pfk::graph_add_march<T>(g, &node, prev, a, h->march_ty, h->march_cols, h->p.batch);
+        else if (h->fused == PF_FUSED_MARCH) e = pfk::graph_add_march_k2<T>(g, &node, prev, a, h->k2_ty, h->p.batch);
+        else e = pfk::graph_add_step<T>(g, &node, prev, a, h->K, h->p.batch);
         prev = node;
     }
     hipGraphExec_t ex = nullptr;
@@ -335,8 +341,11 @@ int enqueue_steps(pf_handle* h, int64_t n)
         set_parity<T>(h, a, parity);
         a.nsub = plan[l];
         a.step = h->step + (int64_t)l;  // one step per launch whenever draws are on (K = 1)
-        const hipError_t e = K == 1 ? pfk::launch_march<T>(a, h->march_ty, h->march_cols, p->batch, h->stream)
-                                    : pfk::launch_step<T>(a, K, p->batch, h->stream);
+        hipError_t e;
+        if (K == 1) e = pfk::launch_march<T>(a, h->march_ty, h->march_cols, p->batch, h->stream);
+        else if (h->fused != PF_FUSED_MARCH) e = pfk::launch_step<T>(a, K, p->batch, h->stream);
+        else if (a.nsub == 2) e = pfk::launch_march_k2<T>(a, h->k2_ty, p->batch, h->stream);
+        else e = pfk::launch_march<T>(a, h->march_ty, h->march_cols, p->batch, h->stream);  // odd step
         if ((rc = hip_fail(h, e))) return rc;
         parity ^= 1;
     }
@@ -440,8 +449,18 @@ int pf_init(pf_handle** out, const pf_params* p, void* c, void* phi, void* rho, 
     // and for FP64.  The mirror ghosts of a launch must be real rows, so
     // 2K <= ny.
     const long cells = (long)p->nx * p->ny * p->batch;
+    // FP32 Euler runs fuse two steps by default (measured on MI355X): the
+    // LDS tile for one grid of ~0.75M to ~3M cells (1024^2: 155 GLUPS
+    // against 151 for the register march), the register strip march
+    // otherwise when a chunk height divides ny (512^2: 73 against 59 for
+    // single steps; 2048^2 266, 4096^2 297, 8192^2 343 against 221, 171,
+    // 214; 32 x 512^2 274 against 250)
+    const bool f32_euler = p->precision == PF_F32 && p->integrator == PF_EULER && !(p->interface_noise > 0);
+    const bool tile_band = p->batch == 1 && cells >= 786432L && cells < 3000000L;
+    const int k2_auto_ty = cells >= 3000000L ? (p->batch == 1 ? 16 : 8) : 4;
     int K = p->temporal_block;
-    if (K == 0) K = (p->precision == PF_F32 && cells >= 786432L && cells < 3000000L) ? 2 : 1;
+    if (K == 0 && f32_euler) K = tile_band || p->ny % 4 == 0 ? 2 : 1;
+    if (K == 0) K = 1;
     if (p->integrator != PF_EULER || p->interface_noise > 0) K = 1;
     while (K > 1 && 2 * K > p->ny) --K;
     h->K = K;
@@ -465,6 +484,22 @@ int pf_init(pf_handle** out, const pf_params* p, void* c, void* phi, void* rho, 
     const long w1 = (p->nx + 59) / 60 * 64L, w2 = (p->nx + 123) / 124 * 128L;
     const int cols = p->lane_cols ? p->lane_cols : (cells >= 8000000L && w2 <= w1 ? 2 : 1);
     h->march_cols = cols == 2 && two_ok ? 2 : 1;
+    // fused steps: the LDS tile, or the register strip march when asked for
+    // (two steps, chunk heights dividing ny)
+    h->fused = PF_FUSED_TILE;
+    const bool march_k2 = p->fused_kernel == PF_FUSED_MARCH ||
+                          (p->fused_kernel == PF_FUSED_AUTO && p->precision == PF_F32 && !tile_band);
+    if (K == 2 && march_k2) {
+        const int auto_ty = p->fused_kernel == PF_FUSED_MARCH ? 8 : k2_auto_ty;
+        const int want = p->tile_rows == 4 || p->tile_rows == 8 || p->tile_rows == 16 ? p->tile_rows : auto_ty;
+        for (int ty : {want, 8, 4}) {
+            if (p->ny % ty == 0) {
+                h->fused = PF_FUSED_MARCH;
+                h->k2_ty = ty;
+                break;
+            }
+        }
+    }
 
     const double th = p->theta_deg * (3.14159265358979323846 / 180.0);
     h->real.resize(p->batch);
@@ -733,8 +768,16 @@ extern "C" int pf_get_launch(const pf_handle* h, int32_t* temporal_block, int32_
 {
     if (!h || !temporal_block || !tile_rows) return PF_EINVAL;
     *temporal_block = h->K;
-    *tile_rows = h->K == 1 ? h->march_ty : pfk::tile_cfg<float>(h->K).ty;
-    if (h->p.precision == PF_F64 && h->K > 1) *tile_rows = pfk::tile_cfg<double>(h->K).ty;
+    *tile_rows = h->K == 1 ? h->march_ty : (h->fused == PF_FUSED_MARCH ? h->k2_ty : pfk::tile_cfg<float>(h->K).ty);
+    if (h->p.precision == PF_F64 && h->K > 1 && h->fused != PF_FUSED_MARCH)
+        *tile_rows = pfk::tile_cfg<double>(h->K).ty;
+    return PF_OK;
+}
+
+extern "C" int pf_get_fused_kernel(const pf_handle* h, int32_t* kind)
+{
+    if (!h || !kind) return PF_EINVAL;
+    *kind = h->K == 1 ? 0 : h->fused;
     return PF_OK;
 }
 

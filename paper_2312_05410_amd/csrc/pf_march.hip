@@ -362,6 +362,160 @@ __global__ __launch_bounds__(64) void march2_kernel(StepArgs<float> a)
     }
 }
 
+// Two fused steps per march (temporal blocking in registers): the strip is
+// 64 lanes wide with a radius-4 halo, so it writes 56 columns (lanes 4..59),
+// and a TY-row chunk reads TY + 8 rows.  Behind the front of loads the wave
+// runs four stages per row, each lagging the previous: stage 1 and 2 of the
+// first step (giving the intermediate state u1 in registers), then stage 1
+// and 2 of the second step on u1.  The intermediate state obeys the same
+// boundary rule as a stored state: in a substrate/inlet run the u1 rows
+// beyond the substrate or the top take the mirrored interior u1 rows (and
+// the inlet value for rho at the top) before the second step reads them; the
+// chunk heights divide ny, so those rows sit at fixed chunk positions.  Each
+// cell is evaluated by the same per-cell functions in the same order as in
+// two single-step launches, so the result is bitwise identical.
+constexpr int kStripOutK2 = 56;
+
+template <typename T, int TY, int D>
+__global__ __launch_bounds__(64) void march_k2_kernel(StepArgs<T> a)
+{
+    constexpr int NR = TY + 8;
+    const int lane = threadIdx.x;
+    const int b = blockIdx.y;
+    const int nx = a.nx, ny = a.ny;
+    const int nstrip = a.tiles_x;
+
+    const int nblk = a.tiles_x * a.tiles_y;
+    const int bid = blockIdx.x;
+    const int xcd = bid & 7, slot = bid >> 3;
+    const int q8 = nblk >> 3, r8 = nblk & 7;
+    const int tileid = xcd * q8 + (xcd < r8 ? xcd : r8) + slot;
+    const int strip = tileid % nstrip;
+    const int y0 = (tileid / nstrip) * TY;
+
+    int gx = strip * kStripOutK2 - 4 + lane;
+    while (gx < 0) gx += nx;
+    while (gx >= nx) gx -= nx;
+    const int ocol = strip * kStripOutK2 + lane - 4;
+    const bool out_lane = lane >= 4 && lane < 4 + kStripOutK2 && ocol < nx;
+
+    const size_t plane = (size_t)nx * ny;
+    const auto bc = plane_rsrc(a.c + (size_t)b * plane, plane);
+    const auto bp = plane_rsrc(a.phi + (size_t)b * plane, plane);
+    const auto br = plane_rsrc(a.rho + (size_t)b * plane, plane);
+    const auto oc = plane_rsrc(a.c_out + (size_t)b * plane, plane);
+    const auto op = plane_rsrc(a.phi_out + (size_t)b * plane, plane);
+    const auto orr = plane_rsrc(a.rho_out + (size_t)b * plane, plane);
+    const int vo = gx * (int)sizeof(T);
+    const int row_bytes = nx * (int)sizeof(T);
+    const Coef<T> k = a.k;
+    const Real rl = a.real[b];
+    const T vx2h = (T)rl.vx2h, vy2h = (T)rl.vy2h;
+    const int pvd = a.pvd;
+    const bool bot = pvd && y0 == 0;         // rows t < 4 are beyond the substrate
+    const bool top = pvd && y0 + TY == ny;   // rows t >= TY + 4 are beyond the top
+
+    // first step: input u0, stage-1 values, north fluxes
+    T c[NR], p[NR], r[NR];
+    T mc[NR], mp[NR], M[NR], pE[NR], pW[NR], FN[NR];
+    // second step: the same on u1
+    T c1[NR], p1[NR], r1[NR];
+    T mc1[NR], mp1[NR], M1[NR], pE1[NR], pW1[NR], FN1[NR];
+    const RhoCoef<T> rc = rho_coef(k, vx2h, vy2h);
+
+    auto load_row = [&](int t) {
+        const int gj = y0 - 4 + t;
+        int jj;
+        if (pvd) jj = gj < 0 ? -1 - gj : (gj >= ny ? 2 * ny - 1 - gj : gj);
+        else jj = gj < 0 ? gj + ny : (gj >= ny ? gj - ny : gj);
+        jj = jj < 0 ? 0 : (jj >= ny ? ny - 1 : jj);
+        const int so = jj * row_bytes;
+        c[t] = Buf<T>::ld(bc, vo, so);
+        p[t] = Buf<T>::ld(bp, vo, so);
+        const T rv = Buf<T>::ld(br, vo, so);
+        r[t] = (pvd && gj >= ny) ? k.rho_in : rv;
+    };
+    auto inflow = [&](int gj, T rr) {
+        // inflow through the top face in the sub-step that updates row gj
+        if (a.Qcol && top && gj == ny - 1 && out_lane) {
+            double* q = a.Qcol + (size_t)b * nx + ocol;
+            const double rin = (double)k.rho_in, rd = (double)rr;
+            *q = *q + (rl.qa * (rd + rin) + rl.qb * (rin - rd));
+        }
+    };
+
+#pragma unroll
+    for (int t = 0; t < NR; ++t)
+        if (t < 3 + D) load_row(t);
+
+#pragma unroll
+    for (int f = 1; f <= NR; ++f) {
+        if (f + 2 + D < NR) load_row(f + 2 + D);
+        // step 1, stage 1 at row f
+        if (f <= NR - 2) {
+            const T cE = east(c[f]), cW = west(c[f]);
+            pE[f] = east(p[f]);
+            pW[f] = west(p[f]);
+            potentials(k, c[f], cE, cW, c[f + 1], c[f - 1], p[f], pE[f], pW[f], p[f + 1], p[f - 1], mc[f], mp[f],
+                       M[f]);
+        }
+        // step 1, stage 2 at row t = f - 1: u1
+        if (f - 1 >= 2 && f - 1 <= NR - 3) {
+            const int t = f - 1;
+            const int gj = y0 - 4 + t;
+            const bool bottom = pvd && gj == 0;
+            if (t == 2) FN[1] = cflux(M[1], mc[1], M[2], mc[2]);
+            const T FE = cflux(M[t], mc[t], east(M[t]), east(mc[t]));
+            FN[t] = cflux(M[t], mc[t], M[t + 1], mc[t + 1]);
+            update(k, rc, vx2h, vy2h, bottom, c[t], p[t], pE[t], pW[t], p[t + 1], p[t - 1], r[t], east(r[t]),
+                   west(r[t]), r[t + 1], r[t - 1], FE, west(FE), FN[t], FN[t - 1], mp[t], east(mp[t]), west(mp[t]),
+                   mp[t + 1], mp[t - 1], c1[t], p1[t], r1[t]);
+            if (t >= 4 && t < TY + 4) inflow(gj, r[t]);
+            // the boundary rule on u1: at the top the rows beyond the grid
+            // mirror rows already computed; at the substrate rows 2 and 3
+            // mirror rows 5 and 4, complete once row 5 is
+            if (t >= TY + 4 && top) {
+                c1[t] = c1[2 * TY + 7 - t];
+                p1[t] = p1[2 * TY + 7 - t];
+                r1[t] = k.rho_in;
+            }
+            if (t == 5 && bot) {
+                c1[3] = c1[4], p1[3] = p1[4], r1[3] = r1[4];
+                c1[2] = c1[5], p1[2] = p1[5], r1[2] = r1[5];
+            }
+        }
+        // step 2, stage 1 at row t2 = f - 4 (u1 rows t2 - 1 .. t2 + 1 are final)
+        if (f - 4 >= 3 && f - 4 <= NR - 4) {
+            const int t = f - 4;
+            const T cE = east(c1[t]), cW = west(c1[t]);
+            pE1[t] = east(p1[t]);
+            pW1[t] = west(p1[t]);
+            potentials(k, c1[t], cE, cW, c1[t + 1], c1[t - 1], p1[t], pE1[t], pW1[t], p1[t + 1], p1[t - 1],
+                       mc1[t], mp1[t], M1[t]);
+        }
+        // step 2, stage 2 at row t3 = f - 5: the output row
+        if (f - 5 >= 4 && f - 5 <= NR - 5) {
+            const int t = f - 5;
+            const int gj = y0 - 4 + t;
+            const bool bottom = pvd && gj == 0;
+            if (t == 4) FN1[3] = cflux(M1[3], mc1[3], M1[4], mc1[4]);
+            const T FE = cflux(M1[t], mc1[t], east(M1[t]), east(mc1[t]));
+            FN1[t] = cflux(M1[t], mc1[t], M1[t + 1], mc1[t + 1]);
+            T nc, np, nr;
+            update(k, rc, vx2h, vy2h, bottom, c1[t], p1[t], pE1[t], pW1[t], p1[t + 1], p1[t - 1], r1[t],
+                   east(r1[t]), west(r1[t]), r1[t + 1], r1[t - 1], FE, west(FE), FN1[t], FN1[t - 1], mp1[t],
+                   east(mp1[t]), west(mp1[t]), mp1[t + 1], mp1[t - 1], nc, np, nr);
+            if (out_lane) {
+                const int so = gj * row_bytes;
+                Buf<T>::st(nc, oc, vo, so);
+                Buf<T>::st(np, op, vo, so);
+                Buf<T>::st(nr, orr, vo, so);
+            }
+            inflow(gj, r1[t]);
+        }
+    }
+}
+
 // rows of loads in flight ahead of use: short chunks issue all their loads
 // at once, long chunks keep a window of rows in flight
 template <int TY> constexpr int lookahead() { return TY <= 8 ? TY + 1 : 4; }
@@ -433,6 +587,38 @@ hipError_t node_march_ty(hipGraph_t g, hipGraphNode_t* node, hipGraphNode_t dep,
 
 }  // namespace
 
+template <typename T, int TY>
+hipError_t k2_node_or_launch(StepArgs<T> a, int batch, hipStream_t s, hipGraph_t g, hipGraphNode_t* node,
+                             hipGraphNode_t dep)
+{
+    a.tiles_x = (a.nx + kStripOutK2 - 1) / kStripOutK2;
+    a.tiles_y = a.ny / TY;
+    void* fn = (void*)march_k2_kernel<T, TY, lookahead<TY>()>;
+    void* args[] = {&a};
+    if (!g) return hipLaunchKernel(fn, dim3(a.tiles_x * a.tiles_y, batch), dim3(64), args, 0, s);
+    hipKernelNodeParams kp{};
+    kp.func = fn;
+    kp.gridDim = dim3(a.tiles_x * a.tiles_y, batch);
+    kp.blockDim = dim3(64);
+    kp.sharedMemBytes = 0;
+    kp.kernelParams = args;
+    kp.extra = nullptr;
+    return hipGraphAddKernelNode(node, g, dep ? &dep : nullptr, dep ? 1 : 0, &kp);
+}
+
+template <typename T>
+hipError_t k2_dispatch(const StepArgs<T>& a, int ty, int batch, hipStream_t s, hipGraph_t g,
+                       hipGraphNode_t* node, hipGraphNode_t dep)
+{
+    if (ty <= 0 || a.ny % ty != 0 || a.ny < 4) return hipErrorInvalidValue;
+    switch (ty) {
+    case 4: return k2_node_or_launch<T, 4>(a, batch, s, g, node, dep);
+    case 8: return k2_node_or_launch<T, 8>(a, batch, s, g, node, dep);
+    case 16: return k2_node_or_launch<T, 16>(a, batch, s, g, node, dep);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 template <typename T>
 hipError_t launch_march(const StepArgs<T>& a, int ty, int cols, int batch, hipStream_t s)
 {
@@ -463,5 +649,23 @@ template hipError_t graph_add_march<float>(hipGraph_t, hipGraphNode_t*, hipGraph
                                            int, int, int);
 template hipError_t graph_add_march<double>(hipGraph_t, hipGraphNode_t*, hipGraphNode_t, const StepArgs<double>&,
                                             int, int, int);
+
+template <typename T>
+hipError_t launch_march_k2(const StepArgs<T>& a, int ty, int batch, hipStream_t s)
+{
+    return k2_dispatch<T>(a, ty, batch, s, nullptr, nullptr, nullptr);
+}
+template <typename T>
+hipError_t graph_add_march_k2(hipGraph_t g, hipGraphNode_t* node, hipGraphNode_t dep, const StepArgs<T>& a, int ty,
+                              int batch)
+{
+    return k2_dispatch<T>(a, ty, batch, nullptr, g, node, dep);
+}
+template hipError_t launch_march_k2<float>(const StepArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_march_k2<double>(const StepArgs<double>&, int, int, hipStream_t);
+template hipError_t graph_add_march_k2<float>(hipGraph_t, hipGraphNode_t*, hipGraphNode_t, const StepArgs<float>&,
+                                              int, int);
+template hipError_t graph_add_march_k2<double>(hipGraph_t, hipGraphNode_t*, hipGraphNode_t,
+                                               const StepArgs<double>&, int, int);
 
 }  // namespace pfk

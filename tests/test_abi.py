@@ -40,6 +40,7 @@ def test_params_struct_layout():
     assert _lib.PFParamsC.integrator.offset == 44
     assert _lib.PFParamsC.interface_noise.offset == 56 + 21 * 8 + 16
     assert _lib.PFParamsC.lane_cols.offset == 56 + 21 * 8 + 24
+    assert _lib.PFParamsC.fused_kernel.offset == 56 + 21 * 8 + 28
     assert ctypes.sizeof(_lib.PFParamsC) == 56 + 21 * 8 + 32
 
 
@@ -107,6 +108,8 @@ def test_init_rejects_bad_pointers_and_workspace():
     assert _init(p, tile_rows=12)[0] == _lib.PF_EINVAL
     assert _init(p, lane_cols=3)[0] == _lib.PF_EINVAL
     assert _init(p, lane_cols=-1)[0] == _lib.PF_EINVAL
+    assert _init(p, fused_kernel=3)[0] == _lib.PF_EINVAL
+    assert _init(p, fused_kernel=2, temporal_block=3)[0] == _lib.PF_EINVAL
     assert _init(p.replace(precision="f64"), temporal_block=3)[0] == _lib.PF_EINVAL
     L = _lib.load()
     assert L.pf_step_n(None, 3) == _lib.PF_EINVAL

@@ -289,6 +289,51 @@ def test_two_columns_per_lane_is_bitwise(shape):
         assert np.array_equal(out[0][1], out[1][1]), str(variant)
 
 
+@pytest.mark.parametrize("prec,bc,shape", [("f32", "pvd", (150, 96)), ("f64", "pvd", (130, 64)),
+                                           ("f32", "periodic", (120, 48)), ("f32", "pvd", (6, 16)),
+                                           ("f32", "pvd", (100, 8))])
+def test_two_step_march_is_bitwise(prec, bc, shape):
+    """The register strip march fusing two steps equals single-step
+    launches bit for bit (state and inflow) at every chunk height dividing
+    ny, for odd step counts (the last step alone), graph replay and plain
+    launches."""
+    nx, ny = shape
+    announce(f"two-step march {prec} {bc} {nx}x{ny}")
+    p = PFParams(nx=nx, ny=ny, precision=prec, bc_mode=bc, theta_deg=61.0, v0=0.85)
+    state = random_state(29, 1, ny, nx)
+    ref = Sim(p, state=state, temporal_block=1, lane_cols=1)
+    ref.step(37)
+    ref.step(141)
+    base, qb = ref.state(), ref.inflow()
+    ref.close()
+    for rows in (4, 8, 16):
+        if ny % rows:
+            continue
+        for gm in (0, 1):
+            sim = Sim(p, state=state, temporal_block=2, tile_rows=rows, fused_kernel=2, graph_mode=gm)
+            assert sim.fused_kernel == 2 and sim.launch == (2, rows)
+            sim.step(37)
+            sim.step(141)
+            for u, v in zip(sim.state(), base):
+                assert np.array_equal(u, v), f"rows={rows} graph_mode={gm}"
+            assert np.array_equal(sim.inflow(), qb), f"rows={rows} graph_mode={gm}"
+            sim.close()
+
+
+def test_two_step_march_f64_matches_oracle():
+    announce("two-step march f64 vs oracle 96x64")
+    p = PFParams(nx=96, ny=64, precision="f64", theta_deg=70.0, v0=0.9, seed=4)
+    state = random_state(30, 1, 64, 96)
+    sim = Sim(p, state=state, temporal_block=2, fused_kernel=2)
+    assert sim.fused_kernel == 2
+    sim.step(60)
+    s = oracle.State(p, *state).step(60)
+    for a, b in zip(sim.state(), (s.c, s.phi, s.rho)):
+        assert np.linalg.norm(a - b) / np.linalg.norm(b) <= 1e-12
+    np.testing.assert_allclose(sim.mass(), s.mass(), rtol=1e-11, atol=1e-12)
+    sim.close()
+
+
 def test_two_columns_need_even_rows_and_fp32():
     announce("two columns per lane fallback")
     for q in (PFParams(nx=151, ny=40, precision="f32"), PFParams(nx=150, ny=40, precision="f64")):
