@@ -338,12 +338,13 @@ def unet_leg(args):
     x1 = torch.rand(n, cfg.height, cfg.width, 32, device="cuda").to(torch.bfloat16)
     x2 = torch.rand(n, cfg.height, cfg.width, 32, device="cuda").to(torch.bfloat16)
     w = torch.rand(9, 32, 64, device="cuda") - 0.5
-    U.conv3x3_fwd(x1, w, x2)
+    wp = U.conv3x3_prepare(w, 32, 32)
+    y = U.conv3x3_fwd_prepared(x1, wp, 32, x2)
     torch.cuda.synchronize()
     reps = 50
     e0.record()
     for _ in range(reps):
-        U.conv3x3_fwd(x1, w, x2)
+        U.conv3x3_fwd_prepared(x1, wp, 32, x2, out=y)
     e1.record()
     torch.cuda.synchronize()
     conv_s = e0.elapsed_time(e1) / reps / 1e3

@@ -133,6 +133,17 @@ size_t unet_op_workspace_bytes(int n, int H, int W, int Cmax);
  * NULL with C2 = 0); zero padding. */
 int unet_conv3x3_fwd(int n, int H, int W, const uint16_t* x1, int C1, const uint16_t* x2, int C2, const float* w,
                      int Cout, float* y, void* workspace, size_t workspace_bytes, void* stream);
+/* The same in two parts, for callers that apply one weight many times
+ * (inference, benchmarks): unet_conv3x3_prepare writes w's BF16 MFMA operand
+ * into the caller's wprep (256-byte aligned, at least
+ * unet_conv3x3_prep_bytes(C1, C2, Cout) bytes; 0 means invalid sizes), and
+ * unet_conv3x3_fwd_prepared runs the convolution from it, launching the
+ * convolution kernel alone.  wprep belongs to the caller and stays valid
+ * until it changes w or frees it; PF_EINVAL on bad sizes or alignment. */
+size_t unet_conv3x3_prep_bytes(int C1, int C2, int Cout);
+int unet_conv3x3_prepare(const float* w, int C1, int C2, int Cout, void* wprep, size_t bytes, void* stream);
+int unet_conv3x3_fwd_prepared(int n, int H, int W, const uint16_t* x1, int C1, const uint16_t* x2, int C2,
+                              const void* wprep, int Cout, float* y, void* stream);
 /* Input gradient: dx1 [n][H][W][C1], dx2 [n][H][W][C2] (or NULL) from
  * dy [n][H][W][Cout]. */
 int unet_conv3x3_dgrad(int n, int H, int W, const uint16_t* dy, int Cout, const float* w, int C1, int C2, float* dx1,

@@ -452,12 +452,13 @@ int pf_init(pf_handle** out, const pf_params* p, void* c, void* phi, void* rho, 
     // FP32 Euler runs fuse two steps by default (measured on MI355X): the
     // LDS tile for one grid of ~0.75M to ~3M cells (1024^2: 155 GLUPS
     // against 151 for the register march), the register strip march
-    // otherwise when a chunk height divides ny (512^2: 73 against 59 for
-    // single steps; 2048^2 266, 4096^2 297, 8192^2 343 against 221, 171,
-    // 214; 32 x 512^2 274 against 250)
+    // otherwise when a chunk height divides ny, with 16-row chunks from ~3M
+    // cells and 4 below (512^2: 73 against 59 for single steps; 2048^2 266,
+    // 4096^2 297, 8192^2 343 against 221, 171, 214; 32 x 512^2 308 against
+    // 250; deeper load look-ahead for 16-row chunks measured slower)
     const bool f32_euler = p->precision == PF_F32 && p->integrator == PF_EULER && !(p->interface_noise > 0);
     const bool tile_band = p->batch == 1 && cells >= 786432L && cells < 3000000L;
-    const int k2_auto_ty = cells >= 3000000L ? (p->batch == 1 ? 16 : 8) : 4;
+    const int k2_auto_ty = cells >= 3000000L ? 16 : 4;
     int K = p->temporal_block;
     if (K == 0 && f32_euler) K = tile_band || p->ny % 4 == 0 ? 2 : 1;
     if (K == 0) K = 1;

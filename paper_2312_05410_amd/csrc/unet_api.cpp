@@ -163,7 +163,7 @@ struct Bufs {
     float* yd[kMaxLevels];
     uint16_t *ad[kMaxLevels], *d[kMaxLevels];
     float* std_[kMaxLevels];
-    float *yh, *sth, *hout;
+    float *yh, *sth;
     float *jump, *h0, *h1, *f, *sc[kMaxLevels];
     float* gcoef;                   // GN forward coefficients [2][n][C] (shared by every GN)
     float *mdf, *mdh1, *mdh0;
@@ -254,7 +254,6 @@ void carve(Net& net, char* base, Bufs& b)
         const long P0 = net.P(0, n);
         b.yh = m.take<float>(P0 * c.out_ch);
         b.sth = m.take<float>((size_t)n * c.head_groups * 2);
-        b.hout = m.take<float>(P0 * c.out_ch);
         b.gout = m.take<float>(P0 * c.out_ch);
         b.dyh = m.take<uint16_t>(P0 * c.out_ch);
         note_gn(net.P(0, 1), c.out_ch, c.head_groups);
@@ -532,9 +531,10 @@ int forward(unet_handle* h, int n, const float* jump, const float* c, const floa
         ConvArgs a = conv_args(net.head, n, Hl(0), Wl(0), b.ad[0], nullptr);
         a.out_f32 = b.yh;
         GNArgs g = gn_args(h, net.head, n, P0, b.yh, b.sth);
-        g.z_f32 = b.hout;
+        g.res_jump = b.jump;  // the normalisation writes u + dt head directly
+        g.res_in[0] = c, g.res_in[1] = phi, g.res_in[2] = rho;
+        g.res_out[0] = oc, g.res_out[1] = ophi, g.res_out[2] = orho;
         RCHECK(conv_gn(h, a, kConvFwd, g));
-        UCHECK(residual_out(b.hout, b.jump, c, phi, rho, oc, ophi, orho, n, (int)P0, s));
     }
     h->last_n = train ? n : 0;
     return PF_OK;
@@ -798,23 +798,33 @@ size_t unet_op_workspace_bytes(int n, int H, int W, int Cmax)
     return wbytes + r256(4 * part) + r256(4 * csum) + r256(8 * (size_t)n * 5 * C) + 4096;
 }
 
-int unet_conv3x3_fwd(int n, int H, int W, const uint16_t* x1, int C1, const uint16_t* x2, int C2, const float* w,
-                     int Cout, float* y, void* workspace, size_t workspace_bytes, void* stream)
+size_t unet_conv3x3_prep_bytes(int C1, int C2, int Cout)
 {
-    if (!dims_ok(n, H, W) || C1 <= 0 || C2 < 0 || Cout <= 0 || !al(x1, 8) || !al(w, 4) || !al(y, 4) ||
-        !al(workspace, 256))
+    if (C1 <= 0 || C2 < 0 || Cout <= 0) return 0;
+    return r256(2 * 9 * r128(Cout) * r32(C1 + C2));
+}
+
+int unet_conv3x3_prepare(const float* w, int C1, int C2, int Cout, void* wprep, size_t bytes, void* stream)
+{
+    if (C1 <= 0 || C2 < 0 || Cout <= 0 || !al(w, 4) || !al(wprep, 256)) return PF_EINVAL;
+    if (bytes < unet_conv3x3_prep_bytes(C1, C2, Cout)) return PF_EINVAL;
+    const int K = C1 + C2;
+    UCHECK(weight_prep(w, 9, Cout, K, (uint16_t*)wprep, (int)r128(Cout), (int)r32(K), nullptr, 0, 0,
+                       (hipStream_t)stream));
+    return PF_OK;
+}
+
+int unet_conv3x3_fwd_prepared(int n, int H, int W, const uint16_t* x1, int C1, const uint16_t* x2, int C2,
+                              const void* wprep, int Cout, float* y, void* stream)
+{
+    if (!dims_ok(n, H, W) || C1 <= 0 || C2 < 0 || Cout <= 0 || !al(x1, 8) || !al(wprep, 256) || !al(y, 4))
         return PF_EINVAL;
     if (C2 > 0 && (!al(x2, 8) || C1 % 4)) return PF_EINVAL;
     const int K = C1 + C2;
-    OpWs ws{(char*)workspace, workspace_bytes};
-    uint16_t* wf = ws.take<uint16_t>(9 * r128(Cout) * r32(K));
-    if (!ws.ok) return PF_EINVAL;
-    hipStream_t s = (hipStream_t)stream;
-    UCHECK(weight_prep(w, 9, Cout, K, wf, (int)r128(Cout), (int)r32(K), nullptr, 0, 0, s));
     ConvArgs a{};
     a.in1 = x1;
     a.in2 = C2 ? x2 : nullptr;
-    a.Wt = wf;
+    a.Wt = (const uint16_t*)wprep;
     a.out_f32 = y;
     a.N = n;
     a.H = H;
@@ -824,8 +834,22 @@ int unet_conv3x3_fwd(int n, int H, int W, const uint16_t* x1, int C1, const uint
     a.Nout = a.O1 = Cout;
     a.ldk = (int)r32(K);
     a.ldo = (int)r128(Cout);
-    UCHECK(conv_gemm(a, kConvFwd, s));
+    UCHECK(conv_gemm(a, kConvFwd, (hipStream_t)stream));
     return PF_OK;
+}
+
+int unet_conv3x3_fwd(int n, int H, int W, const uint16_t* x1, int C1, const uint16_t* x2, int C2, const float* w,
+                     int Cout, float* y, void* workspace, size_t workspace_bytes, void* stream)
+{
+    if (!dims_ok(n, H, W) || C1 <= 0 || C2 < 0 || Cout <= 0 || !al(x1, 8) || !al(w, 4) || !al(y, 4) ||
+        !al(workspace, 256))
+        return PF_EINVAL;
+    if (C2 > 0 && (!al(x2, 8) || C1 % 4)) return PF_EINVAL;
+    const size_t wb = unet_conv3x3_prep_bytes(C1, C2, Cout);
+    if (workspace_bytes < wb) return PF_EINVAL;
+    const int rc = unet_conv3x3_prepare(w, C1, C2, Cout, workspace, wb, stream);
+    if (rc != PF_OK) return rc;
+    return unet_conv3x3_fwd_prepared(n, H, W, x1, C1, x2, C2, workspace, Cout, y, stream);
 }
 
 int unet_conv3x3_dgrad(int n, int H, int W, const uint16_t* dy, int Cout, const float* w, int C1, int C2, float* dx1,

@@ -106,6 +106,11 @@ struct GNArgs {
     float* coef;           // forward workspace [2][N][C] (16-byte aligned) or null: the
                            // normalisation as A y + B per channel, A = gamma rstd,
                            // B = beta - A mean
+    // forward, C = 3, or null: instead of z, write the prediction
+    // res_out[f][n][p] = res_in[f][n][p] + res_jump[n] z[n][p][f] (the head)
+    const float* res_jump;
+    const float* res_in[3];
+    float* res_out[3];
 };
 hipError_t gn_forward(const GNArgs& a, hipStream_t s);
 hipError_t gn_backward(const GNArgs& a, hipStream_t s);
@@ -121,9 +126,6 @@ hipError_t maxpool_bwd(const uint16_t* x, const float* dy, float* dx, int N, int
 // Network input: x[n][p][0..3] = (c - 1/2, phi, rho - 1, jump[n]) as BF16.
 hipError_t assemble_input(const float* c, const float* phi, const float* rho, const float* jump, uint16_t* x, int N,
                           int P, hipStream_t s);
-// out_f[n][p] = in_f[n][p] + jump[n] head[n][p][f] for the three fields.
-hipError_t residual_out(const float* head, const float* jump, const float* c, const float* phi, const float* rho,
-                        float* oc, float* ophi, float* orho, int N, int P, hipStream_t s);
 
 // Time basis f(jump) (two sin layers of width Hd) and the per-level FiLM
 // scales s_l = w_l f.

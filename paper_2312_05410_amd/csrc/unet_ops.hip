@@ -105,9 +105,22 @@ __global__ __launch_bounds__(256) void gn_stats_finish(GNArgs a)
     __shared__ double sh[2][256];
     const int i = blockIdx.x, n = i / a.G, g = i % a.G, Cg = a.C / a.G;
     double v[2] = {0.0, 0.0};
-    // the group's channels are contiguous: [n][g Cg .. (g+1) Cg)[chunks][2]
+    // the group's channels are contiguous: [n][g Cg .. (g+1) Cg)[chunks][2];
+    // eight independent loads in flight per thread, then the remainder
     const float2* o = (const float2*)a.csum + ((size_t)n * a.C + g * Cg) * a.chunks;
-    for (int e = threadIdx.x; e < Cg * a.chunks; e += 256) {
+    const int total = Cg * a.chunks;
+    int e = threadIdx.x;
+    for (; e + 7 * 256 < total; e += 8 * 256) {
+        float2 q[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) q[u] = o[e + u * 256];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            v[0] += q[u].x;
+            v[1] += q[u].y;
+        }
+    }
+    for (; e < total; e += 256) {
         const float2 q = o[e];
         v[0] += q.x;
         v[1] += q.y;
@@ -149,6 +162,26 @@ __global__ __launch_bounds__(256) void gn_apply_kernel(GNArgs a)
             const float zs = z * a.scale[n * a.C + c];
             if (a.zs_f32) a.zs_f32[i] = zs;
             if (a.zs_bf16) a.zs_bf16[i] = f2bf(zs);
+        }
+    }
+}
+
+// The three-channel head: normalise each pixel's channels and add the
+// leap-scaled result to the state (prediction = u + dt head); one pixel per
+// thread.
+__global__ __launch_bounds__(256) void gn_apply_res_kernel(GNArgs a)
+{
+    const size_t total = (size_t)a.N * a.P;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (size_t)gridDim.x * 256) {
+        const int n = (int)(i / a.P);
+        const float dt = a.res_jump[n];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            const float* st = a.stats + 2 * (n * a.G + f / (3 / a.G));
+            const float av = fmaf(a.gamma[f], (a.y[3 * i + f] - st[0]) * st[1], a.beta[f]);
+            const float z = a.gelu ? gelu(av) : av;
+            if (a.z_f32) a.z_f32[3 * i + f] = z;
+            a.res_out[f][i] = fmaf(dt, z, a.res_in[f][i]);
         }
     }
 }
@@ -439,18 +472,6 @@ __global__ __launch_bounds__(256) void assemble_kernel(const float* c, const flo
     }
 }
 
-__global__ __launch_bounds__(256) void residual_kernel(const float* head, const float* jump, const float* c,
-                                                       const float* phi, const float* rho, float* oc, float* ophi,
-                                                       float* orho, int P, size_t total)
-{
-    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (size_t)gridDim.x * 256) {
-        const float dt = jump[i / P];
-        oc[i] = fmaf(dt, head[3 * i], c[i]);
-        ophi[i] = fmaf(dt, head[3 * i + 1], phi[i]);
-        orho[i] = fmaf(dt, head[3 * i + 2], rho[i]);
-    }
-}
-
 // -------------------------------------------------------------------- MLP
 constexpr int kMlpThreads = 1024;
 
@@ -460,6 +481,7 @@ template <int G>
 __device__ __forceinline__ float row_dot(const float* W, const float* x, int len, int j, int k)
 {
     float s = 0.f;
+#pragma unroll 8
     for (int i = k; i < len; i += G) s = fmaf(W[(size_t)j * len + i], x[i], s);
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off);
@@ -704,7 +726,10 @@ hipError_t gn_forward(const GNArgs& a_in, hipStream_t s)
         hipLaunchKernelGGL(gn_stats_kernel, dim3(a.chunks, a.N), dim3(256), 0, s, a, chunk_px(a.P));
     }
     hipLaunchKernelGGL(gn_stats_finish, dim3(a.N * a.G), dim3(256), 0, s, a);
-    if (vec) {
+    if (a.res_jump) {
+        if (a.C != 3 || (a.G != 1 && a.G != 3)) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(gn_apply_res_kernel, dim3(grid_for((size_t)a.N * a.P)), dim3(256), 0, s, a);
+    } else if (vec) {
         const size_t items = (size_t)a.N * a.P * (a.C / 8) / (a.pool_bf16 ? 4 : 1);
         hipLaunchKernelGGL(gn_apply8_kernel, dim3(grid_for(items)), dim3(256), 0, s, a);
     } else {
@@ -748,16 +773,6 @@ hipError_t assemble_input(const float* c, const float* phi, const float* rho, co
     const size_t n = (size_t)N * P;
     if (!n) return hipSuccess;
     hipLaunchKernelGGL(assemble_kernel, dim3(grid_for(n)), dim3(256), 0, s, c, phi, rho, jump, x, N, P);
-    return hipGetLastError();
-}
-
-hipError_t residual_out(const float* head, const float* jump, const float* c, const float* phi, const float* rho,
-                        float* oc, float* ophi, float* orho, int N, int P, hipStream_t s)
-{
-    const size_t n = (size_t)N * P;
-    if (!n) return hipSuccess;
-    hipLaunchKernelGGL(residual_kernel, dim3(grid_for(n)), dim3(256), 0, s, head, jump, c, phi, rho, oc, ophi, orho,
-                       P, n);
     return hipGetLastError();
 }
 

@@ -21,7 +21,8 @@ _I = ctypes.c_int
 UNET_EXPORTS = (
     "unet_param_count", "unet_param_entry", "unet_workspace_bytes", "unet_create", "unet_prepare",
     "unet_forward", "unet_forward_infer", "unet_backward", "unet_adam", "unet_destroy", "unet_op_workspace_bytes",
-    "unet_conv3x3_fwd", "unet_conv3x3_dgrad", "unet_conv3x3_wgrad", "unet_up_fwd", "unet_up_dgrad",
+    "unet_conv3x3_fwd", "unet_conv3x3_prep_bytes", "unet_conv3x3_prepare", "unet_conv3x3_fwd_prepared",
+    "unet_conv3x3_dgrad", "unet_conv3x3_wgrad", "unet_up_fwd", "unet_up_dgrad",
     "unet_up_wgrad", "unet_groupnorm_fwd", "unet_groupnorm_bwd", "unet_maxpool_fwd", "unet_maxpool_bwd",
 )
 
@@ -89,6 +90,10 @@ def lib():
         L.unet_op_workspace_bytes.argtypes = [_I] * 4
         L.unet_op_workspace_bytes.restype = sz
         L.unet_conv3x3_fwd.argtypes = [_I, _I, _I, _H, _I, _H, _I, _H, _I, _H, _H, sz, _H]
+        L.unet_conv3x3_prep_bytes.argtypes = [_I, _I, _I]
+        L.unet_conv3x3_prep_bytes.restype = sz
+        L.unet_conv3x3_prepare.argtypes = [_H, _I, _I, _I, _H, sz, _H]
+        L.unet_conv3x3_fwd_prepared.argtypes = [_I, _I, _I, _H, _I, _H, _I, _H, _I, _H, _H]
         L.unet_conv3x3_dgrad.argtypes = [_I, _I, _I, _H, _I, _H, _I, _I, _H, _H, _H, sz, _H]
         L.unet_conv3x3_wgrad.argtypes = [_I, _I, _I, _H, _I, _H, _I, _H, _I, _H, _H, sz, _H]
         L.unet_up_fwd.argtypes = [_I, _I, _I, _H, _I, _H, _I, _H, _H, sz, _H]
@@ -99,7 +104,8 @@ def lib():
         L.unet_maxpool_fwd.argtypes = [_I] * 4 + [_H, _H, _H]
         L.unet_maxpool_bwd.argtypes = [_I] * 4 + [_H, _H, _H, _H]
         for name in UNET_EXPORTS:
-            if name not in ("unet_param_count", "unet_workspace_bytes", "unet_destroy", "unet_op_workspace_bytes"):
+            if name not in ("unet_param_count", "unet_workspace_bytes", "unet_destroy", "unet_op_workspace_bytes",
+                            "unet_conv3x3_prep_bytes"):
                 getattr(L, name).restype = _I
         _ready = True
     return L
@@ -245,6 +251,32 @@ def conv3x3_fwd(x1, w, x2=None):
     ws = _ws(n, H, W, max(C1 + C2, Cout), x1.device)
     _check(lib().unet_conv3x3_fwd(n, H, W, x1.data_ptr(), C1, _ptr(x2), C2, w.data_ptr(), Cout, y.data_ptr(),
                                   ws.data_ptr(), ws.numel(), _stream()), "unet_conv3x3_fwd")
+    return y
+
+
+def conv3x3_prepare(w, C1, C2=0):
+    """BF16 MFMA operand of w [9][Cout][C1+C2] (a device byte tensor)."""
+    import torch
+
+    Cout = w.shape[1]
+    nb = lib().unet_conv3x3_prep_bytes(C1, C2, Cout)
+    if nb == 0:
+        raise ValueError("invalid convolution sizes")
+    wp = torch.empty(nb, dtype=torch.uint8, device=w.device)
+    _check(lib().unet_conv3x3_prepare(w.data_ptr(), C1, C2, Cout, wp.data_ptr(), nb, _stream()),
+           "unet_conv3x3_prepare")
+    return wp
+
+
+def conv3x3_fwd_prepared(x1, wp, Cout, x2=None, out=None):
+    """conv3x3_fwd from a prepared operand (the convolution kernel alone)."""
+    import torch
+
+    n, H, W, C1 = x1.shape
+    C2 = 0 if x2 is None else x2.shape[3]
+    y = out if out is not None else torch.empty(n, H, W, Cout, dtype=torch.float32, device=x1.device)
+    _check(lib().unet_conv3x3_fwd_prepared(n, H, W, x1.data_ptr(), C1, _ptr(x2), C2, wp.data_ptr(), Cout,
+                                           y.data_ptr(), _stream()), "unet_conv3x3_fwd_prepared")
     return y
 
 

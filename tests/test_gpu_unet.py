@@ -111,6 +111,26 @@ def test_conv3x3_fwd_dgrad_wgrad(n, H, W, C1, C2, Cout):
     check_bound(dwg, gw.numpy(), bw.numpy(), 2 * n * H * W + 16, "wgrad")
 
 
+@pytest.mark.parametrize("n,H,W,C1,C2,Cout", [(2, 10, 13, 8, 12, 40), (5, 64, 64, 32, 32, 32), (1, 9, 7, 4, 0, 32)])
+def test_conv3x3_prepared_equals_plain(n, H, W, C1, C2, Cout):
+    """The two-part forward (weights prepared once, then the convolution
+    kernel alone, applied twice) equals the one-call forward bit for bit."""
+    import torch
+
+    from paper_2312_05410_amd import unet as U
+
+    announce(f"conv3x3 prepared n{n} {H}x{W} C1={C1} C2={C2} Cout={Cout}")
+    x1 = dev_bf16(bf16_exact(5, (n, H, W, C1)))
+    x2 = dev_bf16(bf16_exact(6, (n, H, W, C2))) if C2 else None
+    w = dev_f32(bf16_exact(7, (9, Cout, C1 + C2), exp=9))
+    y = U.conv3x3_fwd(x1, w, x2)
+    wp = U.conv3x3_prepare(w, C1, C2)
+    y1 = U.conv3x3_fwd_prepared(x1, wp, Cout, x2)
+    y2 = U.conv3x3_fwd_prepared(x1, wp, Cout, x2, out=torch.empty_like(y1))
+    torch.cuda.synchronize()
+    assert torch.equal(y, y1) and torch.equal(y, y2)
+
+
 @pytest.mark.parametrize("n,H,W,Cin,Cout", [(2, 5, 7, 12, 8), (1, 8, 8, 64, 32), (3, 3, 5, 256, 128)])
 def test_up_fwd_dgrad_wgrad(n, H, W, Cin, Cout):
     import torch
