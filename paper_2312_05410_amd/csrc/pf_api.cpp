@@ -135,6 +135,7 @@ struct pf_handle {
     int march_cols = 1;                  // K == 1: grid columns per lane (2: FP32, even nx)
     int fused = PF_FUSED_TILE;           // K >= 2: LDS tile or register strip march (K == 2)
     int k2_ty = 8;                       // register strip march: rows per wave
+    int k2_cols = 1;                     // register strip march: grid columns per lane
     int last_hip = 0;
     hipGraph_t graph = nullptr;          // chain of kGraphLen full-K launches
     hipGraphExec_t gexec = nullptr;
@@ -280,7 +281,7 @@ int ensure_graph(pf_handle* h)
         }
         hipGraphNode_t node = nullptr;
         if (h->K == 1) e = pfk::graph_add_march<T>(g, &node, prev, a, h->march_ty, h->march_cols, h->p.batch);
-        else if (h->fused == PF_FUSED_MARCH) e = pfk::graph_add_march_k2<T>(g, &node, prev, a, h->k2_ty, h->p.batch);
+        else if (h->fused == PF_FUSED_MARCH) e = pfk::graph_add_march_k2<T>(g, &node, prev, a, h->k2_ty, h->k2_cols, h->p.batch);
         else e = pfk::graph_add_step<T>(g, &node, prev, a, h->K, h->p.batch);
         prev = node;
     }
@@ -344,7 +345,7 @@ int enqueue_steps(pf_handle* h, int64_t n)
         hipError_t e;
         if (K == 1) e = pfk::launch_march<T>(a, h->march_ty, h->march_cols, p->batch, h->stream);
         else if (h->fused != PF_FUSED_MARCH) e = pfk::launch_step<T>(a, K, p->batch, h->stream);
-        else if (a.nsub == 2) e = pfk::launch_march_k2<T>(a, h->k2_ty, p->batch, h->stream);
+        else if (a.nsub == 2) e = pfk::launch_march_k2<T>(a, h->k2_ty, h->k2_cols, p->batch, h->stream);
         else e = pfk::launch_march<T>(a, h->march_ty, h->march_cols, p->batch, h->stream);  // odd step
         if ((rc = hip_fail(h, e))) return rc;
         parity ^= 1;
@@ -456,11 +457,15 @@ int pf_init(pf_handle** out, const pf_params* p, void* c, void* phi, void* rho, 
     // cells and 4 below (512^2: 73 against 59 for single steps; 2048^2 266,
     // 4096^2 297, 8192^2 343 against 221, 171, 214; 32 x 512^2 308 against
     // 250; deeper load look-ahead for 16-row chunks measured slower)
-    const bool f32_euler = p->precision == PF_F32 && p->integrator == PF_EULER && !(p->interface_noise > 0);
-    const bool tile_band = p->batch == 1 && cells >= 786432L && cells < 3000000L;
+    const bool plain_euler = p->integrator == PF_EULER && !(p->interface_noise > 0);
+    const bool f32 = p->precision == PF_F32;
+    const bool tile_band = f32 && p->batch == 1 && cells >= 786432L && cells < 3000000L;
     const int k2_auto_ty = cells >= 3000000L ? 16 : 4;
     int K = p->temporal_block;
-    if (K == 0 && f32_euler) K = tile_band || p->ny % 4 == 0 ? 2 : 1;
+    // FP64 fuses two steps only on large grids (4096^2: 146 GLUPS against
+    // 102 for single steps; 1024^2: 84 against 82)
+    if (K == 0 && plain_euler && f32) K = tile_band || p->ny % 4 == 0 ? 2 : 1;
+    if (K == 0 && plain_euler && !f32) K = cells >= 3000000L && p->ny % 4 == 0 ? 2 : 1;
     if (K == 0) K = 1;
     if (p->integrator != PF_EULER || p->interface_noise > 0) K = 1;
     while (K > 1 && 2 * K > p->ny) --K;
@@ -488,8 +493,8 @@ int pf_init(pf_handle** out, const pf_params* p, void* c, void* phi, void* rho, 
     // fused steps: the LDS tile, or the register strip march when asked for
     // (two steps, chunk heights dividing ny)
     h->fused = PF_FUSED_TILE;
-    const bool march_k2 = p->fused_kernel == PF_FUSED_MARCH ||
-                          (p->fused_kernel == PF_FUSED_AUTO && p->precision == PF_F32 && !tile_band);
+    const bool march_k2 = p->fused_kernel == PF_FUSED_MARCH || (p->fused_kernel == PF_FUSED_AUTO && !tile_band &&
+                                                               (f32 || p->temporal_block == 0));
     if (K == 2 && march_k2) {
         const int auto_ty = p->fused_kernel == PF_FUSED_MARCH ? 8 : k2_auto_ty;
         const int want = p->tile_rows == 4 || p->tile_rows == 8 || p->tile_rows == 16 ? p->tile_rows : auto_ty;
@@ -497,6 +502,8 @@ int pf_init(pf_handle** out, const pf_params* p, void* c, void* phi, void* rho, 
             if (p->ny % ty == 0) {
                 h->fused = PF_FUSED_MARCH;
                 h->k2_ty = ty;
+                // two columns per lane only on request (lane_cols = 2), FP32, even nx
+                h->k2_cols = p->lane_cols == 2 && two_ok ? 2 : 1;
                 break;
             }
         }
@@ -785,6 +792,6 @@ extern "C" int pf_get_fused_kernel(const pf_handle* h, int32_t* kind)
 extern "C" int pf_get_lane_cols(const pf_handle* h, int32_t* lane_cols)
 {
     if (!h || !lane_cols) return PF_EINVAL;
-    *lane_cols = h->K == 1 ? h->march_cols : 1;
+    *lane_cols = h->K == 1 ? h->march_cols : (h->fused == PF_FUSED_MARCH ? h->k2_cols : 1);
     return PF_OK;
 }

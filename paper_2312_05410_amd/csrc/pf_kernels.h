@@ -80,13 +80,14 @@ hipError_t graph_add_march(hipGraph_t g, hipGraphNode_t* node, hipGraphNode_t de
                            int ty, int cols, int batch);
 
 // Two fused steps per launch in the register strip march (Euler, no
-// variants), chunks of ty in {4, 8, 16} rows with ty dividing ny; a launch
-// always advances two steps.
+// variants), chunks of ty in {4, 8, 16} rows with ty dividing ny, cols grid
+// columns per lane (2: FP32 with even nx only); a launch always advances
+// two steps.
 template <typename T>
-hipError_t launch_march_k2(const StepArgs<T>& a, int ty, int batch, hipStream_t s);
+hipError_t launch_march_k2(const StepArgs<T>& a, int ty, int cols, int batch, hipStream_t s);
 template <typename T>
 hipError_t graph_add_march_k2(hipGraph_t g, hipGraphNode_t* node, hipGraphNode_t dep, const StepArgs<T>& a,
-                              int ty, int batch);
+                              int ty, int cols, int batch);
 
 // Append one stepper launch as a kernel node of graph g after node dep
 // (dep == nullptr: no dependency).

@@ -291,7 +291,8 @@ def test_two_columns_per_lane_is_bitwise(shape):
 
 @pytest.mark.parametrize("prec,bc,shape", [("f32", "pvd", (150, 96)), ("f64", "pvd", (130, 64)),
                                            ("f32", "periodic", (120, 48)), ("f32", "pvd", (6, 16)),
-                                           ("f32", "pvd", (100, 8))])
+                                           ("f32", "pvd", (100, 8)), ("f32", "pvd", (250, 32)),
+                                           ("f32", "pvd", (121, 16))])
 def test_two_step_march_is_bitwise(prec, bc, shape):
     """The register strip march fusing two steps equals single-step
     launches bit for bit (state and inflow) at every chunk height dividing
@@ -309,14 +310,16 @@ def test_two_step_march_is_bitwise(prec, bc, shape):
     for rows in (4, 8, 16):
         if ny % rows:
             continue
-        for gm in (0, 1):
-            sim = Sim(p, state=state, temporal_block=2, tile_rows=rows, fused_kernel=2, graph_mode=gm)
+        for gm, cols in ((0, 1), (1, 1), (0, 2)):
+            sim = Sim(p, state=state, temporal_block=2, tile_rows=rows, fused_kernel=2, graph_mode=gm,
+                      lane_cols=cols)
             assert sim.fused_kernel == 2 and sim.launch == (2, rows)
+            assert sim.lane_cols == (cols if prec == "f32" and nx % 2 == 0 else 1)
             sim.step(37)
             sim.step(141)
             for u, v in zip(sim.state(), base):
-                assert np.array_equal(u, v), f"rows={rows} graph_mode={gm}"
-            assert np.array_equal(sim.inflow(), qb), f"rows={rows} graph_mode={gm}"
+                assert np.array_equal(u, v), f"rows={rows} graph_mode={gm} cols={cols}"
+            assert np.array_equal(sim.inflow(), qb), f"rows={rows} graph_mode={gm} cols={cols}"
             sim.close()
 
 
