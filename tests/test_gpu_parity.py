@@ -407,8 +407,22 @@ def test_full_size_production_parity():
     announce("dns_1024 f32 full-size")
     p = workloads.dns_production(0)
     K = workloads.BENCH_TEMPORAL_BLOCK["f32"]
-    sim, ref = run_pair(p, initial_state(p), 10 * K, 1e-6, temporal_block=K)
+    sim, ref = run_pair(p, initial_state(p), 20, 1e-6, temporal_block=K)
+    assert sim.step_count == 20
     np.testing.assert_allclose(sim.mass(), ref.mass(), rtol=1e-6)
+    sim.close()
+
+
+@pytest.mark.parametrize("n,prec,steps,tol", [(8192, "f32", 4, 1e-6), (4096, "f64", 6, F64_TOL)])
+def test_full_size_large_grids(n, prec, steps, tol):
+    """The large-grid throughput shapes (two fused steps in the register
+    march by default) against the oracle on the whole grid."""
+    announce(f"dns_{n} {prec} full-size")
+    p = workloads.dns_production(0, n=n, precision=prec)
+    K = workloads.BENCH_TEMPORAL_BLOCK[prec]
+    sim, ref = run_pair(p, initial_state(p), steps, tol, temporal_block=K)
+    assert sim.launch[0] == 2 and sim.fused_kernel == 2
+    np.testing.assert_allclose(sim.mass(), ref.mass(), rtol=1e-6 if prec == "f32" else 1e-11)
     sim.close()
 
 
@@ -421,9 +435,10 @@ def test_full_size_batched_sampled():
     dt = oracle.resolve_dt(p)
     p = p.replace(dt=dt)
     state = initial_state(p)
-    n = 6 * K
+    n = 12
     sim = Sim(p, state=state, temporal_block=K)
     sim.step(n)
+    assert sim.step_count == n
     out = sim.state()
     for b in (0, 13, 31):
         pb = p.replace(batch=1, seed=p.seed + b, v0=float(p.v0_per[b]), c0=float(p.c0_per[b]),
