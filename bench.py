@@ -56,6 +56,9 @@ def parse():
     ap.add_argument("--temporal-block", type=int, default=None)
     ap.add_argument("--lane-cols", type=int, default=0, help="single-step kernel: grid columns per lane (0: auto)")
     ap.add_argument("--graph-mode", type=int, default=0, help="0: replay HIP graphs of launches; 1: plain launches")
+    ap.add_argument("--fused", type=int, default=0,
+                    help="kernel of fused launches: 1 LDS tile, 2 register march, 3 resident stepper (0: auto)")
+    ap.add_argument("--tile-rows", type=int, default=0, help="rows per wave / tile height (0: auto)")
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -112,6 +115,8 @@ def launches_for(steps: int, K: int) -> int:
 def kernel_name(prec: str, K: int, rows: int, base: bool = False, noise: bool = False, cols: int = 1,
                 fused: int = 1) -> str:
     t = "float" if prec == "f32" else "double"
+    if fused == 3:                                # resident stepper: one launch per call
+        return f"resident_kernel<{rows}>"
     if K == 2 and fused == 2:                     # two steps in the register strip march
         return f"march_k2_kernel<{t}, {rows}, {rows + 1 if rows <= 8 else 4}>"
     if K == 1:
@@ -135,7 +140,8 @@ def gpu_leg(args, p, steps, warmup, K):
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    sim = Simulator(p, temporal_block=K, graph_mode=args.graph_mode, lane_cols=args.lane_cols)
+    sim = Simulator(p, temporal_block=K, graph_mode=args.graph_mode, lane_cols=args.lane_cols,
+                    fused_kernel=args.fused, tile_rows=args.tile_rows)
     Kr, rows = sim.launch
     cols = sim.lane_cols
     fused = sim.fused_kernel
@@ -146,7 +152,8 @@ def gpu_leg(args, p, steps, warmup, K):
     sim.close()
     cells = p.nx * p.ny * p.batch
     glups = cells * steps / dt_s / 1e9
-    return dict(seconds=dt_s, wall=wall, glups=glups, launches=launches_for(steps, Kr), K=Kr, rows=rows, cols=cols,
+    launches = 1 if fused == 3 and steps >= 2 else launches_for(steps, Kr)
+    return dict(seconds=dt_s, wall=wall, glups=glups, launches=launches, K=Kr, rows=rows, cols=cols,
                 fused=fused)
 
 

@@ -89,9 +89,19 @@ enum pf_integrator { PF_EULER = 0, PF_MIDPOINT = 1 };
  *   interface_noise also runs plain launches (no graph replay).
  */
 /* Kernel of the launches that fuse several steps: a 64 x TY tile staged in
- * LDS (any K), or the register strip march (K = 2: one wave per 64-column
- * strip, radius-4 halo, the intermediate state kept in registers). */
-enum pf_fused { PF_FUSED_AUTO = 0, PF_FUSED_TILE = 1, PF_FUSED_MARCH = 2 };
+ * LDS (any K), the register strip march (K = 2: one wave per 64-column
+ * strip, radius-4 halo, the intermediate state kept in registers), or the
+ * resident stepper: one cooperative launch per pf_step_n call (of at least
+ * 2 steps; a single step runs the single-step kernel) in which every
+ * workgroup keeps a 64 x TY tile of the state in LDS for all the steps and
+ * trades its 2-cell rim with its neighbours after each step through the
+ * workspace.  The resident stepper needs FP32, explicit Euler without
+ * interface draws, temporal_block 0 or 1, nx a multiple of 64, a tile height
+ * TY in {8, 16, 32} dividing ny (tile_rows, else the library's choice) and
+ * a grid of at most 2^21 cells whose tiles the device can keep resident at
+ * once (about 1M cells on MI355X); else pf_init returns PF_EINVAL.  Its
+ * results are bitwise equal to the other kernels'. */
+enum pf_fused { PF_FUSED_AUTO = 0, PF_FUSED_TILE = 1, PF_FUSED_MARCH = 2, PF_FUSED_RESIDENT = 3 };
 
 typedef struct pf_params {
     int32_t nx, ny, batch;        /* grid cells and independent realisations */
@@ -103,8 +113,9 @@ typedef struct pf_params {
     int32_t temporal_block;       /* steps fused per launch: 1..4 (FP32), 1..2 (FP64); 0: library's
                                      choice by precision and grid size; lowered so that 2K <= ny */
     int32_t graph_mode;           /* 0: long runs replay a HIP graph of launches; 1: plain launches */
-    int32_t tile_rows;            /* single-step kernel: rows per wave (4, 8, 16, 32); 0: library's
-                                     choice by grid size */
+    int32_t tile_rows;            /* single-step kernel: rows per wave (4, 8, 16, 32); resident
+                                     stepper: tile height (8, 16, 32); 0: library's choice by grid
+                                     size */
     int32_t integrator;           /* pf_integrator */
     uint64_t seed;                /* seeded initial condition: realisation b uses seed + b */
     double h;                     /* grid spacing */
@@ -121,12 +132,15 @@ typedef struct pf_params {
                                      an even nx; else 1 is used); 0: library's choice */
     int32_t fused_kernel;         /* pf_fused: kernel of launches that fuse steps (temporal_block
                                      > 1); PF_FUSED_MARCH fuses exactly 2, with tile_rows (4, 8 or 16,
-                                     dividing ny; else 8 or 4) rows per wave; 0: library's choice */
+                                     dividing ny; else 8 or 4) rows per wave; PF_FUSED_RESIDENT: the
+                                     resident stepper (conditions above); 0: library's choice */
 } pf_params;
 
 /* Bytes of device workspace a handle for *p needs (ping-pong copy of the
  * state, per-column FP64 inflow accumulators, per-realisation constants,
- * FP64 reduction partials).  Returns 0 if *p is invalid. */
+ * FP64 reduction partials and, for grids the resident stepper may run, its
+ * rim buffers: 2 x tiles x 3 x (256 + 4 TY) 8-byte words).  Returns 0 if *p
+ * is invalid. */
 size_t pf_workspace_bytes(const pf_params* p);
 
 /* Explicit-Euler stability limit of *p on the host, in FP64:
@@ -178,16 +192,18 @@ int pf_set_inflow(pf_handle* h, const double* Q);
 void pf_destroy(pf_handle* h);
 
 /* Launch shape a handle uses: steps fused per launch (1: single-step
- * strip-march kernel; 2..4: LDS-tiled kernel) and rows per wave / tile. */
+ * strip-march kernel or the resident stepper, which exchanges rims after
+ * every step; 2..4: LDS-tiled kernel or register march) and rows per wave /
+ * tile. */
 int pf_get_launch(const pf_handle* h, int32_t* temporal_block, int32_t* tile_rows);
 
 /* Grid columns per lane of the single-step kernel the handle launches (1 or
  * 2; 1 whenever temporal_block > 1).  PF_EINVAL on a null argument. */
 int pf_get_lane_cols(const pf_handle* h, int32_t* lane_cols);
 
-/* pf_fused kind of the handle's fused launches (PF_FUSED_TILE or
- * PF_FUSED_MARCH; 0 when each launch is one step).  PF_EINVAL on a null
- * argument. */
+/* pf_fused kind of the handle's fused launches (PF_FUSED_TILE,
+ * PF_FUSED_MARCH or PF_FUSED_RESIDENT; 0 when each launch is one step).
+ * PF_EINVAL on a null argument. */
 int pf_get_fused_kernel(const pf_handle* h, int32_t* kind);
 
 /* ------------------------------------------------------------------ adjoint

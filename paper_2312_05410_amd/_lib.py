@@ -23,7 +23,7 @@ PF_F32, PF_F64 = 0, 1
 PF_BC_PVD, PF_BC_PERIODIC = 0, 1
 PF_INIT_SEEDED, PF_INIT_KEEP = 0, 1
 PF_INTEGRATOR = {"euler": 0, "midpoint": 1}
-PF_FUSED_TILE, PF_FUSED_MARCH = 1, 2
+PF_FUSED_TILE, PF_FUSED_MARCH, PF_FUSED_RESIDENT = 1, 2, 3
 
 EXPORTS = (
     "pf_workspace_bytes", "pf_dt_limit", "pf_init", "pf_step_n", "pf_mass", "pf_energy",

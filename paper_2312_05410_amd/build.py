@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpf.so")
-SOURCES = ["pf_march.hip", "pf_step.hip", "pf_adjoint.hip", "pf_kernels.hip", "pf_api.cpp",
+SOURCES = ["pf_march.hip", "pf_step.hip", "pf_resident.hip", "pf_adjoint.hip", "pf_kernels.hip", "pf_api.cpp",
            "unet_conv.hip", "unet_ops.hip", "unet_api.cpp"]
 
 HIPCC_FLAGS = [

@@ -18,13 +18,40 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kGraphLen = 64;   // launches per graph replay (even: parity is preserved)
+constexpr long kResAutoMin = 1L << 18;   // resident stepper by default from this many cells
 
 size_t round_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 struct Layout {
     size_t state[3];
-    size_t qcol, real, c0, qstage, partials, results, total;
+    size_t qcol, real, c0, qstage, partials, results, rim, rctl, total;
 };
+
+constexpr long kResMaxCells = 1L << 21;   // resident stepper: cells per launch at most
+
+// Tile height of the resident stepper for *p, 0 where it does not run: FP32
+// explicit Euler without interface draws, asked for or left to the library
+// (temporal_block 0) from 2^18 cells (measured on MI355X: 512^2 79.9 GLUPS
+// against 72.1 for the two-step march, 1024^2 218 against 156 for the LDS
+// tile, 4 x 512^2 238 against 154; 256^2 16 against 25), 64-column tiles, a
+// height dividing ny: the one asked for, else the largest of 32, 16, 8
+// (512^2: 79.9 GLUPS with 32 rows, 73.8 with 16).  Whether the device keeps
+// every tile resident is checked when the handle is created.
+int resident_th(const pf_params* p)
+{
+    if (p->precision != PF_F32 || p->integrator != PF_EULER || p->interface_noise > 0) return 0;
+    const long cells = (long)p->nx * p->ny * p->batch;
+    if (p->nx % 64 || cells > kResMaxCells) return 0;
+    if (p->fused_kernel == PF_FUSED_AUTO) {
+        if (p->temporal_block != 0 || cells < kResAutoMin) return 0;
+    } else if (p->fused_kernel != PF_FUSED_RESIDENT || p->temporal_block > 1) {
+        return 0;
+    }
+    if (p->tile_rows >= 8) return p->ny % p->tile_rows == 0 && p->fused_kernel == PF_FUSED_RESIDENT ? p->tile_rows : 0;
+    for (int t : {32, 16, 8})
+        if (p->ny % t == 0) return t;
+    return 0;
+}
 
 size_t esize(const pf_params* p) { return p->precision == PF_F64 ? 8 : 4; }
 
@@ -45,6 +72,10 @@ Layout layout(const pf_params* p)
     L.qstage = take(B * sizeof(double));
     L.partials = take(B * (size_t)pfk::kRedBlocks * 4 * sizeof(double));
     L.results = take(B * 5 * sizeof(double));
+    const int th = resident_th(p);
+    const size_t tiles = th ? B * (size_t)(p->nx / 64) * (size_t)(p->ny / th) : 0;
+    L.rim = take(th ? 2 * tiles * 3 * pfk::resident_rim_words(th) * sizeof(uint64_t) : 0);
+    L.rctl = take(th ? 2 * sizeof(uint64_t) : 0);
     L.total = off;
     return L;
 }
@@ -72,10 +103,11 @@ int validate(const pf_params* p)
         return PF_EINVAL;
     if (p->integrator != PF_EULER && p->integrator != PF_MIDPOINT) return PF_EINVAL;
     if (p->lane_cols < 0 || p->lane_cols > 2) return PF_EINVAL;
-    if (p->fused_kernel < 0 || p->fused_kernel > PF_FUSED_MARCH) return PF_EINVAL;
+    if (p->fused_kernel < 0 || p->fused_kernel > PF_FUSED_RESIDENT) return PF_EINVAL;
     // the register strip march fuses exactly two steps
     if (p->fused_kernel == PF_FUSED_MARCH && p->temporal_block > 2) return PF_EINVAL;
     if (!std::isfinite(p->interface_noise) || p->interface_noise < 0 || p->interface_noise > 1) return PF_EINVAL;
+    if (p->fused_kernel == PF_FUSED_RESIDENT && resident_th(p) == 0) return PF_EINVAL;
     // the variants run on the single-step kernel
     if ((p->integrator != PF_EULER || p->interface_noise > 0) && p->temporal_block > 1) return PF_EINVAL;
     if (!finite_all({p->h, p->dt, p->dt_factor, p->W_c, p->W_phi, p->kappa_c, p->kappa_phi, p->MA_bulk,
@@ -136,6 +168,8 @@ struct pf_handle {
     int fused = PF_FUSED_TILE;           // K >= 2: LDS tile or register strip march (K == 2)
     int k2_ty = 8;                       // register strip march: rows per wave
     int k2_cols = 1;                     // register strip march: grid columns per lane
+    int res_th = 0;                      // resident stepper: tile height (0: not used)
+    int res_ntx = 0, res_nty = 0;        // resident stepper: tiles per row / column
     int last_hip = 0;
     hipGraph_t graph = nullptr;          // chain of kGraphLen full-K launches
     hipGraphExec_t gexec = nullptr;
@@ -318,11 +352,41 @@ int enqueue_midpoint(pf_handle* h, int64_t n)
     return PF_OK;
 }
 
+// Resident stepper: all n >= 2 steps in one cooperative launch, in place on
+// the caller's buffers, in chunks below 2^31 steps.
+int enqueue_resident(pf_handle* h, int64_t n)
+{
+    pfk::ResArgs ra{};
+    ra.s = step_args<float>(h);
+    ra.s.c = (const float*)h->f[0];
+    ra.s.phi = (const float*)h->f[1];
+    ra.s.rho = (const float*)h->f[2];
+    ra.s.c_out = (float*)h->f[0];
+    ra.s.phi_out = (float*)h->f[1];
+    ra.s.rho_out = (float*)h->f[2];
+    ra.s.nsub = 1;
+    ra.rim = (uint64_t*)(h->ws + h->L.rim);
+    ra.ctl = (uint64_t*)(h->ws + h->L.rctl);
+    ra.batch = h->p.batch;
+    ra.ntx = h->res_ntx;
+    ra.nty = h->res_nty;
+    constexpr int64_t kChunk = (int64_t)1 << 30;
+    while (n > 0) {
+        // never leave a single step for the last chunk
+        ra.n = (int)(n > kChunk + 1 ? kChunk : n);
+        const int rc = hip_fail(h, pfk::launch_resident(ra, h->res_th, h->stream));
+        if (rc) return rc;
+        n -= ra.n;
+    }
+    return PF_OK;
+}
+
 template <typename T>
 int enqueue_steps(pf_handle* h, int64_t n)
 {
     const pf_params* p = &h->p;
     if (p->integrator == PF_MIDPOINT) return enqueue_midpoint<T>(h, n);
+    if (h->res_th && n >= 2) return enqueue_resident(h, n);
     const int K = h->K;
     const bool noise = p->interface_noise > 0;
     pfk::StepArgs<T> a = step_args<T>(h);
@@ -509,6 +573,21 @@ int pf_init(pf_handle** out, const pf_params* p, void* c, void* phi, void* rho, 
         }
     }
 
+    // the resident stepper, where the device keeps every tile resident; a
+    // single step (n == 1) then runs the single-step kernel
+    if (const int rth = resident_th(p)) {
+        const int ntx = p->nx / 64, nty = p->ny / rth;
+        if ((long)p->batch * ntx * nty <= pfk::resident_capacity(rth)) {
+            h->res_th = rth;
+            h->res_ntx = ntx;
+            h->res_nty = nty;
+            h->K = 1;
+        } else if (p->fused_kernel == PF_FUSED_RESIDENT) {
+            delete h;
+            return PF_EINVAL;
+        }
+    }
+
     const double th = p->theta_deg * (3.14159265358979323846 / 180.0);
     h->real.resize(p->batch);
     h->c0.resize(p->batch);
@@ -530,6 +609,8 @@ int pf_init(pf_handle** out, const pf_params* p, void* c, void* phi, void* rho, 
         e = hipMemcpyAsync(h->ws + L.c0, h->c0.data(), p->batch * sizeof(double), hipMemcpyHostToDevice,
                            h->stream);
     if (e == hipSuccess) e = pfk::launch_set_inflow((double*)(h->ws + L.qcol), nullptr, p->nx, p->batch, h->stream);
+    // rim words start with tag 0, which no generation uses; epoch and abort 0
+    if (e == hipSuccess && L.total > L.rim) e = hipMemsetAsync(h->ws + L.rim, 0, L.total - L.rim, h->stream);
     if (e == hipSuccess && p->init_mode == PF_INIT_SEEDED) {
         pfk::InitArgs ia{};
         ia.seed = p->seed;
@@ -777,6 +858,7 @@ extern "C" int pf_get_launch(const pf_handle* h, int32_t* temporal_block, int32_
     if (!h || !temporal_block || !tile_rows) return PF_EINVAL;
     *temporal_block = h->K;
     *tile_rows = h->K == 1 ? h->march_ty : (h->fused == PF_FUSED_MARCH ? h->k2_ty : pfk::tile_cfg<float>(h->K).ty);
+    if (h->res_th) *tile_rows = h->res_th;
     if (h->p.precision == PF_F64 && h->K > 1 && h->fused != PF_FUSED_MARCH)
         *tile_rows = pfk::tile_cfg<double>(h->K).ty;
     return PF_OK;
@@ -785,7 +867,7 @@ extern "C" int pf_get_launch(const pf_handle* h, int32_t* temporal_block, int32_
 extern "C" int pf_get_fused_kernel(const pf_handle* h, int32_t* kind)
 {
     if (!h || !kind) return PF_EINVAL;
-    *kind = h->K == 1 ? 0 : h->fused;
+    *kind = h->res_th ? PF_FUSED_RESIDENT : (h->K == 1 ? 0 : h->fused);
     return PF_OK;
 }
 

@@ -89,6 +89,25 @@ template <typename T>
 hipError_t graph_add_march_k2(hipGraph_t g, hipGraphNode_t* node, hipGraphNode_t dep, const StepArgs<T>& a,
                               int ty, int cols, int batch);
 
+// Resident stepper: one cooperative launch advances FP32 Euler grids by n >= 2
+// steps with each 64 x th tile (th in {8, 16, 32}) held in LDS, trading 2-cell
+// rims after every step through rim[2][tiles][3][resident_rim_words(th)]
+// tagged words; ctl[0] is the generation-tag epoch (advanced by n after the
+// launch), ctl[1] the sticky abort word.  In place: s.c == s.c_out etc.
+// nx = 64 ntx, ny = th nty.
+struct ResArgs {
+    StepArgs<float> s;
+    uint64_t* rim;
+    uint64_t* ctl;
+    int n;
+    int batch, ntx, nty;
+};
+size_t resident_rim_words(int th);
+// Tiles the device keeps co-resident for tile height th (0: no cooperative
+// launch).
+int resident_capacity(int th);
+hipError_t launch_resident(const ResArgs& a, int th, hipStream_t s);
+
 // Append one stepper launch as a kernel node of graph g after node dep
 // (dep == nullptr: no dependency).
 template <typename T>

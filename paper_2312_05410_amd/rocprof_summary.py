@@ -25,7 +25,7 @@ import statistics
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-STEPPER_SOURCES = ("csrc/pf_cell.h", "csrc/pf_march.hip", "csrc/pf_step.hip", "csrc/pf_kernels.h")
+STEPPER_SOURCES = ("csrc/pf_cell.h", "csrc/pf_march.hip", "csrc/pf_step.hip", "csrc/pf_resident.hip", "csrc/pf_kernels.h")
 
 
 def stepper_hash() -> str:

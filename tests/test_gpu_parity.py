@@ -337,6 +337,79 @@ def test_two_step_march_f64_matches_oracle():
     sim.close()
 
 
+@pytest.mark.parametrize("bc,shape,th,batch", [
+    ("pvd", (128, 96), 8, 1), ("pvd", (192, 64), 16, 2), ("periodic", (128, 64), 32, 1),
+    ("pvd", (256, 128), 32, 1), ("pvd", (64, 32), 32, 1), ("periodic", (64, 16), 8, 3),
+    ("pvd", (320, 48), 16, 1)])
+def test_resident_stepper_is_bitwise(bc, shape, th, batch):
+    """The resident stepper (one cooperative launch per call, tiles held in
+    LDS, inner cells computed while the rims are traded through tagged
+    words) equals single-step launches bit for bit, state and inflow, over
+    calls of 2, 3, 37, 1 (the single-step kernel) and 141 steps in a row;
+    one tile column, one tile row and batches included."""
+    nx, ny = shape
+    announce(f"resident {bc} {batch}x{nx}x{ny} th={th}")
+    p = PFParams(nx=nx, ny=ny, batch=batch, precision="f32", bc_mode=bc, theta_deg=61.0, v0=0.85)
+    state = random_state(31, batch, ny, nx)
+    ref = Sim(p, state=state, temporal_block=1, lane_cols=1)
+    sim = Sim(p, state=state, fused_kernel=3, tile_rows=th)
+    assert sim.fused_kernel == 3 and sim.launch == (1, th)
+    for n in (2, 3, 37, 1, 141):
+        ref.step(n)
+        sim.step(n)
+        for u, v in zip(sim.state(), ref.state()):
+            assert np.array_equal(u, v), f"after a call of {n} steps"
+        assert np.array_equal(sim.inflow(), ref.inflow()), f"after a call of {n} steps"
+    ref.close()
+    sim.close()
+
+
+def test_resident_stepper_matches_oracle():
+    """FP32 resident stepper against the FP64 oracle: 128^2, 1000 steps, the
+    library's tile height."""
+    announce("resident vs oracle 128x128 f32")
+    p = workloads.dns_small(0, "f32")
+    dt = oracle.resolve_dt(p)
+    p = p.replace(dt=dt)
+    state = initial_state(p)
+    sim = Sim(p, state=state, fused_kernel=3)
+    assert sim.fused_kernel == 3
+    ref = oracle.State(p, *state, dt=dt)
+    sim.step(1000)
+    ref.step(1000)
+    compare(sim.state(), ref, F32_TOL, "resident")
+    np.testing.assert_allclose(sim.mass(), ref.mass(), rtol=2e-6, atol=1e-6)
+    np.testing.assert_allclose(sim.energy(), ref.energy(), rtol=1e-5)
+    sim.close()
+
+
+def test_resident_abort_word_poisons_the_state():
+    """A set abort word (forced from the host; the kernel only reads it) makes
+    every tile stop at once and write NaN, which the diagnostics report; a
+    new handle on the same workspace size starts clean."""
+    announce("resident abort word")
+    import torch
+    from paper_2312_05410_amd._lib import PFError, PF_ENONFINITE
+
+    p = PFParams(nx=128, ny=64, precision="f32")
+    sim = Sim(p, fused_kernel=3)
+    assert sim.fused_kernel == 3
+    ws = sim.workspace
+    # the control words (epoch, abort) are the workspace's last 256-byte block
+    ws[-256 + 8:-256 + 16] = torch.tensor([1, 0, 0, 0, 0, 0, 0, 0], dtype=torch.uint8, device=ws.device)
+    torch.cuda.synchronize()
+    sim.step(5)
+    assert np.isnan(sim.state()[0]).all()
+    with pytest.raises(PFError) as ei:
+        sim.mass()
+    assert ei.value.code == PF_ENONFINITE
+    sim.close()
+    again = Sim(p, fused_kernel=3)
+    again.step(5)
+    assert np.isfinite(again.mass()).all()
+    again.close()
+
+
 def test_two_columns_need_even_rows_and_fp32():
     announce("two columns per lane fallback")
     for q in (PFParams(nx=151, ny=40, precision="f32"), PFParams(nx=150, ny=40, precision="f64")):
@@ -408,6 +481,7 @@ def test_full_size_production_parity():
     p = workloads.dns_production(0)
     K = workloads.BENCH_TEMPORAL_BLOCK["f32"]
     sim, ref = run_pair(p, initial_state(p), 20, 1e-6, temporal_block=K)
+    assert sim.fused_kernel == 3 and sim.launch == (1, 32)   # the resident stepper
     assert sim.step_count == 20
     np.testing.assert_allclose(sim.mass(), ref.mass(), rtol=1e-6)
     sim.close()
