@@ -157,9 +157,11 @@ def gpu_leg(args, p, steps, warmup, K):
                 fused=fused)
 
 
-def measured_traffic(workload: str, kernel: str):
+def measured_traffic(workload: str, kernel: str, steps_per_launch: int = 0):
     """HBM bytes per launch from the committed counter summary of this
-    workload, if it was taken on the current stepper sources and kernel."""
+    workload, if it was taken on the current stepper sources and kernel (for
+    a kernel whose launch runs a whole call, the summary's bytes per step
+    times the steps of this launch)."""
     from paper_2312_05410_amd import rocprof_summary
 
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
@@ -172,6 +174,8 @@ def measured_traffic(workload: str, kernel: str):
             kv[k.strip()] = v.strip()
     if kv.get("stepper_source_sha256_16") != rocprof_summary.stepper_hash() or kv.get("kernel") != kernel:
         return None
+    if "hbm_bytes_per_step" in kv and steps_per_launch:
+        return float(kv["hbm_bytes_per_step"]) * steps_per_launch
     return float(kv["hbm_bytes_per_launch"])
 
 
@@ -479,7 +483,7 @@ def main():
         kname = kernel_name(prec, g["K"], g["rows"], noise=noise, cols=g["cols"], fused=g["fused"])
     launch_s = g["seconds"] / g["launches"]
     achieved = bytes_per_launch / launch_s / 1e9
-    tb = measured_traffic(args.workload, kname)
+    tb = measured_traffic(args.workload, kname, steps if g["fused"] == 3 and g["launches"] == 1 else 0)
     traffic = None if tb is None else round(tb / launch_s / 1e9, 1)
     result = {
         "metric": "phase-field GLUPS & %HBM peak",

@@ -116,6 +116,8 @@ def main(argv=None):
     t.add_argument("--ref-bytes", type=int, default=512 * 1024 * 1024)
     t.add_argument("--out")
     t.add_argument("--command", default="")
+    t.add_argument("--steps-per-launch", type=int, default=0,
+                   help="steps each dispatch advances (a launch that runs a whole call): also per step")
     a = ap.parse_args(argv)
     if a.cmd == "stats":
         for name, calls, avg, mn, mx, pct in stats(a.dir, a.kernel):
@@ -138,6 +140,9 @@ def main(argv=None):
              f"hbm_read_bytes_per_launch: {r['fetch_bytes']:.0f}",
              f"hbm_write_bytes_per_launch: {r['write_bytes']:.0f}",
              f"hbm_bytes_per_launch: {r['fetch_bytes'] + r['write_bytes']:.0f}"]
+    if a.steps_per_launch:
+        lines += [f"steps_per_launch: {a.steps_per_launch}",
+                  f"hbm_bytes_per_step: {(r['fetch_bytes'] + r['write_bytes']) / a.steps_per_launch:.0f}"]
     if a.command:
         lines.insert(0, f"command: {a.command}")
     text = "\n".join(lines) + "\n"
