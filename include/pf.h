@@ -114,8 +114,9 @@ typedef struct pf_params {
                                      choice by precision and grid size; lowered so that 2K <= ny */
     int32_t graph_mode;           /* 0: long runs replay a HIP graph of launches; 1: plain launches */
     int32_t tile_rows;            /* single-step kernel: rows per wave (4, 8, 16, 32); resident
-                                     stepper: tile height (8, 16, 32); 0: library's choice by grid
-                                     size */
+                                     stepper: tile height (8, 16, 32; a height asked for with
+                                     fused_kernel 0 keeps the strip-march kernels); 0: library's
+                                     choice by grid size */
     int32_t integrator;           /* pf_integrator */
     uint64_t seed;                /* seeded initial condition: realisation b uses seed + b */
     double h;                     /* grid spacing */

@@ -47,7 +47,12 @@ int resident_th(const pf_params* p)
     } else if (p->fused_kernel != PF_FUSED_RESIDENT || p->temporal_block > 1) {
         return 0;
     }
-    if (p->tile_rows >= 8) return p->ny % p->tile_rows == 0 && p->fused_kernel == PF_FUSED_RESIDENT ? p->tile_rows : 0;
+    if (p->tile_rows != 0) {
+        // a chunk height asked for: the resident stepper only on request, at
+        // a tile height it has
+        const bool has = p->tile_rows == 8 || p->tile_rows == 16 || p->tile_rows == 32;
+        return p->fused_kernel == PF_FUSED_RESIDENT && has && p->ny % p->tile_rows == 0 ? p->tile_rows : 0;
+    }
     for (int t : {32, 16, 8})
         if (p->ny % t == 0) return t;
     return 0;

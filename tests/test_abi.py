@@ -75,6 +75,31 @@ def test_workspace_bytes():
     assert _lib.workspace_bytes(p.replace(precision="f64")) > n
 
 
+def _ws(p, **kw):
+    s, keep = _lib.to_c(p, **kw)
+    return _lib.load().pf_workspace_bytes(ctypes.byref(s))
+
+
+def test_resident_stepper_shapes_and_workspace():
+    """The resident stepper's shape rules are checked before anything runs;
+    its rim buffers (2 x tiles x 3 x (256 + 4 TY) 8-byte words) and its
+    256-byte control block are in the workspace exactly when it may run."""
+    base = PFParams(nx=128, ny=64, precision="f32")
+    n0 = _ws(base)                                   # 8192 cells: no resident stepper by default
+    assert _ws(base, fused_kernel=3) - n0 == 2 * 4 * 3 * (256 + 4 * 32) * 8 + 256          # TY 32: 2 x 2 tiles
+    assert _ws(base, fused_kernel=3, tile_rows=8) - n0 == 2 * 16 * 3 * (256 + 4 * 8) * 8 + 256
+    assert _ws(base, fused_kernel=3, temporal_block=1) == _ws(base, fused_kernel=3)
+    big = PFParams(nx=512, ny=512, precision="f32")  # 2^18 cells: the default
+    assert _ws(big) - _ws(big, temporal_block=2) == 2 * 128 * 3 * (256 + 4 * 32) * 8 + 256
+    assert _ws(big, tile_rows=8) == _ws(big, temporal_block=2)   # a chunk height asked for: no resident
+    for bad in (dict(nx=100), dict(precision="f64"), dict(integrator="midpoint"), dict(interface_noise=0.1),
+                dict(ny=60), dict(nx=2048, ny=2048)):
+        assert _ws(base.replace(**bad), fused_kernel=3) == 0, bad
+    assert _ws(base, fused_kernel=3, temporal_block=2) == 0
+    assert _ws(base, fused_kernel=3, tile_rows=4) == 0
+    assert _ws(base, fused_kernel=4) == 0
+
+
 def _init(p, ptrs=(4096, 8192, 12288), ws=1 << 20, wsize=None, **kw):
     L = _lib.load()
     s, keep = _lib.to_c(p, **kw)
