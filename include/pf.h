@@ -100,7 +100,9 @@ enum pf_integrator { PF_EULER = 0, PF_MIDPOINT = 1 };
  * TY in {8, 16, 32} dividing ny (tile_rows, else the library's choice) and
  * a grid of at most 2^21 cells whose tiles the device can keep resident at
  * once (about 1M cells on MI355X); else pf_init returns PF_EINVAL.  Its
- * results are bitwise equal to the other kernels'. */
+ * results are bitwise equal to the other kernels'.  A resident launch takes
+ * every workgroup slot of the device for its duration: calls of several
+ * handles on one device must not run concurrently on different streams. */
 enum pf_fused { PF_FUSED_AUTO = 0, PF_FUSED_TILE = 1, PF_FUSED_MARCH = 2, PF_FUSED_RESIDENT = 3 };
 
 typedef struct pf_params {
