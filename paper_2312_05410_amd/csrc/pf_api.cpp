@@ -519,21 +519,23 @@ int pf_init(pf_handle** out, const pf_params* p, void* c, void* phi, void* rho, 
     // and for FP64.  The mirror ghosts of a launch must be real rows, so
     // 2K <= ny.
     const long cells = (long)p->nx * p->ny * p->batch;
-    // FP32 Euler runs fuse two steps by default (measured on MI355X): the
-    // LDS tile for one grid of ~0.75M to ~3M cells (1024^2: 155 GLUPS
-    // against 151 for the register march), the register strip march
-    // otherwise when a chunk height divides ny, with 16-row chunks from ~3M
-    // cells and 4 below (512^2: 73 against 59 for single steps; 2048^2 266,
-    // 4096^2 297, 8192^2 343 against 221, 171, 214; 32 x 512^2 308 against
-    // 250; deeper load look-ahead for 16-row chunks measured slower)
+    // FP32 Euler runs fuse two steps by default (measured on MI355X) in the
+    // register strip march when a chunk height divides ny: 16-row chunks
+    // from ~3M cells, 8 for one grid of ~0.75M to ~3M cells, 4 below (512^2:
+    // 73 against 59 for single steps; 2048 x 1024: 203 against 178 with 4
+    // rows and 162 for the LDS tile; 1000 x 800: 145 against 138 and 121;
+    // 2048^2 266, 4096^2 297, 8192^2 343 against 221, 171, 214 for single
+    // steps; 32 x 512^2 308 against 250; deeper load look-ahead for 16-row
+    // chunks measured slower), else the LDS tile for such a grid (any ny;
+    // 1000^2: 152 against 144); the resident stepper takes precedence
     const bool plain_euler = p->integrator == PF_EULER && !(p->interface_noise > 0);
     const bool f32 = p->precision == PF_F32;
-    const bool tile_band = f32 && p->batch == 1 && cells >= 786432L && cells < 3000000L;
-    const int k2_auto_ty = cells >= 3000000L ? 16 : 4;
+    const bool mid_band = f32 && p->batch == 1 && cells >= 786432L && cells < 3000000L;
+    const int k2_auto_ty = cells >= 3000000L ? 16 : (mid_band ? 8 : 4);
     int K = p->temporal_block;
     // FP64 fuses two steps only on large grids (4096^2: 146 GLUPS against
     // 102 for single steps; 1024^2: 84 against 82)
-    if (K == 0 && plain_euler && f32) K = tile_band || p->ny % 4 == 0 ? 2 : 1;
+    if (K == 0 && plain_euler && f32) K = mid_band || p->ny % 4 == 0 ? 2 : 1;
     if (K == 0 && plain_euler && !f32) K = cells >= 3000000L && p->ny % 4 == 0 ? 2 : 1;
     if (K == 0) K = 1;
     if (p->integrator != PF_EULER || p->interface_noise > 0) K = 1;
@@ -559,11 +561,11 @@ int pf_init(pf_handle** out, const pf_params* p, void* c, void* phi, void* rho, 
     const long w1 = (p->nx + 59) / 60 * 64L, w2 = (p->nx + 123) / 124 * 128L;
     const int cols = p->lane_cols ? p->lane_cols : (cells >= 8000000L && w2 <= w1 ? 2 : 1);
     h->march_cols = cols == 2 && two_ok ? 2 : 1;
-    // fused steps: the LDS tile, or the register strip march when asked for
-    // (two steps, chunk heights dividing ny)
+    // fused steps: the register strip march (two steps, chunk heights
+    // dividing ny) as asked for or by default, else the LDS tile
     h->fused = PF_FUSED_TILE;
-    const bool march_k2 = p->fused_kernel == PF_FUSED_MARCH || (p->fused_kernel == PF_FUSED_AUTO && !tile_band &&
-                                                               (f32 || p->temporal_block == 0));
+    const bool march_k2 = p->fused_kernel == PF_FUSED_MARCH ||
+                          (p->fused_kernel == PF_FUSED_AUTO && (f32 || p->temporal_block == 0));
     if (K == 2 && march_k2) {
         const int auto_ty = p->fused_kernel == PF_FUSED_MARCH ? 8 : k2_auto_ty;
         const int want = p->tile_rows == 4 || p->tile_rows == 8 || p->tile_rows == 16 ? p->tile_rows : auto_ty;
