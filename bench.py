@@ -11,9 +11,10 @@ timing starts; W untimed steps are followed by exactly K timed steps
 bracketed by device synchronisation.  Prints one JSON line with GLUPS
 (giga lattice-site updates per second), the roofline of the stepper kernel
 (algorithmic bytes per launch over the event-timed average launch duration,
-against the 8 TB/s HBM peak; with two fused steps per launch the effective
-rate can exceed the peak), the HBM bytes per launch from the committed
-counter summary when it matches the sources, a size sweep for the bandwidth
+against the 8 TB/s HBM peak; with two fused steps per launch, or the
+resident stepper's one launch per call that keeps the state on chip, the
+effective rate can exceed the peak), the HBM bytes per launch from the
+committed counter summary when it matches the sources, a size sweep for the bandwidth
 claim at working sets larger than the 256 MB Infinity Cache, a plain device
 copy rate, and the FP64 CPU oracle timed on a bounded sample on the host
 cores.  Other workloads: dns_8192_f32, batched_32x512_f32, dns_small_128_f64,
