@@ -364,6 +364,28 @@ def test_resident_stepper_is_bitwise(bc, shape, th, batch):
     sim.close()
 
 
+@pytest.mark.parametrize("nx,ny,batch", [(512, 512, 1), (512, 512, 4), (1024, 768, 1)])
+def test_resident_default_shapes_are_bitwise(nx, ny, batch):
+    """Where the library picks the resident stepper by itself (the blended
+    run's 512^2 DNS, four realisations of it, a 0.79M-cell grid), production
+    initial conditions stepped by it equal single-step launches bit for bit,
+    state and inflow."""
+    announce(f"resident default {batch}x{nx}x{ny}")
+    p = workloads.dns_production(0, n=nx).replace(ny=ny, batch=batch)
+    state = initial_state(p)
+    sim = Sim(p, state=state)
+    ref = Sim(p, state=state, temporal_block=1)
+    assert sim.fused_kernel == 3 and ref.fused_kernel == 0
+    for n in (64, 201):
+        sim.step(n)
+        ref.step(n)
+    for u, v in zip(sim.state(), ref.state()):
+        assert np.array_equal(u, v)
+    assert np.array_equal(sim.inflow(), ref.inflow())
+    sim.close()
+    ref.close()
+
+
 def test_resident_stepper_matches_oracle():
     """FP32 resident stepper against the FP64 oracle: 128^2, 1000 steps, the
     library's tile height."""
