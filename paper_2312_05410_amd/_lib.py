@@ -283,7 +283,8 @@ class Simulator:
     @property
     def fused_kernel(self) -> int:
         """Kernel of the fused launches: 1 LDS tile, 2 register strip march,
-        0 when each launch is one step."""
+        3 resident stepper (one launch per call), 0 when each launch is one
+        step."""
         c = ctypes.c_int32()
         self._check(load().pf_get_fused_kernel(self._h, ctypes.byref(c)), "pf_get_fused_kernel")
         return c.value

@@ -511,13 +511,11 @@ int pf_init(pf_handle** out, const pf_params* p, void* c, void* phi, void* rho, 
     for (int f = 0; f < 3; ++f) h->w[f] = h->ws + L.state[f];
     h->stream = (hipStream_t)stream;
     h->dt = dt;
-    // Launch shape.  Fused steps per launch K: as requested, else (measured
-    // on MI355X) two steps through the LDS-tiled kernel for FP32 grids of
-    // ~0.75M to ~3M cells per launch, where one step does not fill the GPU,
-    // and the single-step strip-march kernel otherwise (below ~0.75M cells
-    // the tiled kernel has too few tiles and its longer launches cost more)
-    // and for FP64.  The mirror ghosts of a launch must be real rows, so
-    // 2K <= ny.
+    // Launch shape.  Fused steps per launch K: as requested, else by
+    // precision, grid size and variant (the rules below, measured on
+    // MI355X); the resident stepper, where it runs, replaces them all for
+    // calls of two or more steps.  The mirror ghosts of a launch must be real
+    // rows, so 2K <= ny.
     const long cells = (long)p->nx * p->ny * p->batch;
     // FP32 Euler runs fuse two steps by default (measured on MI355X) in the
     // register strip march when a chunk height divides ny: 16-row chunks
