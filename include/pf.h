@@ -94,9 +94,10 @@ enum pf_integrator { PF_EULER = 0, PF_MIDPOINT = 1 };
  * resident stepper: one cooperative launch per pf_step_n call (of at least
  * 2 steps; a single step runs the single-step kernel) in which every
  * workgroup keeps a 64 x TY tile of the state in LDS for all the steps and
- * trades its 2-cell rim with its neighbours after each step through the
- * workspace.  The resident stepper needs FP32, explicit Euler without
- * interface draws, temporal_block 0 or 1, nx a multiple of 64, a tile height
+ * trades its 2-cell rim with its neighbours after each step (and each
+ * midpoint half step) through the workspace.  The resident stepper needs
+ * FP32, explicit Euler or the midpoint method without interface draws,
+ * temporal_block 0 or 1, nx a multiple of 64, a tile height
  * TY in {8, 16, 32} dividing ny (tile_rows, else the library's choice) and
  * a grid of at most 2^21 cells whose tiles the device can keep resident at
  * once (about 1M cells on MI355X); else pf_init returns PF_EINVAL.  Its

@@ -30,7 +30,7 @@ struct Layout {
 constexpr long kResMaxCells = 1L << 21;   // resident stepper: cells per launch at most
 
 // Tile height of the resident stepper for *p, 0 where it does not run: FP32
-// explicit Euler without interface draws, asked for or left to the library
+// explicit Euler or midpoint without interface draws, asked for or left to the library
 // (temporal_block 0) from 2^18 cells (measured on MI355X: 512^2 79.9 GLUPS
 // against 72.1 for the two-step march, 1024^2 218 against 156 for the LDS
 // tile, 4 x 512^2 238 against 154; 256^2 16 against 25), 64-column tiles, a
@@ -39,7 +39,8 @@ constexpr long kResMaxCells = 1L << 21;   // resident stepper: cells per launch 
 // every tile resident is checked when the handle is created.
 int resident_th(const pf_params* p)
 {
-    if (p->precision != PF_F32 || p->integrator != PF_EULER || p->interface_noise > 0) return 0;
+    if (p->precision != PF_F32 || p->interface_noise > 0) return 0;
+    if (p->integrator != PF_EULER && p->integrator != PF_MIDPOINT) return 0;
     const long cells = (long)p->nx * p->ny * p->batch;
     if (p->nx % 64 || cells > kResMaxCells) return 0;
     if (p->fused_kernel == PF_FUSED_AUTO) {
@@ -358,11 +359,13 @@ int enqueue_midpoint(pf_handle* h, int64_t n)
 }
 
 // Resident stepper: all n >= 2 steps in one cooperative launch, in place on
-// the caller's buffers, in chunks below 2^31 steps.
+// the caller's buffers, in chunks of at most 2^29 steps.
 int enqueue_resident(pf_handle* h, int64_t n)
 {
     pfk::ResArgs ra{};
     ra.s = step_args<float>(h);
+    ra.kh = make_coef<float>(&h->p, 0.5 * h->dt);
+    ra.mid = h->p.integrator == PF_MIDPOINT;
     ra.s.c = (const float*)h->f[0];
     ra.s.phi = (const float*)h->f[1];
     ra.s.rho = (const float*)h->f[2];
@@ -375,7 +378,7 @@ int enqueue_resident(pf_handle* h, int64_t n)
     ra.batch = h->p.batch;
     ra.ntx = h->res_ntx;
     ra.nty = h->res_nty;
-    constexpr int64_t kChunk = (int64_t)1 << 30;
+    constexpr int64_t kChunk = (int64_t)1 << 29;
     while (n > 0) {
         // never leave a single step for the last chunk
         ra.n = (int)(n > kChunk + 1 ? kChunk : n);
@@ -390,8 +393,8 @@ template <typename T>
 int enqueue_steps(pf_handle* h, int64_t n)
 {
     const pf_params* p = &h->p;
-    if (p->integrator == PF_MIDPOINT) return enqueue_midpoint<T>(h, n);
     if (h->res_th && n >= 2) return enqueue_resident(h, n);
+    if (p->integrator == PF_MIDPOINT) return enqueue_midpoint<T>(h, n);
     const int K = h->K;
     const bool noise = p->interface_noise > 0;
     pfk::StepArgs<T> a = step_args<T>(h);

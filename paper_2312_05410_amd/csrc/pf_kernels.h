@@ -89,17 +89,19 @@ template <typename T>
 hipError_t graph_add_march_k2(hipGraph_t g, hipGraphNode_t* node, hipGraphNode_t dep, const StepArgs<T>& a,
                               int ty, int cols, int batch);
 
-// Resident stepper: one cooperative launch advances FP32 Euler grids by n >= 2
-// steps with each 64 x th tile (th in {8, 16, 32}) held in LDS, trading 2-cell
+// Resident stepper: one cooperative launch advances FP32 grids by n >= 2
+// explicit Euler or midpoint steps with each 64 x th tile (th in {8, 16, 32}) held in LDS, trading 2-cell
 // rims after every step through rim[2][tiles][3][resident_rim_words(th)]
 // tagged words; ctl[0] is the generation-tag epoch (advanced by n after the
 // launch), ctl[1] the sticky abort word.  In place: s.c == s.c_out etc.
 // nx = 64 ntx, ny = th nty.
 struct ResArgs {
     StepArgs<float> s;
+    Coef<float> kh;      // midpoint: the half step's constants (dt / 2)
     uint64_t* rim;
     uint64_t* ctl;
     int n;
+    int mid;             // 1: explicit midpoint steps (two rim trades per step)
     int batch, ntx, nty;
 };
 size_t resident_rim_words(int th);

@@ -2,8 +2,8 @@
 // and Methods, "Phase-field modeling of physical vapor deposition"; second-
 // order central differences as stated in "Dataset"; explicit Euler in time).
 //
-// One cooperative launch advances FP32 grids of up to ~1M cells by n steps
-// with the state held on chip.  Each workgroup owns a 64 x TH tile (TH/4
+// One cooperative launch advances FP32 grids of up to ~1M cells by n explicit
+// Euler or midpoint steps with the state held on chip.  Each workgroup owns a 64 x TH tile (TH/4
 // waves, 4 rows per wave, lanes = columns) and keeps the tile and a 2-cell
 // halo of c, phi, rho in LDS for the whole launch; after every step it
 // trades only the 2-cell rim of its tile with its neighbours:
@@ -11,7 +11,10 @@
 //  * step: stage 1 (mu_c, mu_phi, M_c) on the tile plus one cell and stage 2
 //    (the conserved updates, deposition source and vapour transport) on the
 //    tile, out of LDS, with the same per-cell functions as every other
-//    stepper kernel, so the states are bitwise identical to theirs;
+//    stepper kernel, so the states are bitwise identical to theirs.  A
+//    midpoint step is two such passes: the half step u + dt/2 R(u), whose
+//    rim is traded like a step's result while each cell keeps u in
+//    registers, then u + dt R(u_half);
 //  * exchange: every rim cell of the new state is stored as one 8-byte word,
 //    the FP32 value in the low half and a 32-bit generation tag in the high
 //    half, into one of two rim buffers (by step parity) with device-coherent
@@ -156,7 +159,8 @@ struct Resident {
     float vx2h, vy2h, rin;
     double qa, qb, qacc;
     RhoCoef<float> rc;
-    float nc[4], np[4], nr[4];   // the wave's 4 rows after the step
+    float nc[4], np[4], nr[4];   // the wave's 4 rows after the step (or half step)
+    float ubc[4], ubp[4], ubr[4];   // midpoint: the state at the start of the step
 
     __device__ __forceinline__ static int L(int r, int x) { return (r + R) * P + x + R; }
 
@@ -170,10 +174,10 @@ struct Resident {
         return x;
     }
 
-    __device__ __forceinline__ void pot_cell(int l)
+    __device__ __forceinline__ void pot_cell(const Coef<float>& k, int l)
     {
         float mc, mp, M;
-        potentials(a.k, t.c[l], t.c[l + 1], t.c[l - 1], t.c[l + P], t.c[l - P], t.p[l], t.p[l + 1], t.p[l - 1],
+        potentials(k, t.c[l], t.c[l + 1], t.c[l - 1], t.c[l + P], t.c[l - P], t.p[l], t.p[l + 1], t.p[l - 1],
                    t.p[l + P], t.p[l - P], mc, mp, M);
         t.mc[l] = mc;
         t.mp[l] = mp;
@@ -181,7 +185,7 @@ struct Resident {
     }
 
     // stage 1 on the tile plus one cell
-    __device__ __forceinline__ void stage1()
+    __device__ __forceinline__ void stage1(const Coef<float>& k)
     {
         constexpr int m = 1;
         int l = L(rb, lane);
@@ -190,7 +194,7 @@ struct Resident {
         for (int i = 0; i < 4; ++i, l += P) {
             const float cN = t.c[l + P], pN = t.p[l + P];
             float mc, mp, M;
-            potentials(a.k, cC, t.c[l + 1], t.c[l - 1], cN, cS, pC, t.p[l + 1], t.p[l - 1], pN, pS, mc, mp, M);
+            potentials(k, cC, t.c[l + 1], t.c[l - 1], cN, cS, pC, t.p[l + 1], t.p[l - 1], pN, pS, mc, mp, M);
             t.mc[l] = mc;
             t.mp[l] = mp;
             t.M[l] = M;
@@ -203,12 +207,16 @@ struct Resident {
         for (int h = NT - 1 - otid(); h < NM; h += NT) {
             int r, x;
             ring_cell<TH>(h, m, r, x);
-            pot_cell(L(r, x));
+            pot_cell(k, L(r, x));
         }
     }
 
-    // stage 2 on the tile: its updates into nc/np/nr
-    __device__ __forceinline__ void stage2()
+    // stage 2 on the tile: its updates into nc/np/nr.  MODE 0: explicit
+    // Euler; 1: the midpoint method's half step (the cell's own state kept
+    // in ubc/ubp/ubr as the step's base, no inflow); 2: its full step on the
+    // half-step state, added to that base
+    template <int MODE>
+    __device__ __forceinline__ void stage2(const Coef<float>& k)
     {
         int l = L(rb, lane);
         float pS = t.p[l - P], pC = t.p[l], rS = t.r[l - P], rC = t.r[l];
@@ -218,11 +226,17 @@ struct Resident {
         for (int i = 0; i < 4; ++i, l += P) {
             const float pN = t.p[l + P], rN = t.r[l + P], MN = t.M[l + P], mN = t.mc[l + P], qN = t.mp[l + P];
             const bool bottom = pvd && y0 + rb + i == 0;
-            update(a.k, rc, vx2h, vy2h, bottom, t.c[l], pC, t.p[l + 1], t.p[l - 1], pN, pS, rC, t.r[l + 1],
-                   t.r[l - 1], rN, rS, cflux(MC, mC, t.M[l + 1], t.mc[l + 1]),
-                   cflux(t.M[l - 1], t.mc[l - 1], MC, mC), cflux(MC, mC, MN, mN), cflux(MS, mS, MC, mC), qC,
-                   t.mp[l + 1], t.mp[l - 1], qN, qS, nc[i], np[i], nr[i]);
-            if (qrow && i == 3) {
+            const float c0 = t.c[l];
+            if constexpr (MODE == 1) {
+                ubc[i] = c0;
+                ubp[i] = pC;
+                ubr[i] = rC;
+            }
+            update(k, rc, vx2h, vy2h, bottom, c0, pC, t.p[l + 1], t.p[l - 1], pN, pS, rC, t.r[l + 1], t.r[l - 1], rN,
+                   rS, cflux(MC, mC, t.M[l + 1], t.mc[l + 1]), cflux(t.M[l - 1], t.mc[l - 1], MC, mC),
+                   cflux(MC, mC, MN, mN), cflux(MS, mS, MC, mC), qC, t.mp[l + 1], t.mp[l - 1], qN, qS, nc[i], np[i],
+                   nr[i], MODE == 2 ? ubc[i] : c0, MODE == 2 ? ubp[i] : pC, MODE == 2 ? ubr[i] : rC);
+            if (MODE != 1 && qrow && i == 3) {
                 const double rind = (double)rin, rr = (double)rC;
                 qacc += qa * (rr + rind) + qb * (rind - rr);
             }
@@ -268,7 +282,7 @@ struct Resident {
 
 // At most 128 VGPRs (four waves per SIMD), so that 1024^2 (512 tiles of
 // 64 x 32) stays resident at two workgroups per CU.
-template <int TH>
+template <int TH, bool MID>
 __global__ __launch_bounds__(16 * TH) __attribute__((amdgpu_waves_per_eu(4)))
 void resident_kernel(ResArgs ra)
 {
@@ -323,7 +337,7 @@ void resident_kernel(ResArgs ra)
 
     const Real rl = a.real[b];
     St st{a, t, tid, lane, wv, 4 * wv, b, tx, ty, ra.nty, x0, y0, pvd, false, (float)rl.vx2h, (float)rl.vy2h, rin,
-          rl.qa, rl.qb, 0.0, rho_coef(a.k, (float)rl.vx2h, (float)rl.vy2h), {}, {}, {}};
+          rl.qa, rl.qb, 0.0, rho_coef(a.k, (float)rl.vx2h, (float)rl.vy2h), {}, {}, {}, {}, {}, {}};
     // inflow through the top face: the last wave of a top tile holds row ny-1
     st.qrow = pvd && a.Qcol && ty == ra.nty - 1 && wv == G::NW - 1;
     if (st.qrow) st.qacc = a.Qcol[(size_t)b * nx + x0 + lane];
@@ -331,19 +345,35 @@ void resident_kernel(ResArgs ra)
     const size_t par_stride = (size_t)gridDim.x * 3 * RS;
     uint64_t* const own_rim = ra.rim + (size_t)tile * 3 * RS;
 
+
+    // rim generations: one per step; with the midpoint method two, the odd
+    // ones holding the half-step state u_half = u + dt/2 R(u) (the step's
+    // base u stays in registers) and the even ones u' = u + dt R(u_half)
+    const int last = MID ? 2 * ra.n : ra.n;
     __syncthreads();
     bool stop = s_stop != 0;
     int g = 0;
     while (!stop) {
-        st.stage1();
-        __syncthreads();
-        st.stage2();
+        if constexpr (MID) {
+            if ((g & 1) == 0) {
+                st.stage1(ra.kh);
+                __syncthreads();
+                st.template stage2<1>(ra.kh);
+            } else {
+                st.stage1(a.k);
+                __syncthreads();
+                st.template stage2<2>(a.k);
+            }
+        } else {
+            st.stage1(a.k);
+            __syncthreads();
+            st.template stage2<0>(a.k);
+        }
         ++g;
-        if (g == ra.n) {
+        if (g == last) {
             st.write_result();
             break;
         }
-
         // ---- publish the rim of generation g: the first and last two rows
         // straight from registers (whole rows: full cache lines); the
         // exchange's indexing is recomputed every step (st.otid)
@@ -449,29 +479,32 @@ __global__ void epoch_kernel(uint64_t* ctl, int n)
     if (threadIdx.x == 0) ctl[0] += (uint64_t)n;
 }
 
-template <int TH>
+template <int TH, bool MID>
 hipError_t launch_th(const ResArgs& ra, hipStream_t s)
 {
     ResArgs x = ra;
     void* args[] = {&x};
     const int ntiles = ra.batch * ra.ntx * ra.nty;
-    hipError_t e = hipLaunchCooperativeKernel((const void*)resident_kernel<TH>, dim3(ntiles), dim3(RGeo<TH>::NT),
-                                              args, 0, s);
+    hipError_t e = hipLaunchCooperativeKernel((const void*)resident_kernel<TH, MID>, dim3(ntiles),
+                                              dim3(RGeo<TH>::NT), args, 0, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(epoch_kernel, dim3(1), dim3(64), 0, s, ra.ctl, ra.n);
+    // the launch used generations e0 + 1 .. e0 + n (e0 + 2n: two per midpoint step)
+    hipLaunchKernelGGL(epoch_kernel, dim3(1), dim3(64), 0, s, ra.ctl, MID ? 2 * ra.n : ra.n);
     return hipGetLastError();
 }
 
 template <int TH>
 int capacity_th()
 {
-    int dev = 0, coop = 0, cus = 0, nb = 0;
+    int dev = 0, coop = 0, cus = 0, nb = 0, nb2 = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, resident_kernel<TH>, RGeo<TH>::NT, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, resident_kernel<TH, false>, RGeo<TH>::NT, 0) != hipSuccess)
         return 0;
-    return nb * cus;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb2, resident_kernel<TH, true>, RGeo<TH>::NT, 0) != hipSuccess)
+        return 0;
+    return (nb < nb2 ? nb : nb2) * cus;
 }
 
 }  // namespace
@@ -493,12 +526,16 @@ int resident_capacity(int th)
 
 hipError_t launch_resident(const ResArgs& ra, int th, hipStream_t s)
 {
-    if (ra.n < 2 || ra.s.nx % kTW || ra.ntx * kTW != ra.s.nx || ra.nty * th != ra.s.ny || ra.s.ny < th)
+    if (ra.n < 2 || ra.s.nx % kTW || ra.ntx * kTW != ra.s.nx || ra.nty * th != ra.s.ny || ra.s.ny < th ||
+        (ra.mid ? 2 : 1) * (long)ra.n >= (1L << 31))
         return hipErrorInvalidValue;
-    switch (th) {
-    case 8: return launch_th<8>(ra, s);
-    case 16: return launch_th<16>(ra, s);
-    case 32: return launch_th<32>(ra, s);
+    switch (th * 2 + (ra.mid ? 1 : 0)) {
+    case 16: return launch_th<8, false>(ra, s);
+    case 17: return launch_th<8, true>(ra, s);
+    case 32: return launch_th<16, false>(ra, s);
+    case 33: return launch_th<16, true>(ra, s);
+    case 64: return launch_th<32, false>(ra, s);
+    case 65: return launch_th<32, true>(ra, s);
     default: return hipErrorInvalidValue;
     }
 }

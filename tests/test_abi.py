@@ -92,8 +92,9 @@ def test_resident_stepper_shapes_and_workspace():
     big = PFParams(nx=512, ny=512, precision="f32")  # 2^18 cells: the default
     assert _ws(big) - _ws(big, temporal_block=2) == 2 * 128 * 3 * (256 + 4 * 32) * 8 + 256
     assert _ws(big, tile_rows=8) == _ws(big, temporal_block=2)   # a chunk height asked for: no resident
-    for bad in (dict(nx=100), dict(precision="f64"), dict(integrator="midpoint"), dict(interface_noise=0.1),
-                dict(ny=60), dict(nx=2048, ny=2048)):
+    assert _ws(base.replace(integrator="midpoint"), fused_kernel=3) == _ws(base, fused_kernel=3)
+    for bad in (dict(nx=100), dict(precision="f64"), dict(interface_noise=0.1), dict(ny=60),
+                dict(nx=2048, ny=2048)):
         assert _ws(base.replace(**bad), fused_kernel=3) == 0, bad
     assert _ws(base, fused_kernel=3, temporal_block=2) == 0
     assert _ws(base, fused_kernel=3, tile_rows=4) == 0

@@ -386,6 +386,31 @@ def test_resident_default_shapes_are_bitwise(nx, ny, batch):
     ref.close()
 
 
+@pytest.mark.parametrize("bc,shape,th,batch", [("pvd", (128, 96), 8, 1), ("pvd", (192, 64), 16, 2),
+                                                ("periodic", (128, 64), 32, 1), ("pvd", (256, 128), 32, 1)])
+def test_resident_midpoint_is_bitwise(bc, shape, th, batch):
+    """The resident stepper running explicit midpoint steps (the half-step
+    state traded like a step's result, the step's base state kept in
+    registers) equals the two-launch midpoint path bit for bit, state and
+    inflow, over calls of 2, 3, 37, 1 and 141 steps."""
+    nx, ny = shape
+    announce(f"resident midpoint {bc} {batch}x{nx}x{ny} th={th}")
+    p = PFParams(nx=nx, ny=ny, batch=batch, precision="f32", bc_mode=bc, theta_deg=61.0, v0=0.85,
+                 integrator="midpoint")
+    state = random_state(32, batch, ny, nx)
+    ref = Sim(p, state=state, temporal_block=1)
+    sim = Sim(p, state=state, fused_kernel=3, tile_rows=th)
+    assert sim.fused_kernel == 3 and ref.fused_kernel == 0
+    for n in (2, 3, 37, 1, 141):
+        ref.step(n)
+        sim.step(n)
+        for u, v in zip(sim.state(), ref.state()):
+            assert np.array_equal(u, v), f"after a call of {n} steps"
+        assert np.array_equal(sim.inflow(), ref.inflow()), f"after a call of {n} steps"
+    ref.close()
+    sim.close()
+
+
 def test_resident_call_replays_as_graph():
     """A captured resident call (cooperative launch + epoch advance) replays
     correctly: the generation tags of every replay are fresh. Three replays,
