@@ -117,7 +117,7 @@ def kernel_name(prec: str, K: int, rows: int, base: bool = False, noise: bool = 
                 fused: int = 1, mid: bool = False) -> str:
     t = "float" if prec == "f32" else "double"
     if fused == 3:                                # resident stepper: one launch per call
-        return f"resident_kernel<{rows}, {'true' if mid else 'false'}>"
+        return f"resident_kernel<{rows}, {'true' if mid else 'false'}, {'true' if noise else 'false'}>"
     if K == 2 and fused == 2:                     # two steps in the register strip march
         return f"march_k2_kernel<{t}, {rows}, {rows + 1 if rows <= 8 else 4}>"
     if K == 1:
@@ -476,7 +476,7 @@ def main():
         # the resident stepper: one launch per call, both stages of every step
         word = BYTES_PER_LUP[prec] // 6
         bytes_per_launch = sum(MIDPOINT_WORDS) * word * cells * steps / g["launches"]
-        kname = kernel_name(prec, 1, g["rows"], fused=3, mid=True)
+        kname = kernel_name(prec, 1, g["rows"], noise=noise, fused=3, mid=True)
     elif p.integrator == "midpoint":
         # two launches per step; the roofline is that of the pair
         word = BYTES_PER_LUP[prec] // 6

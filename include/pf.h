@@ -76,17 +76,21 @@ enum pf_integrator { PF_EULER = 0, PF_MIDPOINT = 1 };
  *
  * Model variants (Materials and Methods, "Dataset"; Introduction):
  *   integrator PF_MIDPOINT: the explicit midpoint method of the paper's
- *     solver, u' = u + dt R(u + dt/2 R(u)) (two launches per step, the
- *     first into the workspace, the second in place); same stability limit;
+ *     solver, u' = u + dt R(u + dt/2 R(u)) (in the resident stepper where it
+ *     runs, else two launches per step, the first into the workspace, the
+ *     second in place); same stability limit;
  *   interface_noise > 0: the paper's random interface composition, read as:
  *     after every step each cell on the vapour side (phi' < 0) takes a
  *     fresh composition drawn from N(c0_b, interface_noise^2) truncated to
- *     [0, 1].  The draw is FP64 Box-Muller on SplitMix64 uniforms of the
+ *     [0, 1].  The draw is Box-Muller on SplitMix64 uniforms of the
  *     stream (seed + b) ^ 0x2B7E151628AED2A6, counters 16 (s nx ny + j nx + i)
  *     + 2a, + 2a + 1 for attempt a = 0..7 at global step s (pf_get_step),
- *     first draw inside [0, 1] kept, else c0_b.
- *   Both variants run the single-step kernel (temporal_block 0 or 1);
- *   interface_noise also runs plain launches (no graph replay).
+ *     first draw inside [0, 1] kept, else c0_b; evaluated in the run's
+ *     precision (FP32 runs: the hardware logarithm, square root and cosine,
+ *     within ~3e-7 of the FP64 draw).
+ *   Both variants run the resident stepper where it applies (below), else
+ *   the single-step kernel (temporal_block 0 or 1); interface_noise then
+ *   runs plain launches (no graph replay).
  */
 /* Kernel of the launches that fuse several steps: a 64 x TY tile staged in
  * LDS (any K), the register strip march (K = 2: one wave per 64-column
@@ -96,8 +100,8 @@ enum pf_integrator { PF_EULER = 0, PF_MIDPOINT = 1 };
  * workgroup keeps a 64 x TY tile of the state in LDS for all the steps and
  * trades its 2-cell rim with its neighbours after each step (and each
  * midpoint half step) through the workspace.  The resident stepper needs
- * FP32, explicit Euler or the midpoint method without interface draws,
- * temporal_block 0 or 1, nx a multiple of 64, a tile height
+ * FP32, explicit Euler or the midpoint method (with or without interface
+ * draws), temporal_block 0 or 1, nx a multiple of 64, a tile height
  * TY in {8, 16, 32} dividing ny (tile_rows, else the library's choice) and
  * a grid of at most 2^21 cells whose tiles the device can keep resident at
  * once (about 1M cells on MI355X); else pf_init returns PF_EINVAL.  Its

@@ -30,7 +30,8 @@ struct Layout {
 constexpr long kResMaxCells = 1L << 21;   // resident stepper: cells per launch at most
 
 // Tile height of the resident stepper for *p, 0 where it does not run: FP32
-// explicit Euler or midpoint without interface draws, asked for or left to the library
+// explicit Euler or midpoint, with or without interface draws, asked for or
+// left to the library
 // (temporal_block 0) from 2^18 cells (measured on MI355X: 512^2 79.9 GLUPS
 // against 72.1 for the two-step march, 1024^2 218 against 156 for the LDS
 // tile, 4 x 512^2 238 against 154; 256^2 16 against 25), 64-column tiles, a
@@ -39,7 +40,7 @@ constexpr long kResMaxCells = 1L << 21;   // resident stepper: cells per launch 
 // every tile resident is checked when the handle is created.
 int resident_th(const pf_params* p)
 {
-    if (p->precision != PF_F32 || p->interface_noise > 0) return 0;
+    if (p->precision != PF_F32) return 0;
     if (p->integrator != PF_EULER && p->integrator != PF_MIDPOINT) return 0;
     const long cells = (long)p->nx * p->ny * p->batch;
     if (p->nx % 64 || cells > kResMaxCells) return 0;
@@ -366,6 +367,7 @@ int enqueue_resident(pf_handle* h, int64_t n)
     ra.s = step_args<float>(h);
     ra.kh = make_coef<float>(&h->p, 0.5 * h->dt);
     ra.mid = h->p.integrator == PF_MIDPOINT;
+    ra.s.noise = h->p.interface_noise;
     ra.s.c = (const float*)h->f[0];
     ra.s.phi = (const float*)h->f[1];
     ra.s.rho = (const float*)h->f[2];
@@ -379,12 +381,14 @@ int enqueue_resident(pf_handle* h, int64_t n)
     ra.ntx = h->res_ntx;
     ra.nty = h->res_nty;
     constexpr int64_t kChunk = (int64_t)1 << 29;
-    while (n > 0) {
+    int64_t done = 0;
+    while (done < n) {
         // never leave a single step for the last chunk
-        ra.n = (int)(n > kChunk + 1 ? kChunk : n);
+        ra.n = (int)(n - done > kChunk + 1 ? kChunk : n - done);
+        ra.s.step = h->step + done;   // keys the interface draws
         const int rc = hip_fail(h, pfk::launch_resident(ra, h->res_th, h->stream));
         if (rc) return rc;
-        n -= ra.n;
+        done += ra.n;
     }
     return PF_OK;
 }

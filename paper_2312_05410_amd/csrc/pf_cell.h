@@ -165,5 +165,45 @@ __device__ __noinline__ double trunc_gauss(uint64_t seed, uint64_t counter0, dou
     return mean;
 }
 
+// The same draw in FP32 arithmetic (FP32 runs): same stream, counters,
+// attempts and bounds test, on the hardware base-2 logarithm, square root
+// and cosine (whose argument is in revolutions, so cos(2 pi u2) takes u2
+// itself).  log2 u1 keeps FP32's relative precision over the whole range:
+// up to 1/2 from u1 itself; above from w = 1 - u1 (an integer times 2^-53,
+// rounded once) as log2(1 - w) = log2(v) w / (1 - v) with v = 1 - w rounded
+// and 1 - v exact (Goldberg's form of log1p), or -w / ln 2 where v rounds
+// to 1.
+__device__ __forceinline__ float trunc_gauss_f32(uint64_t seed, uint64_t counter0, float mean, float sigma)
+{
+    for (int a = 0; a < 8; ++a) {
+        const uint64_t k1 = mix64(seed, counter0 + 2ull * a) >> 11;   // u1 = (k1 + 1) 2^-53
+        const uint64_t k2 = mix64(seed, counter0 + 2ull * a + 1ull) >> 11;   // u2 = k2 2^-53
+        const bool hi = k1 >= (1ull << 52);
+        const float f = (float)(hi ? (1ull << 53) - 1ull - k1 : k1 + 1ull) * 0x1.0p-53f;   // w or u1
+        const float v = hi ? 1.f - f : f;
+        float l2 = __builtin_amdgcn_logf(v);
+        if (hi) l2 = v == 1.f ? -f * 1.4426950408889634f : l2 * (f * __builtin_amdgcn_rcpf(1.f - v));
+        const float z = __builtin_amdgcn_sqrtf(-2.f * 0.6931471805599453f * l2) *
+                        __builtin_amdgcn_cosf((float)k2 * 0x1.0p-53f);
+        const float x = mean + sigma * z;
+        if (x >= 0.f && x <= 1.f) return x;
+    }
+    return mean;
+}
+
+// The interface draw in the precision of the run.
+template <typename T>
+__device__ __forceinline__ T interface_draw(uint64_t seed, uint64_t counter0, double mean, double sigma);
+template <>
+__device__ __forceinline__ double interface_draw<double>(uint64_t seed, uint64_t counter0, double mean, double sigma)
+{
+    return trunc_gauss(seed, counter0, mean, sigma);
+}
+template <>
+__device__ __forceinline__ float interface_draw<float>(uint64_t seed, uint64_t counter0, double mean, double sigma)
+{
+    return trunc_gauss_f32(seed, counter0, (float)mean, (float)sigma);
+}
+
 }  // namespace cell
 }  // namespace pfk

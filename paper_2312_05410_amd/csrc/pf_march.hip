@@ -183,7 +183,7 @@ __global__ __launch_bounds__(64) void march_kernel(StepArgs<T> a)
                    mp[t], east(mp[t]), west(mp[t]), mp[t + 1], mp[t - 1], nc, np, nr, cb0, pb0, rb0);
             if (NOISE && gj < ny && out_lane && np < T(0)) {
                 const uint64_t id = (uint64_t)a.step * plane + (uint64_t)gj * nx + ocol;
-                nc = (T)trunc_gauss(rl.nseed, id * 16ull, rl.c0, a.noise);
+                nc = interface_draw<T>(rl.nseed, id * 16ull, rl.c0, a.noise);
             }
             if (gj < ny) {
                 if (out_lane) {
@@ -340,8 +340,8 @@ __global__ __launch_bounds__(64) void march2_kernel(StepArgs<float> a)
                    mp[t].b, qE, mp[t].a, mp[t + 1].b, mp[t - 1].b, nc.b, np.b, nr.b, cb0.b, pb0.b, rb0.b);
             if (NOISE && gj < ny && out_lane) {
                 const uint64_t id = (uint64_t)a.step * plane + (uint64_t)gj * nx + ocol;
-                if (np.a < T(0)) nc.a = (T)trunc_gauss(rl.nseed, id * 16ull, rl.c0, a.noise);
-                if (np.b < T(0)) nc.b = (T)trunc_gauss(rl.nseed, (id + 1ull) * 16ull, rl.c0, a.noise);
+                if (np.a < T(0)) nc.a = interface_draw<T>(rl.nseed, id * 16ull, rl.c0, a.noise);
+                if (np.b < T(0)) nc.b = interface_draw<T>(rl.nseed, (id + 1ull) * 16ull, rl.c0, a.noise);
             }
             if (gj < ny) {
                 if (out_lane) {

@@ -14,7 +14,9 @@
 //    stepper kernel, so the states are bitwise identical to theirs.  A
 //    midpoint step is two such passes: the half step u + dt/2 R(u), whose
 //    rim is traded like a step's result while each cell keeps u in
-//    registers, then u + dt R(u_half);
+//    registers, then u + dt R(u_half).  With interface draws on, the cells
+//    that end a step on the vapour side then take their draw (FP32, keyed
+//    by global step and cell as in every other stepper kernel);
 //  * exchange: every rim cell of the new state is stored as one 8-byte word,
 //    the FP32 value in the low half and a 32-bit generation tag in the high
 //    half, into one of two rim buffers (by step parity) with device-coherent
@@ -161,6 +163,8 @@ struct Resident {
     RhoCoef<float> rc;
     float nc[4], np[4], nr[4];   // the wave's 4 rows after the step (or half step)
     float ubc[4], ubp[4], ubr[4];   // midpoint: the state at the start of the step
+    uint64_t nseed;                 // interface draws: the realisation's stream,
+    float c0, sigma;                // mean and standard deviation
 
     __device__ __forceinline__ static int L(int r, int x) { return (r + R) * P + x + R; }
 
@@ -253,6 +257,17 @@ struct Resident {
         }
     }
 
+    // interface draws after global step `step`: the wave's cells that end
+    // the step on the vapour side take a fresh composition
+    __device__ __forceinline__ void draw(long long step)
+    {
+        const int xt = otid(), xlane = xt & 63, xrb = 4 * (xt >> 6);
+        const uint64_t id = (uint64_t)step * ((uint64_t)a.nx * a.ny) + (uint64_t)(y0 + xrb) * a.nx + x0 + xlane;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            if (np[i] < 0.f) nc[i] = trunc_gauss_f32(nseed, (id + (uint64_t)i * a.nx) * 16ull, c0, sigma);
+    }
+
     // the tile's cells of the final state and the inflow accumulators
     __device__ __forceinline__ void write_result()
     {
@@ -281,8 +296,9 @@ struct Resident {
 };
 
 // At most 128 VGPRs (four waves per SIMD), so that 1024^2 (512 tiles of
-// 64 x 32) stays resident at two workgroups per CU.
-template <int TH, bool MID>
+// 64 x 32) stays resident at two workgroups per CU.  MID: the midpoint
+// method; NZ: interface draws after every step.
+template <int TH, bool MID, bool NZ>
 __global__ __launch_bounds__(16 * TH) __attribute__((amdgpu_waves_per_eu(4)))
 void resident_kernel(ResArgs ra)
 {
@@ -337,7 +353,8 @@ void resident_kernel(ResArgs ra)
 
     const Real rl = a.real[b];
     St st{a, t, tid, lane, wv, 4 * wv, b, tx, ty, ra.nty, x0, y0, pvd, false, (float)rl.vx2h, (float)rl.vy2h, rin,
-          rl.qa, rl.qb, 0.0, rho_coef(a.k, (float)rl.vx2h, (float)rl.vy2h), {}, {}, {}, {}, {}, {}};
+          rl.qa, rl.qb, 0.0, rho_coef(a.k, (float)rl.vx2h, (float)rl.vy2h), {}, {}, {}, {}, {}, {},
+          rl.nseed, (float)rl.c0, (float)a.noise};
     // inflow through the top face: the last wave of a top tile holds row ny-1
     st.qrow = pvd && a.Qcol && ty == ra.nty - 1 && wv == G::NW - 1;
     if (st.qrow) st.qacc = a.Qcol[(size_t)b * nx + x0 + lane];
@@ -363,11 +380,13 @@ void resident_kernel(ResArgs ra)
                 st.stage1(a.k);
                 __syncthreads();
                 st.template stage2<2>(a.k);
+                if constexpr (NZ) st.draw(a.step + g / 2);
             }
         } else {
             st.stage1(a.k);
             __syncthreads();
             st.template stage2<0>(a.k);
+            if constexpr (NZ) st.draw(a.step + g);
         }
         ++g;
         if (g == last) {
@@ -479,13 +498,13 @@ __global__ void epoch_kernel(uint64_t* ctl, int n)
     if (threadIdx.x == 0) ctl[0] += (uint64_t)n;
 }
 
-template <int TH, bool MID>
+template <int TH, bool MID, bool NZ>
 hipError_t launch_th(const ResArgs& ra, hipStream_t s)
 {
     ResArgs x = ra;
     void* args[] = {&x};
     const int ntiles = ra.batch * ra.ntx * ra.nty;
-    hipError_t e = hipLaunchCooperativeKernel((const void*)resident_kernel<TH, MID>, dim3(ntiles),
+    hipError_t e = hipLaunchCooperativeKernel((const void*)resident_kernel<TH, MID, NZ>, dim3(ntiles),
                                               dim3(RGeo<TH>::NT), args, 0, s);
     if (e != hipSuccess) return e;
     // the launch used generations e0 + 1 .. e0 + n (e0 + 2n: two per midpoint step)
@@ -493,18 +512,35 @@ hipError_t launch_th(const ResArgs& ra, hipStream_t s)
     return hipGetLastError();
 }
 
+template <int TH, bool MID, bool NZ>
+int blocks_per_cu()
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, resident_kernel<TH, MID, NZ>, RGeo<TH>::NT, 0) != hipSuccess)
+        return 0;
+    return nb;
+}
+
+// co-resident tiles of every instantiation at this height
 template <int TH>
 int capacity_th()
 {
-    int dev = 0, coop = 0, cus = 0, nb = 0, nb2 = 0;
+    int dev = 0, coop = 0, cus = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, resident_kernel<TH, false>, RGeo<TH>::NT, 0) != hipSuccess)
-        return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb2, resident_kernel<TH, true>, RGeo<TH>::NT, 0) != hipSuccess)
-        return 0;
-    return (nb < nb2 ? nb : nb2) * cus;
+    int nb = blocks_per_cu<TH, false, false>();
+    for (int v : {blocks_per_cu<TH, true, false>(), blocks_per_cu<TH, false, true>(), blocks_per_cu<TH, true, true>()})
+        nb = v < nb ? v : nb;
+    return nb * cus;
+}
+
+template <int TH>
+hipError_t launch_h(const ResArgs& ra, hipStream_t s)
+{
+    const bool nz = ra.s.noise > 0;
+    if (ra.mid) return nz ? launch_th<TH, true, true>(ra, s) : launch_th<TH, true, false>(ra, s);
+    return nz ? launch_th<TH, false, true>(ra, s) : launch_th<TH, false, false>(ra, s);
 }
 
 }  // namespace
@@ -529,13 +565,10 @@ hipError_t launch_resident(const ResArgs& ra, int th, hipStream_t s)
     if (ra.n < 2 || ra.s.nx % kTW || ra.ntx * kTW != ra.s.nx || ra.nty * th != ra.s.ny || ra.s.ny < th ||
         (ra.mid ? 2 : 1) * (long)ra.n >= (1L << 31))
         return hipErrorInvalidValue;
-    switch (th * 2 + (ra.mid ? 1 : 0)) {
-    case 16: return launch_th<8, false>(ra, s);
-    case 17: return launch_th<8, true>(ra, s);
-    case 32: return launch_th<16, false>(ra, s);
-    case 33: return launch_th<16, true>(ra, s);
-    case 64: return launch_th<32, false>(ra, s);
-    case 65: return launch_th<32, true>(ra, s);
+    switch (th) {
+    case 8: return launch_h<8>(ra, s);
+    case 16: return launch_h<16>(ra, s);
+    case 32: return launch_h<32>(ra, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -93,7 +93,9 @@ def test_resident_stepper_shapes_and_workspace():
     assert _ws(big) - _ws(big, temporal_block=2) == 2 * 128 * 3 * (256 + 4 * 32) * 8 + 256
     assert _ws(big, tile_rows=8) == _ws(big, temporal_block=2)   # a chunk height asked for: no resident
     assert _ws(base.replace(integrator="midpoint"), fused_kernel=3) == _ws(base, fused_kernel=3)
-    for bad in (dict(nx=100), dict(precision="f64"), dict(interface_noise=0.1), dict(ny=60),
+    assert _ws(base.replace(interface_noise=0.1), fused_kernel=3) == _ws(base, fused_kernel=3)
+    assert _ws(big.replace(interface_noise=0.1)) == _ws(big)          # draws in the resident stepper too
+    for bad in (dict(nx=100), dict(precision="f64"), dict(ny=60),
                 dict(nx=2048, ny=2048)):
         assert _ws(base.replace(**bad), fused_kernel=3) == 0, bad
     assert _ws(base, fused_kernel=3, temporal_block=2) == 0

@@ -411,6 +411,54 @@ def test_resident_midpoint_is_bitwise(bc, shape, th, batch):
     sim.close()
 
 
+@pytest.mark.parametrize("integrator,bc,shape,th,batch", [
+    ("euler", "pvd", (128, 96), 8, 1), ("euler", "pvd", (192, 64), 16, 2), ("euler", "periodic", (128, 64), 32, 1),
+    ("midpoint", "pvd", (128, 64), 32, 2), ("midpoint", "pvd", (256, 96), 16, 1)])
+def test_resident_interface_draws_are_bitwise(integrator, bc, shape, th, batch):
+    """With interface draws on, the resident stepper draws the same FP32
+    compositions on the same cells as single-step launches (keyed by the
+    global step across calls of 2, 3, 37, 1 and 141 steps): states and
+    inflow equal bit for bit, for both integrators."""
+    nx, ny = shape
+    announce(f"resident draws {integrator} {bc} {batch}x{nx}x{ny} th={th}")
+    p = PFParams(nx=nx, ny=ny, batch=batch, precision="f32", bc_mode=bc, theta_deg=61.0, v0=0.85,
+                 integrator=integrator, interface_noise=0.1, seed=17)
+    state = random_state(33, batch, ny, nx)
+    ref = Sim(p, state=state, temporal_block=1)
+    sim = Sim(p, state=state, fused_kernel=3, tile_rows=th)
+    assert sim.fused_kernel == 3 and ref.fused_kernel == 0
+    vapour = 0
+    for n in (2, 3, 37, 1, 141):
+        ref.step(n)
+        sim.step(n)
+        for u, v in zip(sim.state(), ref.state()):
+            assert np.array_equal(u, v), f"after a call of {n} steps"
+        assert np.array_equal(sim.inflow(), ref.inflow()), f"after a call of {n} steps"
+        vapour += int((sim.state()[1] < 0).sum())
+    assert vapour > 0   # the draws were exercised
+    ref.close()
+    sim.close()
+
+
+def test_resident_interface_draws_default_shape():
+    """512^2 production initial condition with draws: the library picks the
+    resident stepper and its states equal single-step launches bit for bit."""
+    announce("resident draws default 512x512")
+    p = workloads.dns_production(0, n=512).replace(interface_noise=0.1)
+    state = initial_state(p)
+    sim = Sim(p, state=state)
+    ref = Sim(p, state=state, temporal_block=1)
+    assert sim.fused_kernel == 3 and ref.fused_kernel == 0
+    for n in (64, 201):
+        sim.step(n)
+        ref.step(n)
+    for u, v in zip(sim.state(), ref.state()):
+        assert np.array_equal(u, v)
+    assert np.array_equal(sim.inflow(), ref.inflow())
+    sim.close()
+    ref.close()
+
+
 def test_resident_call_replays_as_graph():
     """A captured resident call (cooperative launch + epoch advance) replays
     correctly: the generation tags of every replay are fresh. Three replays,

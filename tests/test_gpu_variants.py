@@ -111,6 +111,34 @@ def test_interface_draws_f32():
     assert bad.mean() < 1e-3
 
 
+@pytest.mark.parametrize("fused", [0, 3])
+def test_interface_draws_f32_values(fused):
+    """FP32 draws (single-step launches and the resident stepper) against the
+    oracle's FP64 draws, two steps: on cells that both sides leave on the
+    vapour side, c is the second step's draw and differs from the FP64 one by
+    the FP32 evaluation only.  Bound: u1 rounded once, the hardware log2 and
+    square root to 1 ulp, its cosine of revolutions to 1.3e-7 absolute (each
+    measured over 2^22 arguments on gfx950), then mean + sigma z rounded
+    twice: |dc| <= sigma (3e-7 |z| + 1.3e-7 sqrt(-2 ln u1)) + 2e-7 < 1e-6 for
+    |z| < 6 (measured over 2^22 draws: 1.1e-7 at sigma 0.1)."""
+    from paper_2312_05410_amd._lib import Simulator
+
+    announce(f"interface draws f32 values fused={fused} 128x64")
+    p = PFParams(nx=128, ny=64, precision="f32", interface_noise=0.1, seed=21, theta_deg=70.0)
+    u = initial_state(p)
+    sim = Simulator(p, state=u, fused_kernel=fused, temporal_block=1 if fused == 0 else 0)
+    assert sim.fused_kernel == fused
+    sim.step(2)
+    g = sim.state()
+    sim.close()
+    s = oracle.State(p, *u).step(2)
+    vap = (s.phi < -1e-3) & (g[1] < -1e-3)
+    assert vap.sum() > 1000
+    d = np.abs(g[0][vap].astype(np.float64) - s.c[vap])
+    assert d.max() < 1e-6, f"max |dc| {d.max():.2e}"
+    assert np.std(g[0][vap]) > 0.05
+
+
 @pytest.mark.parametrize("theta", [50.0, 60.0, 70.0, 80.0, 90.0])
 def test_angled_deposition_f64(theta):
     announce(f"angled deposition f64 theta={theta}")
