@@ -167,9 +167,14 @@ int pf_dt_limit(const pf_params* p, double* dt_lim);
 int pf_init(pf_handle** out, const pf_params* p, void* c, void* phi, void* rho,
             void* workspace, size_t workspace_bytes, void* stream);
 
-/* Enqueue n >= 0 explicit Euler steps of every realisation.  When the
- * stream reaches the end of this work, the new state is in the caller's
- * buffers.  Returns without waiting. */
+/* Enqueue n >= 0 steps (the handle's integrator) of every realisation.
+ * When the stream reaches the end of this work, the new state is in the
+ * caller's buffers.  Returns without waiting.  A call may be captured into
+ * a HIP graph: each replay advances the state it finds by n steps (the
+ * step counter of pf_get_step counts enqueued calls only).  With
+ * interface_noise > 0 the draws are keyed by the global step at which the
+ * call starts, which a replay would repeat, so a call on a capturing
+ * stream returns PF_EINVAL and enqueues nothing. */
 int pf_step_n(pf_handle* h, int64_t n);
 
 /* Wait for the stream, then write out[4*b + k] for each realisation b:

@@ -653,6 +653,13 @@ int pf_step_n(pf_handle* h, int64_t n)
 {
     if (!h || n < 0) return PF_EINVAL;
     if (n == 0) return PF_OK;
+    if (h->p.interface_noise > 0) {
+        // the draws are keyed by the global step the call starts at, passed
+        // by value: a captured call would replay the same draws
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(h->stream, &cs) != hipSuccess) (void)hipGetLastError();
+        if (cs != hipStreamCaptureStatusNone) return PF_EINVAL;
+    }
     const int rc = h->p.precision == PF_F64 ? enqueue_steps<double>(h, n) : enqueue_steps<float>(h, n);
     if (rc == PF_OK) h->step += n;
     return rc;

@@ -492,6 +492,33 @@ def test_resident_call_replays_as_graph():
     ref.close()
 
 
+@pytest.mark.filterwarnings("ignore:The CUDA Graph is empty")
+def test_capture_with_interface_draws_is_refused():
+    """Draws are keyed by the step a call starts at: a call with draws on a
+    capturing stream is refused before anything is enqueued (the capture
+    ends cleanly and holds no work), while the same call outside capture
+    runs."""
+    import torch
+
+    from paper_2312_05410_amd._lib import PFError
+
+    announce("capture with interface draws refused")
+    p = workloads.dns_production(0, n=512).replace(interface_noise=0.1)
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        sim = Sim(p)
+    assert sim.fused_kernel == 3
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with pytest.raises(PFError):
+        with torch.cuda.graph(g, stream=sim.stream):
+            sim.step(4)
+    torch.cuda.synchronize()
+    sim.step(4)
+    assert np.isfinite(sim.mass()).all()
+    sim.close()
+
+
 def test_resident_stepper_matches_oracle():
     """FP32 resident stepper against the FP64 oracle: 128^2, 1000 steps, the
     library's tile height."""
