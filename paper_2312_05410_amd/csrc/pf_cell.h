@@ -173,22 +173,37 @@ __device__ __noinline__ double trunc_gauss(uint64_t seed, uint64_t counter0, dou
 // rounded once) as log2(1 - w) = log2(v) w / (1 - v) with v = 1 - w rounded
 // and 1 - v exact (Goldberg's form of log1p), or -w / ln 2 where v rounds
 // to 1.
-__device__ __forceinline__ float trunc_gauss_f32(uint64_t seed, uint64_t counter0, float mean, float sigma)
+// attempt a of the FP32 draw: true with the value in *x when it lies in [0, 1]
+__device__ __forceinline__ bool gauss_attempt_f32(uint64_t seed, uint64_t counter0, int a, float mean, float sigma,
+                                                  float* x)
 {
-    for (int a = 0; a < 8; ++a) {
-        const uint64_t k1 = mix64(seed, counter0 + 2ull * a) >> 11;   // u1 = (k1 + 1) 2^-53
-        const uint64_t k2 = mix64(seed, counter0 + 2ull * a + 1ull) >> 11;   // u2 = k2 2^-53
-        const bool hi = k1 >= (1ull << 52);
-        const float f = (float)(hi ? (1ull << 53) - 1ull - k1 : k1 + 1ull) * 0x1.0p-53f;   // w or u1
-        const float v = hi ? 1.f - f : f;
-        float l2 = __builtin_amdgcn_logf(v);
-        if (hi) l2 = v == 1.f ? -f * 1.4426950408889634f : l2 * (f * __builtin_amdgcn_rcpf(1.f - v));
-        const float z = __builtin_amdgcn_sqrtf(-2.f * 0.6931471805599453f * l2) *
-                        __builtin_amdgcn_cosf((float)k2 * 0x1.0p-53f);
-        const float x = mean + sigma * z;
-        if (x >= 0.f && x <= 1.f) return x;
+    const uint64_t k1 = mix64(seed, counter0 + 2ull * a) >> 11;   // u1 = (k1 + 1) 2^-53
+    const uint64_t k2 = mix64(seed, counter0 + 2ull * a + 1ull) >> 11;   // u2 = k2 2^-53
+    const bool hi = k1 >= (1ull << 52);
+    const float f = (float)(hi ? (1ull << 53) - 1ull - k1 : k1 + 1ull) * 0x1.0p-53f;   // w or u1
+    const float v = hi ? 1.f - f : f;
+    float l2 = __builtin_amdgcn_logf(v);
+    if (hi) l2 = v == 1.f ? -f * 1.4426950408889634f : l2 * (f * __builtin_amdgcn_rcpf(1.f - v));
+    const float z = __builtin_amdgcn_sqrtf(-2.f * 0.6931471805599453f * l2) *
+                    __builtin_amdgcn_cosf((float)k2 * 0x1.0p-53f);
+    *x = mean + sigma * z;
+    return *x >= 0.f && *x <= 1.f;
+}
+
+// attempts a0 .. 7, then the mean
+__device__ __forceinline__ float trunc_gauss_f32_from(uint64_t seed, uint64_t counter0, int a0, float mean,
+                                                      float sigma)
+{
+    for (int a = a0; a < 8; ++a) {
+        float x;
+        if (gauss_attempt_f32(seed, counter0, a, mean, sigma, &x)) return x;
     }
     return mean;
+}
+
+__device__ __forceinline__ float trunc_gauss_f32(uint64_t seed, uint64_t counter0, float mean, float sigma)
+{
+    return trunc_gauss_f32_from(seed, counter0, 0, mean, sigma);
 }
 
 // The interface draw in the precision of the run.

@@ -258,14 +258,22 @@ struct Resident {
     }
 
     // interface draws after global step `step`: the wave's cells that end
-    // the step on the vapour side take a fresh composition
+    // the step on the vapour side take a fresh composition.  The first
+    // attempts of two cells at a time are straight-line code (independent
+    // work to interleave); the rare rejected ones continue from attempt 1.
     __device__ __forceinline__ void draw(long long step)
     {
         const int xt = otid(), xlane = xt & 63, xrb = 4 * (xt >> 6);
         const uint64_t id = (uint64_t)step * ((uint64_t)a.nx * a.ny) + (uint64_t)(y0 + xrb) * a.nx + x0 + xlane;
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-            if (np[i] < 0.f) nc[i] = trunc_gauss_f32(nseed, (id + (uint64_t)i * a.nx) * 16ull, c0, sigma);
+        for (int i = 0; i < 4; i += 2) {
+            const uint64_t k0 = (id + (uint64_t)i * a.nx) * 16ull, k1 = k0 + 16ull * a.nx;
+            float x0v, x1v;
+            const bool ok0 = gauss_attempt_f32(nseed, k0, 0, c0, sigma, &x0v);
+            const bool ok1 = gauss_attempt_f32(nseed, k1, 0, c0, sigma, &x1v);
+            if (np[i] < 0.f) nc[i] = ok0 ? x0v : trunc_gauss_f32_from(nseed, k0, 1, c0, sigma);
+            if (np[i + 1] < 0.f) nc[i + 1] = ok1 ? x1v : trunc_gauss_f32_from(nseed, k1, 1, c0, sigma);
+        }
     }
 
     // the tile's cells of the final state and the inflow accumulators
