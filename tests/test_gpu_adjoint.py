@@ -86,7 +86,7 @@ def test_loss_gradient_f64_matches_oracle():
     v0 = torch.tensor(p.v0, dtype=torch.float64, requires_grad=True)
     L = l2_mismatch(final_state(Ms, v0, p, u0, n, every), target, p.h)
     L.backward()
-    assert float(L) == pytest.approx(L_ref, rel=1e-11)
+    assert float(L.detach()) == pytest.approx(L_ref, rel=1e-11)
     assert float(Ms.grad) == pytest.approx(gM_ref, rel=1e-9)
     assert float(v0.grad) == pytest.approx(gv_ref, rel=1e-9)
 
@@ -118,8 +118,8 @@ def test_adjoint_workload_256(prec):
     L = l2_mismatch(final_state(Ms, v0, p, u0, n, every), target, p.h)
     L.backward()
     rtol = 1e-9 if prec == "f64" else 1e-3
-    print(f"L {float(L):.10e} ref {L_ref:.10e}; dMs {float(Ms.grad):.10e} ref {gM_ref:.10e}; "
+    print(f"L {float(L.detach()):.10e} ref {L_ref:.10e}; dMs {float(Ms.grad):.10e} ref {gM_ref:.10e}; "
           f"dv0 {float(v0.grad):.10e} ref {gv_ref:.10e}", flush=True)
-    assert float(L) == pytest.approx(L_ref, rel=rtol)
+    assert float(L.detach()) == pytest.approx(L_ref, rel=rtol)
     assert float(Ms.grad) == pytest.approx(gM_ref, rel=rtol)
     assert float(v0.grad) == pytest.approx(gv_ref, rel=rtol)
