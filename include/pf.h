@@ -48,7 +48,11 @@ enum pf_status {
     PF_EINVAL = -1,      /* null/misaligned pointer, bad shape, bad enum, bad n */
     PF_EUNSTABLE = -2,   /* dt above the stability limit and allow_unstable == 0 */
     PF_ENONFINITE = -3,  /* a diagnostic came out NaN or infinite */
-    PF_EDEVICE = -4      /* a HIP call failed; see pf_last_hip_error */
+    PF_EDEVICE = -4,     /* a HIP call failed; see pf_last_hip_error */
+    PF_EABORTED = -5     /* the resident stepper gave up a wait for its neighbours (its tiles were
+                            not all resident at once, e.g. another kernel held part of the device):
+                            the state is NaN and the handle stays aborted until pf_init is called
+                            again; reported by the next pf_mass, pf_energy or pf_get_inflow */
 };
 
 enum pf_precision { PF_F32 = 0, PF_F64 = 1 };
@@ -95,7 +99,7 @@ enum pf_integrator { PF_EULER = 0, PF_MIDPOINT = 1 };
 /* Kernel of the launches that fuse several steps: a 64 x TY tile staged in
  * LDS (any K), the register strip march (K = 2: one wave per 64-column
  * strip, radius-4 halo, the intermediate state kept in registers), or the
- * resident stepper: one cooperative launch per pf_step_n call (of at least
+ * resident stepper: one launch per pf_step_n call (of at least
  * 2 steps; a single step runs the single-step kernel) in which every
  * workgroup keeps a 64 x TY tile of the state in LDS for all the steps and
  * trades its 2-cell rim with its neighbours after each step (and each
@@ -107,7 +111,9 @@ enum pf_integrator { PF_EULER = 0, PF_MIDPOINT = 1 };
  * once (about 1M cells on MI355X); else pf_init returns PF_EINVAL.  Its
  * results are bitwise equal to the other kernels'.  A resident launch takes
  * every workgroup slot of the device for its duration: calls of several
- * handles on one device must not run concurrently on different streams. */
+ * handles on one device must not run concurrently on different streams
+ * (a launch whose tiles cannot all be resident gives up after a bounded
+ * wait and reports PF_EABORTED). */
 enum pf_fused { PF_FUSED_AUTO = 0, PF_FUSED_TILE = 1, PF_FUSED_MARCH = 2, PF_FUSED_RESIDENT = 3 };
 
 typedef struct pf_params {
@@ -231,7 +237,10 @@ int pf_get_fused_kernel(const pf_handle* h, int32_t* kind);
  * the state's layout and precision; out_* must not alias lam_*.  The handle
  * supplies the model, dt and the stream (enqueued, returns at once).
  * M_scale must be positive.  A checkpointed reverse sweep calls it once per
- * step, from the last step to the first, on recomputed states. */
+ * step, from the last step to the first, on recomputed states.  The adjoint
+ * exists for explicit Euler without interface draws only: for a handle with
+ * integrator PF_MIDPOINT or interface_noise > 0 the adjoint calls return
+ * PF_EINVAL and pf_adjoint_workspace_bytes returns 0. */
 size_t pf_adjoint_workspace_bytes(const pf_params* p);
 int pf_adjoint_step(pf_handle* h, const void* c, const void* phi, const void* rho,
                     const void* lam_c, const void* lam_phi, const void* lam_rho,

@@ -18,7 +18,7 @@ from .inputs import PFParams
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpf.so")
 
-PF_OK, PF_EINVAL, PF_EUNSTABLE, PF_ENONFINITE, PF_EDEVICE = 0, -1, -2, -3, -4
+PF_OK, PF_EINVAL, PF_EUNSTABLE, PF_ENONFINITE, PF_EDEVICE, PF_EABORTED = 0, -1, -2, -3, -4, -5
 PF_F32, PF_F64 = 0, 1
 PF_BC_PVD, PF_BC_PERIODIC = 0, 1
 PF_INIT_SEEDED, PF_INIT_KEEP = 0, 1

@@ -25,6 +25,9 @@ class _FinalState(torch.autograd.Function):
 
         if not (p.dt > 0):
             raise ValueError("final_state needs a fixed dt (p.dt > 0)")
+        if p.integrator != "euler" or p.interface_noise > 0:
+            raise ValueError("the adjoint is the transpose of the explicit Euler step without interface "
+                             "draws (integrator 'euler', interface_noise 0)")
         q = p.replace(M_scale=float(Ms), v0=float(v0), v0_per=None)
         u = [t.detach().clone().contiguous() for t in (c0, phi0, rho0)]
         sim = Simulator(q, tensors=u, temporal_block=temporal_block)

@@ -77,12 +77,13 @@ Layout layout(const pf_params* p)
     L.real = take(B * sizeof(pfk::Real));
     L.c0 = take(B * sizeof(double));
     L.qstage = take(B * sizeof(double));
-    L.partials = take(B * (size_t)pfk::kRedBlocks * 4 * sizeof(double));
+    L.partials = take(B * (size_t)pfk::reduce_geometry(p->nx, p->ny, p->batch, (int)esize(p)).parts() * 4 *
+                      sizeof(double));
     L.results = take(B * 5 * sizeof(double));
     const int th = resident_th(p);
     const size_t tiles = th ? B * (size_t)(p->nx / 64) * (size_t)(p->ny / th) : 0;
     L.rim = take(th ? 2 * tiles * 3 * pfk::resident_rim_words(th) * sizeof(uint64_t) : 0);
-    L.rctl = take(th ? 2 * sizeof(uint64_t) : 0);
+    L.rctl = take(th ? 3 * sizeof(uint64_t) : 0);   // epoch, abort, completion count
     L.total = off;
     return L;
 }
@@ -359,8 +360,8 @@ int enqueue_midpoint(pf_handle* h, int64_t n)
     return PF_OK;
 }
 
-// Resident stepper: all n >= 2 steps in one cooperative launch, in place on
-// the caller's buffers, in chunks of at most 2^29 steps.
+// Resident stepper: all n >= 2 steps in one launch, in place on the
+// caller's buffers, in chunks of at most 2^29 steps.
 int enqueue_resident(pf_handle* h, int64_t n)
 {
     pfk::ResArgs ra{};
@@ -451,22 +452,29 @@ int run_reduce(pf_handle* h)
     double* partials = (double*)(h->ws + h->L.partials);
     double* res = (double*)(h->ws + h->L.results);
     const double* Qcol = (const double*)(h->ws + h->L.qcol);
-    const int nblk = std::min(pfk::kRedBlocks, p->ny);
+    const pfk::RedGeo g = pfk::reduce_geometry(p->nx, p->ny, p->batch, (int)esize(p));
     hipError_t e;
     if (p->precision == PF_F64)
         e = pfk::launch_reduce<double>((const double*)h->f[0], (const double*)h->f[1], (const double*)h->f[2],
-                                       Qcol, partials, res, a, p->batch, nblk, h->stream);
+                                       Qcol, partials, res, a, g, p->batch, h->stream);
     else
         e = pfk::launch_reduce<float>((const float*)h->f[0], (const float*)h->f[1], (const float*)h->f[2],
-                                      Qcol, partials, res, a, p->batch, nblk, h->stream);
+                                      Qcol, partials, res, a, g, p->batch, h->stream);
     if (e != hipSuccess) return hip_fail(h, e);
     h->host_out.resize((size_t)p->batch * 5);
     e = hipMemcpyAsync(h->host_out.data(), res, h->host_out.size() * sizeof(double), hipMemcpyDeviceToHost,
                        h->stream);
     if (e != hipSuccess) return hip_fail(h, e);
+    // the resident stepper's sticky abort word (a wait it gave up)
+    uint64_t abort_word = 0;
+    if (h->res_th) {
+        e = hipMemcpyAsync(&abort_word, h->ws + h->L.rctl + sizeof(uint64_t), sizeof(uint64_t),
+                           hipMemcpyDeviceToHost, h->stream);
+        if (e != hipSuccess) return hip_fail(h, e);
+    }
     e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_fail(h, e);
-    return PF_OK;
+    return abort_word ? PF_EABORTED : PF_OK;
 }
 
 }  // namespace
@@ -754,6 +762,7 @@ const char* pf_strerror(int code)
     case PF_EUNSTABLE: return "time step above the explicit stability limit";
     case PF_ENONFINITE: return "non-finite diagnostic (state diverged or holds NaN/Inf)";
     case PF_EDEVICE: return "HIP device error";
+    case PF_EABORTED: return "resident stepper abandoned a wait (tiles not co-resident); state is NaN, re-initialise";
     default: return "unknown pf status";
     }
 }
@@ -809,9 +818,17 @@ int adjoint_step_t(pf_handle* h, const void* c, const void* phi, const void* rho
     return hip_fail(h, pfk::launch_adjoint<T>(io, st, p->M_scale, cx, sy, p->h, p->batch, h->stream));
 }
 
+// The adjoint is the transpose of one explicit Euler step without
+// interface draws; other integrators and the random interface composition
+// have no adjoint here.
+bool adj_model_ok(const pf_params* p)
+{
+    return p->integrator == PF_EULER && !(p->interface_noise > 0);
+}
+
 bool adj_ws_ok(const pf_handle* h, const void* ws, size_t bytes)
 {
-    return ws && aligned(ws, kAlign) && bytes >= adj_layout(&h->p).total;
+    return adj_model_ok(&h->p) && ws && aligned(ws, kAlign) && bytes >= adj_layout(&h->p).total;
 }
 
 }  // namespace
@@ -820,7 +837,7 @@ extern "C" {
 
 size_t pf_adjoint_workspace_bytes(const pf_params* p)
 {
-    if (validate(p) != PF_OK) return 0;
+    if (validate(p) != PF_OK || !adj_model_ok(p)) return 0;
     return adj_layout(p).total;
 }
 

@@ -89,12 +89,13 @@ template <typename T>
 hipError_t graph_add_march_k2(hipGraph_t g, hipGraphNode_t* node, hipGraphNode_t dep, const StepArgs<T>& a,
                               int ty, int cols, int batch);
 
-// Resident stepper: one cooperative launch advances FP32 grids by n >= 2
-// explicit Euler or midpoint steps with each 64 x th tile (th in {8, 16, 32}) held in LDS, trading 2-cell
-// rims after every step through rim[2][tiles][3][resident_rim_words(th)]
-// tagged words; ctl[0] is the generation-tag epoch (advanced by n after the
-// launch), ctl[1] the sticky abort word.  In place: s.c == s.c_out etc.
-// nx = 64 ntx, ny = th nty.
+// Resident stepper: one launch advances FP32 grids by n >= 2 explicit Euler
+// or midpoint steps with each 64 x th tile (th in {8, 16, 32}) held in LDS,
+// trading 2-cell rims after every step through
+// rim[2][tiles][3][resident_rim_words(th)] tagged words; ctl[0] is the
+// generation-tag epoch (advanced inside the launch by its last workgroup),
+// ctl[1] the sticky abort word, ctl[2] the launch's completion count (zero
+// between launches).  In place: s.c == s.c_out etc.  nx = 64 ntx, ny = th nty.
 struct ResArgs {
     StepArgs<float> s;
     Coef<float> kh;      // midpoint: the half step's constants (dt / 2)
@@ -105,8 +106,8 @@ struct ResArgs {
     int batch, ntx, nty;
 };
 size_t resident_rim_words(int th);
-// Tiles the device keeps co-resident for tile height th (0: no cooperative
-// launch).
+// Tiles the device keeps co-resident for tile height th (occupancy of every
+// instantiation times the compute units; 0 on a query error).
 int resident_capacity(int th);
 hipError_t launch_resident(const ResArgs& a, int th, hipStream_t s);
 
@@ -130,16 +131,25 @@ hipError_t launch_init(T* c, T* phi, T* rho, const InitArgs& a, int batch, hipSt
 hipError_t launch_set_inflow(double* Qcol, const double* q, int nx, int batch, hipStream_t s);
 
 // Diagnostics: out[b*5 + {0..4}] = h^2 sum c, h^2 sum phi, h^2 sum rho, Q, F_h.
+// One workgroup per band of rows x chunk of columns; the partition depends on
+// the grid's shape and precision only (not on the device), so the FP64 sums
+// are taken in one fixed order.
 struct RedArgs {
     int nx, ny, pvd;
     double h2, Wc, Wphi, half_kc, half_kp;
 };
+struct RedGeo {
+    int vec;       // elements per 16-byte load (4 FP32, 2 FP64), 1 when nx is not a multiple
+    int chunks;    // column chunks of 256 vec columns
+    int rows;      // rows per band
+    int bands;     // bands per realisation
+    int parts() const { return chunks * bands; }
+};
+RedGeo reduce_geometry(int nx, int ny, int batch, int elem_bytes);
 template <typename T>
 hipError_t launch_reduce(const T* c, const T* phi, const T* rho, const double* Qcol,
-                         double* partials, double* out, const RedArgs& a, int batch,
-                         int nblk, hipStream_t s);
-
-constexpr int kRedBlocks = 128;   // partial-sum blocks per realisation
+                         double* partials, double* out, const RedArgs& a, const RedGeo& g, int batch,
+                         hipStream_t s);
 
 // Discrete adjoint of one step: lambda_out = lambda_in + (dR/du)^T dt lambda_in
 // at the state (c, phi, rho); per-cell FP64 parameter gradients accumulate in

@@ -53,43 +53,90 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Per-block FP64 partial sums (c, phi, rho, energy) over rows j = blockIdx.x,
-// blockIdx.x + gridDim.x, ...; fixed assignment and tree, so deterministic.
-template <typename T>
-__global__ __launch_bounds__(256) void reduce_kernel(const T* c, const T* phi, const T* rho,
-                                                     double* partials, RedArgs a)
+// Loads of V consecutive elements (one 16-byte load when V > 1).
+template <typename T, int V>
+struct Vec {
+    T v[V];
+};
+template <typename T, int V>
+__device__ __forceinline__ Vec<T, V> load_vec(const T* p)
 {
-    const int b = blockIdx.y;
+    Vec<T, V> r;
+    if constexpr (V == 4) {
+        const float4 q = *reinterpret_cast<const float4*>(p);
+        r.v[0] = q.x;
+        r.v[1] = q.y;
+        r.v[2] = q.z;
+        r.v[3] = q.w;
+    } else if constexpr (V == 2) {
+        const double2 q = *reinterpret_cast<const double2*>(p);
+        r.v[0] = q.x;
+        r.v[1] = q.y;
+    } else {
+        r.v[0] = p[0];
+    }
+    return r;
+}
+
+// Per-workgroup FP64 partial sums (c, phi, rho, energy) of one band of rows
+// [j0, j0 + rows) and one chunk of 256 V columns of realisation blockIdx.z.
+// Each thread owns V consecutive columns and walks down its band keeping the
+// current row of c and phi in registers: the next row is loaded once, as the
+// north neighbour, and becomes the current row (each row is read once per
+// band); the east neighbour of the last column is the next thread's first,
+// a cache hit.  Energy terms: the double well at every cell, the gradient
+// energy of every x face (periodic wrap included) and of the y faces to
+// the row above (interior faces only for the PVD boundaries; the wrap face
+// too when y is periodic).  Fixed assignment and tree: deterministic.
+template <typename T, int V>
+__global__ __launch_bounds__(256) void reduce_kernel(const T* c, const T* phi, const T* rho,
+                                                     double* partials, RedArgs a, int rows)
+{
+    const int b = blockIdx.z;
     const int nx = a.nx, ny = a.ny;
     const size_t plane = (size_t)nx * ny;
     c += b * plane;
     phi += b * plane;
     rho += b * plane;
+    const int i0 = (blockIdx.x * 256 + threadIdx.x) * V;
+    const int j0 = blockIdx.y * rows;
+    const int j1 = j0 + rows < ny ? j0 + rows : ny;
     double sc = 0, sp = 0, sr = 0, se = 0;
-    for (int j = blockIdx.x; j < ny; j += gridDim.x) {
-        const bool has_n = a.pvd ? (j + 1 < ny) : true;
-        const int jn = j + 1 < ny ? j + 1 : 0;
-        for (int i = threadIdx.x; i < nx; i += 256) {
-            const size_t k = (size_t)j * nx + i;
-            const int ie = i + 1 < nx ? i + 1 : 0;
-            const double cv = (double)c[k], pv = (double)phi[k], rv = (double)rho[k];
-            sc += cv;
-            sp += pv;
-            sr += rv;
-            const double q1 = 1.0 + pv, w = 1.0 - pv * pv;
-            const double pf = 0.25 * (2.0 - pv) * q1 * q1;
-            const double cg = cv * (1.0 - cv);
-            const double f = a.Wc * pf * (cg * cg) + 0.25 * a.Wphi * w * w;
-            const double dcE = (double)c[(size_t)j * nx + ie] - cv;
-            const double dpE = (double)phi[(size_t)j * nx + ie] - pv;
-            double gc = dcE * dcE, gp = dpE * dpE;
-            if (has_n) {
-                const double dcN = (double)c[(size_t)jn * nx + i] - cv;
-                const double dpN = (double)phi[(size_t)jn * nx + i] - pv;
-                gc += dcN * dcN;
-                gp += dpN * dpN;
+    if (i0 < nx) {
+        const int ie = i0 + V < nx ? i0 + V : 0;
+        Vec<T, V> cc = load_vec<T, V>(c + (size_t)j0 * nx + i0);
+        Vec<T, V> pc = load_vec<T, V>(phi + (size_t)j0 * nx + i0);
+        for (int j = j0; j < j1; ++j) {
+            const bool has_n = a.pvd ? (j + 1 < ny) : true;
+            const int jn = j + 1 < ny ? j + 1 : 0;
+            const size_t row = (size_t)j * nx, rown = (size_t)jn * nx;
+            const Vec<T, V> rr = load_vec<T, V>(rho + row + i0);
+            const Vec<T, V> cn = load_vec<T, V>(c + rown + i0);
+            const Vec<T, V> pn = load_vec<T, V>(phi + rown + i0);
+            const double ceE = (double)c[row + ie], peE = (double)phi[row + ie];
+#pragma unroll
+            for (int v = 0; v < V; ++v) {
+                const double cv = (double)cc.v[v], pv = (double)pc.v[v], rv = (double)rr.v[v];
+                sc += cv;
+                sp += pv;
+                sr += rv;
+                const double q1 = 1.0 + pv, w = 1.0 - pv * pv;
+                const double pf = 0.25 * (2.0 - pv) * q1 * q1;
+                const double cg = cv * (1.0 - cv);
+                const double f = a.Wc * pf * (cg * cg) + 0.25 * a.Wphi * w * w;
+                const double dcE = (v + 1 < V ? (double)cc.v[v + 1 < V ? v + 1 : 0] : ceE) - cv;
+                const double dpE = (v + 1 < V ? (double)pc.v[v + 1 < V ? v + 1 : 0] : peE) - pv;
+                double gc = dcE * dcE, gp = dpE * dpE;
+                if (has_n) {
+                    const double dcN = (double)cn.v[v] - cv;
+                    const double dpN = (double)pn.v[v] - pv;
+                    gc += dcN * dcN;
+                    gp += dpN * dpN;
+                }
+                se += a.h2 * f + a.half_kc * gc + a.half_kp * gp;
             }
-            se += a.h2 * f + a.half_kc * gc + a.half_kp * gp;
+            cc = cn;
+            pc = pn;
         }
     }
     __shared__ double red[4][4];
@@ -108,19 +155,31 @@ __global__ __launch_bounds__(256) void reduce_kernel(const T* c, const T* phi, c
     if (threadIdx.x < 4) {
         const int m = threadIdx.x;
         const double v = (red[0][m] + red[1][m]) + (red[2][m] + red[3][m]);
-        partials[((size_t)b * gridDim.x + blockIdx.x) * 4 + m] = v;
+        const size_t part = ((size_t)b * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+        partials[part * 4 + m] = v;
     }
 }
 
-// One block per realisation: sum the partials and the inflow columns.
+// One block per realisation: sum the partials and the inflow columns (each
+// thread in a fixed order; the loops are unrolled so that a thread's loads
+// are in flight together rather than one latency per element).
 __global__ __launch_bounds__(256) void finish_kernel(const double* partials, const double* Qcol,
                                                      double* out, int nblk, int nx, double h2)
 {
     const int b = blockIdx.x;
     double s[5] = {0, 0, 0, 0, 0};
-    for (int i = threadIdx.x; i < nblk; i += 256)
-        for (int m = 0; m < 4; ++m) s[m] += partials[((size_t)b * nblk + i) * 4 + m];
-    for (int i = threadIdx.x; i < nx; i += 256) s[4] += Qcol[(size_t)b * nx + i];
+    const double4* pp = reinterpret_cast<const double4*>(partials) + (size_t)b * nblk;
+#pragma unroll 8
+    for (int i = threadIdx.x; i < nblk; i += 256) {
+        const double4 q = pp[i];
+        s[0] += q.x;
+        s[1] += q.y;
+        s[2] += q.z;
+        s[3] += q.w;
+    }
+    const double* qc = Qcol + (size_t)b * nx;
+#pragma unroll 8
+    for (int i = threadIdx.x; i < nx; i += 256) s[4] += qc[i];
     __shared__ double red[4][5];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int m = 0; m < 5; ++m) {
@@ -159,20 +218,42 @@ hipError_t launch_set_inflow(double* Qcol, const double* q, int nx, int batch, h
     return hipGetLastError();
 }
 
+RedGeo reduce_geometry(int nx, int ny, int batch, int elem_bytes)
+{
+    // about 2048 workgroups per launch (8 per compute unit on MI355X; the
+    // count is a fixed function of the shape so that sums keep one order)
+    RedGeo g{};
+    const int v16 = 16 / elem_bytes;
+    g.vec = nx % v16 == 0 ? v16 : 1;
+    const long cw = 256L * g.vec;
+    g.chunks = (int)((nx + cw - 1) / cw);
+    long want = 2048L / ((long)g.chunks * (batch > 0 ? batch : 1));
+    if (want < 1) want = 1;
+    if (want > ny) want = ny;
+    g.rows = (int)((ny + want - 1) / want);
+    g.bands = (ny + g.rows - 1) / g.rows;
+    return g;
+}
+
 template <typename T>
 hipError_t launch_reduce(const T* c, const T* phi, const T* rho, const double* Qcol,
-                         double* partials, double* out, const RedArgs& a, int batch,
-                         int nblk, hipStream_t s)
+                         double* partials, double* out, const RedArgs& a, const RedGeo& g, int batch,
+                         hipStream_t s)
 {
-    hipLaunchKernelGGL(reduce_kernel<T>, dim3(nblk, batch), dim3(256), 0, s, c, phi, rho, partials, a);
+    const dim3 grid((unsigned)g.chunks, (unsigned)g.bands, (unsigned)batch);
+    constexpr int V16 = 16 / (int)sizeof(T);
+    if (g.vec == V16)
+        hipLaunchKernelGGL((reduce_kernel<T, V16>), grid, dim3(256), 0, s, c, phi, rho, partials, a, g.rows);
+    else
+        hipLaunchKernelGGL((reduce_kernel<T, 1>), grid, dim3(256), 0, s, c, phi, rho, partials, a, g.rows);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(finish_kernel, dim3(batch), dim3(256), 0, s, partials, Qcol, out, nblk, a.nx, a.h2);
+    hipLaunchKernelGGL(finish_kernel, dim3(batch), dim3(256), 0, s, partials, Qcol, out, g.parts(), a.nx, a.h2);
     return hipGetLastError();
 }
 template hipError_t launch_reduce<float>(const float*, const float*, const float*, const double*,
-                                         double*, double*, const RedArgs&, int, int, hipStream_t);
+                                         double*, double*, const RedArgs&, const RedGeo&, int, hipStream_t);
 template hipError_t launch_reduce<double>(const double*, const double*, const double*, const double*,
-                                          double*, double*, const RedArgs&, int, int, hipStream_t);
+                                          double*, double*, const RedArgs&, const RedGeo&, int, hipStream_t);
 
 }  // namespace pfk

@@ -46,7 +46,7 @@ def test_params_struct_layout():
 
 def test_strerror():
     L = _lib.load()
-    for code in (0, -1, -2, -3, -4, 7):
+    for code in (0, -1, -2, -3, -4, -5, 7):
         assert L.pf_strerror(code)
 
 
@@ -269,3 +269,23 @@ def test_variants_need_the_single_step_kernel():
     assert L.pf_workspace_bytes(ctypes.byref(s)) == 0
     s, keep = _lib.to_c(PFParams(nx=16, ny=16, integrator="midpoint", interface_noise=0.1), temporal_block=1)
     assert L.pf_workspace_bytes(ctypes.byref(s)) > 0
+
+
+def test_adjoint_refuses_midpoint_and_interface_draws():
+    """The adjoint is the transpose of the explicit Euler step without
+    interface draws: the workspace query refuses the other model variants
+    (0 bytes), and the autograd wrapper raises before running anything."""
+    L = _lib.load()
+    base = PFParams(nx=64, ny=32, precision="f32", dt=1e-4)
+    for p, ok in ((base, True), (base.replace(integrator="midpoint"), False),
+                  (base.replace(interface_noise=0.1), False)):
+        s, keep = _lib.to_c(p)
+        n = L.pf_adjoint_workspace_bytes(ctypes.byref(s))
+        assert (n > 0) == ok, (p.integrator, p.interface_noise)
+    from paper_2312_05410_amd import adjoint
+
+    torch = pytest.importorskip("torch")
+    u0 = [torch.zeros((1, 32, 64), dtype=torch.float32) for _ in range(3)]
+    for p in (base.replace(integrator="midpoint"), base.replace(interface_noise=0.1)):
+        with pytest.raises(ValueError):
+            adjoint.final_state(1.0, 0.5, p, u0, 4, every=2)

@@ -123,3 +123,28 @@ def test_adjoint_workload_256(prec):
     assert float(L.detach()) == pytest.approx(L_ref, rel=rtol)
     assert float(Ms.grad) == pytest.approx(gM_ref, rel=rtol)
     assert float(v0.grad) == pytest.approx(gv_ref, rel=rtol)
+
+
+def test_adjoint_step_refused_for_other_variants():
+    """A handle with the midpoint integrator or interface draws has no
+    adjoint: pf_adjoint_step, pf_adjoint_reset and pf_adjoint_grad return
+    PF_EINVAL before enqueueing anything."""
+    import torch
+
+    from paper_2312_05410_amd._lib import PF_EINVAL, PFError, Simulator
+
+    announce("adjoint refused for midpoint / interface draws")
+    base = PFParams(nx=64, ny=32, precision="f32")
+    good = Simulator(base)
+    ws = good.adjoint_workspace()
+    st = [t.clone() for t in (good.c, good.phi, good.rho)]
+    lam = [torch.zeros_like(t) for t in st]
+    out = [torch.empty_like(t) for t in st]
+    for q in (base.replace(integrator="midpoint"), base.replace(interface_noise=0.1)):
+        sim = Simulator(q, temporal_block=1)
+        for call in (lambda: sim.adjoint_step(st, lam, out, ws), lambda: sim.adjoint_grad(ws)):
+            with pytest.raises(PFError) as ei:
+                call()
+            assert ei.value.code == PF_EINVAL
+        sim.close()
+    good.close()

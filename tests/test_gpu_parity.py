@@ -51,6 +51,34 @@ def compare(sim_state, ref: oracle.State, tol, label=""):
         assert e <= tol, f"{label} {name}: rel L2 {e:.3e} > {tol:.1e}"
 
 
+def check_increments(got, want, start, steps, prec, label="", rel=None):
+    """Cell by cell: the GPU's increment over the run (got - start) against
+    the oracle's (want - start).  Bound per cell: rel |oracle increment| +
+    2 steps ulp(u) (each step rounds the stored state once; errors carried
+    in from neighbours are of the same order), in the run's precision.  A
+    wrong seam, rim, boundary row or ghost changes that cell's increment by
+    a large fraction of itself, far above this bound, however small the
+    cell's share of the whole-field norm."""
+    if rel is None:
+        rel = 1e-4 if prec == "f32" else 1e-9
+    ftype = np.float32 if prec == "f32" else np.float64
+    for name, g, w, a in zip(("c", "phi", "rho"), got, want, start):
+        g, w, a = (np.asarray(x, dtype=np.float64).reshape(np.shape(w)) for x in (g, w, a))
+        inc = w - a
+        ulp = np.spacing(np.maximum(np.abs(w), np.abs(a)).astype(ftype)).astype(np.float64)
+        bound = rel * np.abs(inc) + 2.0 * steps * ulp
+        err = np.abs(g - w)
+        bad = err > bound
+        if bad.any():
+            k = np.unravel_index(np.argmax(err - bound), err.shape)
+            raise AssertionError(f"{label} {name}: {int(bad.sum())} cells outside the increment bound; worst at "
+                                 f"{tuple(int(i) for i in k)}: |err| {err[k]:.3e}, bound {bound[k]:.3e}, "
+                                 f"increment {inc[k]:.3e}")
+        e = np.linalg.norm(g - w) / max(np.linalg.norm(inc), 1e-300)
+        print(f"{label} {name}: increment rel L2 {e:.2e}, max err/bound {float((err / bound).max()):.2f}",
+              flush=True)
+
+
 def run_pair(p: PFParams, state, n, tol, temporal_block=0, dt=None):
     dt = oracle.resolve_dt(p) if dt is None else dt
     p = p.replace(dt=dt)
@@ -342,7 +370,7 @@ def test_two_step_march_f64_matches_oracle():
     ("pvd", (256, 128), 32, 1), ("pvd", (64, 32), 32, 1), ("periodic", (64, 16), 8, 3),
     ("pvd", (320, 48), 16, 1)])
 def test_resident_stepper_is_bitwise(bc, shape, th, batch):
-    """The resident stepper (one cooperative launch per call, tiles held in
+    """The resident stepper (one launch per call, tiles held in
     LDS, inner cells computed while the rims are traded through tagged
     words) equals single-step launches bit for bit, state and inflow, over
     calls of 2, 3, 37, 1 (the single-step kernel) and 141 steps in a row;
@@ -460,7 +488,7 @@ def test_resident_interface_draws_default_shape():
 
 
 def test_resident_call_replays_as_graph():
-    """A captured resident call (cooperative launch + epoch advance) replays
+    """A captured resident call (one launch that advances the epoch) replays
     correctly: the generation tags of every replay are fresh. Three replays,
     each followed by eager single-step launches of the same steps on a
     second handle and a synchronisation, equal them bit for bit."""
@@ -540,24 +568,26 @@ def test_resident_stepper_matches_oracle():
 
 def test_resident_abort_word_poisons_the_state():
     """A set abort word (forced from the host; the kernel only reads it) makes
-    every tile stop at once and write NaN, which the diagnostics report; a
-    new handle on the same workspace size starts clean."""
+    every tile stop at once and write NaN; the next diagnostic call reports
+    the abort (PF_EABORTED, not a plain non-finite value); a new handle on
+    the same workspace size starts clean."""
     announce("resident abort word")
     import torch
-    from paper_2312_05410_amd._lib import PFError, PF_ENONFINITE
+    from paper_2312_05410_amd._lib import PFError, PF_EABORTED
 
     p = PFParams(nx=128, ny=64, precision="f32")
     sim = Sim(p, fused_kernel=3)
     assert sim.fused_kernel == 3
     ws = sim.workspace
-    # the control words (epoch, abort) are the workspace's last 256-byte block
+    # the control words (epoch, abort, completion count) are the workspace's last 256-byte block
     ws[-256 + 8:-256 + 16] = torch.tensor([1, 0, 0, 0, 0, 0, 0, 0], dtype=torch.uint8, device=ws.device)
     torch.cuda.synchronize()
     sim.step(5)
     assert np.isnan(sim.state()[0]).all()
-    with pytest.raises(PFError) as ei:
-        sim.mass()
-    assert ei.value.code == PF_ENONFINITE
+    for call in (sim.mass, sim.energy, sim.inflow):
+        with pytest.raises(PFError) as ei:
+            call()
+        assert ei.value.code == PF_EABORTED
     sim.close()
     again = Sim(p, fused_kernel=3)
     again.step(5)
@@ -635,9 +665,11 @@ def test_full_size_production_parity():
     announce("dns_1024 f32 full-size")
     p = workloads.dns_production(0)
     K = workloads.BENCH_TEMPORAL_BLOCK["f32"]
-    sim, ref = run_pair(p, initial_state(p), 20, 1e-6, temporal_block=K)
+    start = [np.float32(u).astype(np.float64) for u in initial_state(p)]
+    sim, ref = run_pair(p, start, 20, 1e-6, temporal_block=K)
     assert sim.fused_kernel == 3 and sim.launch == (1, 32)   # the resident stepper
     assert sim.step_count == 20
+    check_increments(sim.state(), (ref.c, ref.phi, ref.rho), start, 20, "f32", "dns_1024")
     np.testing.assert_allclose(sim.mass(), ref.mass(), rtol=1e-6)
     sim.close()
 
@@ -649,8 +681,11 @@ def test_full_size_large_grids(n, prec, steps, tol):
     announce(f"dns_{n} {prec} full-size")
     p = workloads.dns_production(0, n=n, precision=prec)
     K = workloads.BENCH_TEMPORAL_BLOCK[prec]
-    sim, ref = run_pair(p, initial_state(p), steps, tol, temporal_block=K)
+    ftype = np.float32 if prec == "f32" else np.float64
+    start = [ftype(u).astype(np.float64) for u in initial_state(p)]
+    sim, ref = run_pair(p, start, steps, tol, temporal_block=K)
     assert sim.launch[0] == 2 and sim.fused_kernel == 2
+    check_increments(sim.state(), (ref.c, ref.phi, ref.rho), start, steps, prec, f"dns_{n}")
     np.testing.assert_allclose(sim.mass(), ref.mass(), rtol=1e-6 if prec == "f32" else 1e-11)
     sim.close()
 
@@ -663,7 +698,7 @@ def test_full_size_batched_sampled():
     K = workloads.BENCH_TEMPORAL_BLOCK["f32"]
     dt = oracle.resolve_dt(p)
     p = p.replace(dt=dt)
-    state = initial_state(p)
+    state = [np.float32(u).astype(np.float64) for u in initial_state(p)]
     n = 12
     sim = Sim(p, state=state, temporal_block=K)
     sim.step(n)
@@ -677,4 +712,6 @@ def test_full_size_batched_sampled():
         for name, got, want in zip("c phi rho".split(), out, (ref.c, ref.phi, ref.rho)):
             e = rel_l2(got[b], want[0])
             assert e <= 1e-6, f"b={b} {name} {e:.2e}"
+        check_increments([u[b] for u in out], (ref.c[0], ref.phi[0], ref.rho[0]), [u[b] for u in state], n,
+                         "f32", f"batched b={b}")
     sim.close()

@@ -93,3 +93,63 @@ def test_training_reduces_held_out_loss():
     print("held-out loss", before, [h.val_loss for h in hist], flush=True)
     assert hist[-1].val_loss < 0.5 * before
     net.close()
+
+
+# Composition tolerance (increments of the whole run, per field): the leaps
+# dominate the error.  The network computes in BF16 operands with FP32
+# accumulation against the oracle's FP64 arithmetic on the same BF16-rounded
+# operands, and where the FP32 stepper state and the FP64 oracle state lie on
+# opposite sides of a BF16 rounding boundary the two networks see inputs one
+# BF16 step (2^-8 relative) apart.
+BLEND_INC_TOL = 2e-2
+
+
+def test_blended_run_matches_oracle_composition():
+    """The blended schedule on 64^2 FP32 (two cycles of [200 DNS steps, one
+    leap of 2 units], then a 200-step DNS tail; a seeded network whose head
+    is live, gamma 0.02) against the oracle's composition: its FP64 stepper
+    for the DNS blocks and its FP64 U-Net forward with the GPU's BF16
+    roundings for the leaps, from the same seeded initial condition (FP32-
+    rounded, as the GPU stores it).  Per field, the increment of the whole
+    run (final - initial) agrees within BLEND_INC_TOL relative L2, and
+    pointwise within BLEND_INC_TOL of the largest increment."""
+    import torch
+
+    import oracle
+    from oracle import unet_oracle as uo
+    from paper_2312_05410_amd import surrogate as S
+    from paper_2312_05410_amd.inputs import initial_state
+    from paper_2312_05410_amd.unet import UNet, UNetConfig
+
+    announce("blended run vs oracle composition 64^2")
+    n, seed, dns, jumps, steps = 64, 5, 200, 2, 1000
+    cfg = UNetConfig(height=n, width=n, base=8, levels=3, groups=4, mlp_hidden=16, basis=16, max_batch=1)
+    net = UNet(cfg, seed=3)
+    prm = net.param_dict()
+    prm["head.gamma"][:] = 0.02
+    net.set_params(prm)
+    state, _, _ = S.blended_run(net, seed=seed, steps=steps, dns_block=dns, jumps=jumps, mode="leap", n=n)
+    got = [u[0].double().cpu().numpy() for u in state]
+
+    p = S.blend_params(seed, n=n)
+    dt = 0.2 * oracle.dt_limit(p)
+    q = p.replace(dt=dt)
+    u0 = [np.float32(a).astype(np.float64) for a in initial_state(q)]
+    ref_net = uo.Net(cfg, net.param_dict())
+    st = oracle.State(q, *u0, dt=dt)
+    t = 0
+    while t + dns + jumps * S.JUMP <= steps:
+        st.step(dns)
+        pred = ref_net.forward(st.c, st.phi, st.rho, np.array([float(jumps)]), bf16=True)
+        st = oracle.State(q, *(x.detach().numpy() for x in pred), Q=st.Q, dt=dt, nstep=st.nstep)
+        t += dns + jumps * S.JUMP
+    assert t == 800
+    st.step(steps - t)
+    for name, g, r, a in zip(("c", "phi", "rho"), got, (st.c[0], st.phi[0], st.rho[0]), u0):
+        inc = r - a[0]
+        e = np.linalg.norm(g - r) / np.linalg.norm(inc)
+        m = np.abs(g - r).max() / np.abs(inc).max()
+        print(f"{name}: increment rel L2 {e:.2e}, max abs / max increment {m:.2e}, "
+              f"|increment| {np.linalg.norm(inc):.3e}", flush=True)
+        assert e <= BLEND_INC_TOL and m <= BLEND_INC_TOL, name
+    net.close()

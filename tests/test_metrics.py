@@ -42,3 +42,28 @@ def test_fft_s2_matches_bruteforce():
     np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12)
     np.testing.assert_allclose(metrics.radial_average(torch.tensor(ref), 6).numpy(), mo.radial_average(ref, 6),
                                rtol=0, atol=1e-12)
+
+
+def test_radial_average_hand_binned_annuli():
+    """Annulus membership written out by hand for ny = 3, nx = 5 (rows
+    ry = -2..2, columns rx = 0..4, x displacements folded to the nearest
+    periodic image min(rx, 5 - rx)).  |r| = sqrt(ry^2 + rx_folded^2):
+    k = 0: (0, 0); k = 1: (0, 1), (0, 4) and rx in {0, 1, 4} at ry = +-1;
+    k = 2: (0, 2), (0, 3), rx in {2, 3} at ry = +-1, every rx at ry = +-2
+    (sqrt 8 = 2.83 floors to 2); k = 3: empty.  Without the fold, rx = 3, 4
+    land in k = 3 or beyond; with rounding instead of floor, sqrt 2 and
+    sqrt 8 move to k = 1 -> 1 and 2 -> 3; either mistake changes these means."""
+    ny, nx = 3, 5
+    s = uniform01(31, np.arange((2 * ny - 1) * nx)).reshape(2 * ny - 1, nx)
+
+    def at(ry, rx):
+        return s[ry + ny - 1, rx]
+
+    k0 = [at(0, 0)]
+    k1 = [at(0, 1), at(0, 4)] + [at(ry, rx) for ry in (-1, 1) for rx in (0, 1, 4)]
+    k2 = [at(0, 2), at(0, 3)] + [at(ry, rx) for ry in (-1, 1) for rx in (2, 3)] + \
+         [at(ry, rx) for ry in (-2, 2) for rx in range(5)]
+    assert len(k0) + len(k1) + len(k2) == s.size
+    want = np.array([np.mean(k0), np.mean(k1), np.mean(k2), 0.0])
+    np.testing.assert_allclose(mo.radial_average(s, 4), want, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(metrics.radial_average(torch.tensor(s), 4).numpy(), want, rtol=0, atol=1e-15)
