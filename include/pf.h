@@ -49,10 +49,12 @@ enum pf_status {
     PF_EUNSTABLE = -2,   /* dt above the stability limit and allow_unstable == 0 */
     PF_ENONFINITE = -3,  /* a diagnostic came out NaN or infinite */
     PF_EDEVICE = -4,     /* a HIP call failed; see pf_last_hip_error */
-    PF_EABORTED = -5     /* the resident stepper gave up a wait for its neighbours (its tiles were
+    PF_EABORTED = -5,    /* the resident stepper gave up a wait for its neighbours (its tiles were
                             not all resident at once, e.g. another kernel held part of the device):
                             the state is NaN and the handle stays aborted until pf_init is called
                             again; reported by the next pf_mass, pf_energy or pf_get_inflow */
+    PF_ESCRATCH = -6     /* pf_diagnostics_noalloc: the input needs more partial sums than its
+                            static scratch holds (see pf_diagnostics_noalloc_limit) */
 };
 
 enum pf_precision { PF_F32 = 0, PF_F64 = 1 };
@@ -251,6 +253,31 @@ int pf_adjoint_reset(pf_handle* h, void* adj_workspace, size_t adj_bytes);
 /* Wait for the stream and write out[2*b] = dL/dM_scale, out[2*b+1] = dL/dv0
  * of realisation b, summed in FP64 in a fixed order. */
 int pf_adjoint_grad(pf_handle* h, void* adj_workspace, size_t adj_bytes, double* out);
+
+/* ------------------------------------------------ allocation-free variant
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * diagnostics of pf_mass and pf_energy for caller-given fields, with no
+ * handle and no workspace.  c, phi, rho: device buffers laid out as for
+ * pf_init ([batch][ny][nx], precision per p->precision, 16-byte aligned);
+ * out: a device array of batch x 4 doubles that receives, per realisation
+ * b, out[4*b + 0..2] = h^2 sum c, h^2 sum phi, h^2 sum rho and out[4*b + 3]
+ * = F_h, the same values pf_mass and pf_energy report for these fields
+ * (same kernels, same fixed summation order; no inflow, which is handle
+ * state).  Enqueued on `stream` (a hipStream_t of the current device, or
+ * NULL), returns without waiting; nothing is allocated or freed.  The
+ * partial sums live in a static device array of
+ * pf_diagnostics_noalloc_limit() bytes (1 MiB) that each GPU the library
+ * runs on holds until the process ends, found on the first call on a
+ * device.  Every call on a GPU shares that GPU's array (it holds the last
+ * call's partials; nothing in it needs clearing): calls that overlap on one
+ * GPU (different streams, or host threads) race.  Returns PF_EINVAL on a
+ * bad argument or a stream of another device, PF_ESCRATCH when batch x the
+ * partial count (about 2048 per launch) needs more than the array, and
+ * PF_EDEVICE on a HIP error. */
+int pf_diagnostics_noalloc(const pf_params* p, const void* c, const void* phi, const void* rho,
+                           double* out, void* stream);
+size_t pf_diagnostics_noalloc_limit(void);
 
 /* Text of a pf_status code. */
 const char* pf_strerror(int code);

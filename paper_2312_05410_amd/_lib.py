@@ -18,7 +18,7 @@ from .inputs import PFParams
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpf.so")
 
-PF_OK, PF_EINVAL, PF_EUNSTABLE, PF_ENONFINITE, PF_EDEVICE, PF_EABORTED = 0, -1, -2, -3, -4, -5
+PF_OK, PF_EINVAL, PF_EUNSTABLE, PF_ENONFINITE, PF_EDEVICE, PF_EABORTED, PF_ESCRATCH = 0, -1, -2, -3, -4, -5, -6
 PF_F32, PF_F64 = 0, 1
 PF_BC_PVD, PF_BC_PERIODIC = 0, 1
 PF_INIT_SEEDED, PF_INIT_KEEP = 0, 1
@@ -30,6 +30,7 @@ EXPORTS = (
     "pf_get_step", "pf_set_step", "pf_get_dt", "pf_get_inflow", "pf_set_inflow",
     "pf_destroy", "pf_strerror", "pf_last_hip_error", "pf_get_launch", "pf_get_lane_cols", "pf_get_fused_kernel",
     "pf_adjoint_workspace_bytes", "pf_adjoint_step", "pf_adjoint_reset", "pf_adjoint_grad",
+    "pf_diagnostics_noalloc", "pf_diagnostics_noalloc_limit",
 )
 
 
@@ -118,6 +119,10 @@ def load():
         L.pf_adjoint_reset.restype = ctypes.c_int
         L.pf_adjoint_grad.argtypes = [H, H, ctypes.c_size_t, dp]
         L.pf_adjoint_grad.restype = ctypes.c_int
+        L.pf_diagnostics_noalloc.argtypes = [P, H, H, H, H, H]
+        L.pf_diagnostics_noalloc.restype = ctypes.c_int
+        L.pf_diagnostics_noalloc_limit.argtypes = []
+        L.pf_diagnostics_noalloc_limit.restype = ctypes.c_size_t
         _lib = L
     return _lib
 
@@ -170,6 +175,21 @@ def workspace_bytes(p: PFParams) -> int:
     if n == 0:
         raise PFError(PF_EINVAL, "pf_workspace_bytes")
     return int(n)
+
+
+def diagnostics_noalloc(p: PFParams, c, phi, rho, out, stream=None) -> None:
+    """Enqueue pf_diagnostics_noalloc: out (a float64 device tensor of
+    batch x 4) receives h^2 sum c, h^2 sum phi, h^2 sum rho and F_h per
+    realisation of the device tensors c, phi, rho; no allocation, no wait."""
+    import torch
+
+    s, _keep = to_c(p)
+    if stream is None:
+        stream = torch.cuda.current_stream(c.device)
+    rc = load().pf_diagnostics_noalloc(ctypes.byref(s), c.data_ptr(), phi.data_ptr(), rho.data_ptr(),
+                                       out.data_ptr(), stream.cuda_stream)
+    if rc:
+        raise PFError(rc, "pf_diagnostics_noalloc")
 
 
 def dt_limit(p: PFParams) -> float:

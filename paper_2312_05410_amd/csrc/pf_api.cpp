@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -763,6 +764,7 @@ const char* pf_strerror(int code)
     case PF_ENONFINITE: return "non-finite diagnostic (state diverged or holds NaN/Inf)";
     case PF_EDEVICE: return "HIP device error";
     case PF_EABORTED: return "resident stepper abandoned a wait (tiles not co-resident); state is NaN, re-initialise";
+    case PF_ESCRATCH: return "input too large for the static scratch of pf_diagnostics_noalloc";
     default: return "unknown pf status";
     }
 }
@@ -912,4 +914,83 @@ extern "C" int pf_get_lane_cols(const pf_handle* h, int32_t* lane_cols)
     if (!h || !lane_cols) return PF_EINVAL;
     *lane_cols = h->K == 1 ? h->march_cols : (h->fused == PF_FUSED_MARCH ? h->k2_cols : 1);
     return PF_OK;
+}
+
+// ------------------------------------------------ allocation-free diagnostics
+//
+// pf_diagnostics_noalloc keeps its reduction partials in a file-scope device
+// array instead of a workspace.  In host code `scratch` names a host-side
+// stand-in, not device memory: the device address of each GPU's copy comes
+// from hipGetSymbolAddress, looked up once per device on the first call with
+// that device current, and only that address is passed to kernels.
+
+namespace {
+
+constexpr size_t kScratchBytes = (size_t)1 << 20;   // per GPU, held until the process ends
+constexpr int kMaxDevices = 64;
+
+__device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's scratch array (looked up once per
+// device); nullptr with *err set on failure.
+void* scratch_address(int dev, hipError_t* err)
+{
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            *err = e != hipSuccess ? e : hipErrorInvalidSymbol;
+            return nullptr;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" size_t pf_diagnostics_noalloc_limit(void) { return kScratchBytes; }
+
+extern "C" int pf_diagnostics_noalloc(const pf_params* p, const void* c, const void* phi, const void* rho,
+                                      double* out, void* stream)
+{
+    if (validate(p) != PF_OK) return PF_EINVAL;
+    if (!c || !phi || !rho || !out) return PF_EINVAL;
+    if (!aligned(c, 16) || !aligned(phi, 16) || !aligned(rho, 16) || !aligned(out, sizeof(double)))
+        return PF_EINVAL;
+    const pfk::RedGeo g = pfk::reduce_geometry(p->nx, p->ny, p->batch, (int)esize(p));
+    const size_t need = (size_t)p->batch * (size_t)g.parts() * 4 * sizeof(double);
+    if (need > kScratchBytes) return PF_ESCRATCH;
+    // the stream's device must be the current one (its scratch copy is used)
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return PF_EDEVICE;
+    hipStream_t s = (hipStream_t)stream;
+    if (s) {
+        int sdev = -1;
+        if (hipStreamGetDevice(s, &sdev) != hipSuccess) return PF_EDEVICE;
+        if (sdev != dev) return PF_EINVAL;
+    }
+    hipError_t e = hipSuccess;
+    double* partials = (double*)scratch_address(dev, &e);
+    if (!partials) return PF_EDEVICE;
+    pfk::RedArgs a{};
+    a.nx = p->nx;
+    a.ny = p->ny;
+    a.pvd = p->bc_mode == PF_BC_PVD;
+    a.h2 = p->h * p->h;
+    a.Wc = p->W_c;
+    a.Wphi = p->W_phi;
+    a.half_kc = 0.5 * p->kappa_c;
+    a.half_kp = 0.5 * p->kappa_phi;
+    if (p->precision == PF_F64)
+        e = pfk::launch_reduce<double>((const double*)c, (const double*)phi, (const double*)rho, nullptr, partials,
+                                       out, a, g, p->batch, s);
+    else
+        e = pfk::launch_reduce<float>((const float*)c, (const float*)phi, (const float*)rho, nullptr, partials, out,
+                                      a, g, p->batch, s);
+    return e == hipSuccess ? PF_OK : PF_EDEVICE;
 }

@@ -130,7 +130,8 @@ hipError_t launch_init(T* c, T* phi, T* rho, const InitArgs& a, int batch, hipSt
 // Qcol[b][i] = (i == 0 ? q[b] : 0)  (q == nullptr: all zero)
 hipError_t launch_set_inflow(double* Qcol, const double* q, int nx, int batch, hipStream_t s);
 
-// Diagnostics: out[b*5 + {0..4}] = h^2 sum c, h^2 sum phi, h^2 sum rho, Q, F_h.
+// Diagnostics: out[b*5 + {0..4}] = h^2 sum c, h^2 sum phi, h^2 sum rho, Q, F_h;
+// with Qcol == nullptr, out[b*4 + {0..3}] = h^2 sum c, h^2 sum phi, h^2 sum rho, F_h.
 // One workgroup per band of rows x chunk of columns; the partition depends on
 // the grid's shape and precision only (not on the device), so the FP64 sums
 // are taken in one fixed order.

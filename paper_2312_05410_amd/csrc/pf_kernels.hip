@@ -160,7 +160,9 @@ __global__ __launch_bounds__(256) void reduce_kernel(const T* c, const T* phi, c
     }
 }
 
-// One block per realisation: sum the partials and the inflow columns (each
+// One block per realisation: sum the partials and the inflow columns
+// (out[b][5]); without inflow columns (Qcol null) the masses and the energy
+// only (out[b][4]).  Each
 // thread in a fixed order; the loops are unrolled so that a thread's loads
 // are in flight together rather than one latency per element).
 __global__ __launch_bounds__(256) void finish_kernel(const double* partials, const double* Qcol,
@@ -177,9 +179,11 @@ __global__ __launch_bounds__(256) void finish_kernel(const double* partials, con
         s[2] += q.z;
         s[3] += q.w;
     }
-    const double* qc = Qcol + (size_t)b * nx;
+    if (Qcol) {
+        const double* qc = Qcol + (size_t)b * nx;
 #pragma unroll 8
-    for (int i = threadIdx.x; i < nx; i += 256) s[4] += qc[i];
+        for (int i = threadIdx.x; i < nx; i += 256) s[4] += qc[i];
+    }
     __shared__ double red[4][5];
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     for (int m = 0; m < 5; ++m) {
@@ -190,11 +194,18 @@ __global__ __launch_bounds__(256) void finish_kernel(const double* partials, con
     if (threadIdx.x == 0) {
         double t[5];
         for (int m = 0; m < 5; ++m) t[m] = (red[0][m] + red[1][m]) + (red[2][m] + red[3][m]);
-        out[b * 5 + 0] = h2 * t[0];
-        out[b * 5 + 1] = h2 * t[1];
-        out[b * 5 + 2] = h2 * t[2];
-        out[b * 5 + 3] = t[4];
-        out[b * 5 + 4] = t[3];
+        if (Qcol) {
+            out[b * 5 + 0] = h2 * t[0];
+            out[b * 5 + 1] = h2 * t[1];
+            out[b * 5 + 2] = h2 * t[2];
+            out[b * 5 + 3] = t[4];
+            out[b * 5 + 4] = t[3];
+        } else {
+            out[b * 4 + 0] = h2 * t[0];
+            out[b * 4 + 1] = h2 * t[1];
+            out[b * 4 + 2] = h2 * t[2];
+            out[b * 4 + 3] = t[3];
+        }
     }
 }
 

@@ -46,7 +46,7 @@ def test_params_struct_layout():
 
 def test_strerror():
     L = _lib.load()
-    for code in (0, -1, -2, -3, -4, -5, 7):
+    for code in (0, -1, -2, -3, -4, -5, -6, 7):
         assert L.pf_strerror(code)
 
 
