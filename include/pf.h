@@ -165,7 +165,11 @@ size_t pf_workspace_bytes(const pf_params* p);
  * The largest of v0 / v0_per enters dt_adv.  PF_EINVAL on bad input. */
 int pf_dt_limit(const pf_params* p, double* dt_lim);
 
-/* Create a handle that steps the caller's buffers c, phi, rho in place.
+/* Paper: Materials and Methods, "Phase-field modeling of physical vapor
+ * deposition" (the three fields c, phi, rho of a film growing from a flat
+ * substrate under an incoming vapour flux) and "Dataset" (seeded initial
+ * compositions around c0, a uniform 2-D grid).
+ * Create a handle that steps the caller's buffers c, phi, rho in place.
  * PF_INIT_SEEDED writes the seeded initial condition (c = c0 + c_noise
  * (2U - 1) from SplitMix64, a flat tanh film of height film_h, rho =
  * rho_in (1 - phi)/2); PF_INIT_KEEP takes the buffers' contents as the
@@ -175,7 +179,13 @@ int pf_dt_limit(const pf_params* p, double* dt_lim);
 int pf_init(pf_handle** out, const pf_params* p, void* c, void* phi, void* rho,
             void* workspace, size_t workspace_bytes, void* stream);
 
-/* Enqueue n >= 0 steps (the handle's integrator) of every realisation.
+/* Paper: Materials and Methods, "Phase-field modeling of physical vapor
+ * deposition" (the Cahn-Hilliard equation of c with the mobility
+ * M_c = M^Bulk + M^Surf, that of phi with the deposition source S, and the
+ * convection-diffusion of rho with the sink -S) discretised as "Dataset"
+ * states (second-order central differences; explicit time stepping, the
+ * paper's midpoint method as PF_MIDPOINT).
+ * Enqueue n >= 0 steps (the handle's integrator) of every realisation.
  * When the stream reaches the end of this work, the new state is in the
  * caller's buffers.  Returns without waiting.  A call may be captured into
  * a HIP graph: each replay advances the state it finds by n steps (the
@@ -185,14 +195,30 @@ int pf_init(pf_handle** out, const pf_params* p, void* c, void* phi, void* rho,
  * stream returns PF_EINVAL and enqueues nothing. */
 int pf_step_n(pf_handle* h, int64_t n);
 
-/* Wait for the stream, then write out[4*b + k] for each realisation b:
+/* One explicit Euler step (the handle's model and dt) from the state (c,
+ * phi, rho) into (c_out, phi_out, rho_out): device buffers with the state's
+ * layout and precision, the outputs distinct from the inputs.  The handle's
+ * own buffers, inflow accumulators and step counter are untouched (no
+ * inflow is accumulated).  For recomputing the states of a checkpointed
+ * reverse sweep without copies.  Enqueued; PF_EINVAL for a midpoint or
+ * interface-draw handle.  Paper: as pf_step_n. */
+int pf_step_out(pf_handle* h, const void* c, const void* phi, const void* rho,
+                void* c_out, void* phi_out, void* rho_out);
+
+/* Paper: the conservation form of the c and phi equations in Materials and
+ * Methods (masses change only through the deposition flux, which the
+ * inflow Q accounts for).
+ * Wait for the stream, then write out[4*b + k] for each realisation b:
  * k = 0..2 the masses h^2 sum c, h^2 sum phi, h^2 sum rho, and k = 3 the
  * cumulative vapour inflow Q through the top face.  Sums are accumulated in
  * FP64 in a fixed order (deterministic).  PF_ENONFINITE if any is not
  * finite. */
 int pf_mass(pf_handle* h, double* out);
 
-/* Wait for the stream, then write out[b] = discrete free energy
+/* Paper: the free-energy functional the chemical potentials derive from
+ * (Materials and Methods, "Phase-field modeling of physical vapor
+ * deposition"; its double-well and gradient terms as read above).
+ * Wait for the stream, then write out[b] = discrete free energy
  * F_h = h^2 sum f(c, phi) + (kappa_c/2) sum_faces (dc)^2
  *       + (kappa_phi/2) sum_faces (dphi)^2 in FP64 (all x faces, interior y
  * faces, plus the wrap faces in PF_BC_PERIODIC).  PF_ENONFINITE if any is

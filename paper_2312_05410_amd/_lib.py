@@ -27,7 +27,7 @@ PF_FUSED_TILE, PF_FUSED_MARCH, PF_FUSED_RESIDENT = 1, 2, 3
 
 EXPORTS = (
     "pf_workspace_bytes", "pf_dt_limit", "pf_init", "pf_step_n", "pf_mass", "pf_energy",
-    "pf_get_step", "pf_set_step", "pf_get_dt", "pf_get_inflow", "pf_set_inflow",
+    "pf_get_step", "pf_set_step", "pf_get_dt", "pf_get_inflow", "pf_set_inflow", "pf_step_out",
     "pf_destroy", "pf_strerror", "pf_last_hip_error", "pf_get_launch", "pf_get_lane_cols", "pf_get_fused_kernel",
     "pf_adjoint_workspace_bytes", "pf_adjoint_step", "pf_adjoint_reset", "pf_adjoint_grad",
     "pf_diagnostics_noalloc", "pf_diagnostics_noalloc_limit",
@@ -89,6 +89,8 @@ def load():
         L.pf_dt_limit.argtypes = [P, dp]
         L.pf_init.argtypes = [ctypes.POINTER(H), P, H, H, H, H, ctypes.c_size_t, H]
         L.pf_step_n.argtypes = [H, ctypes.c_int64]
+        L.pf_step_out.argtypes = [H] * 7
+        L.pf_step_out.restype = ctypes.c_int
         L.pf_mass.argtypes = [H, dp]
         L.pf_energy.argtypes = [H, dp]
         L.pf_get_step.argtypes = [H, ctypes.POINTER(ctypes.c_int64)]
@@ -257,6 +259,13 @@ class Simulator:
 
     def step(self, n: int) -> "Simulator":
         self._check(load().pf_step_n(self._h, int(n)), "pf_step_n")
+        return self
+
+    def step_out(self, src, dst) -> "Simulator":
+        """One Euler step from the (c, phi, rho) tensors `src` into `dst`
+        (pf_step_out: no inflow, the handle's own state untouched)."""
+        self._check(load().pf_step_out(self._h, *(u.data_ptr() for u in src), *(u.data_ptr() for u in dst)),
+                    "pf_step_out")
         return self
 
     def mass(self) -> np.ndarray:

@@ -5,8 +5,9 @@ the deposition rate, through the library's discrete adjoint.
 stepper from u0 = (c, phi, rho) and returns the final fields; as a
 torch.autograd.Function its backward sweeps the steps in reverse with the
 hand-written adjoint kernels (pf_adjoint_step), recomputing each segment of
-`every` steps from a stored checkpoint, so memory holds n/every checkpoints
-plus one segment instead of all n states.  Gradients are taken at fixed dt
+`every` steps from a stored checkpoint into a ring of `every` states
+allocated once (each state stepped out of place from the previous one), so memory holds n/every checkpoints plus one segment
+instead of all n states.  Gradients are taken at fixed dt
 (p.dt must be set) and are summed over the realisations of the batch.
 Every step, forward and reverse, runs in the HIP library; torch only holds
 the buffers and copies checkpoints.
@@ -50,21 +51,24 @@ class _FinalState(torch.autograd.Function):
         lam = [g.detach().to(dtype).contiguous() if g is not None else torch.zeros_like(ctx.ckpts[0][i])
                for i, g in enumerate((gc, gphi, grho))]
         nxt = [torch.empty_like(t) for t in lam]
-        work = [torch.empty_like(t) for t in ctx.ckpts[0]]
-        rec = Simulator(q, tensors=work, temporal_block=ctx.temporal_block)
+        # the recomputed states of one segment live in a ring allocated once:
+        # slot t holds (c, phi, rho) after t steps of the segment, each slot
+        # stepped from the previous one by pf_step_out (one launch, no copy)
+        shape = ctx.ckpts[0][0].shape
+        ring = torch.empty((every, 3) + tuple(shape), dtype=dtype, device=lam[0].device)
+        rec = Simulator(q, tensors=[ring[0, 0], ring[0, 1], ring[0, 2]], temporal_block=ctx.temporal_block)
         ws = rec.adjoint_workspace()
+        slot = lambda t: [ring[t, 0], ring[t, 1], ring[t, 2]]
         nseg = len(ctx.ckpts)
         for sg in range(nseg - 1, -1, -1):
             s0 = sg * every
             length = min(every, n - s0)
-            for w, ck in zip(work, ctx.ckpts[sg]):
-                w.copy_(ck)
-            states = [[t.clone() for t in work]]
-            for _ in range(1, length):
-                rec.step(1)
-                states.append([t.clone() for t in work])
+            for f, ck in enumerate(ctx.ckpts[sg]):
+                ring[0, f].copy_(ck)
+            for t in range(1, length):
+                rec.step_out(slot(t - 1), slot(t))
             for t in range(length - 1, -1, -1):
-                rec.adjoint_step(states[t], lam, nxt, ws)
+                rec.adjoint_step(slot(t), lam, nxt, ws)
                 lam, nxt = nxt, lam
         g = rec.adjoint_grad(ws).sum(axis=0)
         rec.close()

@@ -674,6 +674,36 @@ int pf_step_n(pf_handle* h, int64_t n)
     return rc;
 }
 
+int pf_step_out(pf_handle* h, const void* c, const void* phi, const void* rho, void* c_out, void* phi_out,
+                void* rho_out)
+{
+    if (!h) return PF_EINVAL;
+    const void* ptrs[6] = {c, phi, rho, c_out, phi_out, rho_out};
+    for (const void* q : ptrs)
+        if (!q || !aligned(q, 16)) return PF_EINVAL;
+    if (c_out == c || phi_out == phi || rho_out == rho) return PF_EINVAL;
+    if (h->p.integrator != PF_EULER || h->p.interface_noise > 0) return PF_EINVAL;
+    hipError_t e;
+    if (h->p.precision == PF_F64) {
+        pfk::StepArgs<double> a = step_args<double>(h);
+        a.c = (const double*)c, a.phi = (const double*)phi, a.rho = (const double*)rho;
+        a.c_out = (double*)c_out, a.phi_out = (double*)phi_out, a.rho_out = (double*)rho_out;
+        a.Qcol = nullptr;
+        a.nsub = 1;
+        a.step = h->step;
+        e = pfk::launch_march<double>(a, h->march_ty, h->march_cols, h->p.batch, h->stream);
+    } else {
+        pfk::StepArgs<float> a = step_args<float>(h);
+        a.c = (const float*)c, a.phi = (const float*)phi, a.rho = (const float*)rho;
+        a.c_out = (float*)c_out, a.phi_out = (float*)phi_out, a.rho_out = (float*)rho_out;
+        a.Qcol = nullptr;
+        a.nsub = 1;
+        a.step = h->step;
+        e = pfk::launch_march<float>(a, h->march_ty, h->march_cols, h->p.batch, h->stream);
+    }
+    return hip_fail(h, e);
+}
+
 int pf_mass(pf_handle* h, double* out)
 {
     if (!h || !out) return PF_EINVAL;

@@ -487,10 +487,10 @@ int forward(unet_handle* h, int n, const float* jump, const float* c, const floa
     auto Hl = [&](int l) { return net.c.height >> l; };
     auto Wl = [&](int l) { return net.c.width >> l; };
     const long P0 = net.P(0, 1);
-    // the jumps are kept for the backward pass
-    UCHECK(hipMemcpyAsync(b.jump, jump, sizeof(float) * n, hipMemcpyDeviceToDevice, s));
-    UCHECK(assemble_input(c, phi, rho, b.jump, b.xin, n, (int)P0, s));
-    UCHECK(mlp_forward(mlp_args(h, n, b.jump), s));
+    // input assembly, time basis and FiLM scales in one launch, which also
+    // keeps a copy of the jumps (read by the head's normalisation and the
+    // backward pass)
+    UCHECK(prologue_forward(mlp_args(h, n, jump), c, phi, rho, b.xin, (int)P0, b.jump, s));
     // encoder: z_l = block(down(z_{l-1})), zs_l = z_l * (w_l f(dt)); the
     // normalisation kernel also pools z_l for the next level
     for (int l = 0; l < L; ++l) {

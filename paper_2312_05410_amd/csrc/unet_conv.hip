@@ -262,7 +262,36 @@ __global__ __launch_bounds__(256) void gemm32_kernel(ConvArgs a)
     }
     // acc[i][j][e]: pixel pm + 16 i + 4 (lane / 16) + e, channel on + 16 j + r
     const int rq = (lane >> 4) * 4;
-    if (MODE == kUpFwd) {
+    if constexpr (MODE == kUpFwd) {
+        if (a.out_bf16 && !a.out_f32 && ((a.Nout >> 2) & 7) == 0) {
+            // BF16 output staged through LDS as [pixel][output column] and
+            // written back as 16-byte runs of 8 channels of one output pixel
+            // (consecutive threads take consecutive runs: the two sub-pixels
+            // of a row and the next input pixel's are adjacent in memory)
+            constexpr int BM = WGM * TM * 16, BN = WGN * TN * 16, LP = BN + 8;
+            __shared__ __align__(16) uint16_t stg[BM * LP];
+            const int pl = (wv % WGM) * TM * 16, ol = (wv / WGM) * TN * 16;
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) stg[(pl + 16 * i + rq + e) * LP + ol + 16 * j + r] = f2bf(acc[i][j][e]);
+            __syncthreads();
+            const unsigned Co = (unsigned)a.Nout >> 2, W2 = 2u * (unsigned)a.W;
+            const int pb = blockIdx.x * BM, obase = blockIdx.y * BN;
+            for (int idx = threadIdx.x; idx < BM * (BN / 8); idx += 256) {
+                const int p = idx / (BN / 8), q = idx - p * (BN / 8);
+                const int gp = pb + p, o = obase + 8 * q;
+                if (gp >= P || o >= a.Nout) continue;
+                const Pix t = pix(gp, a.H, a.W, P);
+                const unsigned sub = (unsigned)o / Co, co = (unsigned)o - sub * Co;
+                const unsigned dst = ((((unsigned)t.n * 2u * (unsigned)a.H + 2u * (unsigned)t.y + (sub >> 1)) * W2 +
+                                       2u * (unsigned)t.x + (sub & 1)) * Co + co);
+                *(uint4*)(a.out_bf16 + dst) = *(const uint4*)(&stg[p * LP + 8 * q]);
+            }
+            return;
+        }
         // sub-pixel scatter: one coordinate decomposition per 4 pixels (the
         // next three step along the row, wrapping where W is not a multiple
         // of 4) and the sub-pixel / channel split once per column tile
@@ -382,19 +411,24 @@ __global__ __launch_bounds__(256) void gemm32_kernel(ConvArgs a)
 // banks) and every tap reads its operands from there; the next chunk is
 // loaded into registers while the current one is used.  Wave w takes tile rows TH/4 w .. and their TW/16 16-pixel
 // segments (TM = TH/4 * TW/16 operand tiles).
-constexpr int kLdsPix = 40;  // BF16 elements per staged pixel (32 + 8 pad)
-
-template <int MODE, int TN, int TH, int TW>
+// KC input channels per staged chunk (32, or 64 where every chunk stays
+// inside one input: half as many load -> barrier -> multiply rounds, which
+// bound the small grids of the deep levels); staged rows of KC + 8 BF16
+// elements (80 or 144 bytes: 8 consecutive rows start 16 bytes apart modulo
+// 128, so the MFMA-layout reads are conflict-free)
+template <int MODE, int TN, int TH, int TW, int KC>
 __global__ __launch_bounds__(256) void conv3_lds_kernel(ConvArgs a)
 {
+    constexpr int LP = KC + 8;              // BF16 elements per staged row
+    constexpr int PPX = KC / 8;             // 16-byte pieces per staged row
     constexpr int HP = TH + 2, WP = TW + 2, NPX = HP * WP;
     constexpr int SEG = TW / 16, TM = (TH / 4) * SEG;
-    constexpr int NA = NPX * 4;             // 16-byte halo pieces per chunk
-    constexpr int NB = 9 * TN * 16 * 4;     // 16-byte weight pieces per chunk
+    constexpr int NA = NPX * PPX;           // 16-byte halo pieces per chunk
+    constexpr int NB = 9 * TN * 16 * PPX;   // 16-byte weight pieces per chunk
     constexpr int NLD = (NA + NB + 255) / 256;
-    // one chunk's halo [NPX][kLdsPix] and weights [9][TN 16][kLdsPix]
-    __shared__ __align__(16) uint16_t lds[(NPX + 9 * TN * 16) * kLdsPix];
-    uint16_t* const wl = lds + NPX * kLdsPix;
+    // one chunk's halo [NPX][LP] and weights [9][TN 16][LP]
+    __shared__ __align__(16) uint16_t lds[(NPX + 9 * TN * 16) * LP];
+    uint16_t* const wl = lds + NPX * LP;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, tid = threadIdx.x;
     const int r = lane & 15, kq = (lane >> 4) * 8;
     const int tx = (a.W + TW - 1) / TW, ty = (a.H + TH - 1) / TH;
@@ -402,7 +436,7 @@ __global__ __launch_bounds__(256) void conv3_lds_kernel(ConvArgs a)
     const int n = blockIdx.x / tpb, t = blockIdx.x - n * tpb;
     const int y0 = (t / tx) * TH, x0 = (t % tx) * TW;
     const int on = blockIdx.y * (TN * 16);
-    const int K = a.C1 + a.C2, nk = K / 32;
+    const int K = a.C1 + a.C2, nk = K / KC;
     // this lane's operand pixel in each of its TM tiles (tile coordinates)
     int ry[TM], cx[TM];
 #pragma unroll
@@ -416,11 +450,11 @@ __global__ __launch_bounds__(256) void conv3_lds_kernel(ConvArgs a)
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
 
-    // piece e < NA: halo pixel e / 4, channels 8 (e % 4) ..; else weight row
-    // (tap, o) = (e - NA) / 4 of the chunk, k = 8 ((e - NA) % 4) ..
+    // piece e < NA: halo pixel e / PPX, channels 8 (e % PPX) ..; else weight
+    // row (tap, o) = (e - NA) / PPX of the chunk, k = 8 ((e - NA) % PPX) ..
     uint4 stage[NLD];
     auto gload = [&](int kc) {
-        const int k0 = kc * 32;
+        const int k0 = kc * KC;
         const bool first = k0 < a.C1;
         const uint16_t* src = first ? a.in1 : a.in2;
         const int C = first ? a.C1 : a.C2, c0 = first ? k0 : k0 - a.C1;
@@ -429,12 +463,12 @@ __global__ __launch_bounds__(256) void conv3_lds_kernel(ConvArgs a)
             const int e = tid + 256 * u;
             uint4 v = make_uint4(0, 0, 0, 0);
             if (e < NA) {
-                const int px = e >> 2, q = e & 3;
+                const int px = e / PPX, q = e % PPX;
                 const int gy = y0 - 1 + px / WP, gx = x0 - 1 + px % WP;
                 if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W)
                     v = *(const uint4*)(src + (((long)n * a.H + gy) * a.W + gx) * C + c0 + 8 * q);
             } else if (e < NA + NB) {
-                const int row = (e - NA) >> 2, q = (e - NA) & 3;
+                const int row = (e - NA) / PPX, q = (e - NA) % PPX;
                 const int tap = row / (TN * 16), o = row - tap * (TN * 16);
                 v = *(const uint4*)(a.Wt + ((size_t)tap * a.ldo + on + o) * a.ldk + k0 + 8 * q);
             }
@@ -445,7 +479,7 @@ __global__ __launch_bounds__(256) void conv3_lds_kernel(ConvArgs a)
 #pragma unroll
         for (int u = 0; u < NLD; ++u) {
             const int e = tid + 256 * u;
-            if (e < NA + NB) *(uint4*)(&lds[(e >> 2) * kLdsPix + 8 * (e & 3)]) = stage[u];
+            if (e < NA + NB) *(uint4*)(&lds[(e / PPX) * LP + 8 * (e % PPX)]) = stage[u];
         }
     };
     gload(0);
@@ -461,17 +495,21 @@ __global__ __launch_bounds__(256) void conv3_lds_kernel(ConvArgs a)
                 dy = -dy;
                 dx = -dx;
             }
-            bf16x8 B[TN], A[TM];
 #pragma unroll
-            for (int j = 0; j < TN; ++j) B[j] = *(const bf16x8*)(&wl[(tap * TN * 16 + 16 * j + r) * kLdsPix + kq]);
-#pragma unroll
-            for (int i = 0; i < TM; ++i)
-                A[i] = *(const bf16x8*)(&lds[((ry[i] + 1 + dy) * WP + cx[i] + 1 + dx) * kLdsPix + kq]);
-#pragma unroll
-            for (int i = 0; i < TM; ++i)
+            for (int ks = 0; ks < KC / 32; ++ks) {
+                bf16x8 B[TN], A[TM];
 #pragma unroll
                 for (int j = 0; j < TN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[i], B[j], acc[i][j], 0, 0, 0);
+                    B[j] = *(const bf16x8*)(&wl[(tap * TN * 16 + 16 * j + r) * LP + 32 * ks + kq]);
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+                    A[i] = *(const bf16x8*)(&lds[((ry[i] + 1 + dy) * WP + cx[i] + 1 + dx) * LP + 32 * ks + kq]);
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[i], B[j], acc[i][j], 0, 0, 0);
+            }
         }
     }
     __syncthreads();   // LDS is reused by the epilogue's reduction
@@ -896,8 +934,12 @@ void launch_lds(const ConvArgs& a, hipStream_t s)
 {
     const int tn = lds_tn(a);
     dim3 grid((unsigned)(lds_tiles(a) * a.N), (unsigned)((a.Nout + 16 * tn - 1) / (16 * tn)));
-    if (tn == 2) hipLaunchKernelGGL((conv3_lds_kernel<MODE, 2, kLdsTH, kLdsTW>), grid, dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((conv3_lds_kernel<MODE, 1, kLdsTH, kLdsTW>), grid, dim3(256), 0, s, a);
+    // 64-channel chunks for the 16-channel blocks of the small grids (every
+    // chunk inside one of the concatenated inputs)
+    const bool kc64 = tn == 1 && a.C1 % 64 == 0 && a.C2 % 64 == 0 && a.ldk % 64 == 0;
+    if (tn == 2) hipLaunchKernelGGL((conv3_lds_kernel<MODE, 2, kLdsTH, kLdsTW, 32>), grid, dim3(256), 0, s, a);
+    else if (kc64) hipLaunchKernelGGL((conv3_lds_kernel<MODE, 1, kLdsTH, kLdsTW, 64>), grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((conv3_lds_kernel<MODE, 1, kLdsTH, kLdsTW, 32>), grid, dim3(256), 0, s, a);
 }
 
 }  // namespace

@@ -123,10 +123,6 @@ int gn_chunks(int P);
 hipError_t maxpool_fwd(const uint16_t* x, uint16_t* y, int N, int H, int W, int C, hipStream_t s);
 hipError_t maxpool_bwd(const uint16_t* x, const float* dy, float* dx, int N, int H, int W, int C, hipStream_t s);
 
-// Network input: x[n][p][0..3] = (c - 1/2, phi, rho - 1, jump[n]) as BF16.
-hipError_t assemble_input(const float* c, const float* phi, const float* rho, const float* jump, uint16_t* x, int N,
-                          int P, hipStream_t s);
-
 // Time basis f(jump) (two sin layers of width Hd) and the per-level FiLM
 // scales s_l = w_l f.
 struct MLPArgs {
@@ -151,7 +147,11 @@ struct MLPArgs {
     int N, Hd, F, L;
     int C[kMaxLevels];
 };
-hipError_t mlp_forward(const MLPArgs& a, hipStream_t s);
+// Forward prologue in one launch: the network input x[n][p] = BF16 (c - 1/2,
+// phi, rho - 1, jump[n]), the time basis f(jump) and every level's FiLM
+// scales (a.jump the caller's jumps; jump_copy, or null, receives them)
+hipError_t prologue_forward(const MLPArgs& a, const float* c, const float* phi, const float* rho, uint16_t* x, int P,
+                            float* jump_copy, hipStream_t s);
 hipError_t mlp_backward(const MLPArgs& a, hipStream_t s);
 
 // Relative MSE per field: L = sum_f sum (pred - tgt)^2 / sum tgt^2.

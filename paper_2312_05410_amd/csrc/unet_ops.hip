@@ -99,33 +99,51 @@ __device__ __forceinline__ void block_sum(double (*sh)[256], double* v)
     for (int q = 0; q < Q; ++q) v[q] = sh[q][0];
 }
 
-// mean and 1/sqrt(var + eps) of one (sample, group) per block
-__global__ __launch_bounds__(256) void gn_stats_finish(GNArgs a)
+// mean and 1/sqrt(var + eps) of one (sample, group) per block of 1024
+// threads: every thread's loads are in flight together (four per thread
+// cover the 4096 partial pairs of a 4-channel group over 1024 tiles), then
+// a fixed shuffle tree per wave and the 16 waves in order
+constexpr int kFinThreads = 1024;
+__global__ __launch_bounds__(kFinThreads) void gn_stats_finish(GNArgs a)
 {
-    __shared__ double sh[2][256];
     const int i = blockIdx.x, n = i / a.G, g = i % a.G, Cg = a.C / a.G;
     double v[2] = {0.0, 0.0};
-    // the group's channels are contiguous: [n][g Cg .. (g+1) Cg)[chunks][2];
-    // eight independent loads in flight per thread, then the remainder
+    // the group's channels are contiguous: [n][g Cg .. (g+1) Cg)[chunks][2]
     const float2* o = (const float2*)a.csum + ((size_t)n * a.C + g * Cg) * a.chunks;
     const int total = Cg * a.chunks;
     int e = threadIdx.x;
-    for (; e + 7 * 256 < total; e += 8 * 256) {
-        float2 q[8];
+    for (; e + 3 * kFinThreads < total; e += 4 * kFinThreads) {
+        float2 q[4];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) q[u] = o[e + u * 256];
+        for (int u = 0; u < 4; ++u) q[u] = o[e + u * kFinThreads];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
+        for (int u = 0; u < 4; ++u) {
             v[0] += q[u].x;
             v[1] += q[u].y;
         }
     }
-    for (; e < total; e += 256) {
+    for (; e < total; e += kFinThreads) {
         const float2 q = o[e];
         v[0] += q.x;
         v[1] += q.y;
     }
-    block_sum<2>(sh, v);
+    {
+        __shared__ double shw[2][kFinThreads / 64];
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_xor(v[q], off, 64);
+            if (lane == 0) shw[q][wv] = v[q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            double t = 0.0;
+            for (int w = 0; w < kFinThreads / 64; ++w) t += shw[q][w];
+            v[q] = t;
+        }
+    }
     __shared__ float ms[2];
     if (threadIdx.x == 0) {
         const double M = (double)Cg * a.P;
@@ -138,7 +156,7 @@ __global__ __launch_bounds__(256) void gn_stats_finish(GNArgs a)
     }
     if (!a.coef) return;
     __syncthreads();
-    for (int c = g * Cg + threadIdx.x; c < (g + 1) * Cg; c += 256) {
+    for (int c = g * Cg + threadIdx.x; c < (g + 1) * Cg; c += kFinThreads) {
         const float A = a.gamma[c] * ms[1];
         a.coef[(size_t)n * a.C + c] = A;
         a.coef[(size_t)(a.N + n) * a.C + c] = fmaf(-A, ms[0], a.beta[c]);
@@ -453,24 +471,6 @@ __global__ __launch_bounds__(256) void pool_bwd_kernel(const uint16_t* x, const 
     }
 }
 
-// ------------------------------------------------------- input / output
-__global__ __launch_bounds__(256) void assemble_kernel(const float* c, const float* phi, const float* rho,
-                                                       const float* jump, uint16_t* x, int N, int P)
-{
-    const size_t total = (size_t)N * P;
-    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (size_t)gridDim.x * 256) {
-        const int n = (int)(i / P);
-        // centred before rounding: BF16 keeps ~3 significant digits of the
-        // value, and the composition fluctuations around 1/2 and the vapour
-        // density deficit below 1 are far smaller than the values themselves
-        ushort4 v;
-        v.x = f2bf(c[i] - 0.5f);
-        v.y = f2bf(phi[i]);
-        v.z = f2bf(rho[i] - 1.0f);
-        v.w = f2bf(jump[n]);
-        *(ushort4*)(x + 4 * i) = v;
-    }
-}
 
 // -------------------------------------------------------------------- MLP
 constexpr int kMlpThreads = 1024;
@@ -488,43 +488,69 @@ __device__ __forceinline__ float row_dot(const float* W, const float* x, int len
     return s;
 }
 
-// f = W2 sin(W1 sin(W0 t + b0) + b1) + b2; one block per sample, 4 lanes
-// per output row (rows <= 256).
-__global__ __launch_bounds__(kMlpThreads) void mlp_fwd_kernel(MLPArgs a)
-{
-    __shared__ float a0[256], a1[256];
-    const int n = blockIdx.x, tid = threadIdx.x, j = tid >> 2, k = tid & 3;
-    const float t = a.jump[n];
-    for (int q = tid; q < a.Hd; q += blockDim.x) {
-        const float h = fmaf(a.W0[q], t, a.b0[q]);
-        a.h0[n * a.Hd + q] = h;
-        a0[q] = sinf(h);
-    }
-    __syncthreads();
-    {
-        const float h = row_dot<4>(a.W1, a0, a.Hd, j < a.Hd ? j : 0, k) + (j < a.Hd ? a.b1[j] : 0.f);
-        if (j < a.Hd && k == 0) {
-            a.h1[n * a.Hd + j] = h;
-            a1[j] = sinf(h);
-        }
-    }
-    __syncthreads();
-    {
-        const float v = row_dot<4>(a.W2, a1, a.Hd, j < a.F ? j : 0, k) + (j < a.F ? a.b2[j] : 0.f);
-        if (j < a.F && k == 0) a.f[n * a.F + j] = v;
-    }
-}
 
-// s_l[n][c] = sum_i Wl[c][i] f[n][i] for every level; rows of all levels
-// numbered consecutively, 8 lanes per row; grid (rows / 32, N).
-__global__ __launch_bounds__(256) void film_kernel(MLPArgs a)
+
+// The forward's prologue in one launch: blocks (n, l) < N L evaluate the
+// time basis f = W2 sin(W1 sin(W0 t + b0) + b1) + b2 of sample n (block (n, 0) keeps h0, h1, f for the
+// backward pass) and then the FiLM scales of level l, s_l = Wl f (8 lanes
+// per row); the other blocks assemble the network input, BF16 (c - 1/2,
+// phi, rho - 1, jump) per pixel, centred before rounding (BF16 keeps ~3
+// significant digits, and the composition fluctuations around 1/2 and the
+// vapour deficit below 1 are far smaller than the values themselves), and
+// the first of them copies the jumps.
+__global__ __launch_bounds__(kMlpThreads) void prologue_kernel(MLPArgs a, const float* c, const float* phi,
+                                                              const float* rho, uint16_t* x, int P,
+                                                              float* jump_copy)
 {
-    const int n = blockIdx.y, row = blockIdx.x * 32 + (threadIdx.x >> 3), k = threadIdx.x & 7;
-    int l = 0, c = row;
-    while (l < a.L && c >= a.C[l]) c -= a.C[l++];
-    const bool ok = l < a.L;
-    const float v = row_dot<8>(ok ? a.Wl[l] : a.Wl[0], a.f + (size_t)n * a.F, a.F, ok ? c : 0, k);
-    if (ok && k == 0) a.sc[l][n * a.C[l] + c] = v;
+    const int tid = threadIdx.x;
+    const int mlp_blocks = a.N * a.L;
+    if ((int)blockIdx.x < mlp_blocks) {
+        __shared__ float a0[256], a1[256], fs[256];
+        const int n = blockIdx.x / a.L, l = blockIdx.x % a.L, j = tid >> 2, k = tid & 3;
+        const bool keep = l == 0;
+        const float t = a.jump[n];
+        for (int q = tid; q < a.Hd; q += blockDim.x) {
+            const float h = fmaf(a.W0[q], t, a.b0[q]);
+            if (keep) a.h0[n * a.Hd + q] = h;
+            a0[q] = sinf(h);
+        }
+        __syncthreads();
+        {
+            const float h = row_dot<4>(a.W1, a0, a.Hd, j < a.Hd ? j : 0, k) + (j < a.Hd ? a.b1[j] : 0.f);
+            if (j < a.Hd && k == 0) {
+                if (keep) a.h1[n * a.Hd + j] = h;
+                a1[j] = sinf(h);
+            }
+        }
+        __syncthreads();
+        {
+            const float v = row_dot<4>(a.W2, a1, a.Hd, j < a.F ? j : 0, k) + (j < a.F ? a.b2[j] : 0.f);
+            if (j < a.F && k == 0) {
+                if (keep) a.f[n * a.F + j] = v;
+                fs[j] = v;
+            }
+        }
+        __syncthreads();
+        const int kk = tid & 7;
+        for (int row = tid >> 3; row < a.C[l]; row += kMlpThreads / 8) {
+            const float v = row_dot<8>(a.Wl[l], fs, a.F, row, kk);
+            if (kk == 0) a.sc[l][n * a.C[l] + row] = v;
+        }
+        return;
+    }
+    const size_t total = (size_t)a.N * P;
+    if (jump_copy && (int)blockIdx.x == mlp_blocks)
+        for (int n = tid; n < a.N; n += kMlpThreads) jump_copy[n] = a.jump[n];
+    const size_t nthreads = (size_t)(gridDim.x - mlp_blocks) * kMlpThreads;
+    for (size_t i = (size_t)(blockIdx.x - mlp_blocks) * kMlpThreads + tid; i < total; i += nthreads) {
+        const int n = (int)(i / P);
+        ushort4 v;
+        v.x = f2bf(c[i] - 0.5f);
+        v.y = f2bf(phi[i]);
+        v.z = f2bf(rho[i] - 1.0f);
+        v.w = f2bf(a.jump[n]);
+        *(ushort4*)(x + 4 * i) = v;
+    }
 }
 
 // Backward, per sample: df = sum_l Wl^T ds_l, dh1 = cos(h1) W2^T df,
@@ -725,7 +751,7 @@ hipError_t gn_forward(const GNArgs& a_in, hipStream_t s)
         a.chunks = gn_chunks(a.P);
         hipLaunchKernelGGL(gn_stats_kernel, dim3(a.chunks, a.N), dim3(256), 0, s, a, chunk_px(a.P));
     }
-    hipLaunchKernelGGL(gn_stats_finish, dim3(a.N * a.G), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(gn_stats_finish, dim3(a.N * a.G), dim3(kFinThreads), 0, s, a);
     if (a.res_jump) {
         if (a.C != 3 || (a.G != 1 && a.G != 3)) return hipErrorInvalidValue;
         hipLaunchKernelGGL(gn_apply_res_kernel, dim3(grid_for((size_t)a.N * a.P)), dim3(256), 0, s, a);
@@ -767,22 +793,20 @@ hipError_t maxpool_bwd(const uint16_t* x, const float* dy, float* dx, int N, int
     return hipGetLastError();
 }
 
-hipError_t assemble_input(const float* c, const float* phi, const float* rho, const float* jump, uint16_t* x, int N,
-                          int P, hipStream_t s)
-{
-    const size_t n = (size_t)N * P;
-    if (!n) return hipSuccess;
-    hipLaunchKernelGGL(assemble_kernel, dim3(grid_for(n)), dim3(256), 0, s, c, phi, rho, jump, x, N, P);
-    return hipGetLastError();
-}
 
-hipError_t mlp_forward(const MLPArgs& a, hipStream_t s)
+
+hipError_t prologue_forward(const MLPArgs& a, const float* c, const float* phi, const float* rho, uint16_t* x, int P,
+                            float* jump_copy, hipStream_t s)
 {
     if (a.N <= 0) return hipSuccess;
-    hipLaunchKernelGGL(mlp_fwd_kernel, dim3(a.N), dim3(kMlpThreads), 0, s, a);
-    int rows = 0;
-    for (int l = 0; l < a.L; ++l) rows += a.C[l];
-    hipLaunchKernelGGL(film_kernel, dim3((rows + 31) / 32, a.N), dim3(256), 0, s, a);
+    for (int l = 0; l < a.L; ++l)
+        if (a.C[l] > 256 * 8 || a.Hd > 256 || a.F > 256) return hipErrorInvalidValue;
+    const size_t items = (size_t)a.N * P;
+    size_t ab = (items + kMlpThreads - 1) / kMlpThreads;
+    if (ab > 2048) ab = 2048;
+    if (ab < 1) ab = 1;
+    hipLaunchKernelGGL(prologue_kernel, dim3((unsigned)(a.N * a.L + ab)), dim3(kMlpThreads), 0, s, a, c, phi, rho,
+                       x, P, jump_copy);
     return hipGetLastError();
 }
 

@@ -715,3 +715,35 @@ def test_full_size_batched_sampled():
         check_increments([u[b] for u in out], (ref.c[0], ref.phi[0], ref.rho[0]), [u[b] for u in state], n,
                          "f32", f"batched b={b}")
     sim.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_step_out_equals_one_step(prec):
+    """pf_step_out (one step out of place, used by the adjoint's
+    recomputation) equals one pf_step_n step bit for bit, and leaves the
+    handle's own state, inflow and step counter untouched; refused for the
+    midpoint integrator."""
+    import torch
+
+    from paper_2312_05410_amd._lib import PFError
+
+    announce(f"step_out {prec}")
+    p = PFParams(nx=100, ny=77, batch=2, precision=prec, theta_deg=70.0)
+    state = random_state(61, 2, 77, 100)
+    sim = Sim(p, state=state, temporal_block=1)
+    ref = Sim(p, state=state, temporal_block=1)
+    dst = [torch.empty_like(u) for u in (sim.c, sim.phi, sim.rho)]
+    before = sim.state()
+    sim.step_out((sim.c, sim.phi, sim.rho), dst)
+    ref.step(1)
+    torch.cuda.synchronize()
+    for u, v in zip(dst, ref.state()):
+        assert np.array_equal(u.double().cpu().numpy(), v)
+    for u, v in zip(sim.state(), before):
+        assert np.array_equal(u, v)
+    assert sim.step_count == 0 and np.all(sim.inflow() == 0)
+    mid = Sim(p.replace(integrator="midpoint"), state=state, temporal_block=1)
+    with pytest.raises(PFError):
+        mid.step_out((mid.c, mid.phi, mid.rho), dst)
+    for s in (sim, ref, mid):
+        s.close()
