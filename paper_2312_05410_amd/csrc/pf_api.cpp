@@ -179,6 +179,7 @@ struct pf_handle {
     int k2_cols = 1;                     // register strip march: grid columns per lane
     int res_th = 0;                      // resident stepper: tile height (0: not used)
     int res_ntx = 0, res_nty = 0;        // resident stepper: tiles per row / column
+    uint32_t res_epoch = 0;              // resident stepper: generations traded by eager launches (mod 2^30)
     int last_hip = 0;
     hipGraph_t graph = nullptr;          // chain of kGraphLen full-K launches
     hipGraphExec_t gexec = nullptr;
@@ -382,14 +383,21 @@ int enqueue_resident(pf_handle* h, int64_t n)
     ra.batch = h->p.batch;
     ra.ntx = h->res_ntx;
     ra.nty = h->res_nty;
+    // a launch captured in a graph takes its tags from the device epoch (a
+    // replay repeats the arguments); eager launches from the host's count
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(h->stream, &cs) != hipSuccess) (void)hipGetLastError();
+    ra.dev_epoch = cs != hipStreamCaptureStatusNone;
     constexpr int64_t kChunk = (int64_t)1 << 29;
     int64_t done = 0;
     while (done < n) {
         // never leave a single step for the last chunk
         ra.n = (int)(n - done > kChunk + 1 ? kChunk : n - done);
         ra.s.step = h->step + done;   // keys the interface draws
+        ra.e0 = h->res_epoch;
         const int rc = hip_fail(h, pfk::launch_resident(ra, h->res_th, h->stream));
         if (rc) return rc;
+        if (!ra.dev_epoch) h->res_epoch = (h->res_epoch + (uint32_t)(ra.mid ? 2 * ra.n : ra.n)) & 0x3FFFFFFFu;
         done += ra.n;
     }
     return PF_OK;

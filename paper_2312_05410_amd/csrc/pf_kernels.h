@@ -92,10 +92,13 @@ hipError_t graph_add_march_k2(hipGraph_t g, hipGraphNode_t* node, hipGraphNode_t
 // Resident stepper: one launch advances FP32 grids by n >= 2 explicit Euler
 // or midpoint steps with each 64 x th tile (th in {8, 16, 32}) held in LDS,
 // trading 2-cell rims after every step through
-// rim[2][tiles][3][resident_rim_words(th)] tagged words; ctl[0] is the
-// generation-tag epoch (advanced inside the launch by its last workgroup),
-// ctl[1] the sticky abort word, ctl[2] the launch's completion count (zero
-// between launches).  In place: s.c == s.c_out etc.  nx = 64 ntx, ny = th nty.
+// rim[2][tiles][3][resident_rim_words(th)] tagged words.  The tags of a
+// launch are e0 + generation: e0 is passed by the host (below 2^30, top bit
+// clear), or, for a launch captured in a graph (dev_epoch), read from the
+// device epoch ctl[0] with the top bit set, and the launch's last
+// workgroup (counted in ctl[2], zero between launches) advances ctl[0].
+// ctl[1] is the sticky abort word.  In place: s.c == s.c_out etc.
+// nx = 64 ntx, ny = th nty.
 struct ResArgs {
     StepArgs<float> s;
     Coef<float> kh;      // midpoint: the half step's constants (dt / 2)
@@ -104,6 +107,8 @@ struct ResArgs {
     int n;
     int mid;             // 1: explicit midpoint steps (two rim trades per step)
     int batch, ntx, nty;
+    uint32_t e0;         // host epoch (dev_epoch == 0)
+    int dev_epoch;       // 1: tags from the device epoch (graph capture)
 };
 size_t resident_rim_words(int th);
 // Tiles the device keeps co-resident for tile height th (occupancy of every

@@ -7,6 +7,8 @@
 `stats` prints the per-kernel summary of a `--kernel-trace --stats` run
 (CSV output); `dbstats` the same from the SQLite database rocprofv3 writes
 by default (`*_results.db`), grouped by kernel and grid.
+`counters` prints SQ counter metrics (occupancy, VALU issue, wait and MFMA
+fractions, LDS conflicts) of one kernel from a `--pmc` run.
 `traffic` reads two `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs of the same
 program, whose first large device copy (--ref-bytes bytes, read once and
 written once) calibrates the counters: each counter is scaled by
@@ -99,6 +101,57 @@ def traffic(fetch_dir: str, write_dir: str, kernel: str, ref_bytes: int):
                 launches=min(len(kf), len(kw)))
 
 
+def counters(d: str, kernel: str, cus: int = 256, simds: int = 1024, xcds: int = 8):
+    """Per-dispatch SQ counter metrics of the kernels whose name contains
+    `kernel` (median over their dispatches).  GRBM_GUI_ACTIVE is the sum over
+    the XCDs (cycles per XCD = value / xcds); SQ_*_CYCLES and SQ_WAIT_* are
+    in quad-cycles (4 clocks), SQ_VALU_MFMA_BUSY_CYCLES in clocks per SIMD."""
+    import collections
+
+    rows = list(csv.DictReader(open(_one(os.path.join(d, "**", "*counter_collection.csv")))))
+    disp = collections.OrderedDict()
+    for r in rows:
+        if kernel not in r["Kernel_Name"]:
+            continue
+        e = disp.setdefault(r["Dispatch_Id"], {"us": (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3,
+                                               "c": collections.defaultdict(float)})
+        e["c"][r["Counter_Name"]] += float(r["Counter_Value"])
+    if not disp:
+        raise SystemExit(f"no dispatch of a kernel matching {kernel!r}")
+    out = collections.defaultdict(list)
+    for e in disp.values():
+        c, us = e["c"], e["us"]
+        out["duration_us"].append(us)
+        cyc = c.get("GRBM_GUI_ACTIVE", 0.0) / xcds
+        if cyc:
+            out["cycles_per_xcd"].append(cyc)
+            out["clock_GHz"].append(cyc / us / 1e3)
+        if "SQ_WAVES" in c:
+            out["waves"].append(c["SQ_WAVES"])
+        if cyc and "SQ_WAVE_CYCLES" in c:
+            out["mean_waves_per_CU"].append(4 * c["SQ_WAVE_CYCLES"] / (cus * cyc))
+        if cyc and "SQ_INSTS_VALU" in c:
+            out["valu_wave_instructions"].append(c["SQ_INSTS_VALU"])
+            # a wave64 FP32 VALU instruction occupies its SIMD for 2 clocks
+            out["valu_issue_fraction"].append(2 * c["SQ_INSTS_VALU"] / (simds * cyc))
+        for name, key in (("SQ_WAIT_ANY", "wait_any_fraction_of_wave_time"),
+                          ("SQ_WAIT_INST_ANY", "wait_issue_fraction_of_wave_time"),
+                          ("SQ_ACTIVE_INST_VALU", "valu_active_fraction_of_wave_time"),
+                          ("SQ_ACTIVE_INST_LDS", "lds_active_fraction_of_wave_time")):
+            if name in c and c.get("SQ_WAVE_CYCLES"):
+                out[key].append(c[name] / c["SQ_WAVE_CYCLES"])
+        if cyc and "SQ_VALU_MFMA_BUSY_CYCLES" in c:
+            out["mfma_busy_fraction"].append(c["SQ_VALU_MFMA_BUSY_CYCLES"] / (simds * cyc))
+        if "SQ_INSTS_MFMA" in c:
+            out["mfma_instructions"].append(c["SQ_INSTS_MFMA"])
+        if c.get("SQ_LDS_IDX_ACTIVE", 0) > c.get("SQ_LDS_BANK_CONFLICT", 0):
+            out["lds_conflicts_per_access"].append(
+                c.get("SQ_LDS_BANK_CONFLICT", 0) / (c["SQ_LDS_IDX_ACTIVE"] - c.get("SQ_LDS_BANK_CONFLICT", 0)))
+        if "SQ_WAIT_INST_LDS" in c and c.get("SQ_WAVE_CYCLES"):
+            out["wait_lds_issue_fraction_of_wave_time"].append(c["SQ_WAIT_INST_LDS"] / c["SQ_WAVE_CYCLES"])
+    return len(disp), {k: statistics.median(v) for k, v in out.items()}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -109,6 +162,11 @@ def main(argv=None):
     s2.add_argument("dir")
     s2.add_argument("--kernel")
     s2.add_argument("--top", type=int, default=40)
+    q = sub.add_parser("counters")
+    q.add_argument("dir")
+    q.add_argument("--kernel", required=True)
+    q.add_argument("--command", default="")
+    q.add_argument("--out")
     t = sub.add_parser("traffic")
     t.add_argument("fetch_dir")
     t.add_argument("write_dir")
@@ -128,6 +186,17 @@ def main(argv=None):
         for name, grid, calls, avg, mn, mx, pct in dbstats(a.dir, a.kernel, a.top):
             print(f"{name}\n    grid {grid}  calls {calls}  avg {avg / 1e3:.3f} us  min {mn / 1e3:.3f}  "
                   f"max {mx / 1e3:.3f}  share {pct:.2f} %")
+        return
+    if a.cmd == "counters":
+        n, m = counters(a.dir, a.kernel)
+        lines = ([f"command: {a.command}"] if a.command else []) + [
+            f"kernel: {a.kernel}", f"stepper_source_sha256_16: {stepper_hash()}", f"dispatches: {n}",
+            "medians over the dispatches:"] + [f"{k}: {v:.4g}" for k, v in m.items()]
+        text = "\n".join(lines) + "\n"
+        if a.out:
+            with open(a.out, "w") as fh:
+                fh.write(text)
+        sys.stdout.write(text)
         return
     r = traffic(a.fetch_dir, a.write_dir, a.kernel, a.ref_bytes)
     lines = [f"kernel: {a.kernel}",
