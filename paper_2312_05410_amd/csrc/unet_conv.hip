@@ -241,23 +241,45 @@ __global__ __launch_bounds__(256) void gemm32_kernel(ConvArgs a)
 #pragma unroll
         for (int j = 0; j < TN; ++j) B[j] = ld8(wt + (size_t)(16 * j) * a.ldk);
     };
-    // register double buffer: the loads of iteration it + 1 are in flight
-    // while the MFMAs of iteration it run
-    bf16x8 A[TM], B[TN];
-    load(0, A, B);
-    for (int it = 0; it < iters; ++it) {
-        bf16x8 An[TM], Bn[TN];
-        if (it + 1 < iters) load(it + 1, An, Bn);
+    if constexpr (MODE == kUpFwd || MODE == kFirst) {
+        // few K steps (the up-sampling's 2-8, the first layer's 2): the
+        // operands of GI steps are loaded back to back, so a block waits
+        // for one memory latency per group instead of one per step
+        constexpr int GI = TM + TN <= 4 ? 4 : 2;
+        for (int g0 = 0; g0 < iters; g0 += GI) {
+            bf16x8 A[GI][TM], B[GI][TN];
 #pragma unroll
-        for (int i = 0; i < TM; ++i)
+            for (int u = 0; u < GI; ++u)
+                if (g0 + u < iters) load(g0 + u, A[u], B[u]);
 #pragma unroll
-            for (int j = 0; j < TN; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[i], B[j], acc[i][j], 0, 0, 0);
-        if (it + 1 < iters) {
+            for (int u = 0; u < GI; ++u) {
+                if (g0 + u >= iters) break;
 #pragma unroll
-            for (int i = 0; i < TM; ++i) A[i] = An[i];
+                for (int i = 0; i < TM; ++i)
 #pragma unroll
-            for (int j = 0; j < TN; ++j) B[j] = Bn[j];
+                    for (int j = 0; j < TN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[u][i], B[u][j], acc[i][j], 0, 0, 0);
+            }
+        }
+    } else {
+        // register double buffer: the loads of iteration it + 1 are in flight
+        // while the MFMAs of iteration it run
+        bf16x8 A[TM], B[TN];
+        load(0, A, B);
+        for (int it = 0; it < iters; ++it) {
+            bf16x8 An[TM], Bn[TN];
+            if (it + 1 < iters) load(it + 1, An, Bn);
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[i], B[j], acc[i][j], 0, 0, 0);
+            if (it + 1 < iters) {
+#pragma unroll
+                for (int i = 0; i < TM; ++i) A[i] = An[i];
+#pragma unroll
+                for (int j = 0; j < TN; ++j) B[j] = Bn[j];
+            }
         }
     }
     // acc[i][j][e]: pixel pm + 16 i + 4 (lane / 16) + e, channel on + 16 j + r

@@ -307,6 +307,85 @@ __global__ __launch_bounds__(256) void gn_apply8_kernel(GNArgs a)
     }
 }
 
+// The same with the affine coefficients (the network forward): a thread
+// takes eight channels of four pixels (the 2x2 window of one pooled pixel,
+// or four consecutive pixels of one sample), loads the channels' A, B and
+// FiLM scale once and all four pixels' inputs before the arithmetic, which
+// is that of gn_apply8_kernel (bitwise equal results).
+__global__ __launch_bounds__(256) void gn_apply8x4_kernel(GNArgs a)
+{
+    const unsigned C8 = (unsigned)a.C / 8u;
+    const bool pool = a.pool_bf16 != nullptr;
+    const unsigned Ho = (unsigned)a.H / 2u, Wo = (unsigned)a.W / 2u;
+    const unsigned groups = pool ? (unsigned)a.N * Ho * Wo : (unsigned)a.N * ((unsigned)a.P / 4u);
+    const unsigned total = groups * C8;
+    for (unsigned it = blockIdx.x * 256u + threadIdx.x; it < total; it += gridDim.x * 256u) {
+        const unsigned q = it / C8;
+        const int c0 = (int)(it - q * C8) * 8;
+        int n;
+        size_t idx[4];
+        if (pool) {
+            const unsigned q2 = q / Wo;
+            const int xo = (int)(q - q2 * Wo);
+            const int yo = (int)(q2 % Ho);
+            n = (int)(q2 / Ho);
+#pragma unroll
+            for (int w = 0; w < 4; ++w)
+                idx[w] = (((size_t)n * a.H + 2 * yo + (w >> 1)) * a.W + 2 * xo + (w & 1)) * a.C + c0;
+        } else {
+            const unsigned per = (unsigned)a.P / 4u;
+            n = (int)(q / per);
+            const size_t p0 = (size_t)n * a.P + 4 * (size_t)(q - (unsigned)n * per);
+#pragma unroll
+            for (int w = 0; w < 4; ++w) idx[w] = (p0 + w) * a.C + c0;
+        }
+        float A[8], B[8], S[8], yv[4][8];
+        ld8f(a.coef + (size_t)n * a.C + c0, A);
+        ld8f(a.coef + (size_t)(a.N + n) * a.C + c0, B);
+        if (a.scale) ld8f(a.scale + (size_t)n * a.C + c0, S);
+#pragma unroll
+        for (int w = 0; w < 4; ++w) ld8f(a.y + idx[w], yv[w]);
+        float m[8];
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            float z[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const float av = fmaf(A[u], yv[w][u], B[u]);
+                z[u] = a.gelu ? gelu(av) : av;
+            }
+            const size_t i = idx[w];
+            if (a.z_f32) {
+                *(float4*)(a.z_f32 + i) = make_float4(z[0], z[1], z[2], z[3]);
+                *(float4*)(a.z_f32 + i + 4) = make_float4(z[4], z[5], z[6], z[7]);
+            }
+            if (a.z_bf16) *(uint4*)(a.z_bf16 + i) = pack8(z);
+            if (a.scale) {
+                float zs[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) zs[u] = z[u] * S[u];
+                if (a.zs_f32) {
+                    *(float4*)(a.zs_f32 + i) = make_float4(zs[0], zs[1], zs[2], zs[3]);
+                    *(float4*)(a.zs_f32 + i + 4) = make_float4(zs[4], zs[5], zs[6], zs[7]);
+                }
+                if (a.zs_bf16) *(uint4*)(a.zs_bf16 + i) = pack8(zs);
+            }
+            if (pool) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const float r = bf2f(f2bf(z[u]));
+                    m[u] = w ? fmaxf(m[u], r) : r;
+                }
+            }
+        }
+        if (pool) {
+            const unsigned q2 = q / Wo;
+            const int xo = (int)(q - q2 * Wo), yo = (int)(q2 % Ho);
+            *(uint4*)(a.pool_bf16 + (((size_t)n * Ho + yo) * Wo + xo) * a.C + c0) = pack8(m);
+        }
+    }
+}
+
 // Backward pass 1: per-(sample, chunk, channel) sums of g, g * xhat and
 // dB * z, where g = dL/da (a = gamma xhat + beta).
 struct BwdElem {
@@ -755,6 +834,9 @@ hipError_t gn_forward(const GNArgs& a_in, hipStream_t s)
     if (a.res_jump) {
         if (a.C != 3 || (a.G != 1 && a.G != 3)) return hipErrorInvalidValue;
         hipLaunchKernelGGL(gn_apply_res_kernel, dim3(grid_for((size_t)a.N * a.P)), dim3(256), 0, s, a);
+    } else if (vec && a.coef && (a.pool_bf16 || a.P % 4 == 0)) {
+        const size_t items = (size_t)a.N * a.P * (a.C / 8) / 4;
+        hipLaunchKernelGGL(gn_apply8x4_kernel, dim3(grid_for(items)), dim3(256), 0, s, a);
     } else if (vec) {
         const size_t items = (size_t)a.N * a.P * (a.C / 8) / (a.pool_bf16 ? 4 : 1);
         hipLaunchKernelGGL(gn_apply8_kernel, dim3(grid_for(items)), dim3(256), 0, s, a);
