@@ -456,7 +456,7 @@ MLPArgs mlp_args(unet_handle* h, int n, const float* jump)
 // Convolution whose output feeds a group normalisation: the wide kernel's
 // epilogue writes the normalisation's partial sums when a sample's pixels
 // split evenly into its blocks.
-int conv_gn(unet_handle* h, ConvArgs a, int mode, GNArgs g)
+int conv_gn(unet_handle* h, ConvArgs a, int mode, GNArgs g, const MLPArgs* mlp = nullptr, float* jump_copy = nullptr)
 {
     const int chunks = conv_stat_chunks(a, mode);
     if (chunks > 0) {
@@ -465,7 +465,7 @@ int conv_gn(unet_handle* h, ConvArgs a, int mode, GNArgs g)
         g.chunks = chunks;
     }
     UCHECK(conv_gemm(a, mode, h->stream));
-    UCHECK(gn_forward(g, h->stream));
+    UCHECK(gn_forward(g, h->stream, mlp, jump_copy));
     return PF_OK;
 }
 
@@ -487,15 +487,26 @@ int forward(unet_handle* h, int n, const float* jump, const float* c, const floa
     auto Hl = [&](int l) { return net.c.height >> l; };
     auto Wl = [&](int l) { return net.c.width >> l; };
     const long P0 = net.P(0, 1);
-    // input assembly, time basis and FiLM scales in one launch, which also
-    // keeps a copy of the jumps (read by the head's normalisation and the
-    // backward pass)
-    UCHECK(prologue_forward(mlp_args(h, n, jump), c, phi, rho, b.xin, (int)P0, b.jump, s));
+    const MLPArgs mlp = mlp_args(h, n, jump);
+    // inference: the first layer gathers its input from the state fields and
+    // its normalisation launch also evaluates the time basis and the FiLM
+    // scales (and copies the jumps); training keeps the assembled input for
+    // the weight gradient, so input assembly, time basis and FiLM scales run
+    // as one launch first.  Both copy the jumps, which the head's
+    // normalisation and the backward pass read.
+    const bool fused = !train && mlp_fused_ok(mlp);
+    if (!fused) UCHECK(prologue_forward(mlp, c, phi, rho, b.xin, (int)P0, b.jump, s));
     // encoder: z_l = block(down(z_{l-1})), zs_l = z_l * (w_l f(dt)); the
     // normalisation kernel also pools z_l for the next level
     for (int l = 0; l < L; ++l) {
         const Conv& k = net.enc[l];
-        ConvArgs a = conv_args(k, n, Hl(l), Wl(l), l ? b.q[l - 1] : b.xin, nullptr);
+        ConvArgs a = conv_args(k, n, Hl(l), Wl(l), l ? b.q[l - 1] : fused ? nullptr : b.xin, nullptr);
+        if (!l && fused) {
+            a.raw[0] = c;
+            a.raw[1] = phi;
+            a.raw[2] = rho;
+            a.jump = jump;
+        }
         a.out_f32 = b.y[l];
         GNArgs g = gn_args(h, k, n, net.P(l, 1), b.y[l], b.st[l]);
         g.scale = b.sc[l];
@@ -504,7 +515,7 @@ int forward(unet_handle* h, int n, const float* jump, const float* c, const floa
         g.pool_bf16 = l < L - 1 ? b.q[l] : nullptr;
         g.H = Hl(l);
         g.W = Wl(l);
-        RCHECK(conv_gn(h, a, l ? kConvFwd : kFirst, g));
+        RCHECK(conv_gn(h, a, l ? kConvFwd : kFirst, g, !l && fused ? &mlp : nullptr, b.jump));
     }
     // bottom block
     {

@@ -42,6 +42,11 @@ __device__ __forceinline__ uint16_t f2bf(float f)
     return (uint16_t)(u >> 16);
 }
 
+// 16-byte non-temporal store (streamed past the caches: the data are read
+// back by a later kernel, not by this one)
+typedef unsigned int u32x4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void st16nt(void* p, uint4 v) { __builtin_nontemporal_store(__builtin_bit_cast(u32x4v, v), (u32x4v*)p); }
+
 struct Pix {
     int n, y, x;
     bool ok;
@@ -141,11 +146,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(ConvArgs a)
                     const int Co = a.Nout >> 2, sub = o / Co, co = o - sub * Co;
                     const size_t idx =
                         (((size_t)q.n * 2 * a.H + 2 * q.y + (sub >> 1)) * 2 * a.W + 2 * q.x + (sub & 1)) * Co + co;
-                    if (a.out_f32) a.out_f32[idx] = v;
+                    if (a.out_f32) __builtin_nontemporal_store(v, a.out_f32 + idx);
                     if (a.out_bf16) a.out_bf16[idx] = f2bf(v);
                 } else if (o < a.O1) {
                     const size_t idx = (size_t)p * a.O1 + o;
-                    if (a.out_f32) a.out_f32[idx] = v;
+                    if (a.out_f32) __builtin_nontemporal_store(v, a.out_f32 + idx);
                     if (a.out_bf16) a.out_bf16[idx] = f2bf(v);
                 } else {
                     const size_t idx = (size_t)p * (a.Nout - a.O1) + (o - a.O1);
@@ -189,6 +194,42 @@ __global__ __launch_bounds__(256) void gemm32_kernel(ConvArgs a)
     const int nk = (K + 31) / 32;  // K chunks per tap
     const int iters = ntaps * nk;
     const uint16_t* wlane = a.Wt + (size_t)(on + r) * a.ldk + kq;
+    // kFirst from the state fields, where a block's BM pixels lie in one row
+    // (W a multiple of BM): the three rows y - 1, y, y + 1 over columns
+    // x0 - 1 .. x0 + BM are staged once in LDS as the assembled 4-channel
+    // BF16 input (each pixel loaded once, coalesced, every load issued before
+    // the first is used; indices clamped into the grid, and taps outside it
+    // zeroed when the operands are gathered from LDS)
+    constexpr int BMr = WGM * TM * 16, kSW = BMr + 2, kStageIt = (3 * kSW + 255) / 256;
+    [[maybe_unused]] const uint2* xs = nullptr;
+    [[maybe_unused]] int xs_x0 = 0;
+    if constexpr (MODE == kFirst) {
+        __shared__ uint2 xst[kStageIt * 256];
+        if (a.raw[0] && a.W % BMr == 0) {
+            const int pb = blockIdx.x * BMr, row = pb / a.W, n0 = row / a.H, y0 = row - n0 * a.H;
+            xs_x0 = pb - row * a.W;
+            const float jv = a.jump[n0];
+            float v[kStageIt][3];
+#pragma unroll
+            for (int u = 0; u < kStageIt; ++u) {
+                const int e = threadIdx.x + 256 * u, sr = e / kSW, sc = e - sr * kSW;
+                const int yy = min(max(y0 - 1 + sr, 0), a.H - 1), xx = min(max(xs_x0 - 1 + sc, 0), a.W - 1);
+                const long q = ((long)n0 * a.H + yy) * a.W + xx;
+                v[u][0] = a.raw[0][q];
+                v[u][1] = a.raw[1][q];
+                v[u][2] = a.raw[2][q];
+            }
+            const uint32_t jb = (uint32_t)f2bf(jv) << 16;
+#pragma unroll
+            for (int u = 0; u < kStageIt; ++u) {
+                const uint32_t lo = (uint32_t)f2bf(v[u][0] - 0.5f) | ((uint32_t)f2bf(v[u][1]) << 16);
+                const uint32_t hi = (uint32_t)f2bf(v[u][2] - 1.0f) | jb;
+                xst[threadIdx.x + 256 * u] = make_uint2(lo, hi);
+            }
+            __syncthreads();
+            xs = xst;
+        }
+    }
     // operands of iteration `it` (tap it / nk, channels 32 (it % nk) ..) in
     // the MFMA lane layout; zero outside the grid
     auto load = [&](int it, bf16x8* A, bf16x8* B) {
@@ -203,7 +244,46 @@ __global__ __launch_bounds__(256) void gemm32_kernel(ConvArgs a)
             }
         }
         const bf16x8 zero = __builtin_bit_cast(bf16x8, make_uint4(0, 0, 0, 0));
-        if (MODE == kFirst) {
+        if (MODE == kFirst && xs) {
+            // from the staged rows: tap (dy, dx) of column x is row dy + 1,
+            // column x - x0 + 1 + dx of the stage
+            const int t0 = (k0 + kq) >> 2;
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                uint2 h[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int t = t0 + u, tc = t < 9 ? t : 8;
+                    const int dy = tc / 3 - 1, dx = tc % 3 - 1, yy = px[i].y + dy, xx = px[i].x + dx;
+                    const bool ok = px[i].ok && t < 9 && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
+                    const int e = (dy + 1) * kSW + px[i].x - xs_x0 + 1 + dx;
+                    const uint2 g = xs[min(max(e, 0), 3 * kSW - 1)];
+                    h[u] = ok ? g : make_uint2(0, 0);
+                }
+                A[i] = __builtin_bit_cast(bf16x8, make_uint4(h[0].x, h[0].y, h[1].x, h[1].y));
+            }
+        } else if (MODE == kFirst && a.raw[0]) {
+            // the same operand assembled from the state fields: indices are
+            // clamped into the grid so that every load is issued
+            // unconditionally, and taps outside it are zeroed afterwards
+            const int t0 = (k0 + kq) >> 2;
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                uint2 h[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int t = t0 + u, tc = t < 9 ? t : 8;
+                    const int yy = px[i].y + tc / 3 - 1, xx = px[i].x + tc % 3 - 1;
+                    const bool ok = px[i].ok && t < 9 && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
+                    const long q = ((long)px[i].n * a.H + min(max(yy, 0), a.H - 1)) * a.W + min(max(xx, 0), a.W - 1);
+                    const float cv = a.raw[0][q], pv = a.raw[1][q], rv = a.raw[2][q], jv = a.jump[px[i].n];
+                    const uint32_t lo = (uint32_t)f2bf(cv - 0.5f) | ((uint32_t)f2bf(pv) << 16);
+                    const uint32_t hi = (uint32_t)f2bf(rv - 1.0f) | ((uint32_t)f2bf(jv) << 16);
+                    h[u] = ok ? make_uint2(lo, hi) : make_uint2(0, 0);
+                }
+                A[i] = __builtin_bit_cast(bf16x8, make_uint4(h[0].x, h[0].y, h[1].x, h[1].y));
+            }
+        } else if (MODE == kFirst) {
             // k = 4 tap + c: this lane's 8 values are taps t0 and t0 + 1
             const int t0 = (k0 + kq) >> 2;
 #pragma unroll
@@ -310,7 +390,7 @@ __global__ __launch_bounds__(256) void gemm32_kernel(ConvArgs a)
                 const unsigned sub = (unsigned)o / Co, co = (unsigned)o - sub * Co;
                 const unsigned dst = ((((unsigned)t.n * 2u * (unsigned)a.H + 2u * (unsigned)t.y + (sub >> 1)) * W2 +
                                        2u * (unsigned)t.x + (sub & 1)) * Co + co);
-                *(uint4*)(a.out_bf16 + dst) = *(const uint4*)(&stg[p * LP + 8 * q]);
+                st16nt(a.out_bf16 + dst, *(const uint4*)(&stg[p * LP + 8 * q]));
             }
             return;
         }
@@ -350,34 +430,58 @@ __global__ __launch_bounds__(256) void gemm32_kernel(ConvArgs a)
                     if (on + 16 * j + r >= a.Nout) continue;
                     const unsigned idx = row + offj[j];
                     const float v = acc[i][j][e];
-                    if (a.out_f32) a.out_f32[idx] = v;
+                    if (a.out_f32) __builtin_nontemporal_store(v, a.out_f32 + idx);
                     if (a.out_bf16) a.out_bf16[idx] = f2bf(v);
                 }
             }
         }
         return;
     }
-#pragma unroll
-    for (int j = 0; j < TN; ++j) {
-        const int o = on + 16 * j + r;
-        if (o >= a.Nout) continue;
+    constexpr int BM = WGM * TM * 16, BN = WGN * TN * 16;
+    if ((MODE == kFirst || MODE == kConvFwd) && a.out_f32 && !a.out_bf16 && a.O1 == a.Nout && a.Nout == BN) {
+        // the block holds every output channel of its BM consecutive pixels,
+        // so its FP32 output is one contiguous run: staged through LDS as
+        // [pixel][channel] and written back as 16-byte pieces in order
+        constexpr int LPF = BN + 4;   // 4 lane groups land 16 banks apart
+        __shared__ __align__(16) float stf[BM * LPF];
+        const int pl = (wv % WGM) * TM * 16, ol = (wv / WGM) * TN * 16;
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int p = pm + 16 * i + rq + e;
-                if (p >= P) continue;
-                const float v = acc[i][j][e];
-                if (o < a.O1) {
-                    const size_t idx = (size_t)p * a.O1 + o;
-                    if (a.out_f32) a.out_f32[idx] = v;
-                    if (a.out_bf16) a.out_bf16[idx] = f2bf(v);
-                } else {
-                    const size_t idx = (size_t)p * (a.Nout - a.O1) + (o - a.O1);
-                    if (a.out2_f32) a.out2_f32[idx] = v;
-                    if (a.out2_bf16) a.out2_bf16[idx] = f2bf(v);
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) stf[(pl + 16 * i + rq + e) * LPF + ol + 16 * j + r] = acc[i][j][e];
+        __syncthreads();
+        const int pb = blockIdx.x * BM;
+        for (int idx = threadIdx.x; idx < BM * (BN / 4); idx += 256) {
+            const int p = idx / (BN / 4), q = idx - p * (BN / 4);
+            if (pb + p >= P) break;
+            const f32x4 v = *(const f32x4*)(&stf[p * LPF + 4 * q]);
+            __builtin_nontemporal_store(v, (f32x4*)(a.out_f32 + (size_t)(pb + p) * BN + 4 * q));
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const int o = on + 16 * j + r;
+            if (o >= a.Nout) continue;
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int p = pm + 16 * i + rq + e;
+                    if (p >= P) continue;
+                    const float v = acc[i][j][e];
+                    if (o < a.O1) {
+                        const size_t idx = (size_t)p * a.O1 + o;
+                        if (a.out_f32) __builtin_nontemporal_store(v, a.out_f32 + idx);
+                        if (a.out_bf16) a.out_bf16[idx] = f2bf(v);
+                    } else {
+                        const size_t idx = (size_t)p * (a.Nout - a.O1) + (o - a.O1);
+                        if (a.out2_f32) a.out2_f32[idx] = v;
+                        if (a.out2_bf16) a.out2_bf16[idx] = f2bf(v);
+                    }
                 }
-            }
+        }
     }
     if ((MODE == kConvFwd || MODE == kFirst) && a.gsum) {
         // per-channel sum and sum of squares over the block's pixels (all in
@@ -535,34 +639,69 @@ __global__ __launch_bounds__(256) void conv3_lds_kernel(ConvArgs a)
         }
     }
     __syncthreads();   // LDS is reused by the epilogue's reduction
-    // acc[i][j][e]: pixel (ry[i], segment base + 4 (lane / 16) + e), channel on + 16 j + r
+    // acc[i][j][e]: pixel (ry[i], segment base + 4 (lane / 16) + e), channel on + 16 j + r.
+    // FP32 outputs are written with non-temporal stores: a later kernel
+    // reads them, and streamed lines cost less at the end of this one
+    // (measured: the decoder's 512^2 layer 23 against 27 us)
     const int rq = (lane >> 4) * 4;
     float s1[TN], s2[TN];
 #pragma unroll
     for (int j = 0; j < TN; ++j) s1[j] = s2[j] = 0.f;
+    static_assert(TH * TW * TN * 16 * 4 <= (int)sizeof(lds), "the staged output tile fits in LDS");
+    if (MODE == kConvFwd && a.out_f32 && !a.out_bf16 && a.O1 == a.Nout && a.Nout <= TN * 16 && on == 0 &&
+        a.W % TW == 0 && (TW * a.Nout) % 4 == 0) {
+        // the block holds every output channel of its tile, so each tile row
+        // of its FP32 output is one contiguous run of TW Nout values: staged
+        // through LDS in memory order and written back as 16-byte pieces
+        float* stg = (float*)&lds[0];
 #pragma unroll
-    for (int j = 0; j < TN; ++j) {
-        const int o = on + 16 * j + r;
+        for (int j = 0; j < TN; ++j) {
+            const int o = 16 * j + r;
 #pragma unroll
-        for (int i = 0; i < TM; ++i)
+            for (int i = 0; i < TM; ++i)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int y = y0 + ry[i], x = x0 + (i % SEG) * 16 + rq + e;
-                if (o >= a.Nout || y >= a.H || x >= a.W) continue;
-                const float v = acc[i][j][e];
-                s1[j] += v;
-                s2[j] = fmaf(v, v, s2[j]);
-                const size_t p = ((size_t)n * a.H + y) * a.W + x;
-                if (o < a.O1) {
-                    const size_t idx = p * a.O1 + o;
-                    if (a.out_f32) a.out_f32[idx] = v;
-                    if (a.out_bf16) a.out_bf16[idx] = f2bf(v);
-                } else {
-                    const size_t idx = p * (a.Nout - a.O1) + (o - a.O1);
-                    if (a.out2_f32) a.out2_f32[idx] = v;
-                    if (a.out2_bf16) a.out2_bf16[idx] = f2bf(v);
+                for (int e = 0; e < 4; ++e) {
+                    if (o >= a.Nout || y0 + ry[i] >= a.H) continue;
+                    const float v = acc[i][j][e];
+                    s1[j] += v;
+                    s2[j] = fmaf(v, v, s2[j]);
+                    stg[(ry[i] * TW + (i % SEG) * 16 + rq + e) * a.Nout + o] = v;
                 }
-            }
+        }
+        __syncthreads();
+        const int rows = min(TH, a.H - y0), run4 = TW * a.Nout / 4;
+        for (int idx = tid; idx < rows * run4; idx += 256) {
+            const int yy = idx / run4, q = idx - yy * run4;
+            const f32x4 v = *(const f32x4*)(&stg[yy * TW * a.Nout + 4 * q]);
+            __builtin_nontemporal_store(
+                v, (f32x4*)(a.out_f32 + (((size_t)n * a.H + y0 + yy) * a.W + x0) * a.Nout + 4 * q));
+        }
+        __syncthreads();   // the reduction below reuses LDS
+    } else {
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const int o = on + 16 * j + r;
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int y = y0 + ry[i], x = x0 + (i % SEG) * 16 + rq + e;
+                    if (o >= a.Nout || y >= a.H || x >= a.W) continue;
+                    const float v = acc[i][j][e];
+                    s1[j] += v;
+                    s2[j] = fmaf(v, v, s2[j]);
+                    const size_t p = ((size_t)n * a.H + y) * a.W + x;
+                    if (o < a.O1) {
+                        const size_t idx = p * a.O1 + o;
+                        if (a.out_f32) __builtin_nontemporal_store(v, a.out_f32 + idx);
+                        if (a.out_bf16) a.out_bf16[idx] = f2bf(v);
+                    } else {
+                        const size_t idx = p * (a.Nout - a.O1) + (o - a.O1);
+                        if (a.out2_f32) a.out2_f32[idx] = v;
+                        if (a.out2_bf16) a.out2_bf16[idx] = f2bf(v);
+                    }
+                }
+        }
     }
     if (MODE == kConvFwd && a.gsum) {
         // per-channel sums over the tile: the 4 lane groups, then the 4 waves
@@ -970,7 +1109,8 @@ bool conv_wide_ok(const ConvArgs& a, int mode)
 {
     const auto al = [](const void* p, uintptr_t b) { return ((uintptr_t)p & (b - 1)) == 0; };
     if (mode == kFirst)
-        return a.C1 == 4 && a.C2 == 0 && a.ldk == 64 && a.ldo % 128 == 0 && al(a.in1, 8) && al(a.Wt, 16);
+        return a.C1 == 4 && a.C2 == 0 && a.ldk == 64 && a.ldo % 128 == 0 &&
+               (a.raw[0] ? a.raw[1] && a.raw[2] && a.jump : al(a.in1, 8)) && al(a.Wt, 16);
     const bool chans = mode == kUpDgrad ? (a.C1 % 128 == 0 && a.C2 == 0) : (a.C1 % 32 == 0 && a.C2 % 32 == 0);
     return chans && a.ldk % 32 == 0 && a.ldo % 128 == 0 && al(a.in1, 16) && (!a.in2 || al(a.in2, 16)) &&
            al(a.Wt, 16);

@@ -36,6 +36,10 @@ struct ConvArgs {
     // normalisation, [N][Nout][conv_stat_chunks()][2] = (sum, sum of
     // squares); only when conv_stat_chunks() > 0
     float* gsum;
+    // kFirst only, or null: gather the network input straight from the state
+    // fields, x = BF16 (c - 1/2, phi, rho - 1, jump[n]) (in1 unused)
+    const float* raw[3];
+    const float* jump;
 };
 
 struct WgradArgs {
@@ -112,7 +116,10 @@ struct GNArgs {
     const float* res_in[3];
     float* res_out[3];
 };
-hipError_t gn_forward(const GNArgs& a, hipStream_t s);
+// mlp (or null): the same launch also evaluates the time basis and every
+// level's FiLM scales (mlp_fused_ok must hold) and copies the jumps to
+// jump_copy (or not, if null)
+hipError_t gn_forward(const GNArgs& a, hipStream_t s, const struct MLPArgs* mlp = nullptr, float* jump_copy = nullptr);
 hipError_t gn_backward(const GNArgs& a, hipStream_t s);
 size_t gn_csum_floats(int N, int P, int C);
 int gn_chunks(int P);
@@ -153,6 +160,9 @@ struct MLPArgs {
 hipError_t prologue_forward(const MLPArgs& a, const float* c, const float* phi, const float* rho, uint16_t* x, int P,
                             float* jump_copy, hipStream_t s);
 hipError_t mlp_backward(const MLPArgs& a, hipStream_t s);
+// True when gn_forward can take the MLP (widths up to 128, FiLM rows up to
+// 256 per level).
+bool mlp_fused_ok(const MLPArgs& a);
 
 // Relative MSE per field: L = sum_f sum (pred - tgt)^2 / sum tgt^2.
 // Writes dL/dhead = jump[n] dL/dpred as [N][P][3] (NHWC, the head's layout)

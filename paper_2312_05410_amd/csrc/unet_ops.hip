@@ -14,6 +14,11 @@
 namespace pfu {
 namespace {
 
+// 16-byte non-temporal store (streamed past the caches: the data are read
+// back by a later kernel, not by this one)
+typedef unsigned int u32x4v __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void st16nt(void* p, uint4 v) { __builtin_nontemporal_store(__builtin_bit_cast(u32x4v, v), (u32x4v*)p); }
+
 __device__ __forceinline__ float bf2f(uint16_t v) { return __builtin_bit_cast(float, (uint32_t)v << 16); }
 
 __device__ __forceinline__ uint16_t f2bf(float f)
@@ -45,6 +50,58 @@ __device__ __forceinline__ float gelu_grad(float a)
 // Threads of a reduction block: the largest multiple of C not above 256, so
 // every thread keeps one channel.
 __device__ __forceinline__ int red_threads(int C) { return (256 / C) * C; }
+
+// Sums over the 32 lanes of each half wave with data-parallel-primitive
+// moves (swap adjacent lanes, then pairs, then the two quads of each 8, the
+// two 8s of each 16) and one swizzle between the two 16s: every step adds a
+// partner that holds the same partial sum's counterpart, so after each step
+// all lanes of the group hold the same value (addition commutes exactly)
+// and no LDS permute round trip is waited for.
+template <int CTRL>
+__device__ __forceinline__ int dpp(int v)
+{
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ float dppf(float v)
+{
+    return __builtin_bit_cast(float, dpp<CTRL>(__builtin_bit_cast(int, v)));
+}
+template <int CTRL>
+__device__ __forceinline__ double dppd(double v)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)dpp<CTRL>((int)(unsigned)b), hi = (unsigned)dpp<CTRL>((int)(unsigned)(b >> 32));
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ float swz16f(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_ds_swizzle(__builtin_bit_cast(int, v), 0x401F));
+}
+__device__ __forceinline__ double swz16d(double v)
+{
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = (unsigned)__builtin_amdgcn_ds_swizzle((int)(unsigned)b, 0x401F);
+    const unsigned hi = (unsigned)__builtin_amdgcn_ds_swizzle((int)(unsigned)(b >> 32), 0x401F);
+    return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+constexpr int kXor1 = 0xB1, kXor2 = 0x4E, kHalfMirror = 0x141, kMirror = 0x140;
+__device__ __forceinline__ float sum32(float v)
+{
+    v += dppf<kXor1>(v);
+    v += dppf<kXor2>(v);
+    v += dppf<kHalfMirror>(v);
+    v += dppf<kMirror>(v);
+    return v + swz16f(v);
+}
+__device__ __forceinline__ double sum32(double v)
+{
+    v += dppd<kXor1>(v);
+    v += dppd<kXor2>(v);
+    v += dppd<kHalfMirror>(v);
+    v += dppd<kMirror>(v);
+    return v + swz16d(v);
+}
 
 // pixels per reduction chunk: a multiple of 64, at most 256 chunks per sample
 int chunk_px(int P)
@@ -104,9 +161,9 @@ __device__ __forceinline__ void block_sum(double (*sh)[256], double* v)
 // cover the 4096 partial pairs of a 4-channel group over 1024 tiles), then
 // a fixed shuffle tree per wave and the 16 waves in order
 constexpr int kFinThreads = 1024;
-__global__ __launch_bounds__(kFinThreads) void gn_stats_finish(GNArgs a)
+__device__ __forceinline__ void finish_group(const GNArgs& a, int i)
 {
-    const int i = blockIdx.x, n = i / a.G, g = i % a.G, Cg = a.C / a.G;
+    const int n = i / a.G, g = i % a.G, Cg = a.C / a.G;
     double v[2] = {0.0, 0.0};
     // the group's channels are contiguous: [n][g Cg .. (g+1) Cg)[chunks][2]
     const float2* o = (const float2*)a.csum + ((size_t)n * a.C + g * Cg) * a.chunks;
@@ -128,19 +185,19 @@ __global__ __launch_bounds__(kFinThreads) void gn_stats_finish(GNArgs a)
         v[1] += q.y;
     }
     {
-        __shared__ double shw[2][kFinThreads / 64];
-        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        // half-wave sums, then the 32 of them in order
+        __shared__ double shw[2][kFinThreads / 32];
+        const int hw = threadIdx.x >> 5;
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) v[q] += __shfl_xor(v[q], off, 64);
-            if (lane == 0) shw[q][wv] = v[q];
+            v[q] = sum32(v[q]);
+            if ((threadIdx.x & 31) == 0) shw[q][hw] = v[q];
         }
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             double t = 0.0;
-            for (int w = 0; w < kFinThreads / 64; ++w) t += shw[q][w];
+            for (int w = 0; w < kFinThreads / 32; ++w) t += shw[q][w];
             v[q] = t;
         }
     }
@@ -162,6 +219,8 @@ __global__ __launch_bounds__(kFinThreads) void gn_stats_finish(GNArgs a)
         a.coef[(size_t)(a.N + n) * a.C + c] = fmaf(-A, ms[0], a.beta[c]);
     }
 }
+
+__global__ __launch_bounds__(kFinThreads) void gn_stats_finish(GNArgs a) { finish_group(a, blockIdx.x); }
 
 __global__ __launch_bounds__(256) void gn_apply_kernel(GNArgs a)
 {
@@ -359,7 +418,7 @@ __global__ __launch_bounds__(256) void gn_apply8x4_kernel(GNArgs a)
                 *(float4*)(a.z_f32 + i) = make_float4(z[0], z[1], z[2], z[3]);
                 *(float4*)(a.z_f32 + i + 4) = make_float4(z[4], z[5], z[6], z[7]);
             }
-            if (a.z_bf16) *(uint4*)(a.z_bf16 + i) = pack8(z);
+            if (a.z_bf16) st16nt(a.z_bf16 + i, pack8(z));
             if (a.scale) {
                 float zs[8];
 #pragma unroll
@@ -368,7 +427,7 @@ __global__ __launch_bounds__(256) void gn_apply8x4_kernel(GNArgs a)
                     *(float4*)(a.zs_f32 + i) = make_float4(zs[0], zs[1], zs[2], zs[3]);
                     *(float4*)(a.zs_f32 + i + 4) = make_float4(zs[4], zs[5], zs[6], zs[7]);
                 }
-                if (a.zs_bf16) *(uint4*)(a.zs_bf16 + i) = pack8(zs);
+                if (a.zs_bf16) st16nt(a.zs_bf16 + i, pack8(zs));
             }
             if (pool) {
 #pragma unroll
@@ -381,7 +440,7 @@ __global__ __launch_bounds__(256) void gn_apply8x4_kernel(GNArgs a)
         if (pool) {
             const unsigned q2 = q / Wo;
             const int xo = (int)(q - q2 * Wo), yo = (int)(q2 % Ho);
-            *(uint4*)(a.pool_bf16 + (((size_t)n * Ho + yo) * Wo + xo) * a.C + c0) = pack8(m);
+            st16nt(a.pool_bf16 + (((size_t)n * Ho + yo) * Wo + xo) * a.C + c0, pack8(m));
         }
     }
 }
@@ -569,6 +628,93 @@ __device__ __forceinline__ float row_dot(const float* W, const float* x, int len
 
 
 
+// One (sample n, level l) block of kMlpThreads threads: the time basis
+// f = W2 sin(W1 sin(W0 t + b0) + b1) + b2 of sample n (level 0 keeps h0,
+// h1 and f for the backward pass), then the FiLM scales s_l = Wl f, for the
+// usual widths (Hd, F <= 128, C_l <= 256).
+__device__ void mlp_block(const MLPArgs& a, int n, int l)
+{
+    // every weight the block reads is loaded into registers at once, so
+    // the chain of three products waits for one round of loads instead of
+    // one per product; 32 lanes per row (lane
+    // k holds columns k, k + 32, ..; each load instruction of a wave
+    // reads two whole 128-byte row segments), rows j0 + 32 m
+    __shared__ float a0[128], a1[128], fs[128];
+    const int tid = threadIdx.x, j0 = tid >> 5, k = tid & 31;
+    const int Hd = a.Hd, F = a.F, Cl = a.C[l];
+    const bool keep = l == 0;
+    // element (r, i) of a rows x len matrix, the indices clamped into
+    // it: the loads are unconditional, so no branch separates them and
+    // all are in flight together (a clamped column meets a zero of the
+    // zero-padded vector, a clamped row's result is not stored)
+    auto ld = [](const float* W, int r, int rows, int i, int len) {
+        return W[(r < rows ? r : rows - 1) * len + (i < len ? i : len - 1)];
+    };
+    float w1[4][4], w2[4][4], wl[8][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int i = k + 32 * u;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            w1[m][u] = ld(a.W1, j0 + 32 * m, Hd, i, Hd);
+            w2[m][u] = ld(a.W2, j0 + 32 * m, F, i, Hd);
+        }
+#pragma unroll
+        for (int m = 0; m < 8; ++m) wl[m][u] = ld(a.Wl[l], j0 + 32 * m, Cl, i, F);
+    }
+    float bj1[4], bj2[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        bj1[m] = ld(a.b1, j0 + 32 * m, Hd, 0, 1);
+        bj2[m] = ld(a.b2, j0 + 32 * m, F, 0, 1);
+    }
+    if (tid < 128) {
+        if (tid >= Hd) a0[tid] = a1[tid] = 0.f;
+        if (tid >= F) fs[tid] = 0.f;
+    }
+    const float t = a.jump[n];
+    if (tid < Hd) {
+        const float h = fmaf(a.W0[tid], t, a.b0[tid]);
+        if (keep) a.h0[n * Hd + tid] = h;
+        a0[tid] = sinf(h);
+    }
+    __syncthreads();
+    // row sum: this lane's columns in order, then the half-wave sum over
+    // the 32 lanes of the row
+    auto dot = [&](const float* w, const float* x) {
+        float v = 0.f;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v = fmaf(w[u], x[k + 32 * u], v);
+        return sum32(v);
+    };
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const int r = j0 + 32 * m;
+        const float h = dot(w1[m], a0) + bj1[m];
+        if (r < Hd && k == 0) {
+            if (keep) a.h1[n * Hd + r] = h;
+            a1[r] = sinf(h);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const int r = j0 + 32 * m;
+        const float v = dot(w2[m], a1) + bj2[m];
+        if (r < F && k == 0) {
+            if (keep) a.f[n * F + r] = v;
+            fs[r] = v;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+        const int r = j0 + 32 * m;
+        const float v = dot(wl[m], fs);
+        if (r < Cl && k == 0) a.sc[l][n * Cl + r] = v;
+    }
+}
+
 // The forward's prologue in one launch: blocks (n, l) < N L evaluate the
 // time basis f = W2 sin(W1 sin(W0 t + b0) + b1) + b2 of sample n (block (n, 0) keeps h0, h1, f for the
 // backward pass) and then the FiLM scales of level l, s_l = Wl f (8 lanes
@@ -583,6 +729,10 @@ __global__ __launch_bounds__(kMlpThreads) void prologue_kernel(MLPArgs a, const 
 {
     const int tid = threadIdx.x;
     const int mlp_blocks = a.N * a.L;
+    if ((int)blockIdx.x < mlp_blocks && a.Hd <= 128 && a.F <= 128 && a.C[blockIdx.x % a.L] <= 256) {
+        mlp_block(a, blockIdx.x / a.L, blockIdx.x % a.L);
+        return;
+    }
     if ((int)blockIdx.x < mlp_blocks) {
         __shared__ float a0[256], a1[256], fs[256];
         const int n = blockIdx.x / a.L, l = blockIdx.x % a.L, j = tid >> 2, k = tid & 3;
@@ -630,6 +780,21 @@ __global__ __launch_bounds__(kMlpThreads) void prologue_kernel(MLPArgs a, const 
         v.w = f2bf(a.jump[n]);
         *(ushort4*)(x + 4 * i) = v;
     }
+}
+
+// The normalisation statistics of the first layer (blocks below N G) with
+// the time basis and FiLM scales (the N L blocks after them, one per sample
+// and level) in one launch; the level-0 blocks also copy the jumps.
+__global__ __launch_bounds__(kFinThreads) void finish_mlp_kernel(GNArgs g, MLPArgs m, float* jump_copy)
+{
+    const int b = blockIdx.x, ng = g.N * g.G;
+    if (b < ng) {
+        finish_group(g, b);
+        return;
+    }
+    const int n = (b - ng) / m.L, l = (b - ng) % m.L;
+    if (jump_copy && l == 0 && threadIdx.x == 0) jump_copy[n] = m.jump[n];
+    mlp_block(m, n, l);
 }
 
 // Backward, per sample: df = sum_l Wl^T ds_l, dh1 = cos(h1) W2^T df,
@@ -818,9 +983,10 @@ int gn_chunks(int P) { return (P + chunk_px(P) - 1) / chunk_px(P); }
 
 size_t gn_csum_floats(int N, int P, int C) { return (size_t)N * gn_chunks(P) * C * 3; }
 
-hipError_t gn_forward(const GNArgs& a_in, hipStream_t s)
+hipError_t gn_forward(const GNArgs& a_in, hipStream_t s, const MLPArgs* mlp, float* jump_copy)
 {
     if (a_in.N <= 0 || a_in.P <= 0) return hipSuccess;
+    if (mlp && (!mlp_fused_ok(*mlp) || mlp->N != a_in.N)) return hipErrorInvalidValue;
     GNArgs a = a_in;
     const bool vec = a.C % 8 == 0 && ((uintptr_t)a.y & 15) == 0;
     if (a.pool_bf16 && (!vec || a.H % 2 || a.W % 2 || (long)a.H * a.W != a.P)) return hipErrorInvalidValue;
@@ -830,7 +996,11 @@ hipError_t gn_forward(const GNArgs& a_in, hipStream_t s)
         a.chunks = gn_chunks(a.P);
         hipLaunchKernelGGL(gn_stats_kernel, dim3(a.chunks, a.N), dim3(256), 0, s, a, chunk_px(a.P));
     }
-    hipLaunchKernelGGL(gn_stats_finish, dim3(a.N * a.G), dim3(kFinThreads), 0, s, a);
+    if (mlp)
+        hipLaunchKernelGGL(finish_mlp_kernel, dim3(a.N * a.G + a.N * mlp->L), dim3(kFinThreads), 0, s, a, *mlp,
+                           jump_copy);
+    else
+        hipLaunchKernelGGL(gn_stats_finish, dim3(a.N * a.G), dim3(kFinThreads), 0, s, a);
     if (a.res_jump) {
         if (a.C != 3 || (a.G != 1 && a.G != 3)) return hipErrorInvalidValue;
         hipLaunchKernelGGL(gn_apply_res_kernel, dim3(grid_for((size_t)a.N * a.P)), dim3(256), 0, s, a);
@@ -876,6 +1046,14 @@ hipError_t maxpool_bwd(const uint16_t* x, const float* dy, float* dx, int N, int
 }
 
 
+
+bool mlp_fused_ok(const MLPArgs& a)
+{
+    if (a.N <= 0 || a.L <= 0 || a.L > kMaxLevels || a.Hd < 1 || a.Hd > 128 || a.F < 1 || a.F > 128) return false;
+    for (int l = 0; l < a.L; ++l)
+        if (a.C[l] < 1 || a.C[l] > 256) return false;
+    return true;
+}
 
 hipError_t prologue_forward(const MLPArgs& a, const float* c, const float* phi, const float* rho, uint16_t* x, int P,
                             float* jump_copy, hipStream_t s)
