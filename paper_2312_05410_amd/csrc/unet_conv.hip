@@ -543,7 +543,7 @@ __global__ __launch_bounds__(256) void gemm32_kernel(ConvArgs a)
 // elements (80 or 144 bytes: 8 consecutive rows start 16 bytes apart modulo
 // 128, so the MFMA-layout reads are conflict-free)
 template <int MODE, int TN, int TH, int TW, int KC>
-__global__ __launch_bounds__(256) void conv3_lds_kernel(ConvArgs a)
+__global__ __launch_bounds__(256, 2) void conv3_lds_kernel(ConvArgs a)
 {
     constexpr int LP = KC + 8;              // BF16 elements per staged row
     constexpr int PPX = KC / 8;             // 16-byte pieces per staged row
@@ -579,33 +579,47 @@ __global__ __launch_bounds__(256) void conv3_lds_kernel(ConvArgs a)
     // piece e < NA: halo pixel e / PPX, channels 8 (e % PPX) ..; else weight
     // row (tap, o) = (e - NA) / PPX of the chunk, k = 8 ((e - NA) % PPX) ..
     uint4 stage[NLD];
+    // Both inputs have the same channel count (or there is one; the launcher
+    // checks), so every piece's source differs between chunks only by the
+    // chunk's channel offset, which goes into a uniform base pointer: the
+    // per-piece byte offsets (~0 for halo pixels outside the image and unused
+    // pieces) are computed once, and a chunk's loads take no index arithmetic.
+    uint32_t goff[NLD];
+#pragma unroll
+    for (int u = 0; u < NLD; ++u) {
+        const int e = tid + 256 * u;
+        goff[u] = ~0u;
+        if (e < NA) {
+            const int px = e / PPX, q = e % PPX;
+            const int gy = y0 - 1 + px / WP, gx = x0 - 1 + px % WP;
+            if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W)
+                goff[u] = 2u * (uint32_t)((((n * a.H + gy) * a.W + gx) * a.C1) + 8 * q);
+        } else if (e < NA + NB) {
+            const int row = (e - NA) / PPX, q = (e - NA) % PPX;
+            const int tap = row / (TN * 16), o = row - tap * (TN * 16);
+            goff[u] = 2u * (uint32_t)((tap * a.ldo + on + o) * a.ldk + 8 * q);
+        }
+    }
     auto gload = [&](int kc) {
         const int k0 = kc * KC;
-        const bool first = k0 < a.C1;
-        const uint16_t* src = first ? a.in1 : a.in2;
-        const int C = first ? a.C1 : a.C2, c0 = first ? k0 : k0 - a.C1;
+        const char* hb = (const char*)(k0 < a.C1 ? a.in1 + k0 : a.in2 + (k0 - a.C1));
+        const char* wb = (const char*)(a.Wt + k0);
 #pragma unroll
         for (int u = 0; u < NLD; ++u) {
             const int e = tid + 256 * u;
             uint4 v = make_uint4(0, 0, 0, 0);
-            if (e < NA) {
-                const int px = e / PPX, q = e % PPX;
-                const int gy = y0 - 1 + px / WP, gx = x0 - 1 + px % WP;
-                if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W)
-                    v = *(const uint4*)(src + (((long)n * a.H + gy) * a.W + gx) * C + c0 + 8 * q);
-            } else if (e < NA + NB) {
-                const int row = (e - NA) / PPX, q = (e - NA) % PPX;
-                const int tap = row / (TN * 16), o = row - tap * (TN * 16);
-                v = *(const uint4*)(a.Wt + ((size_t)tap * a.ldo + on + o) * a.ldk + k0 + 8 * q);
-            }
+            if (goff[u] != ~0u) v = *(const uint4*)((e < NA ? hb : wb) + goff[u]);
             stage[u] = v;
         }
     };
+    // piece e = tid + 256 u lands at row e / PPX, column 8 (e % PPX): 256 is
+    // a multiple of PPX, so that is this thread's first slot plus a constant
+    const int l0 = (tid / PPX) * LP + 8 * (tid % PPX);
     auto lstore = [&]() {
 #pragma unroll
         for (int u = 0; u < NLD; ++u) {
             const int e = tid + 256 * u;
-            if (e < NA + NB) *(uint4*)(&lds[(e / PPX) * LP + 8 * (e % PPX)]) = stage[u];
+            if (e < NA + NB) *(uint4*)(&lds[l0 + (256 / PPX) * LP * u]) = stage[u];
         }
     };
     gload(0);
@@ -675,6 +689,38 @@ __global__ __launch_bounds__(256) void conv3_lds_kernel(ConvArgs a)
             const f32x4 v = *(const f32x4*)(&stg[yy * TW * a.Nout + 4 * q]);
             __builtin_nontemporal_store(
                 v, (f32x4*)(a.out_f32 + (((size_t)n * a.H + y0 + yy) * a.W + x0) * a.Nout + 4 * q));
+        }
+        __syncthreads();   // the reduction below reuses LDS
+    } else if (MODE == kConvFwd && a.out_f32 && !a.out_bf16 && a.O1 == a.Nout && a.Nout % 4 == 0) {
+        // the block's channels [on, on + 16 TN) of each pixel are one 16-byte
+        // aligned run: staged through LDS as [pixel][channel] and written
+        // back as 16-byte pieces
+        constexpr int SP = TN * 16 + 4;   // 4 lane groups land 16 banks apart
+        static_assert(TH * TW * SP * 4 <= (int)sizeof(lds), "the staged output tile fits in LDS");
+        float* stg = (float*)&lds[0];
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const int o = on + 16 * j + r;
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int y = y0 + ry[i], x = x0 + (i % SEG) * 16 + rq + e;
+                    if (o >= a.Nout || y >= a.H || x >= a.W) continue;
+                    const float v = acc[i][j][e];
+                    s1[j] += v;
+                    s2[j] = fmaf(v, v, s2[j]);
+                    stg[(ry[i] * TW + (i % SEG) * 16 + rq + e) * SP + 16 * j + r] = v;
+                }
+        }
+        __syncthreads();
+        const int nq = min(TN * 16, a.Nout - on) / 4;   // 16-byte pieces per pixel
+        for (int idx = tid; idx < TH * TW * nq; idx += 256) {
+            const int pp = idx / nq, q = idx - pp * nq;
+            const int y = y0 + pp / TW, x = x0 + pp % TW;
+            if (y >= a.H || x >= a.W) continue;
+            const f32x4 v = *(const f32x4*)(&stg[pp * SP + 4 * q]);
+            __builtin_nontemporal_store(v, (f32x4*)(a.out_f32 + (((size_t)n * a.H + y) * a.W + x) * a.Nout + on + 4 * q));
         }
         __syncthreads();   // the reduction below reuses LDS
     } else {
@@ -1086,6 +1132,10 @@ int lds_tn(const ConvArgs& a)
 bool lds_ok(const ConvArgs& a, int mode)
 {
     if (mode != kConvFwd && mode != kConvDgrad) return false;
+    // per-piece offsets shared by both inputs, 32-bit byte offsets
+    if ((a.C2 != 0 && a.C2 != a.C1) || (long)a.N * a.H * a.W * a.C1 >= (1l << 30) ||
+        (long)9 * a.ldo * a.ldk >= (1l << 30))
+        return false;
     const long blocks = lds_tiles(a) * a.N * ((a.Nout + 16 * lds_tn(a) - 1) / (16 * lds_tn(a)));
     return blocks >= 256;
 }
