@@ -525,6 +525,17 @@ int forward(unet_handle* h, int n, const float* jump, const float* c, const floa
         g.z_bf16 = b.am;
         RCHECK(conv_gn(h, a, kConvFwd, g));
     }
+    // inference: the head convolution normalises the last decoder block's
+    // output as it loads it (a_0 is not written out)
+    ConvArgs head = conv_args(net.head, n, Hl(0), Wl(0), b.ad[0], nullptr);
+    if (!train) {
+        ConvArgs t = head;
+        t.in1 = nullptr;
+        t.gn_y = b.yd[0];
+        t.gn_coef = b.gcoef;
+        t.gn_gelu = net.dec[0].gelu;
+        if (conv_gn_input_ok(t)) head = t;
+    }
     for (int l = L - 2; l >= 0; --l) {
         // d_l = up(a_{l+1}); block(zs_l (+) d_l)
         const uint16_t* src = l + 1 == L - 1 ? b.am : b.ad[l + 1];
@@ -534,12 +545,12 @@ int forward(unet_handle* h, int n, const float* jump, const float* c, const floa
         ConvArgs a = conv_args(net.dec[l], n, Hl(l), Wl(l), b.zs[l], b.d[l]);
         a.out_f32 = b.yd[l];
         GNArgs g = gn_args(h, net.dec[l], n, net.P(l, 1), b.yd[l], b.std_[l]);
-        g.z_bf16 = b.ad[l];
+        g.z_bf16 = l == 0 && head.gn_y ? nullptr : b.ad[l];
         RCHECK(conv_gn(h, a, kConvFwd, g));
     }
     // head: GN(conv(a_0)) is the rate over the leap, u' = u + dt head
     {
-        ConvArgs a = conv_args(net.head, n, Hl(0), Wl(0), b.ad[0], nullptr);
+        ConvArgs a = head;
         a.out_f32 = b.yh;
         GNArgs g = gn_args(h, net.head, n, P0, b.yh, b.sth);
         g.res_jump = b.jump;  // the normalisation writes u + dt head directly

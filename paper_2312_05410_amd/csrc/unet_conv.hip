@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "unet_gelu.h"
 #include "unet_kernels.h"
 
 namespace pfu {
@@ -542,7 +543,10 @@ __global__ __launch_bounds__(256) void gemm32_kernel(ConvArgs a)
 // bound the small grids of the deep levels); staged rows of KC + 8 BF16
 // elements (80 or 144 bytes: 8 consecutive rows start 16 bytes apart modulo
 // 128, so the MFMA-layout reads are conflict-free)
-template <int MODE, int TN, int TH, int TW, int KC>
+// GNIN: the input is normalised as it is staged (see ConvArgs::gn_y): the
+// halo pieces are loaded as FP32, and each becomes 8 BF16 values with the
+// arithmetic of the normalisation kernel before it is stored in LDS
+template <int MODE, int TN, int TH, int TW, int KC, bool GNIN = false>
 __global__ __launch_bounds__(256, 2) void conv3_lds_kernel(ConvArgs a)
 {
     constexpr int LP = KC + 8;              // BF16 elements per staged row
@@ -593,23 +597,41 @@ __global__ __launch_bounds__(256, 2) void conv3_lds_kernel(ConvArgs a)
             const int px = e / PPX, q = e % PPX;
             const int gy = y0 - 1 + px / WP, gx = x0 - 1 + px % WP;
             if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W)
-                goff[u] = 2u * (uint32_t)((((n * a.H + gy) * a.W + gx) * a.C1) + 8 * q);
+                goff[u] = (GNIN ? 4u : 2u) * (uint32_t)((((n * a.H + gy) * a.W + gx) * a.C1) + 8 * q);
         } else if (e < NA + NB) {
             const int row = (e - NA) / PPX, q = (e - NA) % PPX;
             const int tap = row / (TN * 16), o = row - tap * (TN * 16);
             goff[u] = 2u * (uint32_t)((tap * a.ldo + on + o) * a.ldk + 8 * q);
         }
     }
+    // GNIN: the second 16 bytes of each halo piece, and this thread's 8
+    // channels' A and B (every piece of a thread has channels 8 (tid % PPX) ..)
+    [[maybe_unused]] uint4 stage2[GNIN ? NLD : 1];
+    [[maybe_unused]] float gA[GNIN ? 8 : 1], gB[GNIN ? 8 : 1];
     auto gload = [&](int kc) {
         const int k0 = kc * KC;
-        const char* hb = (const char*)(k0 < a.C1 ? a.in1 + k0 : a.in2 + (k0 - a.C1));
+        const char* hb = GNIN ? (const char*)(a.gn_y + k0)
+                              : (const char*)(k0 < a.C1 ? a.in1 + k0 : a.in2 + (k0 - a.C1));
         const char* wb = (const char*)(a.Wt + k0);
+        if constexpr (GNIN) {
+            const float* cf = a.gn_coef + (size_t)n * a.C1 + k0 + 8 * (tid % PPX);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                gA[i] = cf[i];
+                gB[i] = cf[(size_t)a.N * a.C1 + i];
+            }
+        }
 #pragma unroll
         for (int u = 0; u < NLD; ++u) {
             const int e = tid + 256 * u;
             uint4 v = make_uint4(0, 0, 0, 0);
             if (goff[u] != ~0u) v = *(const uint4*)((e < NA ? hb : wb) + goff[u]);
             stage[u] = v;
+            if constexpr (GNIN) {
+                uint4 v2 = make_uint4(0, 0, 0, 0);
+                if (e < NA && goff[u] != ~0u) v2 = *(const uint4*)(hb + goff[u] + 16);
+                stage2[u] = v2;
+            }
         }
     };
     // piece e = tid + 256 u lands at row e / PPX, column 8 (e % PPX): 256 is
@@ -619,7 +641,25 @@ __global__ __launch_bounds__(256, 2) void conv3_lds_kernel(ConvArgs a)
 #pragma unroll
         for (int u = 0; u < NLD; ++u) {
             const int e = tid + 256 * u;
-            if (e < NA + NB) *(uint4*)(&lds[l0 + (256 / PPX) * LP * u]) = stage[u];
+            uint4 v = stage[u];
+            if constexpr (GNIN) {
+                if (e < NA) {
+                    // z = act(A y + B) as the normalisation kernel forms it;
+                    // halo pixels outside the image stay zero
+                    const float y[8] = {__builtin_bit_cast(float, stage[u].x), __builtin_bit_cast(float, stage[u].y),
+                                        __builtin_bit_cast(float, stage[u].z), __builtin_bit_cast(float, stage[u].w),
+                                        __builtin_bit_cast(float, stage2[u].x), __builtin_bit_cast(float, stage2[u].y),
+                                        __builtin_bit_cast(float, stage2[u].z), __builtin_bit_cast(float, stage2[u].w)};
+                    uint32_t h[8];
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) {
+                        const float av = fmaf(gA[i], y[i], gB[i]);
+                        h[i] = goff[u] != ~0u ? f2bf(a.gn_gelu ? gelu(av) : av) : 0u;
+                    }
+                    v = make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
+                }
+            }
+            if (e < NA + NB) *(uint4*)(&lds[l0 + (256 / PPX) * LP * u]) = v;
         }
     };
     gload(0);
@@ -1148,6 +1188,13 @@ void launch_lds(const ConvArgs& a, hipStream_t s)
     // 64-channel chunks for the 16-channel blocks of the small grids (every
     // chunk inside one of the concatenated inputs)
     const bool kc64 = tn == 1 && a.C1 % 64 == 0 && a.C2 % 64 == 0 && a.ldk % 64 == 0;
+    if constexpr (MODE == kConvFwd) {
+        if (a.gn_y) {   // (32-channel chunks: the FP32 halo doubles the staging registers)
+            if (tn == 2) hipLaunchKernelGGL((conv3_lds_kernel<MODE, 2, kLdsTH, kLdsTW, 32, true>), grid, dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((conv3_lds_kernel<MODE, 1, kLdsTH, kLdsTW, 32, true>), grid, dim3(256), 0, s, a);
+            return;
+        }
+    }
     if (tn == 2) hipLaunchKernelGGL((conv3_lds_kernel<MODE, 2, kLdsTH, kLdsTW, 32>), grid, dim3(256), 0, s, a);
     else if (kc64) hipLaunchKernelGGL((conv3_lds_kernel<MODE, 1, kLdsTH, kLdsTW, 64>), grid, dim3(256), 0, s, a);
     else hipLaunchKernelGGL((conv3_lds_kernel<MODE, 1, kLdsTH, kLdsTW, 32>), grid, dim3(256), 0, s, a);
@@ -1164,6 +1211,12 @@ bool conv_wide_ok(const ConvArgs& a, int mode)
     const bool chans = mode == kUpDgrad ? (a.C1 % 128 == 0 && a.C2 == 0) : (a.C1 % 32 == 0 && a.C2 % 32 == 0);
     return chans && a.ldk % 32 == 0 && a.ldo % 128 == 0 && al(a.in1, 16) && (!a.in2 || al(a.in2, 16)) &&
            al(a.Wt, 16);
+}
+
+bool conv_gn_input_ok(const ConvArgs& a)
+{
+    return a.C2 == 0 && a.gn_y && a.gn_coef && ((uintptr_t)a.gn_y & 15) == 0 && conv_wide_ok(a, kConvFwd) &&
+           lds_ok(a, kConvFwd);
 }
 
 int conv_stat_chunks(const ConvArgs& a, int mode)
@@ -1183,6 +1236,7 @@ hipError_t conv_gemm(const ConvArgs& a, int mode, hipStream_t s)
     // the up-sampling epilogue forms 32-bit element offsets
     if (mode == kUpFwd && (size_t)P * a.Nout >= ((size_t)1 << 31)) return hipErrorInvalidValue;
     if (a.gsum && conv_stat_chunks(a, mode) == 0) return hipErrorInvalidValue;
+    if (a.gn_y && (mode != kConvFwd || !conv_gn_input_ok(a))) return hipErrorInvalidValue;
     if (conv_wide_ok(a, mode) && lds_ok(a, mode)) {
         if (mode == kConvFwd) launch_lds<kConvFwd>(a, s);
         else launch_lds<kConvDgrad>(a, s);

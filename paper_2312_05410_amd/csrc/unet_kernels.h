@@ -40,6 +40,13 @@ struct ConvArgs {
     // fields, x = BF16 (c - 1/2, phi, rho - 1, jump[n]) (in1 unused)
     const float* raw[3];
     const float* jump;
+    // kConvFwd with one input, or null: the input is the normalisation of the
+    // FP32 tensor gn_y ([N][H][W][C1]), x = BF16(act(A y + B)) with A, B per
+    // (sample, channel) from gn_coef ([2][N][C1]) and act the GELU if gn_gelu
+    // (in1 unused)
+    const float* gn_y;
+    const float* gn_coef;
+    int gn_gelu;
 };
 
 struct WgradArgs {
@@ -56,6 +63,9 @@ hipError_t conv_gemm(const ConvArgs& a, int mode, hipStream_t s);
 // multiples of 32 (128 for the up-sampling gradient's 4 sub-pixels),
 // ldk % 32 == 0, ldo % 128 == 0 and 16-byte aligned operands.
 bool conv_wide_ok(const ConvArgs& a, int mode);
+// True when conv_gemm (kConvFwd) can normalise its input as it loads it
+// (a.gn_y, a.gn_coef set; one input; the halo-tile kernel).
+bool conv_gn_input_ok(const ConvArgs& a);
 // Number of per-sample partial sums the kernel conv_gemm picks for
 // (a, mode) writes to a.gsum (forward modes of the wide kernels, when its
 // pixel blocks do not straddle samples), else 0.
@@ -118,7 +128,8 @@ struct GNArgs {
 };
 // mlp (or null): the same launch also evaluates the time basis and every
 // level's FiLM scales (mlp_fused_ok must hold) and copies the jumps to
-// jump_copy (or not, if null)
+// jump_copy (or not, if null).  With no output requested (z, zs, pool and
+// res_jump null) only the statistics and coefficients are computed.
 hipError_t gn_forward(const GNArgs& a, hipStream_t s, const struct MLPArgs* mlp = nullptr, float* jump_copy = nullptr);
 hipError_t gn_backward(const GNArgs& a, hipStream_t s);
 size_t gn_csum_floats(int N, int P, int C);

@@ -9,6 +9,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include "unet_gelu.h"
 #include "unet_kernels.h"
 
 namespace pfu {
@@ -27,24 +28,6 @@ __device__ __forceinline__ uint16_t f2bf(float f)
     if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
     u += 0x7fffu + ((u >> 16) & 1u);
     return (uint16_t)(u >> 16);
-}
-
-// GELU, tanh form: 0.5 a (1 + tanh(sqrt(2/pi) (a + 0.044715 a^3)))
-constexpr float kGeluS = 0.7978845608028654f;
-constexpr float kGeluA = 0.044715f;
-// (1 + tanh u) / 2 = 1 / (1 + exp(-2u)): the logistic form, on the hardware
-// base-2 exponential and reciprocal (exp2 of +-inf gives 0 or inf, so both
-// tails saturate to 0 and 1)
-__device__ __forceinline__ float gelu_s(float a)
-{
-    const float u = kGeluS * fmaf(kGeluA * a, a * a, a);
-    return __builtin_amdgcn_rcpf(1.f + __builtin_amdgcn_exp2f(-2.f * 1.4426950408889634f * u));
-}
-__device__ __forceinline__ float gelu(float a) { return a * gelu_s(a); }
-__device__ __forceinline__ float gelu_grad(float a)
-{
-    const float s = gelu_s(a);
-    return s + 2.f * a * s * (1.f - s) * kGeluS * fmaf(3.f * kGeluA * a, a, 1.f);
 }
 
 // Threads of a reduction block: the largest multiple of C not above 256, so
@@ -1001,6 +984,8 @@ hipError_t gn_forward(const GNArgs& a_in, hipStream_t s, const MLPArgs* mlp, flo
                            jump_copy);
     else
         hipLaunchKernelGGL(gn_stats_finish, dim3(a.N * a.G), dim3(kFinThreads), 0, s, a);
+    // no output requested: the statistics (and coefficients) only
+    if (!a.z_f32 && !a.z_bf16 && !a.zs_f32 && !a.zs_bf16 && !a.pool_bf16 && !a.res_jump) return hipGetLastError();
     if (a.res_jump) {
         if (a.C != 3 || (a.G != 1 && a.G != 3)) return hipErrorInvalidValue;
         hipLaunchKernelGGL(gn_apply_res_kernel, dim3(grid_for((size_t)a.N * a.P)), dim3(256), 0, s, a);

@@ -274,7 +274,12 @@ def check_forward(cfg, params, st, jump, out):
         assert e < max(5e-3, 3 * sens), f"{name}: increment rel L2 {e:.2e}, sensitivity {sens:.2e}"
 
 
-@pytest.mark.parametrize("H,W,levels,base,groups,n", [(32, 32, 3, 8, 4, 2), (24, 40, 4, 8, 2, 3)])
+# batch 1: the inference entry point takes its fused paths (the input
+# gathered by the first layer, the time basis in the first normalisation's
+# launch, the last decoder normalisation applied by the head convolution as
+# it loads), the training forward the separate launches
+@pytest.mark.parametrize("H,W,levels,base,groups,n", [(32, 32, 3, 8, 4, 2), (24, 40, 4, 8, 2, 3),
+                                                      (32, 64, 3, 32, 8, 1)])
 def test_network_forward_matches_oracle(H, W, levels, base, groups, n):
     import torch
 
@@ -291,6 +296,34 @@ def test_network_forward_matches_oracle(H, W, levels, base, groups, n):
     torch.cuda.synchronize()
     check_forward(cfg, params, st, jump, out)
     for a, b in zip(out, inf):  # the inference entry point runs the same arithmetic
+        assert torch.equal(a, b)
+    net.close()
+
+
+def test_inference_paths_equal_training_forward():
+    """At batch 1 the inference entry point takes its fused paths (the first
+    layer gathering its input from the state, the time basis in the first
+    normalisation's launch, the head convolution normalising the last
+    decoder block's output as it loads it); the training forward takes the
+    separate launches.  Both give the same bits.  256^2, so that the head
+    convolution runs on the halo-tile kernel; a live head (gamma 0.5)."""
+    import torch
+
+    from paper_2312_05410_amd.unet import UNet
+
+    announce("inference paths vs training forward 256^2 L3 base32 n1")
+    cfg = _cfg(256, 256, 3, 32, 8, 1)
+    net = UNet(cfg, seed=9)
+    p = net.param_dict()
+    p["head.gamma"][:] = 0.5
+    net.set_params(p)
+    st = [dev_f32(a) for a in _state(61, 1, 256, 256)]
+    jump = dev_f32(np.array([2.0], dtype=np.float32))
+    out = net.forward(*st, jump)
+    inf = net.forward(*st, jump, train=False)
+    torch.cuda.synchronize()
+    for a, b, s0 in zip(out, inf, st):
+        assert not torch.equal(a, s0)   # the head is live
         assert torch.equal(a, b)
     net.close()
 
