@@ -126,7 +126,9 @@ void unet_destroy(unet_handle* h);
  * The kernels of the network one at a time, for tests and benchmarks.
  * Tensors are NHWC; BF16 as uint16_t bit patterns; all other data float.
  * `workspace` holds at least unet_op_workspace_bytes(n, H, W, Cmax) bytes
- * where Cmax bounds every channel count of the call. */
+ * where Cmax bounds every channel count of the call.  Outputs of the
+ * convolutions and normalisations are limited to 2^29 values (PF_EINVAL
+ * beyond). */
 size_t unet_op_workspace_bytes(int n, int H, int W, int Cmax);
 
 /* y[n][H][W][Cout] = conv3x3(x1 (+) x2), w [9][Cout][C1+C2] (x2 may be

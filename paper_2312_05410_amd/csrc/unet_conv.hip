@@ -43,11 +43,6 @@ __device__ __forceinline__ uint16_t f2bf(float f)
     return (uint16_t)(u >> 16);
 }
 
-// 16-byte non-temporal store (streamed past the caches: the data are read
-// back by a later kernel, not by this one)
-typedef unsigned int u32x4v __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ void st16nt(void* p, uint4 v) { __builtin_nontemporal_store(__builtin_bit_cast(u32x4v, v), (u32x4v*)p); }
-
 struct Pix {
     int n, y, x;
     bool ok;
@@ -147,11 +142,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(ConvArgs a)
                     const int Co = a.Nout >> 2, sub = o / Co, co = o - sub * Co;
                     const size_t idx =
                         (((size_t)q.n * 2 * a.H + 2 * q.y + (sub >> 1)) * 2 * a.W + 2 * q.x + (sub & 1)) * Co + co;
-                    if (a.out_f32) __builtin_nontemporal_store(v, a.out_f32 + idx);
+                    if (a.out_f32) stwt(a.out_f32, idx, v);
                     if (a.out_bf16) a.out_bf16[idx] = f2bf(v);
                 } else if (o < a.O1) {
                     const size_t idx = (size_t)p * a.O1 + o;
-                    if (a.out_f32) __builtin_nontemporal_store(v, a.out_f32 + idx);
+                    if (a.out_f32) stwt(a.out_f32, idx, v);
                     if (a.out_bf16) a.out_bf16[idx] = f2bf(v);
                 } else {
                     const size_t idx = (size_t)p * (a.Nout - a.O1) + (o - a.O1);
@@ -391,7 +386,7 @@ __global__ __launch_bounds__(256) void gemm32_kernel(ConvArgs a)
                 const unsigned sub = (unsigned)o / Co, co = (unsigned)o - sub * Co;
                 const unsigned dst = ((((unsigned)t.n * 2u * (unsigned)a.H + 2u * (unsigned)t.y + (sub >> 1)) * W2 +
                                        2u * (unsigned)t.x + (sub & 1)) * Co + co);
-                st16nt(a.out_bf16 + dst, *(const uint4*)(&stg[p * LP + 8 * q]));
+                st16wt(a.out_bf16, 2 * (size_t)dst, *(const uint4*)(&stg[p * LP + 8 * q]));
             }
             return;
         }
@@ -431,7 +426,7 @@ __global__ __launch_bounds__(256) void gemm32_kernel(ConvArgs a)
                     if (on + 16 * j + r >= a.Nout) continue;
                     const unsigned idx = row + offj[j];
                     const float v = acc[i][j][e];
-                    if (a.out_f32) __builtin_nontemporal_store(v, a.out_f32 + idx);
+                    if (a.out_f32) stwt(a.out_f32, idx, v);
                     if (a.out_bf16) a.out_bf16[idx] = f2bf(v);
                 }
             }
@@ -458,7 +453,7 @@ __global__ __launch_bounds__(256) void gemm32_kernel(ConvArgs a)
             const int p = idx / (BN / 4), q = idx - p * (BN / 4);
             if (pb + p >= P) break;
             const f32x4 v = *(const f32x4*)(&stf[p * LPF + 4 * q]);
-            __builtin_nontemporal_store(v, (f32x4*)(a.out_f32 + (size_t)(pb + p) * BN + 4 * q));
+            st16wt(a.out_f32, 4 * ((size_t)(pb + p) * BN + 4 * q), __builtin_bit_cast(uint4, v));
         }
     } else {
 #pragma unroll
@@ -474,7 +469,7 @@ __global__ __launch_bounds__(256) void gemm32_kernel(ConvArgs a)
                     const float v = acc[i][j][e];
                     if (o < a.O1) {
                         const size_t idx = (size_t)p * a.O1 + o;
-                        if (a.out_f32) __builtin_nontemporal_store(v, a.out_f32 + idx);
+                        if (a.out_f32) stwt(a.out_f32, idx, v);
                         if (a.out_bf16) a.out_bf16[idx] = f2bf(v);
                     } else {
                         const size_t idx = (size_t)p * (a.Nout - a.O1) + (o - a.O1);
@@ -694,9 +689,8 @@ __global__ __launch_bounds__(256, 2) void conv3_lds_kernel(ConvArgs a)
     }
     __syncthreads();   // LDS is reused by the epilogue's reduction
     // acc[i][j][e]: pixel (ry[i], segment base + 4 (lane / 16) + e), channel on + 16 j + r.
-    // FP32 outputs are written with non-temporal stores: a later kernel
-    // reads them, and streamed lines cost less at the end of this one
-    // (measured: the decoder's 512^2 layer 23 against 27 us)
+    // FP32 outputs are written through (stwt, st16wt): a later kernel reads
+    // them
     const int rq = (lane >> 4) * 4;
     float s1[TN], s2[TN];
 #pragma unroll
@@ -727,8 +721,8 @@ __global__ __launch_bounds__(256, 2) void conv3_lds_kernel(ConvArgs a)
         for (int idx = tid; idx < rows * run4; idx += 256) {
             const int yy = idx / run4, q = idx - yy * run4;
             const f32x4 v = *(const f32x4*)(&stg[yy * TW * a.Nout + 4 * q]);
-            __builtin_nontemporal_store(
-                v, (f32x4*)(a.out_f32 + (((size_t)n * a.H + y0 + yy) * a.W + x0) * a.Nout + 4 * q));
+            st16wt(a.out_f32, 4 * ((((size_t)n * a.H + y0 + yy) * a.W + x0) * a.Nout + 4 * q),
+                   __builtin_bit_cast(uint4, v));
         }
         __syncthreads();   // the reduction below reuses LDS
     } else if (MODE == kConvFwd && a.out_f32 && !a.out_bf16 && a.O1 == a.Nout && a.Nout % 4 == 0) {
@@ -760,7 +754,7 @@ __global__ __launch_bounds__(256, 2) void conv3_lds_kernel(ConvArgs a)
             const int y = y0 + pp / TW, x = x0 + pp % TW;
             if (y >= a.H || x >= a.W) continue;
             const f32x4 v = *(const f32x4*)(&stg[pp * SP + 4 * q]);
-            __builtin_nontemporal_store(v, (f32x4*)(a.out_f32 + (((size_t)n * a.H + y) * a.W + x) * a.Nout + on + 4 * q));
+            st16wt(a.out_f32, 4 * ((((size_t)n * a.H + y) * a.W + x) * a.Nout + on + 4 * q), __builtin_bit_cast(uint4, v));
         }
         __syncthreads();   // the reduction below reuses LDS
     } else {
@@ -779,7 +773,7 @@ __global__ __launch_bounds__(256, 2) void conv3_lds_kernel(ConvArgs a)
                     const size_t p = ((size_t)n * a.H + y) * a.W + x;
                     if (o < a.O1) {
                         const size_t idx = p * a.O1 + o;
-                        if (a.out_f32) __builtin_nontemporal_store(v, a.out_f32 + idx);
+                        if (a.out_f32) stwt(a.out_f32, idx, v);
                         if (a.out_bf16) a.out_bf16[idx] = f2bf(v);
                     } else {
                         const size_t idx = p * (a.Nout - a.O1) + (o - a.O1);
@@ -1233,8 +1227,9 @@ hipError_t conv_gemm(const ConvArgs& a, int mode, hipStream_t s)
     const long P = (long)a.N * a.H * a.W;
     if (P <= 0 || a.Nout <= 0) return hipSuccess;
     if (mode < kConvFwd || mode > kFirst) return hipErrorInvalidValue;
-    // the up-sampling epilogue forms 32-bit element offsets
-    if (mode == kUpFwd && (size_t)P * a.Nout >= ((size_t)1 << 31)) return hipErrorInvalidValue;
+    // outputs are stored with 32-bit byte offsets (below 2^31: 2^29 FP32
+    // values); the up-sampling epilogue also forms 32-bit element offsets
+    if ((size_t)P * a.Nout >= ((size_t)1 << 29)) return hipErrorInvalidValue;
     if (a.gsum && conv_stat_chunks(a, mode) == 0) return hipErrorInvalidValue;
     if (a.gn_y && (mode != kConvFwd || !conv_gn_input_ok(a))) return hipErrorInvalidValue;
     if (conv_wide_ok(a, mode) && lds_ok(a, mode)) {

@@ -13,6 +13,28 @@ namespace pfu {
 
 constexpr int kMaxLevels = 6;
 
+// Stores of large activations that a later kernel reads: buffer stores
+// written through to memory at device scope (byte offset below 2^31 from
+// base).  Against plain global stores they stream faster, and against
+// non-temporal ones they leave no lines whose write-back delays the start of
+// the next kernel.
+typedef unsigned int u32x4v __attribute__((ext_vector_type(4)));
+constexpr int kStoreSc1 = 16;   // cache-policy bit: device scope (write-through)
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t wt_rsrc(const void* base)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, 0x7FFFFFFF, 0x00020000);
+}
+__device__ __forceinline__ void st16wt(const void* base, size_t byte_off, uint4 v)
+{
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4v, v), wt_rsrc(base), (int)byte_off, 0,
+                                           kStoreSc1);
+}
+__device__ __forceinline__ void stwt(const float* base, size_t idx, float v)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), wt_rsrc(base), (int)(4 * idx), 0,
+                                          kStoreSc1);
+}
+
 // Implicit GEMM out[p][o] = sum_k A[p][k] B[o][k]; see unet_conv.hip for
 // the four gather/scatter modes.
 // kFirst: 3x3 convolution of a 4-channel input with the taps folded into K

@@ -15,11 +15,6 @@
 namespace pfu {
 namespace {
 
-// 16-byte non-temporal store (streamed past the caches: the data are read
-// back by a later kernel, not by this one)
-typedef unsigned int u32x4v __attribute__((ext_vector_type(4)));
-__device__ __forceinline__ void st16nt(void* p, uint4 v) { __builtin_nontemporal_store(__builtin_bit_cast(u32x4v, v), (u32x4v*)p); }
-
 __device__ __forceinline__ float bf2f(uint16_t v) { return __builtin_bit_cast(float, (uint32_t)v << 16); }
 
 __device__ __forceinline__ uint16_t f2bf(float f)
@@ -241,7 +236,7 @@ __global__ __launch_bounds__(256) void gn_apply_res_kernel(GNArgs a)
             const float av = fmaf(a.gamma[f], (a.y[3 * i + f] - st[0]) * st[1], a.beta[f]);
             const float z = a.gelu ? gelu(av) : av;
             if (a.z_f32) a.z_f32[3 * i + f] = z;
-            a.res_out[f][i] = fmaf(dt, z, a.res_in[f][i]);
+            stwt(a.res_out[f], i, fmaf(dt, z, a.res_in[f][i]));
         }
     }
 }
@@ -401,7 +396,7 @@ __global__ __launch_bounds__(256) void gn_apply8x4_kernel(GNArgs a)
                 *(float4*)(a.z_f32 + i) = make_float4(z[0], z[1], z[2], z[3]);
                 *(float4*)(a.z_f32 + i + 4) = make_float4(z[4], z[5], z[6], z[7]);
             }
-            if (a.z_bf16) st16nt(a.z_bf16 + i, pack8(z));
+            if (a.z_bf16) st16wt(a.z_bf16, 2 * i, pack8(z));
             if (a.scale) {
                 float zs[8];
 #pragma unroll
@@ -410,7 +405,7 @@ __global__ __launch_bounds__(256) void gn_apply8x4_kernel(GNArgs a)
                     *(float4*)(a.zs_f32 + i) = make_float4(zs[0], zs[1], zs[2], zs[3]);
                     *(float4*)(a.zs_f32 + i + 4) = make_float4(zs[4], zs[5], zs[6], zs[7]);
                 }
-                if (a.zs_bf16) st16nt(a.zs_bf16 + i, pack8(zs));
+                if (a.zs_bf16) st16wt(a.zs_bf16, 2 * i, pack8(zs));
             }
             if (pool) {
 #pragma unroll
@@ -423,7 +418,7 @@ __global__ __launch_bounds__(256) void gn_apply8x4_kernel(GNArgs a)
         if (pool) {
             const unsigned q2 = q / Wo;
             const int xo = (int)(q - q2 * Wo), yo = (int)(q2 % Ho);
-            st16nt(a.pool_bf16 + (((size_t)n * Ho + yo) * Wo + xo) * a.C + c0, pack8(m));
+            st16wt(a.pool_bf16, 2 * ((((size_t)n * Ho + yo) * Wo + xo) * a.C + c0), pack8(m));
         }
     }
 }
@@ -973,7 +968,8 @@ hipError_t gn_forward(const GNArgs& a_in, hipStream_t s, const MLPArgs* mlp, flo
     GNArgs a = a_in;
     const bool vec = a.C % 8 == 0 && ((uintptr_t)a.y & 15) == 0;
     if (a.pool_bf16 && (!vec || a.H % 2 || a.W % 2 || (long)a.H * a.W != a.P)) return hipErrorInvalidValue;
-    if ((size_t)a.N * a.P * a.C >= ((size_t)1 << 31)) return hipErrorInvalidValue;
+    // (outputs are stored with 32-bit byte offsets: below 2^31 bytes)
+    if ((size_t)a.N * a.P * a.C >= ((size_t)1 << 29)) return hipErrorInvalidValue;
     if (a.coef && ((uintptr_t)a.coef & 15)) return hipErrorInvalidValue;
     if (!a.sums_ready) {
         a.chunks = gn_chunks(a.P);
