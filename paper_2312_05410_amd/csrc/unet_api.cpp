@@ -509,6 +509,7 @@ int forward(unet_handle* h, int n, const float* jump, const float* c, const floa
         }
         a.out_f32 = b.y[l];
         GNArgs g = gn_args(h, k, n, net.P(l, 1), b.y[l], b.st[l]);
+        g.stats_internal = !train;
         g.scale = b.sc[l];
         g.z_bf16 = train ? b.z[l] : nullptr;
         g.zs_bf16 = b.zs[l];
@@ -522,6 +523,7 @@ int forward(unet_handle* h, int n, const float* jump, const float* c, const floa
         ConvArgs a = conv_args(net.mid, n, Hl(L - 1), Wl(L - 1), b.zs[L - 1], nullptr);
         a.out_f32 = b.ym;
         GNArgs g = gn_args(h, net.mid, n, net.P(L - 1, 1), b.ym, b.stm);
+        g.stats_internal = !train;
         g.z_bf16 = b.am;
         RCHECK(conv_gn(h, a, kConvFwd, g));
     }
@@ -545,6 +547,7 @@ int forward(unet_handle* h, int n, const float* jump, const float* c, const floa
         ConvArgs a = conv_args(net.dec[l], n, Hl(l), Wl(l), b.zs[l], b.d[l]);
         a.out_f32 = b.yd[l];
         GNArgs g = gn_args(h, net.dec[l], n, net.P(l, 1), b.yd[l], b.std_[l]);
+        g.stats_internal = !train;
         g.z_bf16 = l == 0 && head.gn_y ? nullptr : b.ad[l];
         RCHECK(conv_gn(h, a, kConvFwd, g));
     }

@@ -142,6 +142,10 @@ struct GNArgs {
     float* coef;           // forward workspace [2][N][C] (16-byte aligned) or null: the
                            // normalisation as A y + B per channel, A = gamma rstd,
                            // B = beta - A mean
+    // forward: the statistics and coefficients need not be written out
+    // (inference), so a batch-1 launch may finish them inside the
+    // normalisation blocks
+    int stats_internal;
     // forward, C = 3, or null: instead of z, write the prediction
     // res_out[f][n][p] = res_in[f][n][p] + res_jump[n] z[n][p][f] (the head)
     const float* res_jump;
