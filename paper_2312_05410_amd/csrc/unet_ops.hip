@@ -761,31 +761,46 @@ __device__ void mlp_block(const MLPArgs& a, int n, int l)
         for (int u = 0; u < 4; ++u) v = fmaf(w[u], x[k + 32 * u], v);
         return sum32(v);
     };
+    // every lane of a half wave holds each of its rows' sums; lane k < R
+    // finishes row j0 + 32 k (one sine per layer runs on several lanes at
+    // once instead of one row after another on lane 0)
+    auto pick = [&](const float* v, int R) {
+        float x = v[0];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        const int r = j0 + 32 * m;
-        const float h = dot(w1[m], a0) + bj1[m];
-        if (r < Hd && k == 0) {
-            if (keep) a.h1[n * Hd + r] = h;
-            a1[r] = sinf(h);
+        for (int m = 1; m < 8; ++m)
+            if (m < R && k == m) x = v[m];
+        return x;
+    };
+    {
+        float h[8] = {};
+#pragma unroll
+        for (int m = 0; m < 4; ++m) h[m] = dot(w1[m], a0) + bj1[m];
+        const int r = j0 + 32 * k;
+        if (k < 4 && r < Hd) {
+            const float x = pick(h, 4);
+            if (keep) a.h1[n * Hd + r] = x;
+            a1[r] = sinf(x);
         }
     }
     __syncthreads();
+    {
+        float v[8] = {};
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        const int r = j0 + 32 * m;
-        const float v = dot(w2[m], a1) + bj2[m];
-        if (r < F && k == 0) {
-            if (keep) a.f[n * F + r] = v;
-            fs[r] = v;
+        for (int m = 0; m < 4; ++m) v[m] = dot(w2[m], a1) + bj2[m];
+        const int r = j0 + 32 * k;
+        if (k < 4 && r < F) {
+            const float x = pick(v, 4);
+            if (keep) a.f[n * F + r] = x;
+            fs[r] = x;
         }
     }
     __syncthreads();
+    {
+        float v[8];
 #pragma unroll
-    for (int m = 0; m < 8; ++m) {
-        const int r = j0 + 32 * m;
-        const float v = dot(wl[m], fs);
-        if (r < Cl && k == 0) a.sc[l][n * Cl + r] = v;
+        for (int m = 0; m < 8; ++m) v[m] = dot(wl[m], fs);
+        const int r = j0 + 32 * k;
+        if (k < 8 && r < Cl) a.sc[l][n * Cl + r] = pick(v, 8);
     }
 }
 
