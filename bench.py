@@ -382,7 +382,7 @@ def unet_leg(args):
                       "inference_tflops_batch1": round(fwd / (infer_ms / 1e3) / 1e12, 1)},
            "roofline": {"bound": "mfma", "achieved": round(achieved, 1), "peak": MFMA_BF16_PEAK_TFLOPS,
                         "unit": "TFLOP/s", "frac": round(achieved / MFMA_BF16_PEAK_TFLOPS, 4), "traffic": None,
-                        "kernel": "conv3_lds_kernel<0, 2, 8, 32> (conv3x3 64->32, 5 x 512^2)",
+                        "kernel": "conv3_lds_kernel<0, 2, 8, 32, 32, false> (conv3x3 64->32, 5 x 512^2)",
                         "avg_launch_us": round(conv_s * 1e6, 2), "flops_per_launch": conv_flops}}
     if not args.no_cpu:
         res["cpu_baseline"] = unet_cpu_leg(cfg, args.cpu_seconds)

@@ -9,6 +9,11 @@
 by default (`*_results.db`), grouped by kernel and grid.
 `counters` prints SQ counter metrics (occupancy, VALU issue, wait and MFMA
 fractions, LDS conflicts) of one kernel from a `--pmc` run.
+`sequence` splits a `--kernel-trace` run into the launch sequences that
+begin with a kernel whose name contains START (and whose next kernel's name
+contains NEXT, if given) and prints, position by position, the median
+duration over the sequences of the most common length (e.g. the kernels of
+one network forward).
 `traffic` reads two `--pmc FETCH_SIZE` / `--pmc WRITE_SIZE` runs of the same
 program, whose first large device copy (--ref-bytes bytes, read once and
 written once) calibrates the counters: each counter is scaled by
@@ -54,6 +59,27 @@ def stats(d: str, kernel: str | None = None):
         out.append((r["Name"], int(r["Calls"]), float(r["AverageNs"]), float(r["MinNs"]), float(r["MaxNs"]),
                     float(r["Percentage"])))
     return out
+
+
+def sequence(d: str, start: str, nxt: str | None = None):
+    rows = sorted(csv.DictReader(open(_one(os.path.join(d, "**", "*kernel_trace.csv")))),
+                  key=lambda r: int(r["Start_Timestamp"]))
+    heads = [i for i, r in enumerate(rows) if start in r["Kernel_Name"] and
+             (nxt is None or (i + 1 < len(rows) and nxt in rows[i + 1]["Kernel_Name"]))]
+    seqs = []
+    for i, h in enumerate(heads):
+        end = heads[i + 1] if i + 1 < len(heads) else len(rows)
+        seqs.append(rows[h:end])
+    if not seqs:
+        raise SystemExit(f"no sequence starts with {start}")
+    n = statistics.mode(len(q) for q in seqs[:-1] or seqs)
+    seqs = [q[:n] for q in seqs if len(q) >= n]
+    out = []
+    for k in range(n):
+        dur = [(int(q[k]["End_Timestamp"]) - int(q[k]["Start_Timestamp"])) / 1e3 for q in seqs]
+        out.append((seqs[-1][k]["Kernel_Name"], statistics.median(dur)))
+    span = statistics.median((int(q[-1]["End_Timestamp"]) - int(q[0]["Start_Timestamp"])) / 1e3 for q in seqs)
+    return len(seqs), out, span
 
 
 def _counter(d: str, name: str):
@@ -167,6 +193,10 @@ def main(argv=None):
     q.add_argument("--kernel", required=True)
     q.add_argument("--command", default="")
     q.add_argument("--out")
+    sq = sub.add_parser("sequence")
+    sq.add_argument("dir")
+    sq.add_argument("--start", required=True)
+    sq.add_argument("--next")
     t = sub.add_parser("traffic")
     t.add_argument("fetch_dir")
     t.add_argument("write_dir")
@@ -186,6 +216,14 @@ def main(argv=None):
         for name, grid, calls, avg, mn, mx, pct in dbstats(a.dir, a.kernel, a.top):
             print(f"{name}\n    grid {grid}  calls {calls}  avg {avg / 1e3:.3f} us  min {mn / 1e3:.3f}  "
                   f"max {mx / 1e3:.3f}  share {pct:.2f} %")
+        return
+    if a.cmd == "sequence":
+        n, seq, span = sequence(a.dir, a.start, a.next)
+        print(f"{n} sequences of {len(seq)} launches; median duration per position (us):")
+        for i, (name, us) in enumerate(seq):
+            print(f"{i:3d} {us:8.2f}  {name}")
+        print(f"sum of the medians {sum(u for _, u in seq):.1f} us; median span first start to last end "
+              f"{span:.1f} us")
         return
     if a.cmd == "counters":
         n, m = counters(a.dir, a.kernel)
