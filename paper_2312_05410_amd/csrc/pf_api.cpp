@@ -176,7 +176,6 @@ struct pf_handle {
     int march_cols = 1;                  // K == 1: grid columns per lane (2: FP32, even nx)
     int fused = PF_FUSED_TILE;           // K >= 2: LDS tile or register strip march (K == 2)
     int k2_ty = 8;                       // register strip march: rows per wave
-    int k2_cols = 1;                     // register strip march: grid columns per lane
     int res_th = 0;                      // resident stepper: tile height (0: not used)
     int res_ntx = 0, res_nty = 0;        // resident stepper: tiles per row / column
     uint32_t res_epoch = 0;              // resident stepper: generations traded by eager launches (mod 2^30)
@@ -325,7 +324,7 @@ int ensure_graph(pf_handle* h)
         }
         hipGraphNode_t node = nullptr;
         if (h->K == 1) e = pfk::graph_add_march<T>(g, &node, prev, a, h->march_ty, h->march_cols, h->p.batch);
-        else if (h->fused == PF_FUSED_MARCH) e = pfk::graph_add_march_k2<T>(g, &node, prev, a, h->k2_ty, h->k2_cols, h->p.batch);
+        else if (h->fused == PF_FUSED_MARCH) e = pfk::graph_add_march_k2<T>(g, &node, prev, a, h->k2_ty, h->p.batch);
         else e = pfk::graph_add_step<T>(g, &node, prev, a, h->K, h->p.batch);
         prev = node;
     }
@@ -431,7 +430,7 @@ int enqueue_steps(pf_handle* h, int64_t n)
         hipError_t e;
         if (K == 1) e = pfk::launch_march<T>(a, h->march_ty, h->march_cols, p->batch, h->stream);
         else if (h->fused != PF_FUSED_MARCH) e = pfk::launch_step<T>(a, K, p->batch, h->stream);
-        else if (a.nsub == 2) e = pfk::launch_march_k2<T>(a, h->k2_ty, h->k2_cols, p->batch, h->stream);
+        else if (a.nsub == 2) e = pfk::launch_march_k2<T>(a, h->k2_ty, p->batch, h->stream);
         else e = pfk::launch_march<T>(a, h->march_ty, h->march_cols, p->batch, h->stream);  // odd step
         if ((rc = hip_fail(h, e))) return rc;
         parity ^= 1;
@@ -595,8 +594,6 @@ int pf_init(pf_handle** out, const pf_params* p, void* c, void* phi, void* rho, 
             if (p->ny % ty == 0) {
                 h->fused = PF_FUSED_MARCH;
                 h->k2_ty = ty;
-                // two columns per lane only on request (lane_cols = 2), FP32, even nx
-                h->k2_cols = p->lane_cols == 2 && two_ok ? 2 : 1;
                 break;
             }
         }
@@ -950,7 +947,7 @@ extern "C" int pf_get_fused_kernel(const pf_handle* h, int32_t* kind)
 extern "C" int pf_get_lane_cols(const pf_handle* h, int32_t* lane_cols)
 {
     if (!h || !lane_cols) return PF_EINVAL;
-    *lane_cols = h->K == 1 ? h->march_cols : (h->fused == PF_FUSED_MARCH ? h->k2_cols : 1);
+    *lane_cols = h->K == 1 ? h->march_cols : 1;
     return PF_OK;
 }
 

@@ -80,14 +80,13 @@ hipError_t graph_add_march(hipGraph_t g, hipGraphNode_t* node, hipGraphNode_t de
                            int ty, int cols, int batch);
 
 // Two fused steps per launch in the register strip march (Euler, no
-// variants), chunks of ty in {4, 8, 16} rows with ty dividing ny, cols grid
-// columns per lane (2: FP32 with even nx only); a launch always advances
-// two steps.
+// variants), chunks of ty in {4, 8, 16} rows with ty dividing ny, one grid
+// column per lane; a launch always advances two steps.
 template <typename T>
-hipError_t launch_march_k2(const StepArgs<T>& a, int ty, int cols, int batch, hipStream_t s);
+hipError_t launch_march_k2(const StepArgs<T>& a, int ty, int batch, hipStream_t s);
 template <typename T>
 hipError_t graph_add_march_k2(hipGraph_t g, hipGraphNode_t* node, hipGraphNode_t dep, const StepArgs<T>& a,
-                              int ty, int cols, int batch);
+                              int ty, int batch);
 
 // Resident stepper: one launch advances FP32 grids by n >= 2 explicit Euler
 // or midpoint steps with each 64 x th tile (th in {8, 16, 32}) held in LDS,

@@ -516,159 +516,6 @@ __global__ __launch_bounds__(64) void march_k2_kernel(StepArgs<T> a)
     }
 }
 
-// The two-step march with two grid columns per lane (FP32, even nx): the
-// pair layout of march2_kernel (8-byte loads, one neighbour exchange per
-// field and pair) on the four stages of march_k2_kernel; 128-column strips
-// with a radius-4 halo write 120 columns (lanes 2..61).  Bitwise equal to the
-// other kernels.
-constexpr int kStripOutK22 = 120;
-
-template <int TY, int D>
-__global__ __launch_bounds__(64) void march2_k2_kernel(StepArgs<float> a)
-{
-    using T = float;
-    constexpr int NR = TY + 8;
-    const int lane = threadIdx.x;
-    const int b = blockIdx.y;
-    const int nx = a.nx, ny = a.ny;
-    const int nstrip = a.tiles_x;
-
-    const int nblk = a.tiles_x * a.tiles_y;
-    const int bid = blockIdx.x;
-    const int xcd = bid & 7, slot = bid >> 3;
-    const int q8 = nblk >> 3, r8 = nblk & 7;
-    const int tileid = xcd * q8 + (xcd < r8 ? xcd : r8) + slot;
-    const int strip = tileid % nstrip;
-    const int y0 = (tileid / nstrip) * TY;
-
-    int gx = strip * kStripOutK22 - 4 + 2 * lane;   // even: the wrapped pair stays contiguous
-    while (gx < 0) gx += nx;
-    while (gx >= nx) gx -= nx;
-    const int ocol = strip * kStripOutK22 + 2 * lane - 4;
-    const bool out_lane = lane >= 2 && lane < 2 + kStripOutK22 / 2 && ocol < nx;
-
-    const size_t plane = (size_t)nx * ny;
-    const auto bc = plane_rsrc(a.c + (size_t)b * plane, plane);
-    const auto bp = plane_rsrc(a.phi + (size_t)b * plane, plane);
-    const auto br = plane_rsrc(a.rho + (size_t)b * plane, plane);
-    const auto oc = plane_rsrc(a.c_out + (size_t)b * plane, plane);
-    const auto op = plane_rsrc(a.phi_out + (size_t)b * plane, plane);
-    const auto orr = plane_rsrc(a.rho_out + (size_t)b * plane, plane);
-    const int vo = gx * (int)sizeof(T);
-    const int row_bytes = nx * (int)sizeof(T);
-    const Coef<T> k = a.k;
-    const Real rl = a.real[b];
-    const T vx2h = (T)rl.vx2h, vy2h = (T)rl.vy2h;
-    const int pvd = a.pvd;
-    const bool bot = pvd && y0 == 0;
-    const bool top = pvd && y0 + TY == ny;
-
-    F2 c[NR], p[NR], r[NR];
-    F2 mc[NR], mp[NR], M[NR], pE[NR], pW[NR], FN[NR];
-    F2 c1[NR], p1[NR], r1[NR];
-    F2 mc1[NR], mp1[NR], M1[NR], pE1[NR], pW1[NR], FN1[NR];
-    const RhoCoef<T> rc = rho_coef(k, vx2h, vy2h);
-
-    auto load_row = [&](int t) {
-        const int gj = y0 - 4 + t;
-        int jj;
-        if (pvd) jj = gj < 0 ? -1 - gj : (gj >= ny ? 2 * ny - 1 - gj : gj);
-        else jj = gj < 0 ? gj + ny : (gj >= ny ? gj - ny : gj);
-        jj = jj < 0 ? 0 : (jj >= ny ? ny - 1 : jj);
-        const int so = jj * row_bytes;
-        c[t] = ld2(bc, vo, so);
-        p[t] = ld2(bp, vo, so);
-        const F2 rv = ld2(br, vo, so);
-        const bool inlet = pvd && gj >= ny;
-        r[t] = {inlet ? k.rho_in : rv.a, inlet ? k.rho_in : rv.b};
-    };
-    auto inflow = [&](int gj, F2 rr) {
-        if (a.Qcol && top && gj == ny - 1 && out_lane) {
-            double* q = a.Qcol + (size_t)b * nx + ocol;
-            const double rin = (double)k.rho_in, ra = (double)rr.a, rb = (double)rr.b;
-            q[0] = q[0] + (rl.qa * (ra + rin) + rl.qb * (rin - ra));
-            q[1] = q[1] + (rl.qa * (rb + rin) + rl.qb * (rin - rb));
-        }
-    };
-    // stage 1 of one step at row t of (u, v, w): the pair's first cell takes
-    // its west neighbour from the west lane, the second its east neighbour
-    // from the east lane
-    auto stage1 = [&](F2* u, F2* v, F2* sE, F2* sW, F2* smc, F2* smp, F2* sM, int t) {
-        const T cW = west(u[t].b), cE = east(u[t].a);
-        const T pWv = west(v[t].b), pEv = east(v[t].a);
-        sE[t] = {v[t].b, pEv};
-        sW[t] = {pWv, v[t].a};
-        potentials(k, u[t].a, u[t].b, cW, u[t + 1].a, u[t - 1].a, v[t].a, sE[t].a, sW[t].a, v[t + 1].a, v[t - 1].a,
-                   smc[t].a, smp[t].a, sM[t].a);
-        potentials(k, u[t].b, cE, u[t].a, u[t + 1].b, u[t - 1].b, v[t].b, sE[t].b, sW[t].b, v[t + 1].b, v[t - 1].b,
-                   smc[t].b, smp[t].b, sM[t].b);
-    };
-    // stage 2 of one step at row t: the Euler update of the pair into (nc, np, nr)
-    auto stage2 = [&](F2* u, F2* v, F2* w, F2* sE, F2* sW, F2* smc, F2* smp, F2* sM, F2* sFN, int t, bool bottom,
-                      F2& nc, F2& np, F2& nr) {
-        const T FEa = cflux(sM[t].a, smc[t].a, sM[t].b, smc[t].b);
-        const T FEb = cflux(sM[t].b, smc[t].b, east(sM[t].a), east(smc[t].a));
-        const T FWa = west(FEb);
-        sFN[t].a = cflux(sM[t].a, smc[t].a, sM[t + 1].a, smc[t + 1].a);
-        sFN[t].b = cflux(sM[t].b, smc[t].b, sM[t + 1].b, smc[t + 1].b);
-        const T rW = west(w[t].b), rE = east(w[t].a);
-        const T qW = west(smp[t].b), qE = east(smp[t].a);
-        update(k, rc, vx2h, vy2h, bottom, u[t].a, v[t].a, sE[t].a, sW[t].a, v[t + 1].a, v[t - 1].a, w[t].a, w[t].b,
-               rW, w[t + 1].a, w[t - 1].a, FEa, FWa, sFN[t].a, sFN[t - 1].a, smp[t].a, smp[t].b, qW, smp[t + 1].a,
-               smp[t - 1].a, nc.a, np.a, nr.a);
-        update(k, rc, vx2h, vy2h, bottom, u[t].b, v[t].b, sE[t].b, sW[t].b, v[t + 1].b, v[t - 1].b, w[t].b, rE,
-               w[t].a, w[t + 1].b, w[t - 1].b, FEb, FEa, sFN[t].b, sFN[t - 1].b, smp[t].b, qE, smp[t].a,
-               smp[t + 1].b, smp[t - 1].b, nc.b, np.b, nr.b);
-    };
-
-#pragma unroll
-    for (int t = 0; t < NR; ++t)
-        if (t < 3 + D) load_row(t);
-
-#pragma unroll
-    for (int f = 1; f <= NR; ++f) {
-        if (f + 2 + D < NR) load_row(f + 2 + D);
-        if (f <= NR - 2) stage1(c, p, pE, pW, mc, mp, M, f);
-        if (f - 1 >= 2 && f - 1 <= NR - 3) {
-            const int t = f - 1;
-            const int gj = y0 - 4 + t;
-            if (t == 2) {
-                FN[1].a = cflux(M[1].a, mc[1].a, M[2].a, mc[2].a);
-                FN[1].b = cflux(M[1].b, mc[1].b, M[2].b, mc[2].b);
-            }
-            stage2(c, p, r, pE, pW, mc, mp, M, FN, t, pvd && gj == 0, c1[t], p1[t], r1[t]);
-            if (t >= 4 && t < TY + 4) inflow(gj, r[t]);
-            if (t >= TY + 4 && top) {
-                c1[t] = c1[2 * TY + 7 - t];
-                p1[t] = p1[2 * TY + 7 - t];
-                r1[t] = {k.rho_in, k.rho_in};
-            }
-            if (t == 5 && bot) {
-                c1[3] = c1[4], p1[3] = p1[4], r1[3] = r1[4];
-                c1[2] = c1[5], p1[2] = p1[5], r1[2] = r1[5];
-            }
-        }
-        if (f - 4 >= 3 && f - 4 <= NR - 4) stage1(c1, p1, pE1, pW1, mc1, mp1, M1, f - 4);
-        if (f - 5 >= 4 && f - 5 <= NR - 5) {
-            const int t = f - 5;
-            const int gj = y0 - 4 + t;
-            if (t == 4) {
-                FN1[3].a = cflux(M1[3].a, mc1[3].a, M1[4].a, mc1[4].a);
-                FN1[3].b = cflux(M1[3].b, mc1[3].b, M1[4].b, mc1[4].b);
-            }
-            F2 nc, np, nr;
-            stage2(c1, p1, r1, pE1, pW1, mc1, mp1, M1, FN1, t, pvd && gj == 0, nc, np, nr);
-            if (out_lane) {
-                const int so = gj * row_bytes;
-                st2(nc, oc, vo, so);
-                st2(np, op, vo, so);
-                st2(nr, orr, vo, so);
-            }
-            inflow(gj, r1[t]);
-        }
-    }
-}
-
 // rows of loads in flight ahead of use: short chunks issue all their loads
 // at once, long chunks keep a window of rows in flight
 template <int TY> constexpr int lookahead() { return TY <= 8 ? TY + 1 : 4; }
@@ -741,17 +588,11 @@ hipError_t node_march_ty(hipGraph_t g, hipGraphNode_t* node, hipGraphNode_t dep,
 }  // namespace
 
 template <typename T, int TY>
-hipError_t k2_node_or_launch(StepArgs<T> a, int cols, int batch, hipStream_t s, hipGraph_t g, hipGraphNode_t* node,
+hipError_t k2_node_or_launch(StepArgs<T> a, int batch, hipStream_t s, hipGraph_t g, hipGraphNode_t* node,
                              hipGraphNode_t dep)
 {
     void* fn = (void*)march_k2_kernel<T, TY, lookahead<TY>()>;
     a.tiles_x = (a.nx + kStripOutK2 - 1) / kStripOutK2;
-    if constexpr (sizeof(T) == 4) {
-        if (cols == 2 && a.nx % 2 == 0) {
-            fn = (void*)march2_k2_kernel<TY, lookahead<TY>()>;
-            a.tiles_x = (a.nx + kStripOutK22 - 1) / kStripOutK22;
-        }
-    }
     a.tiles_y = a.ny / TY;
     void* args[] = {&a};
     if (!g) return hipLaunchKernel(fn, dim3(a.tiles_x * a.tiles_y, batch), dim3(64), args, 0, s);
@@ -766,14 +607,14 @@ hipError_t k2_node_or_launch(StepArgs<T> a, int cols, int batch, hipStream_t s, 
 }
 
 template <typename T>
-hipError_t k2_dispatch(const StepArgs<T>& a, int ty, int cols, int batch, hipStream_t s, hipGraph_t g,
-                       hipGraphNode_t* node, hipGraphNode_t dep)
+hipError_t k2_dispatch(const StepArgs<T>& a, int ty, int batch, hipStream_t s, hipGraph_t g, hipGraphNode_t* node,
+                       hipGraphNode_t dep)
 {
     if (ty <= 0 || a.ny % ty != 0 || a.ny < 4) return hipErrorInvalidValue;
     switch (ty) {
-    case 4: return k2_node_or_launch<T, 4>(a, cols, batch, s, g, node, dep);
-    case 8: return k2_node_or_launch<T, 8>(a, cols, batch, s, g, node, dep);
-    case 16: return k2_node_or_launch<T, 16>(a, cols, batch, s, g, node, dep);
+    case 4: return k2_node_or_launch<T, 4>(a, batch, s, g, node, dep);
+    case 8: return k2_node_or_launch<T, 8>(a, batch, s, g, node, dep);
+    case 16: return k2_node_or_launch<T, 16>(a, batch, s, g, node, dep);
     default: return hipErrorInvalidValue;
     }
 }
@@ -810,21 +651,21 @@ template hipError_t graph_add_march<double>(hipGraph_t, hipGraphNode_t*, hipGrap
                                             int, int, int);
 
 template <typename T>
-hipError_t launch_march_k2(const StepArgs<T>& a, int ty, int cols, int batch, hipStream_t s)
+hipError_t launch_march_k2(const StepArgs<T>& a, int ty, int batch, hipStream_t s)
 {
-    return k2_dispatch<T>(a, ty, cols, batch, s, nullptr, nullptr, nullptr);
+    return k2_dispatch<T>(a, ty, batch, s, nullptr, nullptr, nullptr);
 }
 template <typename T>
 hipError_t graph_add_march_k2(hipGraph_t g, hipGraphNode_t* node, hipGraphNode_t dep, const StepArgs<T>& a, int ty,
-                              int cols, int batch)
+                              int batch)
 {
-    return k2_dispatch<T>(a, ty, cols, batch, nullptr, g, node, dep);
+    return k2_dispatch<T>(a, ty, batch, nullptr, g, node, dep);
 }
-template hipError_t launch_march_k2<float>(const StepArgs<float>&, int, int, int, hipStream_t);
-template hipError_t launch_march_k2<double>(const StepArgs<double>&, int, int, int, hipStream_t);
+template hipError_t launch_march_k2<float>(const StepArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_march_k2<double>(const StepArgs<double>&, int, int, hipStream_t);
 template hipError_t graph_add_march_k2<float>(hipGraph_t, hipGraphNode_t*, hipGraphNode_t, const StepArgs<float>&,
-                                              int, int, int);
+                                              int, int);
 template hipError_t graph_add_march_k2<double>(hipGraph_t, hipGraphNode_t*, hipGraphNode_t,
-                                               const StepArgs<double>&, int, int, int);
+                                               const StepArgs<double>&, int, int);
 
 }  // namespace pfk
