@@ -34,6 +34,10 @@ namespace {
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
+// DPP row shifts (within each 16-lane row; a lane whose source lies outside
+// the row keeps the old value)
+constexpr int kRowShl1 = 0x101, kRowShr1 = 0x111;
+
 // round to nearest even (NaN and infinity keep their class)
 __device__ __forceinline__ uint16_t f2bf(float f)
 {
@@ -671,29 +675,52 @@ __global__ __launch_bounds__(256, 2) void conv3_lds_kernel(ConvArgs a)
         lstore();
         __syncthreads();
         if (kc + 1 < nk) gload(kc + 1);
+        // per 32-channel step and tap row: the operands of the row's left
+        // and right taps come from LDS; the centre tap's (one pixel over)
+        // are the left ones moved one lane down each 16-lane row by a DPP
+        // shift, lane 15 taking the right operand of lane 14 (a third fewer
+        // LDS reads)
 #pragma unroll
-        for (int tap = 0; tap < 9; ++tap) {
-            int dy = tap / 3 - 1, dx = tap % 3 - 1;
-            if (MODE == kConvDgrad) {
-                dy = -dy;
-                dx = -dx;
-            }
+        for (int ks = 0; ks < KC / 32; ++ks)
 #pragma unroll
-            for (int ks = 0; ks < KC / 32; ++ks) {
-                bf16x8 B[TN], A[TM];
+            for (int ty = 0; ty < 3; ++ty) {
+                const int dy = MODE == kConvDgrad ? 1 - ty : ty - 1;
+                bf16x8 L[TM], R[TM], M[TM];
 #pragma unroll
-                for (int j = 0; j < TN; ++j)
-                    B[j] = *(const bf16x8*)(&wl[(tap * TN * 16 + 16 * j + r) * LP + 32 * ks + kq]);
+                for (int i = 0; i < TM; ++i) {
+                    const int row = ((ry[i] + 1 + dy) * WP + cx[i]) * LP + 32 * ks + kq;
+                    L[i] = *(const bf16x8*)(&lds[row]);
+                    R[i] = *(const bf16x8*)(&lds[row + 2 * LP]);
+                }
 #pragma unroll
-                for (int i = 0; i < TM; ++i)
-                    A[i] = *(const bf16x8*)(&lds[((ry[i] + 1 + dy) * WP + cx[i] + 1 + dx) * LP + 32 * ks + kq]);
+                for (int i = 0; i < TM; ++i) {
+                    const u32x4v l = __builtin_bit_cast(u32x4v, L[i]), rr = __builtin_bit_cast(u32x4v, R[i]);
+                    u32x4v m;
 #pragma unroll
-                for (int i = 0; i < TM; ++i)
+                    for (int d = 0; d < 4; ++d) {
+                        const int r15 = __builtin_amdgcn_update_dpp(0, (int)rr[d], kRowShr1, 0xF, 0xF, false);
+                        m[d] = (unsigned)__builtin_amdgcn_update_dpp(r15, (int)l[d], kRowShl1, 0xF, 0xF, false);
+                    }
+                    M[i] = __builtin_bit_cast(bf16x8, m);
+                }
+#pragma unroll
+                for (int tx = 0; tx < 3; ++tx) {
+                    const int tap = ty * 3 + tx;
+                    // forward: tap columns -1, 0, +1; input gradient mirrored
+                    const int side = MODE == kConvDgrad ? 2 - tx : tx;
+                    bf16x8 B[TN];
 #pragma unroll
                     for (int j = 0; j < TN; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[i], B[j], acc[i][j], 0, 0, 0);
+                        B[j] = *(const bf16x8*)(&wl[(tap * TN * 16 + 16 * j + r) * LP + 32 * ks + kq]);
+#pragma unroll
+                    for (int i = 0; i < TM; ++i) {
+                        const bf16x8 A = side == 0 ? L[i] : side == 1 ? M[i] : R[i];
+#pragma unroll
+                        for (int j = 0; j < TN; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B[j], acc[i][j], 0, 0, 0);
+                    }
+                }
             }
-        }
     }
     __syncthreads();   // LDS is reused by the epilogue's reduction
     // acc[i][j][e]: pixel (ry[i], segment base + 4 (lane / 16) + e), channel on + 16 j + r.
