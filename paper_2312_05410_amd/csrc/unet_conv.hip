@@ -201,10 +201,17 @@ __global__ __launch_bounds__(256) void gemm32_kernel(ConvArgs a)
     // the first is used; indices clamped into the grid, and taps outside it
     // zeroed when the operands are gathered from LDS)
     constexpr int BMr = WGM * TM * 16, kSW = BMr + 2, kStageIt = (3 * kSW + 255) / 256;
+    // LDS shared by the input stage (kFirst, dead after the operand loads)
+    // and the forward epilogue's output stage (fewer bytes per block: with
+    // ~38 KB four blocks fit on a CU)
+    constexpr int kStfFloats = (MODE == kFirst || MODE == kConvFwd) ? BMr * (WGN * TN * 16 + 4) : 4;
+    constexpr int kXstBytes = MODE == kFirst ? kStageIt * 256 * 8 : 16;
+    constexpr int kSmemBytes = kStfFloats * 4 > kXstBytes ? kStfFloats * 4 : kXstBytes;
+    __shared__ __align__(16) unsigned char smem[kSmemBytes];
     [[maybe_unused]] const uint2* xs = nullptr;
     [[maybe_unused]] int xs_x0 = 0;
     if constexpr (MODE == kFirst) {
-        __shared__ uint2 xst[kStageIt * 256];
+        uint2* xst = (uint2*)smem;
         if (a.raw[0] && a.W % BMr == 0) {
             const int pb = blockIdx.x * BMr, row = pb / a.W, n0 = row / a.H, y0 = row - n0 * a.H;
             xs_x0 = pb - row * a.W;
@@ -451,7 +458,9 @@ __global__ __launch_bounds__(256) void gemm32_kernel(ConvArgs a)
         // so its FP32 output is one contiguous run: staged through LDS as
         // [pixel][channel] and written back as 16-byte pieces in order
         constexpr int LPF = BN + 4;   // 4 lane groups land 16 banks apart
-        __shared__ __align__(16) float stf[BM * LPF];
+        static_assert((MODE != kFirst && MODE != kConvFwd) || BM * LPF <= kStfFloats, "output stage fits");
+        float* stf = (float*)smem;
+        if (MODE == kFirst && xs) __syncthreads();   // every wave is done with the input stage
         const int pl = (wv % WGM) * TM * 16, ol = (wv / WGM) * TN * 16;
 #pragma unroll
         for (int i = 0; i < TM; ++i)
