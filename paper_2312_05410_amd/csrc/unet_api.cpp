@@ -165,6 +165,7 @@ struct Bufs {
     float* std_[kMaxLevels];
     float *yh, *sth;
     float *jump, *h0, *h1, *f, *sc[kMaxLevels];
+    uint32_t* mlpc;                 // [n][L][2]: jump bits and parameter generation of each sc[l][n]
     float* gcoef;                   // GN forward coefficients [2][n][C] (shared by every GN)
     float *mdf, *mdh1, *mdh0;
     // backward
@@ -260,6 +261,7 @@ void carve(Net& net, char* base, Bufs& b)
         part = std::max(part, wgrad_floats(P0, 9, c.out_ch, w[0], 0));
     }
     b.jump = m.take<float>((size_t)n);
+    b.mlpc = m.take<uint32_t>((size_t)n * L * 2);
     b.gcoef = m.take<float>((size_t)2 * n * std::max(w[L - 1], c.out_ch));
     b.h0 = m.take<float>((size_t)n * Hd);
     b.h1 = m.take<float>((size_t)n * Hd);
@@ -307,6 +309,7 @@ struct unet_handle {
     float* grads;
     hipStream_t stream;
     int last_n = 0;
+    uint32_t param_gen = 0;   // advanced whenever the parameters may have changed (never 0 after create)
     explicit unet_handle(const unet_config& c) : net(c) {}
 };
 
@@ -334,6 +337,9 @@ int prep(unet_handle* h, Conv& k)
 int prepare_all(unet_handle* h)
 {
     Net& net = h->net;
+    // the time basis memo (sc[l][n] keyed by jump[n] and this generation)
+    // is void from here on
+    if (++h->param_gen == 0) h->param_gen = 1;
     int rc = PF_OK;
     for (int l = 0; l < net.L && rc == PF_OK; ++l) rc = prep(h, net.enc[l]);
     if (rc == PF_OK) rc = prep(h, net.mid);
@@ -443,6 +449,8 @@ MLPArgs mlp_args(unet_handle* h, int n, const float* jump)
     a.Hd = net.c.mlp_hidden;
     a.F = net.c.basis;
     a.L = net.L;
+    a.cache = h->b.mlpc;
+    a.gen = h->param_gen;
     for (int l = 0; l < net.L; ++l) {
         a.Wl[l] = par(h, net.film[l]);
         a.gWl[l] = grd(h, net.film[l]);
@@ -727,6 +735,11 @@ int unet_create(unet_handle** out, const unet_config* cfg, float* params, float*
     h->params = params;
     h->grads = grads;
     h->stream = (hipStream_t)stream;
+    // no memo entry is valid yet (generation 0 is never used)
+    if (fill_f32((float*)h->b.mlpc, (size_t)cfg->max_batch * h->net.L * 2, 0.f, h->stream) != hipSuccess) {
+        delete h;
+        return PF_EDEVICE;
+    }
     const int rc = prepare_all(h);
     if (rc != PF_OK) {
         delete h;

@@ -190,6 +190,11 @@ struct MLPArgs {
     float* gWl[kMaxLevels];
     int N, Hd, F, L;
     int C[kMaxLevels];
+    // forward memo, or null: [N][L][2] (jump bits, gen) of the last
+    // computation of sc[l][n] (and, for l = 0, h0, h1, f of sample n); a block
+    // whose entry matches jump[n] and gen leaves them as they are
+    uint32_t* cache;
+    uint32_t gen;
 };
 // Forward prologue in one launch: the network input x[n][p] = BF16 (c - 1/2,
 // phi, rho - 1, jump[n]), the time basis f(jump) and every level's FiLM

@@ -708,6 +708,16 @@ __device__ __forceinline__ float row_dot(const float* W, const float* x, int len
 // usual widths (Hd, F <= 128, C_l <= 256).
 __device__ void mlp_block(const MLPArgs& a, int n, int l)
 {
+    // the block's outputs are a function of jump[n] and the parameters: when
+    // neither changed since the block last computed them, they are in place
+    __shared__ int memo_hit;
+    uint32_t* const memo = a.cache ? a.cache + 2 * (n * a.L + l) : nullptr;
+    const uint32_t jbits = __float_as_uint(a.jump[n]);
+    if (memo) {
+        if (threadIdx.x == 0) memo_hit = memo[0] == jbits && memo[1] == a.gen;
+        __syncthreads();
+        if (memo_hit) return;
+    }
     // every weight the block reads is loaded into registers at once, so
     // the chain of three products waits for one round of loads instead of
     // one per product; 32 lanes per row (lane
@@ -801,6 +811,10 @@ __device__ void mlp_block(const MLPArgs& a, int n, int l)
         for (int m = 0; m < 8; ++m) v[m] = dot(wl[m], fs);
         const int r = j0 + 32 * k;
         if (k < 8 && r < Cl) a.sc[l][n * Cl + r] = pick(v, 8);
+    }
+    if (memo && threadIdx.x == 0) {
+        memo[0] = jbits;
+        memo[1] = a.gen;
     }
 }
 

@@ -328,6 +328,48 @@ def test_inference_paths_equal_training_forward():
     net.close()
 
 
+def test_time_basis_memo_follows_jump_and_parameters():
+    """The time basis and FiLM scales of a sample are kept between forward
+    calls while its jump and the parameters stay the same: alternating
+    jumps, and a change of the MLP weights through set_params, give exactly
+    the outputs of a freshly created network."""
+    import torch
+
+    from paper_2312_05410_amd.unet import UNet
+
+    announce("time-basis memo 32x32 L3 base8 n2")
+    cfg = _cfg(32, 32, 3, 8, 4, 2)
+    net = UNet(cfg, seed=12)
+    p = net.param_dict()
+    p["head.gamma"][:] = 0.5
+    net.set_params(p)
+    st = [dev_f32(a) for a in _state(71, 2, 32, 32)]
+    ja = dev_f32(np.array([1.0, 3.0], dtype=np.float32))
+    jb = dev_f32(np.array([2.0, 3.0], dtype=np.float32))
+
+    def run(m, j, train=False):
+        out = m.forward(*st, j, train=train)
+        torch.cuda.synchronize()
+        return [t.clone() for t in out]
+
+    a1, b1, a2 = run(net, ja), run(net, jb), run(net, ja)
+    for x, y, z in zip(a1, b1, a2):
+        assert torch.equal(x, z)
+        assert not torch.equal(x[0], y[0]) and torch.equal(x[1], y[1])   # sample 1 kept its jump
+    fresh = UNet(cfg, params=p)
+    for x, y in zip(b1, run(fresh, jb)):
+        assert torch.equal(x, y)
+    fresh.close()
+    p["mlp.w2"] *= 1.5
+    net.set_params(p)
+    a3 = run(net, ja, train=True)
+    fresh = UNet(cfg, params=p)
+    for x, y, z in zip(a3, run(fresh, ja, train=True), a1):
+        assert torch.equal(x, y) and not torch.equal(x, z)
+    fresh.close()
+    net.close()
+
+
 @pytest.mark.parametrize("H,W,levels,base,groups,n", [(32, 32, 3, 8, 4, 2), (16, 24, 2, 16, 8, 3)])
 def test_network_gradients_match_oracle(H, W, levels, base, groups, n):
     import torch
