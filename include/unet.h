@@ -93,7 +93,11 @@ size_t unet_workspace_bytes(const unet_config* cfg);
 int unet_create(unet_handle** out, const unet_config* cfg, float* params, float* grads, void* workspace,
                 size_t workspace_bytes, void* stream);
 
-/* Refresh the BF16 weight copies after the caller changed `params`. */
+/* Refresh the BF16 weight copies after the caller changed `params`.  It
+ * also voids the forward's memo of the time basis: the time basis and FiLM
+ * scales of a sample are kept between forward calls while its jump and the
+ * parameters stay the same, so a caller that changes `params` must call
+ * this (unet_adam does) before the next forward. */
 int unet_prepare(unet_handle* h);
 
 /* Forward pass of n <= max_batch samples: jump[n] (device floats) is the
