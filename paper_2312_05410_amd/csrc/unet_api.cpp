@@ -70,7 +70,10 @@ struct Conv {
     bool folded = false;             // 4-channel input: forward operand [1][ldo_f][64], k = 4 tap + c
     uint16_t* wf = nullptr;          // BF16 forward operand [taps][ldo_f][ldk_f]
     uint16_t* wt = nullptr;          // BF16 transposed operand (input gradient)
-    int ldo_f = 0, ldk_f = 0, ldo_t = 0, ldk_t = 0;
+    // at most 4 output channels: the input gradient's kFirst operand
+    // [ldo_tk][64], k = 4 tap + c over the mirrored taps
+    uint16_t* wtk = nullptr;
+    int ldo_f = 0, ldk_f = 0, ldo_t = 0, ldk_t = 0, ldo_tk = 0;
 };
 
 struct Net {
@@ -181,6 +184,7 @@ struct Bufs {
     float* ds[kMaxLevels];
     double *lpart, *loss;
     float* wpart;
+    size_t wpart_floats;
     float* csum;
     double* cacc;
     size_t bytes;
@@ -207,6 +211,11 @@ void carve(Net& net, char* base, Bufs& b)
     b.xin = m.take<uint16_t>(net.P(0, n) * 4);
     size_t part = 0, csum = 0;
     int cmax = 0, gmax = 0;
+    // 3x3 weight gradients: the staged kernel's partials or, where the shape
+    // takes it, the halo-tile kernel's
+    auto wg9 = [](long P, int Nout, int C1, int C2) {
+        return std::max(wgrad_floats(P, 9, Nout, C1, C2), wgrad_halo_floats(Nout, C1, C2));
+    };
     auto note_gn = [&](long P1, int C, int G) {
         // partials: the normalisation's own chunks, or one per conv tile (>= 64 pixels)
         csum = std::max(csum, std::max(gn_csum_floats(n, (int)P1, C), (size_t)n * ((P1 + 63) / 64) * C * 3));
@@ -228,7 +237,7 @@ void carve(Net& net, char* base, Bufs& b)
         b.dz[l] = l < L - 1 ? m.take<float>(Pl * w[l]) : nullptr;
         note_gn(net.P(l, 1), w[l], c.groups);
         const Conv& k = net.enc[l];
-        part = std::max(part, wgrad_floats(Pl, 9, k.cout, k.cin1, 0));
+        part = std::max(part, wg9(Pl, k.cout, k.cin1, 0));
     }
     {
         const long Pm = net.P(L - 1, n);
@@ -237,7 +246,7 @@ void carve(Net& net, char* base, Bufs& b)
         b.stm = m.take<float>((size_t)n * c.groups * 2);
         b.dym = m.take<uint16_t>(Pm * w[L - 1]);
         b.dad[L - 1] = m.take<float>(Pm * w[L - 1]);
-        part = std::max(part, wgrad_floats(Pm, 9, w[L - 1], w[L - 1], 0));
+        part = std::max(part, wg9(Pm, w[L - 1], w[L - 1], 0));
     }
     for (int l = 0; l < L - 1; ++l) {
         const long Pl = net.P(l, n);
@@ -248,7 +257,7 @@ void carve(Net& net, char* base, Bufs& b)
         b.dad[l] = m.take<float>(Pl * w[l]);
         b.dyd[l] = m.take<uint16_t>(Pl * w[l]);
         b.dd[l] = m.take<uint16_t>(Pl * w[l]);
-        part = std::max(part, wgrad_floats(Pl, 9, w[l], w[l], w[l]));
+        part = std::max(part, wg9(Pl, w[l], w[l], w[l]));
         part = std::max(part, wgrad_floats(net.P(l + 1, n), 1, 4 * w[l], w[l + 1], 0));
     }
     {
@@ -258,7 +267,7 @@ void carve(Net& net, char* base, Bufs& b)
         b.gout = m.take<float>(P0 * c.out_ch);
         b.dyh = m.take<uint16_t>(P0 * c.out_ch);
         note_gn(net.P(0, 1), c.out_ch, c.head_groups);
-        part = std::max(part, wgrad_floats(P0, 9, c.out_ch, w[0], 0));
+        part = std::max(part, wg9(P0, c.out_ch, w[0], 0));
     }
     b.jump = m.take<float>((size_t)n);
     b.mlpc = m.take<uint32_t>((size_t)n * L * 2);
@@ -272,6 +281,7 @@ void carve(Net& net, char* base, Bufs& b)
     b.lpart = m.take<double>(rel_mse_partial_doubles());
     b.loss = m.take<double>(4);
     b.wpart = m.take<float>(part);
+    b.wpart_floats = part;
     b.csum = m.take<float>(csum);
     b.cacc = m.take<double>((size_t)n * (3 * cmax + 2 * gmax));
     // BF16 operand copies of every weight
@@ -290,6 +300,10 @@ void carve(Net& net, char* base, Bufs& b)
             k.ldo_t = (int)r128(Kc);
             k.ldk_t = (int)r32(R);
             k.wt = m.take<uint16_t>((size_t)k.taps * k.ldo_t * k.ldk_t);
+            if (k.taps == 9 && k.cout <= 4 && k.cin2 == 0) {
+                k.ldo_tk = (int)r128(Kc);
+                k.wtk = m.take<uint16_t>((size_t)k.ldo_tk * 64);
+            }
         }
     };
     for (int l = 0; l < L; ++l) wcopies(net.enc[l], l > 0);
@@ -327,11 +341,36 @@ bool al(const void* p, size_t a) { return p && ((uintptr_t)p % a) == 0; }
 float* par(unet_handle* h, int idx) { return h->params + h->net.params[idx].offset; }
 float* grd(unet_handle* h, int idx) { return h->grads + h->net.params[idx].offset; }
 
-int prep(unet_handle* h, Conv& k)
+// the operand copies of one convolution's weight
+void prep_items(unet_handle* h, const Conv& k, std::vector<PrepItem>& v)
 {
-    if (k.folded) return dev_err(weight_prep_folded(par(h, k.pw), k.cout, k.wf, k.ldo_f, h->stream));
-    const int R = k.taps == 9 ? k.cout : 4 * k.cout, Kc = k.cin1 + k.cin2;
-    return dev_err(weight_prep(par(h, k.pw), k.taps, R, Kc, k.wf, k.ldo_f, k.ldk_f, k.wt, k.ldo_t, k.ldk_t, h->stream));
+    PrepItem p{};
+    p.W = par(h, k.pw);
+    p.taps = k.taps;
+    p.R = k.taps == 9 ? k.cout : 4 * k.cout;
+    p.Kc = k.cin1 + k.cin2;
+    if (k.folded) {
+        p.kind = kPrepFirst;
+        p.fwd = k.wf;
+        p.ldo_f = k.ldo_f;
+        v.push_back(p);
+        return;
+    }
+    p.kind = kPrepPlain;
+    p.fwd = k.wf;
+    p.ldo_f = k.ldo_f;
+    p.ldk_f = k.ldk_f;
+    p.tr = k.wt;
+    p.ldo_t = k.ldo_t;
+    p.ldk_t = k.ldk_t;
+    v.push_back(p);
+    if (k.wtk) {
+        p.kind = kPrepFirstGrad;
+        p.fwd = nullptr;
+        p.tr = k.wtk;
+        p.ldo_t = k.ldo_tk;
+        v.push_back(p);
+    }
 }
 
 int prepare_all(unet_handle* h)
@@ -340,13 +379,14 @@ int prepare_all(unet_handle* h)
     // the time basis memo (sc[l][n] keyed by jump[n] and this generation)
     // is void from here on
     if (++h->param_gen == 0) h->param_gen = 1;
-    int rc = PF_OK;
-    for (int l = 0; l < net.L && rc == PF_OK; ++l) rc = prep(h, net.enc[l]);
-    if (rc == PF_OK) rc = prep(h, net.mid);
-    for (int l = 1; l < net.L && rc == PF_OK; ++l) rc = prep(h, net.up[l]);
-    for (int l = 0; l < net.L - 1 && rc == PF_OK; ++l) rc = prep(h, net.dec[l]);
-    if (rc == PF_OK) rc = prep(h, net.head);
-    return rc;
+    // every weight's operand copies in one launch
+    std::vector<PrepItem> v;
+    for (int l = 0; l < net.L; ++l) prep_items(h, net.enc[l], v);
+    prep_items(h, net.mid, v);
+    for (int l = 1; l < net.L; ++l) prep_items(h, net.up[l], v);
+    for (int l = 0; l < net.L - 1; ++l) prep_items(h, net.dec[l], v);
+    prep_items(h, net.head, v);
+    return dev_err(weight_prep_batch(v.data(), (int)v.size(), h->stream));
 }
 
 ConvArgs conv_args(const Conv& k, int n, int H, int W, const uint16_t* x1, const uint16_t* x2)
@@ -412,6 +452,7 @@ WgradArgs wgrad_args(unet_handle* h, int n, int H, int W, const uint16_t* dy, in
     a.x1 = x1;
     a.x2 = x2;
     a.partial = h->b.wpart;
+    a.partial_cap = h->b.wpart_floats;
     a.N = n;
     a.H = H;
     a.W = W;
@@ -597,7 +638,19 @@ int backward(unet_handle* h, const float* pc, const float* pphi, const float* pr
                           grd(h, net.head.pw), 0, s));
         ConvArgs a = dgrad_args(net.head, n, Hl(0), Wl(0), b.dyh);
         a.out_f32 = b.dad[0];
-        UCHECK(conv_gemm(a, kConvDgrad, s));
+        int mode = kConvDgrad;
+        if (net.head.wtk) {
+            // few output channels: taps folded into K (the first layer's kernel)
+            ConvArgs t = a;
+            t.Wt = net.head.wtk;
+            t.ldk = 64;
+            t.ldo = net.head.ldo_tk;
+            if (conv_wide_ok(t, kFirst)) {
+                a = t;
+                mode = kFirst;
+            }
+        }
+        UCHECK(conv_gemm(a, mode, s));
     }
     // decoder, top to bottom
     for (int l = 0; l < L - 1; ++l) {
@@ -916,6 +969,27 @@ int unet_conv3x3_dgrad(int n, int H, int W, const uint16_t* dy, int Cout, const 
     a.O1 = C1;
     a.ldk = (int)r32(Cout);
     a.ldo = (int)r128(K);
+    if (Cout <= 4 && C2 == 0) {
+        // few gradient channels: taps folded into K, as in the network's head
+        ConvArgs t = a;
+        uint16_t* wk = ws.take<uint16_t>(r128(K) * 64);
+        t.Wt = wk;
+        t.ldk = 64;
+        t.ldo = (int)r128(K);
+        if (ws.ok && conv_wide_ok(t, kFirst)) {
+            PrepItem p{};
+            p.kind = kPrepFirstGrad;
+            p.W = w;
+            p.taps = 9;
+            p.R = Cout;
+            p.Kc = K;
+            p.tr = wk;
+            p.ldo_t = t.ldo;
+            UCHECK(weight_prep_batch(&p, 1, s));
+            UCHECK(conv_gemm(t, kFirst, s));
+            return PF_OK;
+        }
+    }
     UCHECK(conv_gemm(a, kConvDgrad, s));
     return PF_OK;
 }
@@ -940,7 +1014,9 @@ int unet_conv3x3_wgrad(int n, int H, int W, const uint16_t* dy, int Cout, const 
     a.C2 = C2;
     a.Nout = Cout;
     a.chunk = wgrad_chunk(P, 9, Cout, C1, C2);
-    a.partial = ws.take<float>(wgrad_floats(P, 9, Cout, C1, C2));
+    const size_t pf = wgrad_floats(P, 9, Cout, C1, C2);
+    a.partial = ws.take<float>(pf);
+    a.partial_cap = pf;
     if (!ws.ok) return PF_EINVAL;
     UCHECK(conv_wgrad(a, kConvFwd, dw, 0, (hipStream_t)stream));
     return PF_OK;

@@ -25,6 +25,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include "unet_gelu.h"
 #include "unet_kernels.h"
 
@@ -286,6 +288,29 @@ __global__ __launch_bounds__(256) void gemm32_kernel(ConvArgs a)
                     const float cv = a.raw[0][q], pv = a.raw[1][q], rv = a.raw[2][q], jv = a.jump[px[i].n];
                     const uint32_t lo = (uint32_t)f2bf(cv - 0.5f) | ((uint32_t)f2bf(pv) << 16);
                     const uint32_t hi = (uint32_t)f2bf(rv - 1.0f) | ((uint32_t)f2bf(jv) << 16);
+                    h[u] = ok ? make_uint2(lo, hi) : make_uint2(0, 0);
+                }
+                A[i] = __builtin_bit_cast(bf16x8, make_uint4(h[0].x, h[0].y, h[1].x, h[1].y));
+            }
+        } else if (MODE == kFirst && a.C1 < 4) {
+            // one to three channels per pixel (the head's output gradient),
+            // the missing ones zero: indices clamped into the grid so that
+            // the loads are unconditional, taps outside it zeroed afterwards
+            const int t0 = (k0 + kq) >> 2;
+#pragma unroll
+            for (int i = 0; i < TM; ++i) {
+                uint2 h[2];
+#pragma unroll
+                for (int u = 0; u < 2; ++u) {
+                    const int t = t0 + u, tc = t < 9 ? t : 8;
+                    const int yy = px[i].y + tc / 3 - 1, xx = px[i].x + tc % 3 - 1;
+                    const bool ok = px[i].ok && t < 9 && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
+                    const long q = px[i].ok ? ((long)px[i].n * a.H + min(max(yy, 0), a.H - 1)) * a.W +
+                                                  min(max(xx, 0), a.W - 1)
+                                            : 0;
+                    const uint16_t* e = a.in1 + a.C1 * q;
+                    const uint32_t c1 = a.C1 > 1 ? e[1] : 0u, c2 = a.C1 > 2 ? e[2] : 0u;
+                    const uint32_t lo = (uint32_t)e[0] | (c1 << 16), hi = c2;
                     h[u] = ok ? make_uint2(lo, hi) : make_uint2(0, 0);
                 }
                 A[i] = __builtin_bit_cast(bf16x8, make_uint4(h[0].x, h[0].y, h[1].x, h[1].y));
@@ -934,11 +959,13 @@ __global__ __launch_bounds__(256) void wgrad_kernel(WgradArgs a)
 // the transposition is free of bank conflicts.  The next step's operands are
 // loaded into registers while the current step is multiplied.  VEC: all
 // channel counts are multiples of 8 and rows 16-byte aligned (16-byte loads);
-// else 8 guarded 2-byte loads per piece.  FOLD (3x3 layers with fewer than
-// 8 channels on one side): 1 folds the nine taps into the input-channel
-// side (row k' = 9-tap index * K + c of x at the tap's shifted pixel), 2 into
-// the output side (row o' = tap * Nout + o of dy at the pixel shifted back,
-// which pairs the same products); one block then covers all taps.
+// else 8 guarded 2-byte loads per piece; with FOLD 2, VEC concerns the
+// input side; with FOLD 1, dy and the folded 4-channel input, read as 8-byte
+// tap pairs.  FOLD (3x3 layers with fewer than 8 channels on one side): 1
+// folds the nine taps into the input-channel side (row k' = 9-tap index * K
+// + c of x at the tap's shifted pixel), 2 into the output side (row
+// o' = tap * Nout + o of dy at the pixel shifted back, which pairs the same
+// products); one block then covers all taps.
 // blockIdx.z = chunk * taps + tap (taps = 9 unfolded 3x3, else 1).
 constexpr int kWgStep = 64;                // pixels per step
 constexpr int kWgRow = kWgStep + 8;        // LDS row length (elements)
@@ -962,10 +989,10 @@ __global__ __launch_bounds__(256) void wgrad32_kernel(WgradArgs a)
     const int r = lane & 15, kq = (lane >> 4) * 8;
     f32x4 acc[2][2] = {};
 
-    auto piece = [&](const uint16_t* base, int C, int c, bool ok) {
+    auto piece = [&](const uint16_t* base, int C, int c, bool ok, bool vec) {
         uint4 v = make_uint4(0, 0, 0, 0);
         if (!ok) return v;
-        if (VEC) return *(const uint4*)(base + c);
+        if (vec) return *(const uint4*)(base + c);
         uint16_t* e = (uint16_t*)&v;
         for (int j = 0; j < 8; ++j)
             if (c + j < C) e[j] = base[c + j];
@@ -975,17 +1002,36 @@ __global__ __launch_bounds__(256) void wgrad32_kernel(WgradArgs a)
     // field at pixel (y + sy (t / 3 - 1), x + sy (t % 3 - 1)) of sample n
     auto folded = [&](const uint16_t* f, int C, int g, const Pix& q, int sy) {
         uint4 v = make_uint4(0, 0, 0, 0);
-        uint16_t* e = (uint16_t*)&v;
         if (!q.ok) return v;
-        for (int j = 0; j < 8; ++j) {
-            const int row = g + j;
-            if (row >= 9 * C) break;
-            const int t = row / C, c = row - t * C;
-            const int yy = q.y + sy * (t / 3 - 1), xx = q.x + sy * (t % 3 - 1);
-            if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
-                e[j] = f[(((size_t)q.n * a.H + yy) * a.W + xx) * C + c];
+        if (VEC && FOLD == 1) {
+            // C = 4 (the launcher checks): the 8 rows are all channels of
+            // taps g / 4 and g / 4 + 1, one 8-byte load each
+            uint2 h[2] = {make_uint2(0, 0), make_uint2(0, 0)};
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int t = g / 4 + u;
+                const int yy = q.y + sy * (t / 3 - 1), xx = q.x + sy * (t % 3 - 1);
+                if (t < 9 && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
+                    h[u] = *(const uint2*)(f + (((size_t)q.n * a.H + yy) * a.W + xx) * 4);
+            }
+            return make_uint4(h[0].x, h[0].y, h[1].x, h[1].y);
         }
-        return v;
+        // element j (static indices: the pieces stay in registers)
+        uint32_t w[4] = {0u, 0u, 0u, 0u};
+        int t = g / C, c = g - t * C;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            if (t < 9) {
+                const int yy = q.y + sy * (t / 3 - 1), xx = q.x + sy * (t % 3 - 1);
+                if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W)
+                    w[j / 2] |= (uint32_t)f[(((size_t)q.n * a.H + yy) * a.W + xx) * C + c] << (16 * (j & 1));
+                if (++c == C) {
+                    c = 0;
+                    ++t;
+                }
+            }
+        }
+        return make_uint4(w[0], w[1], w[2], w[3]);
     };
     uint4 va[2], vb[2];
     auto gload = [&](int p0) {
@@ -1001,9 +1047,9 @@ __global__ __launch_bounds__(256) void wgrad32_kernel(WgradArgs a)
                 const int Co = a.Nout >> 2, sub = o / Co, co = o - sub * Co;
                 const uint16_t* base =
                     a.dy + (((size_t)q.n * 2 * a.H + 2 * q.y + (sub >> 1)) * 2 * a.W + 2 * q.x + (sub & 1)) * Co;
-                va[u] = piece(base, Co, co, q.ok && o < a.Nout);
+                va[u] = piece(base, Co, co, q.ok && o < a.Nout, VEC);
             } else {
-                va[u] = piece(a.dy + (size_t)p * a.Nout, a.Nout, o, q.ok && o < a.Nout);
+                va[u] = piece(a.dy + (size_t)p * a.Nout, a.Nout, o, q.ok && o < a.Nout, VEC);
             }
             const int k = k0 + sg;
             if (FOLD == 1) {
@@ -1012,8 +1058,8 @@ __global__ __launch_bounds__(256) void wgrad32_kernel(WgradArgs a)
                 const int yy = q.y + dy, xx = q.x + dx;
                 const bool xin = q.ok && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W && k < K;
                 const size_t xo = ((size_t)q.n * a.H + yy) * a.W + xx;
-                if (k < a.C1) vb[u] = piece(a.x1 + xo * a.C1, a.C1, k, xin);
-                else vb[u] = piece(a.x2 + xo * a.C2, a.C2, k - a.C1, xin);
+                if (k < a.C1) vb[u] = piece(a.x1 + xo * a.C1, a.C1, k, xin, VEC);
+                else vb[u] = piece(a.x2 + xo * a.C2, a.C2, k - a.C1, xin, VEC);
             }
         }
     };
@@ -1079,6 +1125,138 @@ __global__ __launch_bounds__(256) void wgrad32_kernel(WgradArgs a)
         }
 }
 
+// Halo-tile weight gradient of a 3x3 convolution, all nine taps in one
+// block: dW[t][o][k] = sum_p dy[p][o] x[p + d(t)][k].  A block owns 32
+// output channels o, 64 input channels k and a run of 4 x 32 pixel tiles of
+// one or more samples; per tile it stages dy [128 px][32 o] and the 6 x 34
+// halo of x [204 px][64 k] in LDS in their memory layout ([pixel][channel],
+// 16-byte pieces) and reads the MFMA operands, whose contraction runs over
+// pixels, with the LDS transpose read: in each 16-lane group, lane i gives
+// the address of row i / 4, columns 4 (i % 4) .. + 3 of a 4 x 16 block of
+// 16-bit values and receives column i, so with rows = 4 consecutive pixels
+// and columns = 16 channels lane i gets channel i at those 4 pixels (two
+// reads make one 8-pixel operand).  Wave w takes input channels 16 w .. of
+// the block's 64, both 16-channel halves of its outputs and all nine taps:
+// per 32-pixel row segment the two dy operands serve the nine taps and each
+// tap's x operand both halves (22 transpose reads for 18 MFMAs; NARROW,
+// fewer than 8 output channels: dy staged by 2-byte loads, one half).  Row
+// pitches of 160 (x) and 96 (dy) bytes put the 16 addresses of a read in
+// distinct banks.  The next tile is loaded into registers while the current
+// one is used.  Pixels outside the image are staged as zeros.
+constexpr int kWhTH = 4, kWhTW = 32, kWhO = 32, kWhK = 64;
+constexpr int kWhXP = kWhK + 16, kWhDP = kWhO + 16;   // row pitches (elements)
+constexpr int kWhBlocks = 512;                        // two blocks per CU
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+
+// 8 consecutive pixels (px + 8 q .. + 7 for this lane's group q) of channel
+// ch + lane % 16 from a [pixel][channel] LDS array of row pitch `pitch`
+__device__ __forceinline__ bf16x8 tr_operand(const uint16_t* base, int pitch, int px, int ch, int lane)
+{
+    const int gl = lane & 15, q = lane >> 4;
+    const uint16_t* p = base + (px + 8 * q + (gl >> 2)) * pitch + ch + 4 * (gl & 3);
+    typedef __attribute__((address_space(3))) s16x4 lds_s16x4;
+    const s16x4 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)p);
+    const s16x4 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s16x4*)(p + 4 * pitch));
+    return __builtin_bit_cast(bf16x8, (s16x8)__builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
+}
+
+template <bool NARROW>
+__global__ __launch_bounds__(256, 2) void wgrad_halo_kernel(WgradArgs a, int tpc)
+{
+    constexpr int HP = kWhTH + 2, WP = kWhTW + 2, NX = HP * WP, ND = kWhTH * kWhTW;
+    constexpr int PX = kWhK / 8, PD = kWhO / 8;
+    constexpr int NA = NX * PX, NB = ND * PD, NLD = (NA + NB + 255) / 256;
+    __shared__ __align__(16) uint16_t xs[NX * kWhXP];
+    __shared__ __align__(16) uint16_t ds[ND * kWhDP];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int o0 = blockIdx.x * kWhO, k0 = blockIdx.y * kWhK, chunk = blockIdx.z;
+    const int K = a.C1 + a.C2;
+    const int tx = (a.W + kWhTW - 1) / kWhTW, tps = tx * ((a.H + kWhTH - 1) / kWhTH);
+    const int T = a.N * tps, t0 = chunk * tpc, t1 = min(T, t0 + tpc);
+    uint4 st[NLD];
+    // piece e = tid + 256 u: x halo pixel e / PX, channels 8 (e % PX) ..;
+    // else dy pixel (e - NA) / PD, channels 8 ((e - NA) % PD) ..
+    auto gload = [&](int t) {
+        const int n = t / tps, tt = t - n * tps, y0 = (tt / tx) * kWhTH, x0 = (tt % tx) * kWhTW;
+#pragma unroll
+        for (int u = 0; u < NLD; ++u) {
+            const int e = tid + 256 * u;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (e < NA) {
+                const int px = e / PX, k = k0 + 8 * (e % PX);
+                const int gy = y0 - 1 + px / WP, gx = x0 - 1 + px % WP;
+                if (gy >= 0 && gy < a.H && gx >= 0 && gx < a.W && k < K) {
+                    const size_t pix = ((size_t)n * a.H + gy) * a.W + gx;
+                    v = k < a.C1 ? *(const uint4*)(a.x1 + pix * a.C1 + k) : *(const uint4*)(a.x2 + pix * a.C2 + (k - a.C1));
+                }
+            } else if (e < NA + NB) {
+                const int px = (e - NA) / PD, o = o0 + 8 * ((e - NA) % PD);
+                const int gy = y0 + px / kWhTW, gx = x0 + px % kWhTW;
+                const size_t pix = ((size_t)n * a.H + gy) * a.W + gx;
+                if (NARROW) {
+                    // fewer than 8 output channels: one piece, 2-byte loads
+                    if (gy < a.H && gx < a.W && o == 0) {
+                        uint16_t h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+                        for (int c = 0; c < 8; ++c)
+                            if (c < a.Nout) h[c] = a.dy[pix * a.Nout + c];
+                        v = make_uint4(h[0] | ((uint32_t)h[1] << 16), h[2] | ((uint32_t)h[3] << 16),
+                                       h[4] | ((uint32_t)h[5] << 16), h[6] | ((uint32_t)h[7] << 16));
+                    }
+                } else if (gy < a.H && gx < a.W && o < a.Nout) {
+                    v = *(const uint4*)(a.dy + pix * a.Nout + o);
+                }
+            }
+            st[u] = v;
+        }
+    };
+    auto lstore = [&]() {
+#pragma unroll
+        for (int u = 0; u < NLD; ++u) {
+            const int e = tid + 256 * u;
+            if (e < NA) *(uint4*)(&xs[(e / PX) * kWhXP + 8 * (e % PX)]) = st[u];
+            else if (e < NA + NB) *(uint4*)(&ds[((e - NA) / PD) * kWhDP + 8 * ((e - NA) % PD)]) = st[u];
+        }
+    };
+    f32x4 acc[9][2];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) acc[t][0] = acc[t][1] = (f32x4){0.f, 0.f, 0.f, 0.f};
+    if (t0 < t1) gload(t0);
+    for (int t = t0; t < t1; ++t) {
+        if (t > t0) __syncthreads();   // every wave is done with the previous tile
+        lstore();
+        __syncthreads();
+        if (t + 1 < t1) gload(t + 1);
+#pragma unroll
+        for (int r = 0; r < kWhTH; ++r) {
+            const bf16x8 A0 = tr_operand(ds, kWhDP, r * kWhTW, 0, lane);
+            const bf16x8 A1 = NARROW ? A0 : tr_operand(ds, kWhDP, r * kWhTW, 16, lane);
+#pragma unroll
+            for (int tap = 0; tap < 9; ++tap) {
+                const int hy = r + tap / 3, hx = tap % 3;   // halo row r + 1 + dy, column + 1 + dx
+                const bf16x8 B = tr_operand(xs, kWhXP, hy * WP + hx, 16 * wv, lane);
+                acc[tap][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, B, acc[tap][0], 0, 0, 0);
+                if (!NARROW) acc[tap][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, B, acc[tap][1], 0, 0, 0);
+            }
+        }
+    }
+    // acc[tap][j][e]: o = o0 + 16 j + 4 (lane / 16) + e, k = k0 + 16 wv + lane % 16
+    const int k = k0 + 16 * wv + (lane & 15), rq = (lane >> 4) * 4;
+    if (k >= K) return;
+#pragma unroll
+    for (int tap = 0; tap < 9; ++tap) {
+        float* part = a.partial + ((size_t)chunk * 9 + tap) * a.Nout * K;
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int o = o0 + 16 * j + rq + e;
+                if (o < a.Nout) part[(size_t)o * K + k] = acc[tap][j][e];
+            }
+    }
+}
+
 // Sum of the per-chunk partials: a block owns 64 consecutive outputs
 // (coalesced rows) and splits the chunks over blockDim.y lanes (chunk c goes
 // to lane c mod blockDim.y), whose sums are combined by a fixed LDS tree, so
@@ -1120,27 +1298,42 @@ static void launch_wsum(const float* partial, float* dW, size_t n, int chunks, i
                        accumulate);
 }
 
-__global__ __launch_bounds__(256) void prep_kernel(const float* W, int taps, int R, int Kc, uint16_t* fwd, int ldo_f,
-                                                   int ldk_f, uint16_t* tr, int ldo_t, int ldk_t)
+// Every item's BF16 operand copies in one launch: element i of the batch
+// belongs to the first item whose end lies above it (items in order).
+__device__ __forceinline__ void prep_elem(const PrepItem& p, uint32_t i)
 {
-    const size_t nf = fwd ? (size_t)taps * ldo_f * ldk_f : 0, nt = tr ? (size_t)taps * ldo_t * ldk_t : 0;
-    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < nf + nt; i += (size_t)gridDim.x * 256) {
+    // 32-bit index arithmetic: every item holds fewer than 2^31 elements
+    if (p.kind == kPrepPlain) {
+        const uint32_t nf = p.fwd ? (uint32_t)(p.taps * p.ldo_f * p.ldk_f) : 0u;
         if (i < nf) {
-            const int k = (int)(i % ldk_f), o = (int)((i / ldk_f) % ldo_f), t = (int)(i / ((size_t)ldk_f * ldo_f));
-            fwd[i] = (o < R && k < Kc) ? f2bf(W[((size_t)t * R + o) * Kc + k]) : 0;
+            const uint32_t ro = i / (uint32_t)p.ldk_f, k = i - ro * (uint32_t)p.ldk_f;
+            const uint32_t t = ro / (uint32_t)p.ldo_f, o = ro - t * (uint32_t)p.ldo_f;
+            p.fwd[i] = ((int)o < p.R && (int)k < p.Kc) ? f2bf(p.W[((size_t)t * p.R + o) * p.Kc + k]) : 0;
         } else {
-            const size_t j = i - nf;
-            const int k = (int)(j % ldk_t), o = (int)((j / ldk_t) % ldo_t), t = (int)(j / ((size_t)ldk_t * ldo_t));
-            tr[j] = (o < Kc && k < R) ? f2bf(W[((size_t)t * R + k) * Kc + o]) : 0;
+            const uint32_t j = i - nf;
+            const uint32_t ro = j / (uint32_t)p.ldk_t, k = j - ro * (uint32_t)p.ldk_t;
+            const uint32_t t = ro / (uint32_t)p.ldo_t, o = ro - t * (uint32_t)p.ldo_t;
+            p.tr[j] = ((int)o < p.Kc && (int)k < p.R) ? f2bf(p.W[((size_t)t * p.R + k) * p.Kc + o]) : 0;
         }
+        return;
+    }
+    const int o = (int)(i / 64), k = (int)(i % 64), t = k / 4, c = k % 4;
+    if (p.kind == kPrepFirst) {
+        p.fwd[i] = (o < p.R && t < 9) ? f2bf(p.W[((size_t)t * p.R + o) * 4 + c]) : 0;
+    } else {
+        // input gradient: output channel o is the weight's input channel,
+        // c its output channel, and the tap is mirrored
+        p.tr[i] = (o < p.Kc && t < 9 && c < p.R) ? f2bf(p.W[((size_t)(8 - t) * p.R + c) * p.Kc + o]) : 0;
     }
 }
 
-__global__ __launch_bounds__(256) void fold_kernel(const float* W, int R, uint16_t* out, int ldo)
+__global__ __launch_bounds__(256) void prep_batch_kernel(PrepBatch b)
 {
-    for (int i = blockIdx.x * 256 + threadIdx.x; i < ldo * 64; i += gridDim.x * 256) {
-        const int o = i / 64, k = i % 64, t = k / 4, c = k % 4;
-        out[i] = (o < R && t < 9) ? f2bf(W[((size_t)t * R + o) * 4 + c]) : 0;
+    const size_t total = b.end[b.n - 1], stride = (size_t)gridDim.x * 256;
+    int j = 0;
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < total; i += stride) {
+        while (i >= b.end[j]) ++j;
+        prep_elem(b.it[j], (uint32_t)(i - (j ? b.end[j - 1] : 0)));
     }
 }
 
@@ -1251,8 +1444,9 @@ bool conv_wide_ok(const ConvArgs& a, int mode)
 {
     const auto al = [](const void* p, uintptr_t b) { return ((uintptr_t)p & (b - 1)) == 0; };
     if (mode == kFirst)
-        return a.C1 == 4 && a.C2 == 0 && a.ldk == 64 && a.ldo % 128 == 0 &&
-               (a.raw[0] ? a.raw[1] && a.raw[2] && a.jump : al(a.in1, 8)) && al(a.Wt, 16);
+        return a.C2 == 0 && a.ldk == 64 && a.ldo % 128 == 0 && al(a.Wt, 16) &&
+               (a.raw[0] ? a.C1 == 4 && a.raw[1] && a.raw[2] && a.jump
+                         : a.in1 && (a.C1 == 4 ? al(a.in1, 8) : a.C1 >= 1 && a.C1 <= 3 && al(a.in1, 2)));
     const bool chans = mode == kUpDgrad ? (a.C1 % 128 == 0 && a.C2 == 0) : (a.C1 % 32 == 0 && a.C2 % 32 == 0);
     return chans && a.ldk % 32 == 0 && a.ldo % 128 == 0 && al(a.in1, 16) && (!a.in2 || al(a.in2, 16)) &&
            al(a.Wt, 16);
@@ -1335,6 +1529,24 @@ int wgrad_blocks_per_chunk(int mode, int Nout, int C1, int C2)
     return taps * ((No + 63) / 64) * ((Ko + 63) / 64);
 }
 
+// The halo-tile kernel's shape conditions and chunking: 8-channel pieces
+// (16-byte aligned) that never straddle the two inputs, and about
+// kWhBlocks blocks over the (o, k) tile pairs and pixel-tile chunks.
+static bool wgrad_halo_shape(int Nout, int C1, int C2)
+{
+    return Nout >= 1 && (Nout < 8 || Nout % 8 == 0) && C1 % 8 == 0 && C2 % 8 == 0 && C1 + C2 >= 8;
+}
+static long wgrad_halo_want(int Nout, int C1, int C2)
+{
+    const long pairs = (long)((Nout + kWhO - 1) / kWhO) * ((C1 + C2 + kWhK - 1) / kWhK);
+    return std::max(1L, (kWhBlocks + pairs - 1) / pairs);
+}
+size_t wgrad_halo_floats(int Nout, int C1, int C2)
+{
+    if (!wgrad_halo_shape(Nout, C1, C2)) return 0;
+    return (size_t)wgrad_halo_want(Nout, C1, C2) * 9 * Nout * (C1 + C2);
+}
+
 hipError_t conv_wgrad(const WgradArgs& a, int mode, float* dW, int accumulate, hipStream_t s)
 {
     const long P = (long)a.N * a.H * a.W;
@@ -1346,20 +1558,46 @@ hipError_t conv_wgrad(const WgradArgs& a, int mode, float* dW, int accumulate, h
         if (!accumulate) launch_wsum(a.partial, dW, n, 0, 0, s);
         return hipGetLastError();
     }
+    const auto al16 = [](const void* q) { return ((uintptr_t)q & 15) == 0; };
+    if (mode == kConvFwd && wgrad_halo_shape(a.Nout, a.C1, a.C2) && (a.Nout < 8 || al16(a.dy)) && al16(a.x1) &&
+        (!a.x2 || al16(a.x2)) && (a.C2 == 0 || a.x2)) {
+        // halo tiles: chunks of whole 4 x 32 pixel tiles, as many as fit the
+        // partial buffer (up to the wanted number)
+        const long tiles = (long)a.N * ((a.H + kWhTH - 1) / kWhTH) * ((a.W + kWhTW - 1) / kWhTW);
+        const size_t per = n;   // floats of one chunk's partial
+        long chunks = std::min(wgrad_halo_want(a.Nout, a.C1, a.C2), tiles);
+        chunks = std::min<long>(chunks, (long)(a.partial_cap / per));
+        if (chunks >= 1) {
+            const int tpc = (int)((tiles + chunks - 1) / chunks);
+            chunks = (tiles + tpc - 1) / tpc;
+            dim3 grid((unsigned)((a.Nout + kWhO - 1) / kWhO), (unsigned)((K + kWhK - 1) / kWhK), (unsigned)chunks);
+            if (a.Nout < 8) hipLaunchKernelGGL(wgrad_halo_kernel<true>, grid, dim3(256), 0, s, a, tpc);
+            else hipLaunchKernelGGL(wgrad_halo_kernel<false>, grid, dim3(256), 0, s, a, tpc);
+            hipError_t e = hipGetLastError();
+            if (e != hipSuccess) return e;
+            launch_wsum(a.partial, dW, n, (int)chunks, accumulate, s);
+            return hipGetLastError();
+        }
+    }
     const int chunks = (int)((P + a.chunk - 1) / a.chunk);
     const int fold = wgrad_fold(mode, a.Nout, a.C1, a.C2);
     const int No = fold == 2 ? 9 * a.Nout : a.Nout, Ko = fold == 1 ? 9 * K : K;
     const int gz = chunks * (mode == kConvFwd && fold == 0 ? 9 : 1);
     dim3 grid((unsigned)((No + 63) / 64), (unsigned)((Ko + 63) / 64), (unsigned)gz);
-    const auto al16 = [](const void* q) { return ((uintptr_t)q & 15) == 0; };
     const bool vec = a.Nout % 8 == 0 && (mode == kConvFwd || (a.Nout / 4) % 8 == 0) && a.C1 % 8 == 0 &&
                      a.C2 % 8 == 0 && al16(a.dy) && al16(a.x1) && (!a.x2 || al16(a.x2));
     // 8-channel pieces must not cross a sub-pixel of the up-sampling's dy
     // or the boundary of a concatenated input
+    // folded: VEC covers the side that is not folded (16-byte pieces) and,
+    // for a folded 4-channel input, its 8-byte tap pairs
     if (fold == 2) {
-        hipLaunchKernelGGL((wgrad32_kernel<kConvFwd, false, 2>), grid, dim3(256), 0, s, a);
+        const bool vx = a.C1 % 8 == 0 && a.C2 % 8 == 0 && al16(a.x1) && (!a.x2 || al16(a.x2));
+        if (vx) hipLaunchKernelGGL((wgrad32_kernel<kConvFwd, true, 2>), grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((wgrad32_kernel<kConvFwd, false, 2>), grid, dim3(256), 0, s, a);
     } else if (fold == 1) {
-        hipLaunchKernelGGL((wgrad32_kernel<kConvFwd, false, 1>), grid, dim3(256), 0, s, a);
+        const bool vd = a.Nout % 8 == 0 && al16(a.dy) && a.C1 == 4 && ((uintptr_t)a.x1 & 7) == 0;
+        if (vd) hipLaunchKernelGGL((wgrad32_kernel<kConvFwd, true, 1>), grid, dim3(256), 0, s, a);
+        else hipLaunchKernelGGL((wgrad32_kernel<kConvFwd, false, 1>), grid, dim3(256), 0, s, a);
     } else if (!vec && ((mode == kUpFwd && (a.Nout / 4) % 8 != 0) || (a.C2 > 0 && a.C1 % 8 != 0))) {
         if (mode == kConvFwd) hipLaunchKernelGGL(wgrad_kernel<kConvFwd>, grid, dim3(256), 0, s, a);
         else hipLaunchKernelGGL(wgrad_kernel<kUpFwd>, grid, dim3(256), 0, s, a);
@@ -1376,20 +1614,58 @@ hipError_t conv_wgrad(const WgradArgs& a, int mode, float* dW, int accumulate, h
     return hipGetLastError();
 }
 
+size_t prep_item_size(const PrepItem& p)
+{
+    if (p.kind == kPrepPlain)
+        return (p.fwd ? (size_t)p.taps * p.ldo_f * p.ldk_f : 0) + (p.tr ? (size_t)p.taps * p.ldo_t * p.ldk_t : 0);
+    return (size_t)(p.kind == kPrepFirst ? p.ldo_f : p.ldo_t) * 64;
+}
+
+hipError_t weight_prep_batch(const PrepItem* items, int n, hipStream_t s)
+{
+    PrepBatch b{};
+    size_t total = 0;
+    for (int i = 0; i < n; ++i) {
+        const size_t m = prep_item_size(items[i]);
+        if (!m) continue;
+        if (m >= ((size_t)1 << 31)) return hipErrorInvalidValue;
+        if (b.n == kMaxPrep) return hipErrorInvalidValue;
+        total += m;
+        b.it[b.n] = items[i];
+        b.end[b.n++] = total;
+    }
+    if (!b.n) return hipSuccess;
+    hipLaunchKernelGGL(prep_batch_kernel, dim3(grid_for(total)), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+
 hipError_t weight_prep_folded(const float* W, int R, uint16_t* out, int ldo, hipStream_t s)
 {
-    hipLaunchKernelGGL(fold_kernel, dim3(grid_for((size_t)ldo * 64)), dim3(256), 0, s, W, R, out, ldo);
-    return hipGetLastError();
+    PrepItem p{};
+    p.kind = kPrepFirst;
+    p.W = W;
+    p.R = R;
+    p.fwd = out;
+    p.ldo_f = ldo;
+    return weight_prep_batch(&p, 1, s);
 }
 
 hipError_t weight_prep(const float* W, int taps, int R, int Kc, uint16_t* fwd, int ldo_f, int ldk_f, uint16_t* tr,
                        int ldo_t, int ldk_t, hipStream_t s)
 {
-    const size_t n = (fwd ? (size_t)taps * ldo_f * ldk_f : 0) + (tr ? (size_t)taps * ldo_t * ldk_t : 0);
-    if (!n) return hipSuccess;
-    hipLaunchKernelGGL(prep_kernel, dim3(grid_for(n)), dim3(256), 0, s, W, taps, R, Kc, fwd, ldo_f, ldk_f, tr, ldo_t,
-                       ldk_t);
-    return hipGetLastError();
+    PrepItem p{};
+    p.kind = kPrepPlain;
+    p.W = W;
+    p.taps = taps;
+    p.R = R;
+    p.Kc = Kc;
+    p.fwd = fwd;
+    p.ldo_f = ldo_f;
+    p.ldk_f = ldk_f;
+    p.tr = tr;
+    p.ldo_t = ldo_t;
+    p.ldk_t = ldk_t;
+    return weight_prep_batch(&p, 1, s);
 }
 
 }  // namespace pfu

@@ -37,8 +37,9 @@ __device__ __forceinline__ void stwt(const float* base, size_t idx, float v)
 
 // Implicit GEMM out[p][o] = sum_k A[p][k] B[o][k]; see unet_conv.hip for
 // the four gather/scatter modes.
-// kFirst: 3x3 convolution of a 4-channel input with the taps folded into K
-// (k = 4 tap + c, weights [1][ldo][64]); forward only.
+// kFirst: 3x3 convolution of a 4-channel input (or of 1-3 channels, the
+// missing ones zero; not from the state fields) with the taps folded into K
+// (k = 4 tap + c, weights [1][ldo][64]).
 enum ConvMode { kConvFwd = 0, kConvDgrad = 1, kUpFwd = 2, kUpDgrad = 3, kFirst = 4 };
 
 struct ConvArgs {
@@ -78,7 +79,13 @@ struct WgradArgs {
     float* partial;        // [chunks][taps][Nout][C1+C2]
     int N, H, W, C1, C2, Nout;
     int chunk;             // pixels per partial product (multiple of 64)
+    // floats the partial buffer holds beyond what `chunk` needs (0: only
+    // that); the halo-tile 3x3 weight gradient runs when its partials fit
+    size_t partial_cap;
 };
+// Partial floats the halo-tile 3x3 weight gradient asks for (0 when the
+// shape does not take it): its chunk count times 9 Nout (C1 + C2).
+size_t wgrad_halo_floats(int Nout, int C1, int C2);
 
 hipError_t conv_gemm(const ConvArgs& a, int mode, hipStream_t s);
 // True when conv_gemm takes the wide 16x16x32 kernel: channel counts
@@ -107,6 +114,25 @@ hipError_t weight_prep(const float* W, int taps, int R, int Kc, uint16_t* fwd, i
 // kFirst operand of a [9][R][4] weight: out[o][4 t + c] = W[t][o][c],
 // [ldo][64] zero padded.
 hipError_t weight_prep_folded(const float* W, int R, uint16_t* out, int ldo, hipStream_t s);
+// Several weights' operand copies in one launch.  kPrepPlain: fwd and tr as
+// weight_prep; kPrepFirst: fwd as weight_prep_folded (ldo_f); kPrepFirstGrad:
+// the kFirst operand of the input gradient of a [9][R][Kc] weight with
+// R <= 4 output channels, tr[o][4 t + c] = W[8 - t][c][o] ([ldo_t][64], zero
+// padded; tap 8 - t is tap t mirrored through the centre).
+enum PrepKind { kPrepPlain = 0, kPrepFirst = 1, kPrepFirstGrad = 2 };
+struct PrepItem {
+    const float* W;
+    uint16_t* fwd;
+    uint16_t* tr;
+    int kind, taps, R, Kc, ldo_f, ldk_f, ldo_t, ldk_t;
+};
+constexpr int kMaxPrep = 24;
+struct PrepBatch {
+    PrepItem it[kMaxPrep];
+    size_t end[kMaxPrep];   // running element counts
+    int n;
+};
+hipError_t weight_prep_batch(const PrepItem* items, int n, hipStream_t s);
 
 // ---------------------------------------------------------------- elementwise
 // Per-channel partial sums over pixel chunks, then finished per sample.

@@ -638,6 +638,131 @@ __global__ __launch_bounds__(256) void gn_bwd_apply_kernel(GNArgs a)
     }
 }
 
+// Eight channels per thread (C % 8 == 0, 256 a multiple of C / 8, every
+// tensor 16-byte aligned): a thread keeps one octet of channels of one
+// sample, so their parameters are loaded once, and reads each tensor's 8
+// values of a pixel as two 16-byte pieces; per element the arithmetic of
+// bwd_elem.
+struct BwdOct {
+    float gamma[8], beta[8], mean[8], rstd[8], scale[8];
+};
+__device__ __forceinline__ void bwd_oct_params(const GNArgs& a, int n, int c0, BwdOct& q)
+{
+    const int Cg = a.C / a.G;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int c = c0 + j;
+        const float* st = a.stats + 2 * (n * a.G + c / Cg);
+        q.gamma[j] = a.gamma[c];
+        q.beta[j] = a.beta[c];
+        q.mean[j] = st[0];
+        q.rstd[j] = st[1];
+        q.scale[j] = a.scale ? a.scale[(size_t)n * a.C + c] : 1.f;
+    }
+}
+__device__ __forceinline__ void bwd_oct(const GNArgs& a, const BwdOct& q, size_t i, float (&g)[8], float (&xh)[8],
+                                        float (&dbz)[8])
+{
+    float y[8], dA[8], dB[8];
+    ld8f(a.y + i, y);
+    if (a.dA) ld8f(a.dA + i, dA);
+    if (a.dB) ld8f(a.dB + i, dB);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        xh[j] = (y[j] - q.mean[j]) * q.rstd[j];
+        const float av = fmaf(q.gamma[j], xh[j], q.beta[j]);
+        const float z = a.gelu ? gelu(av) : av;
+        const float db = a.dB ? dB[j] : 0.f;
+        float dz = a.dA ? dA[j] : 0.f;
+        if (a.dB) dz = fmaf(db, q.scale[j], dz);
+        g[j] = a.gelu ? dz * gelu_grad(av) : dz;
+        dbz[j] = db * z;
+    }
+}
+
+// gn_bwd_reduce_kernel on octets: thread (pixel lane pl, octet o) of
+// PL x O adds pixels pl, pl + PL, .. of the chunk; the PL partial sums of a
+// channel are then added in order
+__global__ __launch_bounds__(256) void gn_bwd_reduce8_kernel(GNArgs a, int CH)
+{
+    __shared__ float sh[3][256 * 8];
+    const int chunk = blockIdx.x, n = blockIdx.y, tid = threadIdx.x;
+    const int O = a.C / 8, PL = 256 / O, o = tid % O, pl = tid / O;
+    float s0[8], s1[8], s2[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) s0[j] = s1[j] = s2[j] = 0.f;
+    BwdOct q;
+    bwd_oct_params(a, n, 8 * o, q);
+    const int pe = min(a.P, (chunk + 1) * CH);
+#pragma unroll 2
+    for (int p = chunk * CH + pl; p < pe; p += PL) {
+        float g[8], xh[8], dbz[8];
+        bwd_oct(a, q, ((size_t)n * a.P + p) * a.C + 8 * o, g, xh, dbz);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            s0[j] += g[j];
+            s1[j] += g[j] * xh[j];
+            s2[j] += dbz[j];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        sh[0][8 * tid + j] = s0[j];
+        sh[1][8 * tid + j] = s1[j];
+        sh[2][8 * tid + j] = s2[j];
+    }
+    __syncthreads();
+    if (tid < a.C) {
+        const int oc = tid / 8, j = tid % 8;
+        float t0 = 0.f, t1 = 0.f, t2 = 0.f;
+        for (int k = 0; k < PL; ++k) {
+            const int e = 8 * (k * O + oc) + j;
+            t0 += sh[0][e];
+            t1 += sh[1][e];
+            t2 += sh[2][e];
+        }
+        float* out = a.csum + (((size_t)n * a.chunks + chunk) * a.C + tid) * 3;
+        out[0] = t0;
+        out[1] = t1;
+        out[2] = t2;
+    }
+}
+
+// gn_bwd_apply_kernel on octets: block row n = blockIdx.y; thread t of the
+// row keeps octet t mod O (the row's stride is a multiple of O) and takes
+// pixels t / O, t / O + stride / O, ..; outputs written through (the input
+// gradient convolution reads them next)
+__global__ __launch_bounds__(256) void gn_bwd_apply8_kernel(GNArgs a)
+{
+    const int n = blockIdx.y, O = a.C / 8;
+    const int t = blockIdx.x * 256 + threadIdx.x, o = t % O;
+    const int ps = gridDim.x * 256 / O;
+    const int Cg = a.C / a.G;
+    const float invM = (float)(1.0 / ((double)Cg * a.P));
+    const double* grp = a.cacc + 3 * (size_t)a.N * a.C;
+    BwdOct q;
+    bwd_oct_params(a, n, 8 * o, q);
+    float S1[8], S2[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int gi = n * a.G + (8 * o + j) / Cg;
+        S1[j] = (float)grp[2 * gi];
+        S2[j] = (float)grp[2 * gi + 1];
+    }
+    for (int p = t / O; p < a.P; p += ps) {
+        const size_t i = ((size_t)n * a.P + p) * a.C + 8 * o;
+        float g[8], xh[8], dbz[8], v[8];
+        bwd_oct(a, q, i, g, xh, dbz);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = q.rstd[j] * (q.gamma[j] * g[j] - fmaf(xh[j], S2[j], S1[j]) * invM);
+        if (a.dy_f32) {
+            st16wt(a.dy_f32, 4 * i, __builtin_bit_cast(uint4, make_float4(v[0], v[1], v[2], v[3])));
+            st16wt(a.dy_f32, 4 * i + 16, __builtin_bit_cast(uint4, make_float4(v[4], v[5], v[6], v[7])));
+        }
+        if (a.dy_bf16) st16wt(a.dy_bf16, 2 * i, pack8(v));
+    }
+}
+
 // --------------------------------------------------------------- pooling
 __global__ __launch_bounds__(256) void pool_fwd_kernel(const uint16_t* x, uint16_t* y, int N, int H, int W, int C)
 {
@@ -901,32 +1026,79 @@ __global__ __launch_bounds__(kFinThreads) void finish_mlp_kernel(GNArgs g, MLPAr
 }
 
 // Backward, per sample: df = sum_l Wl^T ds_l, dh1 = cos(h1) W2^T df,
-// dh0 = cos(h0) W1^T dh1 (saved for the parameter pass).
-__global__ __launch_bounds__(256) void mlp_bwd_sample_kernel(MLPArgs a)
+// dh0 = cos(h0) W1^T dh1 (saved for the parameter pass).  Each product with
+// a transposed matrix (out[c] = sum_r M[r][c] v[r], c < 256) runs on all
+// 16 waves of the block: wave g adds rows g, g + 16, .. and lane q the
+// columns 4q .. 4q + 3 (16-byte loads of whole row segments, several rows'
+// loads in flight at once), and the 16 waves' partial sums are then added
+// in order.
+constexpr int kBwdThreads = 1024, kBwdWaves = kBwdThreads / 64;
+
+__device__ __forceinline__ void colsum_rows(const float* M, int R, int cols, const float* v, int g, int q,
+                                            float (&acc)[4])
 {
-    __shared__ float df[256], dh1[256];
-    const int n = blockIdx.x, tid = threadIdx.x;
-    for (int i = tid; i < a.F; i += blockDim.x) {
-        float v = 0.f;
-        for (int l = 0; l < a.L; ++l)
-            for (int c = 0; c < a.C[l]; ++c) v = fmaf(a.Wl[l][(size_t)c * a.F + i], a.dsc[l][n * a.C[l] + c], v);
-        df[i] = v;
-        a.df[n * a.F + i] = v;
+    const int c0 = 4 * q;
+    if (c0 >= cols) return;
+    if ((cols & 3) == 0 && ((uintptr_t)M & 15) == 0) {
+#pragma unroll 4
+        for (int r = g; r < R; r += kBwdWaves) {
+            const float s = v[r];
+            const float4 w = *(const float4*)(M + (size_t)r * cols + c0);
+            acc[0] = fmaf(w.x, s, acc[0]);
+            acc[1] = fmaf(w.y, s, acc[1]);
+            acc[2] = fmaf(w.z, s, acc[2]);
+            acc[3] = fmaf(w.w, s, acc[3]);
+        }
+    } else {
+#pragma unroll 4
+        for (int r = g; r < R; r += kBwdWaves) {
+            const float s = v[r];
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+                if (c0 + e < cols) acc[e] = fmaf(M[(size_t)r * cols + c0 + e], s, acc[e]);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kBwdThreads) void mlp_bwd_sample_kernel(MLPArgs a)
+{
+    __shared__ float part[kBwdWaves][256];
+    __shared__ float vec[256];
+    const int n = blockIdx.x, tid = threadIdx.x, g = tid >> 6, q = tid & 63;
+    float acc[4];
+    // the 16 waves' partial sums of column tid, added in order (valid for
+    // tid < cols; part is free again on return)
+    auto reduce = [&](int cols) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) part[g][4 * q + e] = acc[e];
+        __syncthreads();
+        float s = 0.f;
+        if (tid < cols)
+            for (int w = 0; w < kBwdWaves; ++w) s += part[w][tid];
+        __syncthreads();
+        return s;
+    };
+    acc[0] = acc[1] = acc[2] = acc[3] = 0.f;
+    for (int l = 0; l < a.L; ++l) colsum_rows(a.Wl[l], a.C[l], a.F, a.dsc[l] + (size_t)n * a.C[l], g, q, acc);
+    const float df = reduce(a.F);
+    if (tid < a.F) {
+        vec[tid] = df;
+        a.df[n * a.F + tid] = df;
     }
     __syncthreads();
-    for (int k = tid; k < a.Hd; k += blockDim.x) {
-        float v = 0.f;
-        for (int i = 0; i < a.F; ++i) v = fmaf(a.W2[(size_t)i * a.Hd + k], df[i], v);
-        v *= cosf(a.h1[n * a.Hd + k]);
-        dh1[k] = v;
-        a.dh1[n * a.Hd + k] = v;
+    acc[0] = acc[1] = acc[2] = acc[3] = 0.f;
+    colsum_rows(a.W2, a.F, a.Hd, vec, g, q, acc);
+    const float s1 = reduce(a.Hd);
+    if (tid < a.Hd) {
+        const float v = s1 * cosf(a.h1[n * a.Hd + tid]);
+        vec[tid] = v;
+        a.dh1[n * a.Hd + tid] = v;
     }
     __syncthreads();
-    for (int k = tid; k < a.Hd; k += blockDim.x) {
-        float v = 0.f;
-        for (int j = 0; j < a.Hd; ++j) v = fmaf(a.W1[(size_t)j * a.Hd + k], dh1[j], v);
-        a.dh0[n * a.Hd + k] = v * cosf(a.h0[n * a.Hd + k]);
-    }
+    acc[0] = acc[1] = acc[2] = acc[3] = 0.f;
+    colsum_rows(a.W1, a.Hd, a.Hd, vec, g, q, acc);
+    const float s0 = reduce(a.Hd);
+    if (tid < a.Hd) a.dh0[n * a.Hd + tid] = s0 * cosf(a.h0[n * a.Hd + tid]);
 }
 
 // Every parameter gradient, one element per thread, summed over the
@@ -1140,10 +1312,23 @@ hipError_t gn_backward(const GNArgs& a_in, hipStream_t s)
     GNArgs a = a_in;
     a.chunks = gn_chunks(a.P);
     const int CH = chunk_px(a.P);
-    hipLaunchKernelGGL(gn_bwd_reduce_kernel, dim3(a.chunks, a.N), dim3(256), 0, s, a, CH);
+    // octets: C % 8 == 0 with C / 8 dividing 256, 16-byte aligned tensors
+    // (outputs stored with 32-bit byte offsets)
+    const auto al16 = [](const void* q) { return ((uintptr_t)q & 15) == 0; };
+    const bool oct = a.C % 8 == 0 && 256 % (a.C / 8) == 0 && al16(a.y) && (!a.dA || al16(a.dA)) &&
+                     (!a.dB || al16(a.dB)) && (!a.dy_f32 || al16(a.dy_f32)) && (!a.dy_bf16 || al16(a.dy_bf16)) &&
+                     (size_t)a.N * a.P * a.C < ((size_t)1 << 29);
+    if (oct) hipLaunchKernelGGL(gn_bwd_reduce8_kernel, dim3(a.chunks, a.N), dim3(256), 0, s, a, CH);
+    else hipLaunchKernelGGL(gn_bwd_reduce_kernel, dim3(a.chunks, a.N), dim3(256), 0, s, a, CH);
     hipLaunchKernelGGL(gn_bwd_chan_kernel, dim3(a.N * a.C), dim3(256), 0, s, a);
     hipLaunchKernelGGL(gn_bwd_finish, dim3(1), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(gn_bwd_apply_kernel, dim3(grid_for((size_t)a.N * a.P * a.C)), dim3(256), 0, s, a);
+    if (oct) {
+        const long items = (long)a.P * (a.C / 8);
+        const long bx = std::min((items + 255) / 256, 2048L);
+        hipLaunchKernelGGL(gn_bwd_apply8_kernel, dim3((unsigned)bx, a.N), dim3(256), 0, s, a);
+    } else {
+        hipLaunchKernelGGL(gn_bwd_apply_kernel, dim3(grid_for((size_t)a.N * a.P * a.C)), dim3(256), 0, s, a);
+    }
     return hipGetLastError();
 }
 
@@ -1191,7 +1376,7 @@ hipError_t prologue_forward(const MLPArgs& a, const float* c, const float* phi, 
 hipError_t mlp_backward(const MLPArgs& a, hipStream_t s)
 {
     if (a.N <= 0) return hipSuccess;
-    hipLaunchKernelGGL(mlp_bwd_sample_kernel, dim3(a.N), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(mlp_bwd_sample_kernel, dim3(a.N), dim3(kBwdThreads), 0, s, a);
     const size_t n = mlp_param_count(a);
     hipLaunchKernelGGL(mlp_bwd_param_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();

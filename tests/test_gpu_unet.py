@@ -75,7 +75,10 @@ def check_bound(gpu, ref, bound, k, what):
                                               (2, 250, 262, 32, 0, 64), (1, 130, 254, 32, 0, 256),
                                               # weight gradients with the taps folded into the input side
                                               # (4 channels) or the output side (3 and 7 channels), many chunks
-                                              (2, 70, 90, 4, 0, 32), (1, 100, 130, 32, 0, 3), (1, 33, 21, 5, 0, 7)])
+                                              (2, 70, 90, 4, 0, 32), (1, 100, 130, 32, 0, 3), (1, 33, 21, 5, 0, 7),
+                                              # input gradient of 1-4 output channels with the taps folded
+                                              # into K (the head's)
+                                              (1, 19, 23, 16, 0, 2)])
 def test_conv3x3_fwd_dgrad_wgrad(n, H, W, C1, C2, Cout):
     import torch
 
