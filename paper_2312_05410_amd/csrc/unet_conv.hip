@@ -588,7 +588,7 @@ __global__ __launch_bounds__(256) void gemm32_kernel(ConvArgs a)
 // halo pieces are loaded as FP32, and each becomes 8 BF16 values with the
 // arithmetic of the normalisation kernel before it is stored in LDS
 template <int MODE, int TN, int TH, int TW, int KC, bool GNIN = false>
-__global__ __launch_bounds__(256, 2) void conv3_lds_kernel(ConvArgs a)
+__global__ __launch_bounds__(256, (TN == 2 && KC == 32) ? 3 : 2) void conv3_lds_kernel(ConvArgs a)
 {
     constexpr int LP = KC + 8;              // BF16 elements per staged row
     constexpr int PPX = KC / 8;             // 16-byte pieces per staged row
@@ -765,6 +765,13 @@ __global__ __launch_bounds__(256, 2) void conv3_lds_kernel(ConvArgs a)
 #pragma unroll
     for (int j = 0; j < TN; ++j) s1[j] = s2[j] = 0.f;
     static_assert(TH * TW * TN * 16 * 4 <= (int)sizeof(lds), "the staged output tile fits in LDS");
+    // the output that takes the block's channels, when it is one
+    const bool part1 = on + TN * 16 <= a.O1, part2 = on >= a.O1;
+    float* const out_f = part1 ? a.out_f32 : part2 ? a.out2_f32 : nullptr;
+    uint16_t* const out_b = part1 ? a.out_bf16 : part2 ? a.out2_bf16 : nullptr;
+    const int out_cs = part1 ? a.O1 : a.Nout - a.O1, out_co = part1 ? on : on - a.O1;
+    const bool stage_out = (part1 || part2) && (out_f != nullptr) != (out_b != nullptr) &&
+                           out_cs % (out_f ? 4 : 8) == 0;
     if (MODE == kConvFwd && a.out_f32 && !a.out_bf16 && a.O1 == a.Nout && a.Nout <= TN * 16 && on == 0 &&
         a.W % TW == 0 && (TW * a.Nout) % 4 == 0) {
         // the block holds every output channel of its tile, so each tile row
@@ -794,10 +801,11 @@ __global__ __launch_bounds__(256, 2) void conv3_lds_kernel(ConvArgs a)
                    __builtin_bit_cast(uint4, v));
         }
         __syncthreads();   // the reduction below reuses LDS
-    } else if (MODE == kConvFwd && a.out_f32 && !a.out_bf16 && a.O1 == a.Nout && a.Nout % 4 == 0) {
+    } else if (stage_out) {
         // the block's channels [on, on + 16 TN) of each pixel are one 16-byte
-        // aligned run: staged through LDS as [pixel][channel] and written
-        // back as 16-byte pieces
+        // aligned run of one output (the first's O1 channels or the second's
+        // Nout - O1, FP32 or BF16): staged through LDS as [pixel][channel]
+        // and written back as 16-byte pieces
         constexpr int SP = TN * 16 + 4;   // 4 lane groups land 16 banks apart
         static_assert(TH * TW * SP * 4 <= (int)sizeof(lds), "the staged output tile fits in LDS");
         float* stg = (float*)&lds[0];
@@ -817,13 +825,24 @@ __global__ __launch_bounds__(256, 2) void conv3_lds_kernel(ConvArgs a)
                 }
         }
         __syncthreads();
-        const int nq = min(TN * 16, a.Nout - on) / 4;   // 16-byte pieces per pixel
+        const int pw = out_f ? 4 : 8;                       // channels per 16-byte piece
+        const int nq = min(TN * 16, out_cs - out_co) / pw;  // pieces per pixel
         for (int idx = tid; idx < TH * TW * nq; idx += 256) {
             const int pp = idx / nq, q = idx - pp * nq;
             const int y = y0 + pp / TW, x = x0 + pp % TW;
             if (y >= a.H || x >= a.W) continue;
-            const f32x4 v = *(const f32x4*)(&stg[pp * SP + 4 * q]);
-            st16wt(a.out_f32, 4 * ((((size_t)n * a.H + y) * a.W + x) * a.Nout + on + 4 * q), __builtin_bit_cast(uint4, v));
+            const size_t e = (((size_t)n * a.H + y) * a.W + x) * out_cs + out_co + pw * q;
+            if (out_f) {
+                const f32x4 v = *(const f32x4*)(&stg[pp * SP + 4 * q]);
+                st16wt(out_f, 4 * e, __builtin_bit_cast(uint4, v));
+            } else {
+                const f32x4 v0 = *(const f32x4*)(&stg[pp * SP + 8 * q]), v1 = *(const f32x4*)(&stg[pp * SP + 8 * q + 4]);
+                const uint32_t w0 = (uint32_t)f2bf(v0[0]) | ((uint32_t)f2bf(v0[1]) << 16);
+                const uint32_t w1 = (uint32_t)f2bf(v0[2]) | ((uint32_t)f2bf(v0[3]) << 16);
+                const uint32_t w2 = (uint32_t)f2bf(v1[0]) | ((uint32_t)f2bf(v1[1]) << 16);
+                const uint32_t w3 = (uint32_t)f2bf(v1[2]) | ((uint32_t)f2bf(v1[3]) << 16);
+                st16wt(out_b, 2 * e, make_uint4(w0, w1, w2, w3));
+            }
         }
         __syncthreads();   // the reduction below reuses LDS
     } else {
