@@ -734,20 +734,46 @@ __global__ __launch_bounds__(256) void gn_bwd_reduce8_kernel(GNArgs a, int CH)
 // gradient convolution reads them next)
 __global__ __launch_bounds__(256) void gn_bwd_apply8_kernel(GNArgs a)
 {
+    __shared__ double sg[2][256];
     const int n = blockIdx.y, O = a.C / 8;
     const int t = blockIdx.x * 256 + threadIdx.x, o = t % O;
     const int ps = gridDim.x * 256 / O;
     const int Cg = a.C / a.G;
     const float invM = (float)(1.0 / ((double)Cg * a.P));
-    const double* grp = a.cacc + 3 * (size_t)a.N * a.C;
+    // the finish of gn_bwd_finish for this sample's groups (the same sums
+    // in the same order), and the parameter gradients from the first blocks
+    for (int g = threadIdx.x; g < a.G; g += 256) {
+        double s1 = 0.0, s2 = 0.0;
+        for (int c = g * Cg; c < (g + 1) * Cg; ++c) {
+            s1 += (double)a.gamma[c] * a.cacc[3 * (n * a.C + c)];
+            s2 += (double)a.gamma[c] * a.cacc[3 * (n * a.C + c) + 1];
+        }
+        sg[0][g] = s1;
+        sg[1][g] = s2;
+    }
+    if (blockIdx.x == 0) {
+        if (n == 0)
+            for (int c = threadIdx.x; c < a.C; c += 256) {
+                double gb = 0.0, gg = 0.0;
+                for (int m = 0; m < a.N; ++m) {
+                    gb += a.cacc[3 * (m * a.C + c)];
+                    gg += a.cacc[3 * (m * a.C + c) + 1];
+                }
+                if (a.dbeta) a.dbeta[c] = (float)gb;
+                if (a.dgamma) a.dgamma[c] = (float)gg;
+            }
+        if (a.dscale)
+            for (int c = threadIdx.x; c < a.C; c += 256) a.dscale[n * a.C + c] = (float)a.cacc[3 * (n * a.C + c) + 2];
+    }
+    __syncthreads();
     BwdOct q;
     bwd_oct_params(a, n, 8 * o, q);
     float S1[8], S2[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-        const int gi = n * a.G + (8 * o + j) / Cg;
-        S1[j] = (float)grp[2 * gi];
-        S2[j] = (float)grp[2 * gi + 1];
+        const int g = (8 * o + j) / Cg;
+        S1[j] = (float)sg[0][g];
+        S2[j] = (float)sg[1][g];
     }
     for (int p = t / O; p < a.P; p += ps) {
         const size_t i = ((size_t)n * a.P + p) * a.C + 8 * o;
@@ -1312,16 +1338,17 @@ hipError_t gn_backward(const GNArgs& a_in, hipStream_t s)
     GNArgs a = a_in;
     a.chunks = gn_chunks(a.P);
     const int CH = chunk_px(a.P);
-    // octets: C % 8 == 0 with C / 8 dividing 256, 16-byte aligned tensors
-    // (outputs stored with 32-bit byte offsets)
+    // octets: C % 8 == 0 with C / 8 dividing 256 and at most 256 groups,
+    // 16-byte aligned tensors (outputs stored with 32-bit byte offsets)
     const auto al16 = [](const void* q) { return ((uintptr_t)q & 15) == 0; };
-    const bool oct = a.C % 8 == 0 && 256 % (a.C / 8) == 0 && al16(a.y) && (!a.dA || al16(a.dA)) &&
+    const bool oct = a.C % 8 == 0 && 256 % (a.C / 8) == 0 && a.G <= 256 && al16(a.y) && (!a.dA || al16(a.dA)) &&
                      (!a.dB || al16(a.dB)) && (!a.dy_f32 || al16(a.dy_f32)) && (!a.dy_bf16 || al16(a.dy_bf16)) &&
                      (size_t)a.N * a.P * a.C < ((size_t)1 << 29);
     if (oct) hipLaunchKernelGGL(gn_bwd_reduce8_kernel, dim3(a.chunks, a.N), dim3(256), 0, s, a, CH);
     else hipLaunchKernelGGL(gn_bwd_reduce_kernel, dim3(a.chunks, a.N), dim3(256), 0, s, a, CH);
     hipLaunchKernelGGL(gn_bwd_chan_kernel, dim3(a.N * a.C), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(gn_bwd_finish, dim3(1), dim3(256), 0, s, a);
+    // the octet apply finishes the group sums and parameter gradients itself
+    if (!oct) hipLaunchKernelGGL(gn_bwd_finish, dim3(1), dim3(256), 0, s, a);
     if (oct) {
         const long items = (long)a.P * (a.C / 8);
         const long bx = std::min((items + 255) / 256, 2048L);
