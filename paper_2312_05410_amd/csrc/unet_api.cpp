@@ -704,7 +704,15 @@ int backward(unet_handle* h, const float* pc, const float* pphi, const float* pr
         const Conv& k = net.enc[l];
         GNArgs g = gn_args(h, k, n, net.P(l, 1), b.y[l], b.st[l]);
         g.scale = b.sc[l];
-        g.dA = l < L - 1 ? b.dz[l] : nullptr;
+        if (l < L - 1) {
+            // dA: the gradient of the pooling into the next level, formed
+            // inside the normalisation's backward
+            g.pool_z = b.z[l];
+            g.pool_dq = b.dq[l];
+            g.pool_tmp = b.dz[l];
+            g.H = Hl(l);
+            g.W = Wl(l);
+        }
         g.dB = b.dzs[l];
         g.dy_bf16 = b.dye[l];
         g.dgamma = grd(h, k.pg);
@@ -717,7 +725,6 @@ int backward(unet_handle* h, const float* pc, const float* pphi, const float* pr
             ConvArgs a = dgrad_args(k, n, Hl(l), Wl(l), b.dye[l]);
             a.out_f32 = b.dq[l - 1];
             UCHECK(conv_gemm(a, kConvDgrad, s));
-            UCHECK(maxpool_bwd(b.z[l - 1], b.dq[l - 1], b.dz[l - 1], n, Hl(l - 1), Wl(l - 1), w[l - 1], s));
         }
     }
     UCHECK(mlp_backward(mlp_args(h, n, b.jump), s));

@@ -159,6 +159,13 @@ struct GNArgs {
     float* dbeta;          // [C] (=)
     float* dscale;         // [N][C] (=), when scale and dB are given
     uint16_t* pool_bf16;   // forward: 2x2 max pool of z (BF16) or null
+    // backward, in place of dA: the gradient of that pool, routed to the
+    // first maximum of each window of pool_z (BF16 z [N][H][W][C]) from
+    // pool_dq ([N][H/2][W/2][C]); pool_tmp ([N][H][W][C] FP32) holds it
+    // where the kernels cannot form it themselves
+    const uint16_t* pool_z;
+    const float* pool_dq;
+    float* pool_tmp;
     int H, W;              // pixel grid of one sample when pooling (H W = P)
     int N, P, C, G;
     int gelu;

@@ -660,12 +660,11 @@ __device__ __forceinline__ void bwd_oct_params(const GNArgs& a, int n, int c0, B
         q.scale[j] = a.scale ? a.scale[(size_t)n * a.C + c] : 1.f;
     }
 }
-__device__ __forceinline__ void bwd_oct(const GNArgs& a, const BwdOct& q, size_t i, float (&g)[8], float (&xh)[8],
-                                        float (&dbz)[8])
+// per element the arithmetic of bwd_elem, dA given (hasA) or zero
+__device__ __forceinline__ void bwd_core(const GNArgs& a, const BwdOct& q, const float (&y)[8], const float (&dA)[8],
+                                         bool hasA, size_t i, float (&g)[8], float (&xh)[8], float (&dbz)[8])
 {
-    float y[8], dA[8], dB[8];
-    ld8f(a.y + i, y);
-    if (a.dA) ld8f(a.dA + i, dA);
+    float dB[8];
     if (a.dB) ld8f(a.dB + i, dB);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
@@ -673,16 +672,62 @@ __device__ __forceinline__ void bwd_oct(const GNArgs& a, const BwdOct& q, size_t
         const float av = fmaf(q.gamma[j], xh[j], q.beta[j]);
         const float z = a.gelu ? gelu(av) : av;
         const float db = a.dB ? dB[j] : 0.f;
-        float dz = a.dA ? dA[j] : 0.f;
+        float dz = hasA ? dA[j] : 0.f;
         if (a.dB) dz = fmaf(db, q.scale[j], dz);
         g[j] = a.gelu ? dz * gelu_grad(av) : dz;
         dbz[j] = db * z;
+    }
+}
+__device__ __forceinline__ void bwd_oct(const GNArgs& a, const BwdOct& q, size_t i, float (&g)[8], float (&xh)[8],
+                                        float (&dbz)[8])
+{
+    float y[8], dA[8];
+    ld8f(a.y + i, y);
+    if (a.dA) ld8f(a.dA + i, dA);
+    bwd_core(a, q, y, dA, a.dA != nullptr, i, g, xh, dbz);
+}
+// POOL: the 2x2 window w (of the sample's H/2 x W/2) of pixels k = 0..3 at
+// (2 yo + k / 2, 2 xo + k % 2): dA of pixel k is the window's pool gradient
+// where k is the first maximum of z in that channel, else 0 (the rule of
+// pool_bwd_kernel); element offsets of the 4 pixels in i[4]
+__device__ __forceinline__ void pool_window(const GNArgs& a, int n, int w, int c0, size_t (&i)[4],
+                                            float (&dA)[4][8])
+{
+    const int Wo = a.W / 2, yo = w / Wo, xo = w - yo * Wo;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) i[k] = (((size_t)n * a.H + 2 * yo + k / 2) * a.W + 2 * xo + k % 2) * a.C + c0;
+    float dq[8];
+    ld8f(a.pool_dq + (((size_t)n * (a.H / 2) + yo) * Wo + xo) * a.C + c0, dq);
+    uint4 zq[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) zq[k] = *(const uint4*)(a.pool_z + i[k]);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        float zk[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t wd = j < 2 ? zq[k].x : j < 4 ? zq[k].y : j < 6 ? zq[k].z : zq[k].w;
+            zk[k] = bf2f((uint16_t)(j & 1 ? wd >> 16 : wd & 0xffffu));
+        }
+        int best = 0;
+        float bv = zk[0];
+#pragma unroll
+        for (int k = 1; k < 4; ++k)
+            if (zk[k] > bv) {
+                bv = zk[k];
+                best = k;
+            }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) dA[k][j] = k == best ? dq[j] : 0.f;
     }
 }
 
 // gn_bwd_reduce_kernel on octets: thread (pixel lane pl, octet o) of
 // PL x O adds pixels pl, pl + PL, .. of the chunk; the PL partial sums of a
 // channel are then added in order
+// POOL: the chunk's CH / 4 pool windows instead of its CH pixels, dA from
+// the pool gradient (pool_window)
+template <bool POOL>
 __global__ __launch_bounds__(256) void gn_bwd_reduce8_kernel(GNArgs a, int CH)
 {
     __shared__ float sh[3][256 * 8];
@@ -693,16 +738,35 @@ __global__ __launch_bounds__(256) void gn_bwd_reduce8_kernel(GNArgs a, int CH)
     for (int j = 0; j < 8; ++j) s0[j] = s1[j] = s2[j] = 0.f;
     BwdOct q;
     bwd_oct_params(a, n, 8 * o, q);
-    const int pe = min(a.P, (chunk + 1) * CH);
-#pragma unroll 2
-    for (int p = chunk * CH + pl; p < pe; p += PL) {
-        float g[8], xh[8], dbz[8];
-        bwd_oct(a, q, ((size_t)n * a.P + p) * a.C + 8 * o, g, xh, dbz);
+    auto add = [&](const float (&g)[8], const float (&xh)[8], const float (&dbz)[8]) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
             s0[j] += g[j];
             s1[j] += g[j] * xh[j];
             s2[j] += dbz[j];
+        }
+    };
+    if constexpr (POOL) {
+        const int CW = CH / 4, we = min(a.P / 4, (chunk + 1) * CW);
+        for (int w = chunk * CW + pl; w < we; w += PL) {
+            size_t i[4];
+            float dA[4][8];
+            pool_window(a, n, w, 8 * o, i, dA);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                float y[8], g[8], xh[8], dbz[8];
+                ld8f(a.y + i[k], y);
+                bwd_core(a, q, y, dA[k], true, i[k], g, xh, dbz);
+                add(g, xh, dbz);
+            }
+        }
+    } else {
+        const int pe = min(a.P, (chunk + 1) * CH);
+#pragma unroll 2
+        for (int p = chunk * CH + pl; p < pe; p += PL) {
+            float g[8], xh[8], dbz[8];
+            bwd_oct(a, q, ((size_t)n * a.P + p) * a.C + 8 * o, g, xh, dbz);
+            add(g, xh, dbz);
         }
     }
 #pragma unroll
@@ -732,6 +796,7 @@ __global__ __launch_bounds__(256) void gn_bwd_reduce8_kernel(GNArgs a, int CH)
 // row keeps octet t mod O (the row's stride is a multiple of O) and takes
 // pixels t / O, t / O + stride / O, ..; outputs written through (the input
 // gradient convolution reads them next)
+template <bool POOL>
 __global__ __launch_bounds__(256) void gn_bwd_apply8_kernel(GNArgs a)
 {
     __shared__ double sg[2][256];
@@ -775,10 +840,8 @@ __global__ __launch_bounds__(256) void gn_bwd_apply8_kernel(GNArgs a)
         S1[j] = (float)sg[0][g];
         S2[j] = (float)sg[1][g];
     }
-    for (int p = t / O; p < a.P; p += ps) {
-        const size_t i = ((size_t)n * a.P + p) * a.C + 8 * o;
-        float g[8], xh[8], dbz[8], v[8];
-        bwd_oct(a, q, i, g, xh, dbz);
+    auto out = [&](size_t i, const float (&g)[8], const float (&xh)[8]) {
+        float v[8];
 #pragma unroll
         for (int j = 0; j < 8; ++j) v[j] = q.rstd[j] * (q.gamma[j] * g[j] - fmaf(xh[j], S2[j], S1[j]) * invM);
         if (a.dy_f32) {
@@ -786,6 +849,28 @@ __global__ __launch_bounds__(256) void gn_bwd_apply8_kernel(GNArgs a)
             st16wt(a.dy_f32, 4 * i + 16, __builtin_bit_cast(uint4, make_float4(v[4], v[5], v[6], v[7])));
         }
         if (a.dy_bf16) st16wt(a.dy_bf16, 2 * i, pack8(v));
+    };
+    if constexpr (POOL) {
+        // items are pool windows (P / 4 per sample)
+        for (int w = t / O; w < a.P / 4; w += ps) {
+            size_t i[4];
+            float dA[4][8];
+            pool_window(a, n, w, 8 * o, i, dA);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                float y[8], g[8], xh[8], dbz[8];
+                ld8f(a.y + i[k], y);
+                bwd_core(a, q, y, dA[k], true, i[k], g, xh, dbz);
+                out(i[k], g, xh);
+            }
+        }
+    } else {
+        for (int p = t / O; p < a.P; p += ps) {
+            const size_t i = ((size_t)n * a.P + p) * a.C + 8 * o;
+            float g[8], xh[8], dbz[8];
+            bwd_oct(a, q, i, g, xh, dbz);
+            out(i, g, xh);
+        }
     }
 }
 
@@ -1336,23 +1421,39 @@ hipError_t gn_backward(const GNArgs& a_in, hipStream_t s)
 {
     if (a_in.N <= 0 || a_in.P <= 0) return hipSuccess;
     GNArgs a = a_in;
+    const bool pool = a.pool_z && a.pool_dq;
+    if (pool && (a.dA || a.H % 2 || a.W % 2 || (long)a.H * a.W != a.P)) return hipErrorInvalidValue;
     a.chunks = gn_chunks(a.P);
     const int CH = chunk_px(a.P);
     // octets: C % 8 == 0 with C / 8 dividing 256 and at most 256 groups,
     // 16-byte aligned tensors (outputs stored with 32-bit byte offsets)
     const auto al16 = [](const void* q) { return ((uintptr_t)q & 15) == 0; };
-    const bool oct = a.C % 8 == 0 && 256 % (a.C / 8) == 0 && a.G <= 256 && al16(a.y) && (!a.dA || al16(a.dA)) &&
-                     (!a.dB || al16(a.dB)) && (!a.dy_f32 || al16(a.dy_f32)) && (!a.dy_bf16 || al16(a.dy_bf16)) &&
-                     (size_t)a.N * a.P * a.C < ((size_t)1 << 29);
-    if (oct) hipLaunchKernelGGL(gn_bwd_reduce8_kernel, dim3(a.chunks, a.N), dim3(256), 0, s, a, CH);
+    const bool oct0 = a.C % 8 == 0 && 256 % (a.C / 8) == 0 && a.G <= 256 && al16(a.y) && (!a.dB || al16(a.dB)) &&
+                      (!a.dy_f32 || al16(a.dy_f32)) && (!a.dy_bf16 || al16(a.dy_bf16)) &&
+                      (size_t)a.N * a.P * a.C < ((size_t)1 << 29);
+    // the pool gradient inside the octet kernels (16-byte aligned z and dq;
+    // CH a multiple of 4 pixels), else formed by pool_bwd_kernel first
+    const bool opool = pool && oct0 && al16(a.pool_z) && al16(a.pool_dq) && CH % 4 == 0;
+    if (pool && !opool) {
+        if (!a.pool_tmp) return hipErrorInvalidValue;
+        const hipError_t e = maxpool_bwd(a.pool_z, a.pool_dq, a.pool_tmp, a.N, a.H, a.W, a.C, s);
+        if (e != hipSuccess) return e;
+        a.dA = a.pool_tmp;
+        a.pool_z = nullptr;
+        a.pool_dq = nullptr;
+    }
+    const bool oct = oct0 && (!a.dA || al16(a.dA));
+    if (opool) hipLaunchKernelGGL(gn_bwd_reduce8_kernel<true>, dim3(a.chunks, a.N), dim3(256), 0, s, a, CH);
+    else if (oct) hipLaunchKernelGGL(gn_bwd_reduce8_kernel<false>, dim3(a.chunks, a.N), dim3(256), 0, s, a, CH);
     else hipLaunchKernelGGL(gn_bwd_reduce_kernel, dim3(a.chunks, a.N), dim3(256), 0, s, a, CH);
     hipLaunchKernelGGL(gn_bwd_chan_kernel, dim3(a.N * a.C), dim3(256), 0, s, a);
     // the octet apply finishes the group sums and parameter gradients itself
     if (!oct) hipLaunchKernelGGL(gn_bwd_finish, dim3(1), dim3(256), 0, s, a);
     if (oct) {
-        const long items = (long)a.P * (a.C / 8);
+        const long items = (long)(opool ? a.P / 4 : a.P) * (a.C / 8);
         const long bx = std::min((items + 255) / 256, 2048L);
-        hipLaunchKernelGGL(gn_bwd_apply8_kernel, dim3((unsigned)bx, a.N), dim3(256), 0, s, a);
+        if (opool) hipLaunchKernelGGL(gn_bwd_apply8_kernel<true>, dim3((unsigned)bx, a.N), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL(gn_bwd_apply8_kernel<false>, dim3((unsigned)bx, a.N), dim3(256), 0, s, a);
     } else {
         hipLaunchKernelGGL(gn_bwd_apply_kernel, dim3(grid_for((size_t)a.N * a.P * a.C)), dim3(256), 0, s, a);
     }
