@@ -7,7 +7,7 @@ network"; appendix on trajectory splitting).
 * train: Adam on the relative squared error, batch 5, through the U-Net's C
   ABI (forward, backward and the optimiser step run in the library).
 * blended_run / dns_run: the alternating schedule and the plain DNS that
-  judges it, timed with HIP events on the stream both use.
+  it is measured against, timed with HIP events on the stream both use.
 
 Readings (where the paper leaves the choice open):
   * one U-Net time unit is JUMP = 100 DNS steps; a call may leap
@@ -240,7 +240,7 @@ def blended_run(net, seed: int = TEST_SEED, steps: int = BLEND_STEPS, dns_block:
 def compare(net, seed: int = TEST_SEED, steps: int = BLEND_STEPS, dt_factors=(0.4, 0.6, 0.8, 0.95),
             reps: int = 3, n: int = BLEND_N, log=print):
     """The blended runs ("leap", "chain") and plain DNS at larger time steps,
-    all judged against plain DNS at 0.2 of the stability limit from the same
+    all compared with plain DNS at 0.2 of the stability limit from the same
     seeded initial condition: final-state relative L2 of each field, relative
     L2 of the phase-A autocorrelation S2 and of its radial average, and the
     best of `reps` timed runs.  "At fixed error": the fastest plain DNS whose
