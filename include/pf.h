@@ -274,6 +274,21 @@ int pf_adjoint_step(pf_handle* h, const void* c, const void* phi, const void* rh
                     const void* lam_c, const void* lam_phi, const void* lam_rho,
                     void* out_c, void* out_phi, void* out_rho,
                     void* adj_workspace, size_t adj_bytes);
+/* One checkpoint segment of that reverse sweep in a single call (the same
+ * launches, in the same order, as the per-step calls; no host round trip
+ * per step).  ring holds len >= 1 states in the state's precision, laid out
+ * [len][3][batch][ny][nx] (slot t = c, phi, rho after t steps of the
+ * segment); slot 0 is the caller's checkpoint and slots 1 .. len-1 are
+ * written here by pf_step_out.  Then for t = len-1 .. 0 it calls
+ * pf_adjoint_step on slot t with the two lambda buffers (lam_*, tmp_*)
+ * taking turns as input and output, starting from lam_*.  On return
+ * *in_tmp is 1 when the adjoint of the segment's first state is in tmp_*
+ * (odd len), else 0 (in lam_*).  The ring belongs to the caller; it must
+ * not overlap the lambda buffers.  Errors as pf_step_out and
+ * pf_adjoint_step (PF_EINVAL on bad arguments; enqueued, returns at once). */
+int pf_adjoint_segment(pf_handle* h, void* ring, int64_t len, void* lam_c, void* lam_phi, void* lam_rho,
+                       void* tmp_c, void* tmp_phi, void* tmp_rho, void* adj_workspace, size_t adj_bytes,
+                       int32_t* in_tmp);
 /* Zero the parameter-gradient accumulators (enqueued). */
 int pf_adjoint_reset(pf_handle* h, void* adj_workspace, size_t adj_bytes);
 /* Wait for the stream and write out[2*b] = dL/dM_scale, out[2*b+1] = dL/dv0

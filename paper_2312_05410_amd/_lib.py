@@ -29,7 +29,7 @@ EXPORTS = (
     "pf_workspace_bytes", "pf_dt_limit", "pf_init", "pf_step_n", "pf_mass", "pf_energy",
     "pf_get_step", "pf_set_step", "pf_get_dt", "pf_get_inflow", "pf_set_inflow", "pf_step_out",
     "pf_destroy", "pf_strerror", "pf_last_hip_error", "pf_get_launch", "pf_get_lane_cols", "pf_get_fused_kernel",
-    "pf_adjoint_workspace_bytes", "pf_adjoint_step", "pf_adjoint_reset", "pf_adjoint_grad",
+    "pf_adjoint_workspace_bytes", "pf_adjoint_step", "pf_adjoint_segment", "pf_adjoint_reset", "pf_adjoint_grad",
     "pf_diagnostics_noalloc", "pf_diagnostics_noalloc_limit",
 )
 
@@ -117,6 +117,9 @@ def load():
         L.pf_adjoint_workspace_bytes.restype = ctypes.c_size_t
         L.pf_adjoint_step.argtypes = [H] * 11 + [ctypes.c_size_t]
         L.pf_adjoint_step.restype = ctypes.c_int
+        L.pf_adjoint_segment.argtypes = [H, H, ctypes.c_int64] + [H] * 7 + [ctypes.c_size_t,
+                                                                            ctypes.POINTER(ctypes.c_int32)]
+        L.pf_adjoint_segment.restype = ctypes.c_int
         L.pf_adjoint_reset.argtypes = [H, H, ctypes.c_size_t]
         L.pf_adjoint_reset.restype = ctypes.c_int
         L.pf_adjoint_grad.argtypes = [H, H, ctypes.c_size_t, dp]
@@ -341,6 +344,16 @@ class Simulator:
         """out = lam + (dR/du)^T dt lam at `state`; (c, phi, rho) tensors each."""
         args = [u.data_ptr() for u in (*state, *lam, *out)]
         self._check(load().pf_adjoint_step(self._h, *args, ws.data_ptr(), ws.numel()), "pf_adjoint_step")
+
+    def adjoint_segment(self, ring, length: int, lam, tmp, ws) -> bool:
+        """One checkpoint segment of the reverse sweep (pf_adjoint_segment):
+        ring [>= length][3][...] holds the checkpoint in slot 0; returns True
+        when the result is in `tmp` (odd length), else it is in `lam`."""
+        flag = ctypes.c_int32(0)
+        args = [u.data_ptr() for u in (*lam, *tmp)]
+        self._check(load().pf_adjoint_segment(self._h, ring.data_ptr(), int(length), *args, ws.data_ptr(), ws.numel(),
+                                              ctypes.byref(flag)), "pf_adjoint_segment")
+        return bool(flag.value)
 
     def adjoint_grad(self, ws) -> np.ndarray:
         """[batch, 2] accumulated (dL/dM_scale, dL/dv0)."""

@@ -58,17 +58,14 @@ class _FinalState(torch.autograd.Function):
         ring = torch.empty((every, 3) + tuple(shape), dtype=dtype, device=lam[0].device)
         rec = Simulator(q, tensors=[ring[0, 0], ring[0, 1], ring[0, 2]], temporal_block=ctx.temporal_block)
         ws = rec.adjoint_workspace()
-        slot = lambda t: [ring[t, 0], ring[t, 1], ring[t, 2]]
         nseg = len(ctx.ckpts)
         for sg in range(nseg - 1, -1, -1):
             s0 = sg * every
             length = min(every, n - s0)
             for f, ck in enumerate(ctx.ckpts[sg]):
                 ring[0, f].copy_(ck)
-            for t in range(1, length):
-                rec.step_out(slot(t - 1), slot(t))
-            for t in range(length - 1, -1, -1):
-                rec.adjoint_step(slot(t), lam, nxt, ws)
+            # recompute the segment and run its adjoint steps in one call
+            if rec.adjoint_segment(ring, length, lam, nxt, ws):
                 lam, nxt = nxt, lam
         g = rec.adjoint_grad(ws).sum(axis=0)
         rec.close()

@@ -8,6 +8,7 @@
 #include "pf_kernels.h"
 
 #include <algorithm>
+#include <utility>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -900,6 +901,33 @@ int pf_adjoint_reset(pf_handle* h, void* adj_workspace, size_t adj_bytes)
     const AdjLayout L = adj_layout(&h->p);
     const size_t cells = (size_t)h->p.batch * h->p.nx * h->p.ny;
     return hip_fail(h, pfk::launch_gacc_zero((double*)((char*)adj_workspace + L.gacc), 2 * cells, h->stream));
+}
+
+int pf_adjoint_segment(pf_handle* h, void* ring, int64_t len, void* lam_c, void* lam_phi, void* lam_rho,
+                       void* tmp_c, void* tmp_phi, void* tmp_rho, void* adj_workspace, size_t adj_bytes,
+                       int32_t* in_tmp)
+{
+    if (!h || !ring || !in_tmp || len < 1 || !adj_ws_ok(h, adj_workspace, adj_bytes)) return PF_EINVAL;
+    const size_t fb = (size_t)h->p.batch * h->p.nx * h->p.ny * (h->p.precision == PF_F64 ? 8 : 4);
+    char* const base = (char*)ring;
+    auto f = [&](int64_t t, int k) -> void* { return base + (size_t)(3 * t + k) * fb; };
+    // the segment's states, each slot stepped from the one before it
+    for (int64_t t = 1; t < len; ++t) {
+        const int rc = pf_step_out(h, f(t - 1, 0), f(t - 1, 1), f(t - 1, 2), f(t, 0), f(t, 1), f(t, 2));
+        if (rc != PF_OK) return rc;
+    }
+    // then the adjoint steps from the last state to the first, the two
+    // lambda buffers taking turns as input and output
+    void* cur[3] = {lam_c, lam_phi, lam_rho};
+    void* nxt[3] = {tmp_c, tmp_phi, tmp_rho};
+    for (int64_t t = len - 1; t >= 0; --t) {
+        const int rc = pf_adjoint_step(h, f(t, 0), f(t, 1), f(t, 2), cur[0], cur[1], cur[2], nxt[0], nxt[1], nxt[2],
+                                       adj_workspace, adj_bytes);
+        if (rc != PF_OK) return rc;
+        std::swap(cur, nxt);
+    }
+    *in_tmp = (int32_t)(len & 1);
+    return PF_OK;
 }
 
 int pf_adjoint_grad(pf_handle* h, void* adj_workspace, size_t adj_bytes, double* out)

@@ -64,6 +64,51 @@ def test_adjoint_step_matches_oracle(prec, bc, theta, shape):
     sim.close()
 
 
+@pytest.mark.parametrize("prec,length", [("f32", 7), ("f32", 8), ("f64", 5)])
+def test_adjoint_segment_equals_step_calls(prec, length):
+    """pf_adjoint_segment against the same recomputation and adjoint steps
+    issued one call at a time: bitwise equal lambda and accumulators, for an
+    odd and an even segment length (the result in either buffer)."""
+    import torch
+
+    from paper_2312_05410_amd._lib import Simulator
+
+    nx, ny = 64, 40
+    announce(f"adjoint segment {prec} length {length}")
+    p = PFParams(nx=nx, ny=ny, bc_mode="pvd", theta_deg=70.0, v0=0.8, M_scale=1.2, precision=prec)
+    p = p.replace(dt=0.2 * oracle.dt_limit(p))
+    c, phi, rho = random_state(61, 1, ny, nx)
+    lam0 = uniform01(62, np.arange(3 * nx * ny)).reshape(3, ny, nx) - 0.5
+    dtype = torch.float64 if prec == "f64" else torch.float32
+    results = []
+    for native in (False, True):
+        ring = torch.empty((length, 3, 1, ny, nx), dtype=dtype, device="cuda")
+        for f, u in enumerate((c, phi, rho)):
+            ring[0, f].copy_(torch.as_tensor(u, dtype=dtype))
+        sim = Simulator(p, tensors=[ring[0, 0], ring[0, 1], ring[0, 2]])
+        ws = sim.adjoint_workspace()
+        lam = [torch.as_tensor(l[None], dtype=dtype, device="cuda").contiguous() for l in lam0]
+        tmp = [torch.empty_like(t) for t in lam]
+        if native:
+            if sim.adjoint_segment(ring, length, lam, tmp, ws):
+                lam, tmp = tmp, lam
+        else:
+            slot = lambda t: [ring[t, 0], ring[t, 1], ring[t, 2]]
+            for t in range(1, length):
+                sim.step_out(slot(t - 1), slot(t))
+            for t in range(length - 1, -1, -1):
+                sim.adjoint_step(slot(t), lam, tmp, ws)
+                lam, tmp = tmp, lam
+        g = sim.adjoint_grad(ws)
+        results.append(([t.cpu().numpy() for t in lam], g, ring.cpu().numpy()))
+        sim.close()
+    (la, ga, ra), (lb, gb, rb) = results
+    np.testing.assert_array_equal(ra, rb)
+    for x, y in zip(la, lb):
+        np.testing.assert_array_equal(x, y)
+    np.testing.assert_array_equal(ga, gb)
+
+
 def test_loss_gradient_f64_matches_oracle():
     """Checkpointed autograd gradient (GPU FP64) equals the oracle's."""
     import torch
