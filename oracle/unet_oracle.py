@@ -22,9 +22,15 @@ weights [4][Cout][Cin] (sub-pixel 2 m + n), MLP matrices [out][in].
 
 `bf16=True` rounds to BF16 where the GPU stores BF16 (network input,
 convolution and up-sampling weights, block outputs, pooled and conditioned
-latents, up-sampled maps); arithmetic stays FP64.  `Net(..., dtype=float32)`
-evaluates the same definitions in FP32; tests use the gap between the two
-to measure how strongly the BF16 roundings amplify accumulation error.
+latents, up-sampled maps); arithmetic stays FP64.  Its gradients pass those
+roundings unchanged and are rounded to BF16 where the GPU stores gradients
+in BF16 instead: the gradient of each block's convolution output (the
+normalisation's backward result, the convolution gradients' operand) and of
+each up-sampled map (the up-sampling gradients' operand); weight gradients
+and the other activation gradients stay unrounded, as the GPU keeps them in
+FP32.  `Net(..., dtype=float32)` evaluates the same definitions in FP32;
+tests use the gap between the two to measure how strongly the BF16
+roundings amplify accumulation error.
 """
 from __future__ import annotations
 
@@ -43,6 +49,31 @@ def _t(a, dtype=torch.float64):
 def round_bf16(u: torch.Tensor) -> torch.Tensor:
     """Nearest BF16 value (ties to even), in u's dtype."""
     return u.to(torch.float32).to(torch.bfloat16).to(u.dtype)
+
+
+class _RoundValue(torch.autograd.Function):
+    """BF16 rounding of a stored value; its gradient passes unchanged."""
+
+    @staticmethod
+    def forward(ctx, u):
+        return round_bf16(u)
+
+    @staticmethod
+    def backward(ctx, g):
+        return g
+
+
+class _RoundGrad(torch.autograd.Function):
+    """Identity on the value; its gradient rounded to BF16 (a gradient the
+    GPU stores in BF16)."""
+
+    @staticmethod
+    def forward(ctx, u):
+        return u.clone()
+
+    @staticmethod
+    def backward(ctx, g):
+        return round_bf16(g)
 
 
 def conv3x3(u: torch.Tensor, w: torch.Tensor) -> torch.Tensor:
@@ -117,9 +148,10 @@ class Net:
         self.eps = float(cfg.gn_eps)
         self.dtype = dtype
         self.p = {k: _t(v, dtype).clone().requires_grad_(requires_grad) for k, v in params.items()}
+        self.R = self.Rg = lambda u: u
 
     def block(self, u, name, G=None, act=True):
-        y = group_norm(conv3x3(u, self.W(name + ".w")), G or self.G, self.p[name + ".gamma"],
+        y = group_norm(self.Rg(conv3x3(u, self.W(name + ".w"))), G or self.G, self.p[name + ".gamma"],
                        self.p[name + ".beta"], self.eps)
         return gelu(y) if act else y
 
@@ -128,7 +160,8 @@ class Net:
 
     def forward(self, c, phi, rho, jump, bf16: bool = False):
         """Prediction (c', phi', rho') for states [n][H][W] and jumps [n]."""
-        self.R = round_bf16 if bf16 else (lambda u: u)
+        self.R = _RoundValue.apply if bf16 else (lambda u: u)
+        self.Rg = _RoundGrad.apply if bf16 else (lambda u: u)
         R = self.R
         c, phi, rho, jump = (_t(a, self.dtype) for a in (c, phi, rho, jump))
         n, H, W = c.shape
@@ -144,7 +177,7 @@ class Net:
                 h = down(R(z))
         a = R(self.block(zs[-1], "mid"))
         for l in range(self.L - 2, -1, -1):
-            d = R(up(a, self.W(f"up{l + 1}.w")))
+            d = self.Rg(R(up(a, self.W(f"up{l + 1}.w"))))
             a = R(self.block(torch.cat([zs[l], d], dim=1), f"dec{l}"))
         head = self.block(a, "head", G=self.Gh, act=False)
         dt = jump.view(n, 1, 1)
@@ -152,8 +185,8 @@ class Net:
 
     def loss_and_grads(self, state, jump, target, bf16: bool = False):
         """Loss of the prediction from `state` against `target` and its
-        gradient for every parameter (FP64; with bf16, the forward rounds as
-        described above and gradients pass the roundings unchanged)."""
+        gradient for every parameter (FP64; with bf16, values and gradients
+        are rounded as described above)."""
         for v in self.p.values():
             if v.grad is not None:
                 v.grad = None

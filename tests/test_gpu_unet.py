@@ -373,7 +373,23 @@ def test_time_basis_memo_follows_jump_and_parameters():
     net.close()
 
 
-@pytest.mark.parametrize("H,W,levels,base,groups,n", [(32, 32, 3, 8, 4, 2), (16, 24, 2, 16, 8, 3)])
+# Per configuration: (limit per tensor, limit for the first two encoder
+# levels' tensors).  The oracle rounds values and gradients to BF16 where the
+# library stores them, so what is left is FP32 against FP64 accumulation
+# turning into one-step BF16 differences.  Where the normalisation groups hold
+# 4 or more channels these stay at the 1e-7..1e-3 level in every deeper
+# tensor; with 2 channels per group (the first case) the normalisation
+# amplifies them in the forward pass already (its loss differs by ~2e-5
+# relative), hence 2e-2 there.  The first two levels' gradients are sums of
+# dy x where GN makes dy zero-mean per group and the inputs are smooth (the
+# first layer's hold a constant channel, the jump, and a nearly constant one,
+# c): the exact sums cancel and one-step differences in the BF16 dy do not,
+# so their limit is 8e-2.
+GRAD_LIMITS = {(32, 32, 3, 8, 4, 2): (2e-2, 8e-2), (32, 32, 3, 8, 2, 2): (1e-3, 8e-2),
+               (16, 24, 2, 16, 8, 3): (1e-3, 8e-2), (128, 128, 3, 32, 8, 2): (5e-3, 8e-2)}
+
+
+@pytest.mark.parametrize("H,W,levels,base,groups,n", list(GRAD_LIMITS))
 def test_network_gradients_match_oracle(H, W, levels, base, groups, n):
     import torch
 
@@ -395,12 +411,7 @@ def test_network_gradients_match_oracle(H, W, levels, base, groups, n):
     Lr, gr = uo.Net(cfg, p0).loss_and_grads(st, jump, tgt, bf16=True)
     print(f"loss {L:.8e} ref {Lr:.8e}", flush=True)
     assert L == pytest.approx(Lr, rel=1e-3)
-    # Limits: the GPU stores every activation gradient in BF16 (relative
-    # rounding 2^-9) and passes at most 2 levels + 2 of them before a weight
-    # gradient, so 2e-2 per tensor.  The first layer's weight gradient is a
-    # sum of dy x where GN makes dy zero-mean per group and the inputs hold a
-    # constant channel (the jump) and a nearly constant one (c): the exact sum
-    # cancels, the BF16 copy of dy does not, so its limit is 8e-2.
+    lim, lim01 = GRAD_LIMITS[(H, W, levels, base, groups, n)]
     num = den = 0.0
     errs = {}
     for name in gr:
@@ -409,7 +420,7 @@ def test_network_gradients_match_oracle(H, W, levels, base, groups, n):
         den += float(np.sum(gr[name] ** 2))
     print("grad rel L2: " + ", ".join(f"{k} {v:.1e}" for k, v in errs.items()), flush=True)
     for name, e in errs.items():
-        assert e < (8e-2 if name == "enc0.w" else 2e-2), f"{name}: grad rel L2 {e:.2e}"
+        assert e < (lim01 if name.startswith(("enc0.", "enc1.")) else lim), f"{name}: grad rel L2 {e:.2e}"
     assert (num / den) ** 0.5 < 1e-2
     net.close()
 
