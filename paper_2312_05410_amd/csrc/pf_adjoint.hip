@@ -7,7 +7,8 @@
 // atomics) in three passes over the grid:
 //   pass 0  forward potentials mu_c, mu_phi, M_c (the shared per-cell code of
 //           the stepper) and the mobility partials dM/dc, dM/dphi;
-//   pass A  cotangents of the intermediates at every cell:
+//   pass A  cotangents of the intermediates at every cell (formed in LDS
+//           by the launch that runs pass B, for its tile and a halo):
 //             mubar = sum_n (M + M_n)(w_c,n - w_c) / 2h^2   (CH operator on w_c)
 //             Mbar  = sum_n (mu_n - mu)(w_c - w_c,n) / 2h^2
 //             nubar = M_phi Lap w_phi,  Sbar = w_phi - w_rho;
@@ -36,16 +37,13 @@ struct AdjArgs {
     T* oc;             // lambda (out)
     T* op;
     T* orr;
-    // scratch [B][ny][nx]: forward intermediates and cotangents
+    // scratch [B][ny][nx]: the forward intermediates of pass 0 (the
+    // cotangents of pass A live in the LDS of the pass-B launch)
     T* mu;
     T* nu;
     T* M;
     T* dMc;
     T* dMp;
-    T* mbar;
-    T* nbar;
-    T* Mbar;
-    T* sig;            // Sbar rho
     double* gacc;      // [2][B][ny][nx] accumulated parameter gradients
     const Real* real;
     Coef<T> k;
@@ -117,15 +115,13 @@ __global__ __launch_bounds__(256) void adj_pass0(AdjArgs<T> a)
     a.dMp[g] = dmp;
 }
 
+// pass A at cell (i, j) of the realisation at offset o: the cotangents
+// mbar, nbar, Mbar and sig (= Sbar rho)
 template <typename T>
-__global__ __launch_bounds__(256) void adj_passA(AdjArgs<T> a)
+__device__ __forceinline__ void passA_cell(const AdjArgs<T>& a, size_t o, int i, int j, T& mbar, T& nbar, T& Mbar,
+                                           T& sig)
 {
-    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
-    const int b = blockIdx.z;
     const int nx = a.nx, ny = a.ny;
-    if (i >= nx || j >= ny) return;
-    const size_t o = (size_t)b * nx * ny;
     const T dt = a.k.dt;
     const int iE = wrapi(i + 1, nx), iW = wrapi(i - 1, nx);
     const int jN = nrow(j + 1, ny, a.pvd), jS = nrow(j - 1, ny, a.pvd);
@@ -143,22 +139,40 @@ __global__ __launch_bounds__(256) void adj_passA(AdjArgs<T> a)
         Mb += (ld(mu, ni[q], nj[q], nx) - m0) * (wc - wn);
         lapw += dt * ld(lp, ni[q], nj[q], nx) - wp;
     }
-    const size_t g = o + (size_t)j * nx + i;
-    a.mbar[g] = a.k.half_ih2 * mb;
-    a.Mbar[g] = a.k.half_ih2 * Mb;
-    a.nbar[g] = a.k.mphi_h2 * lapw;
-    a.sig[g] = (wp - wr) * ld(a.rho + o, i, j, nx);
+    mbar = a.k.half_ih2 * mb;
+    Mbar = a.k.half_ih2 * Mb;
+    nbar = a.k.mphi_h2 * lapw;
+    sig = (wp - wr) * ld(a.rho + o, i, j, nx);
 }
 
+__device__ __forceinline__ int modi(int i, int n) { return ((i % n) + n) % n; }
+
+// Passes A and B in one launch.  The block's 64 x 4 cells and a one-cell
+// halo of pass A's cotangents (the cells pass B reads around them, taken
+// through the forward's neighbour rule: wrap in x, mirror or wrap in y, so
+// each halo cell holds pass A of the cell pass B would read) are formed in
+// LDS, then pass B reads them from there: a launch and a round trip of the
+// cotangents through memory fewer per adjoint step; per cell the same
+// arithmetic as the two passes.
 template <typename T>
-__global__ __launch_bounds__(256) void adj_passB(AdjArgs<T> a)
+__global__ __launch_bounds__(256) void adj_passAB(AdjArgs<T> a)
 {
-    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
+    constexpr int TW = 64, TH = 4, HW = TW + 2, HH = TH + 2;
+    __shared__ T sm[4][HH][HW];   // mbar, nbar, Mbar, sig
+    const int x0 = blockIdx.x * TW, y0 = blockIdx.y * TH;
     const int b = blockIdx.z;
     const int nx = a.nx, ny = a.ny, pvd = a.pvd;
-    if (i >= nx || j >= ny) return;
     const size_t o = (size_t)b * nx * ny;
+    for (int e = threadIdx.x; e < HH * HW; e += 256) {
+        const int hj = e / HW, hi = e - hj * HW;
+        const int gi = modi(x0 - 1 + hi, nx);
+        const int gy = y0 - 1 + hj, gj = pvd ? min(max(gy, 0), ny - 1) : modi(gy, ny);
+        passA_cell(a, o, gi, gj, sm[0][hj][hi], sm[1][hj][hi], sm[2][hj][hi], sm[3][hj][hi]);
+    }
+    __syncthreads();
+    const int li = threadIdx.x & 63, lj = threadIdx.x >> 6;
+    const int i = x0 + li, j = y0 + lj;
+    if (i >= nx || j >= ny) return;
     const Coef<T>& k = a.k;
     const Real rl = a.real[b];
     const T vx2h = (T)rl.vx2h, vy2h = (T)rl.vy2h;
@@ -166,14 +180,12 @@ __global__ __launch_bounds__(256) void adj_passB(AdjArgs<T> a)
     const bool top = pvd && j == ny - 1, bottom = pvd && j == 0;
     const int jN = nrow(j + 1, ny, pvd), jS = nrow(j - 1, ny, pvd);
     const size_t g = o + (size_t)j * nx + i;
-    const T* mbar = a.mbar + o;
-    const T* nbar = a.nbar + o;
-    const T* sig = a.sig + o;
     const T* phi = a.phi + o;
     const T* rho = a.rho + o;
     const T* lr = a.lr + o;
     const T cc = a.c[g], pp = a.phi[g], rr = a.rho[g];
-    const T mb = a.mbar[g], nb = a.nbar[g], Mb = a.Mbar[g];
+    const int hi = li + 1, hj = lj + 1;   // this cell in the LDS halo tile
+    const T mb = sm[0][hj][hi], nb = sm[1][hj][hi], Mb = sm[2][hj][hi];
 
     // pointwise derivatives of mu_c = W_c p g' - ... and mu_phi = W_c p' g - W_phi phi (1-phi^2) - ...
     const T cg = cc * (T(1) - cc);
@@ -187,8 +199,8 @@ __global__ __launch_bounds__(256) void adj_passB(AdjArgs<T> a)
     T gc = mb * k.Wc * p0 * g2 + nb * k.Wc * p1 * g1;
     T gp = mb * k.Wc * p1 * g1 + nb * (k.Wc * p2 * g0 - k.Wphi * (T(1) - T(3) * pp * pp));
     // the Laplacians inside mu_c and mu_phi are symmetric (mirror rule)
-    const T mE = ld(mbar, iE, j, nx), mW = ld(mbar, iW, j, nx), mN = ld(mbar, i, jN, nx), mS = ld(mbar, i, jS, nx);
-    const T nE = ld(nbar, iE, j, nx), nW = ld(nbar, iW, j, nx), nN = ld(nbar, i, jN, nx), nS = ld(nbar, i, jS, nx);
+    const T mE = sm[0][hj][hi + 1], mW = sm[0][hj][hi - 1], mN = sm[0][hj + 1][hi], mS = sm[0][hj - 1][hi];
+    const T nE = sm[1][hj][hi + 1], nW = sm[1][hj][hi - 1], nN = sm[1][hj + 1][hi], nS = sm[1][hj - 1][hi];
     gc += k.kc * (T(4) * mb - ((mE + mW) + (mN + mS)));
     gp += k.kp * (T(4) * nb - ((nE + nW) + (nN + nS)));
     // mobility M_c (its host-scaled coefficients make dMc, dMp derivatives of M_c)
@@ -196,10 +208,10 @@ __global__ __launch_bounds__(256) void adj_passB(AdjArgs<T> a)
     gp += Mb * a.dMp[g];
     // deposition: sig = Sbar rho of every cell whose stencil reads phi here;
     // the mirror ghost row in y turns into an anti-mirrored sig
-    const T s0 = ld(sig, i, j, nx);
-    const T sE = ld(sig, iE, j, nx), sW = ld(sig, iW, j, nx);
-    const T sN = top ? -s0 : ld(sig, i, jN, nx);
-    const T sS = bottom ? -s0 : ld(sig, i, jS, nx);
+    const T s0 = sm[3][hj][hi];
+    const T sE = sm[3][hj][hi + 1], sW = sm[3][hj][hi - 1];
+    const T sN = top ? -s0 : sm[3][hj + 1][hi];
+    const T sS = bottom ? -s0 : sm[3][hj - 1][hi];
     gp += fmaT(vx2h, sW - sE, vy2h * (sS - sN));
     // rho: deposition, then the transposed transport stencil
     const T wp = k.dt * a.lp[g], wr = k.dt * a.lr[g];
@@ -259,8 +271,7 @@ hipError_t adjoint_launch(AdjArgs<T> a, hipStream_t s)
 {
     dim3 grid((a.nx + 63) / 64, (a.ny + 3) / 4, a.batch);
     hipLaunchKernelGGL(adj_pass0<T>, grid, dim3(256), 0, s, a);
-    hipLaunchKernelGGL(adj_passA<T>, grid, dim3(256), 0, s, a);
-    hipLaunchKernelGGL(adj_passB<T>, grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL(adj_passAB<T>, grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -287,10 +298,6 @@ hipError_t launch_adjoint(const AdjointIO<T>& io, const StepArgs<T>& st, double 
     a.M = w + 2 * n;
     a.dMc = w + 3 * n;
     a.dMp = w + 4 * n;
-    a.mbar = w + 5 * n;
-    a.nbar = w + 6 * n;
-    a.Mbar = w + 7 * n;
-    a.sig = w + 8 * n;
     a.gacc = io.gacc;
     a.real = st.real;
     a.k = st.k;

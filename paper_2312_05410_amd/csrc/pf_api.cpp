@@ -825,7 +825,7 @@ AdjLayout adj_layout(const pf_params* p)
         off += round_up(bytes);
         return o;
     };
-    L.scratch = take(9 * cells * esize(p));
+    L.scratch = take(5 * cells * esize(p));   // pass 0's intermediates
     L.gacc = take(2 * cells * sizeof(double));
     L.out = take(2 * (size_t)p->batch * sizeof(double));
     L.total = off;
