@@ -289,6 +289,19 @@ int pf_adjoint_step(pf_handle* h, const void* c, const void* phi, const void* rh
 int pf_adjoint_segment(pf_handle* h, void* ring, int64_t len, void* lam_c, void* lam_phi, void* lam_rho,
                        void* tmp_c, void* tmp_phi, void* tmp_rho, void* adj_workspace, size_t adj_bytes,
                        int32_t* in_tmp);
+/* The two halves of pf_adjoint_segment, for callers that overlap the
+ * recomputation of one segment with the adjoint steps of another (two
+ * handles of the same parameters on two streams, two rings, events between
+ * them).  pf_adjoint_recompute writes slots 1 .. len-1 of ring from slot 0
+ * by pf_step_out on h's stream.  pf_adjoint_sweep runs the adjoint steps
+ * t = len-1 .. 0 over a ring that holds the segment's states, with the
+ * lambda buffers and *in_tmp as in pf_adjoint_segment.  Same layouts,
+ * ownership and errors as pf_adjoint_segment; both are enqueued and return
+ * at once.  pf_adjoint_segment is the recompute followed by the sweep. */
+int pf_adjoint_recompute(pf_handle* h, void* ring, int64_t len);
+int pf_adjoint_sweep(pf_handle* h, void* ring, int64_t len, void* lam_c, void* lam_phi, void* lam_rho,
+                     void* tmp_c, void* tmp_phi, void* tmp_rho, void* adj_workspace, size_t adj_bytes,
+                     int32_t* in_tmp);
 /* Zero the parameter-gradient accumulators (enqueued). */
 int pf_adjoint_reset(pf_handle* h, void* adj_workspace, size_t adj_bytes);
 /* Wait for the stream and write out[2*b] = dL/dM_scale, out[2*b+1] = dL/dv0

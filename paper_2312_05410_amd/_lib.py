@@ -29,7 +29,8 @@ EXPORTS = (
     "pf_workspace_bytes", "pf_dt_limit", "pf_init", "pf_step_n", "pf_mass", "pf_energy",
     "pf_get_step", "pf_set_step", "pf_get_dt", "pf_get_inflow", "pf_set_inflow", "pf_step_out",
     "pf_destroy", "pf_strerror", "pf_last_hip_error", "pf_get_launch", "pf_get_lane_cols", "pf_get_fused_kernel",
-    "pf_adjoint_workspace_bytes", "pf_adjoint_step", "pf_adjoint_segment", "pf_adjoint_reset", "pf_adjoint_grad",
+    "pf_adjoint_workspace_bytes", "pf_adjoint_step", "pf_adjoint_segment", "pf_adjoint_recompute",
+    "pf_adjoint_sweep", "pf_adjoint_reset", "pf_adjoint_grad",
     "pf_diagnostics_noalloc", "pf_diagnostics_noalloc_limit",
 )
 
@@ -120,6 +121,11 @@ def load():
         L.pf_adjoint_segment.argtypes = [H, H, ctypes.c_int64] + [H] * 7 + [ctypes.c_size_t,
                                                                             ctypes.POINTER(ctypes.c_int32)]
         L.pf_adjoint_segment.restype = ctypes.c_int
+        L.pf_adjoint_recompute.argtypes = [H, H, ctypes.c_int64]
+        L.pf_adjoint_recompute.restype = ctypes.c_int
+        L.pf_adjoint_sweep.argtypes = [H, H, ctypes.c_int64] + [H] * 7 + [ctypes.c_size_t,
+                                                                          ctypes.POINTER(ctypes.c_int32)]
+        L.pf_adjoint_sweep.restype = ctypes.c_int
         L.pf_adjoint_reset.argtypes = [H, H, ctypes.c_size_t]
         L.pf_adjoint_reset.restype = ctypes.c_int
         L.pf_adjoint_grad.argtypes = [H, H, ctypes.c_size_t, dp]
@@ -349,11 +355,35 @@ class Simulator:
         """One checkpoint segment of the reverse sweep (pf_adjoint_segment):
         ring [>= length][3][...] holds the checkpoint in slot 0; returns True
         when the result is in `tmp` (odd length), else it is in `lam`."""
+        self._check_ring(ring, length)
         flag = ctypes.c_int32(0)
         args = [u.data_ptr() for u in (*lam, *tmp)]
         self._check(load().pf_adjoint_segment(self._h, ring.data_ptr(), int(length), *args, ws.data_ptr(), ws.numel(),
                                               ctypes.byref(flag)), "pf_adjoint_segment")
         return bool(flag.value)
+
+    def adjoint_recompute(self, ring, length: int) -> None:
+        """Slots 1 .. length-1 of `ring` stepped from slot 0 (pf_adjoint_recompute)."""
+        self._check_ring(ring, length)
+        self._check(load().pf_adjoint_recompute(self._h, ring.data_ptr(), int(length)), "pf_adjoint_recompute")
+
+    def adjoint_sweep(self, ring, length: int, lam, tmp, ws) -> bool:
+        """The adjoint steps over a recomputed ring (pf_adjoint_sweep); the
+        return value as for adjoint_segment."""
+        self._check_ring(ring, length)
+        flag = ctypes.c_int32(0)
+        args = [u.data_ptr() for u in (*lam, *tmp)]
+        self._check(load().pf_adjoint_sweep(self._h, ring.data_ptr(), int(length), *args, ws.data_ptr(), ws.numel(),
+                                            ctypes.byref(flag)), "pf_adjoint_sweep")
+        return bool(flag.value)
+
+    def _check_ring(self, ring, length: int) -> None:
+        want = (3, self.p.batch, self.p.ny, self.p.nx) if self.p.batch > 1 else (3, self.p.ny, self.p.nx)
+        esize = 8 if self.p.precision == "f64" else 4
+        if not ring.is_contiguous() or ring.element_size() != esize or ring.shape[0] < length or tuple(
+                ring.shape[1:]) not in (
+                want, (3, self.p.batch, self.p.ny, self.p.nx)):
+            raise PFError(PF_EINVAL, f"ring of shape {tuple(ring.shape)} for {length} states")
 
     def adjoint_grad(self, ws) -> np.ndarray:
         """[batch, 2] accumulated (dL/dM_scale, dL/dv0)."""

@@ -4,11 +4,11 @@
 // adjoint step produces lambda = lambda' + (dR/du)^T w with w = dt lambda',
 // and accumulates w . dR/dM_scale and w . dR/dv0 per cell in FP64.  The
 // transpose is taken as a gather (each thread owns one output cell, no
-// atomics) in three passes over the grid:
-//   pass 0  forward potentials mu_c, mu_phi, M_c (the shared per-cell code of
-//           the stepper) and the mobility partials dM/dc, dM/dphi;
-//   pass A  cotangents of the intermediates at every cell (formed in LDS
-//           by the launch that runs pass B, for its tile and a halo):
+// atomics) in three passes, all in one launch per step:
+//   pass 0  forward potentials mu_c and M_c (the shared per-cell code of the
+//           stepper), and at the output cell the mobility partials dM/dc,
+//           dM/dphi;
+//   pass A  cotangents of the intermediates:
 //             mubar = sum_n (M + M_n)(w_c,n - w_c) / 2h^2   (CH operator on w_c)
 //             Mbar  = sum_n (mu_n - mu)(w_c - w_c,n) / 2h^2
 //             nubar = M_phi Lap w_phi,  Sbar = w_phi - w_rho;
@@ -18,6 +18,8 @@
 //           ghost in y for Sbar rho) and the transposed vapour
 //           transport (inlet ghost is a constant; the substrate row keeps
 //           its own mirror coefficient).
+// A block forms pass 0 for its tile and two rings of cells around it and
+// pass A for the tile and one ring in LDS, then runs pass B on its tile.
 // The boundary rules are the transposes of the forward step's.
 #include "pf_cell.h"
 
@@ -37,13 +39,6 @@ struct AdjArgs {
     T* oc;             // lambda (out)
     T* op;
     T* orr;
-    // scratch [B][ny][nx]: the forward intermediates of pass 0 (the
-    // cotangents of pass A live in the LDS of the pass-B launch)
-    T* mu;
-    T* nu;
-    T* M;
-    T* dMc;
-    T* dMp;
     double* gacc;      // [2][B][ny][nx] accumulated parameter gradients
     const Real* real;
     Coef<T> k;
@@ -88,104 +83,98 @@ __device__ __forceinline__ void mobility_grad(const Coef<T>& k, T c, T p, T& dmc
     dmp = (p > T(-1) && p < T(1)) ? fmaT(dpb, bulk, de * surf) : T(0);
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void adj_pass0(AdjArgs<T> a)
-{
-    const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-    const int j = blockIdx.y * 4 + (threadIdx.x >> 6);
-    const int b = blockIdx.z;
-    const int nx = a.nx, ny = a.ny;
-    if (i >= nx || j >= ny) return;
-    const size_t o = (size_t)b * nx * ny;
-    const T* c = a.c + o;
-    const T* p = a.phi + o;
-    const int iE = wrapi(i + 1, nx), iW = wrapi(i - 1, nx);
-    const int jN = nrow(j + 1, ny, a.pvd), jS = nrow(j - 1, ny, a.pvd);
-    const T cc = ld(c, i, j, nx), pp = ld(p, i, j, nx);
-    T mu, nu, M;
-    potentials(a.k, cc, ld(c, iE, j, nx), ld(c, iW, j, nx), ld(c, i, jN, nx), ld(c, i, jS, nx),
-               pp, ld(p, iE, j, nx), ld(p, iW, j, nx), ld(p, i, jN, nx), ld(p, i, jS, nx), mu, nu, M);
-    T dmc, dmp;
-    mobility_grad(a.k, cc, pp, dmc, dmp);
-    const size_t g = o + (size_t)j * nx + i;
-    a.mu[g] = mu;
-    a.nu[g] = nu;
-    a.M[g] = M;
-    a.dMc[g] = dmc;
-    a.dMp[g] = dmp;
-}
-
-// pass A at cell (i, j) of the realisation at offset o: the cotangents
-// mbar, nbar, Mbar and sig (= Sbar rho)
-template <typename T>
-__device__ __forceinline__ void passA_cell(const AdjArgs<T>& a, size_t o, int i, int j, T& mbar, T& nbar, T& Mbar,
-                                           T& sig)
-{
-    const int nx = a.nx, ny = a.ny;
-    const T dt = a.k.dt;
-    const int iE = wrapi(i + 1, nx), iW = wrapi(i - 1, nx);
-    const int jN = nrow(j + 1, ny, a.pvd), jS = nrow(j - 1, ny, a.pvd);
-    const int ni[4] = {iE, iW, i, i}, nj[4] = {j, j, jN, jS};
-    const T* lc = a.lc + o;
-    const T* lp = a.lp + o;
-    const T* M = a.M + o;
-    const T* mu = a.mu + o;
-    const T wc = dt * ld(lc, i, j, nx), wp = dt * ld(lp, i, j, nx), wr = dt * ld(a.lr + o, i, j, nx);
-    const T M0 = ld(M, i, j, nx), m0 = ld(mu, i, j, nx);
-    T mb = 0, Mb = 0, lapw = 0;
-    for (int q = 0; q < 4; ++q) {
-        const T wn = dt * ld(lc, ni[q], nj[q], nx);
-        mb += (M0 + ld(M, ni[q], nj[q], nx)) * (wn - wc);
-        Mb += (ld(mu, ni[q], nj[q], nx) - m0) * (wc - wn);
-        lapw += dt * ld(lp, ni[q], nj[q], nx) - wp;
-    }
-    mbar = a.k.half_ih2 * mb;
-    Mbar = a.k.half_ih2 * Mb;
-    nbar = a.k.mphi_h2 * lapw;
-    sig = (wp - wr) * ld(a.rho + o, i, j, nx);
-}
-
 __device__ __forceinline__ int modi(int i, int n) { return ((i % n) + n) % n; }
 
-// Passes A and B in one launch.  The block's 64 x 4 cells and a one-cell
-// halo of pass A's cotangents (the cells pass B reads around them, taken
-// through the forward's neighbour rule: wrap in x, mirror or wrap in y, so
-// each halo cell holds pass A of the cell pass B would read) are formed in
-// LDS, then pass B reads them from there: a launch and a round trip of the
-// cotangents through memory fewer per adjoint step; per cell the same
-// arithmetic as the two passes.
+// One adjoint step for a block's 64 x 4 cells.  Pass 0's mu_c and M_c are
+// formed in LDS for the tile and two rings of cells around it, pass A's
+// cotangents for the tile and one ring, and pass B reads both there.  A ring
+// entry holds the value of the cell that the forward's neighbour rule reads
+// at that place (x wraps; y mirrors under PVD, else wraps); per cell the
+// arithmetic is that of three separate passes over the grid.
 template <typename T>
-__global__ __launch_bounds__(256) void adj_passAB(AdjArgs<T> a)
+__global__ __launch_bounds__(256) void adj_step(AdjArgs<T> a)
 {
-    constexpr int TW = 64, TH = 4, HW = TW + 2, HH = TH + 2;
-    __shared__ T sm[4][HH][HW];   // mbar, nbar, Mbar, sig
+    constexpr int TW = 64, TH = 4;
+    constexpr int AW = TW + 2, AH = TH + 2;   // pass A tile: one ring
+    constexpr int ZW = TW + 4, ZH = TH + 4;   // pass 0 tile: two rings
+    __shared__ T z[2][ZH][ZW];                // mu_c, M_c
+    __shared__ T sm[4][AH][AW];               // mbar, nbar, Mbar, sig
     const int x0 = blockIdx.x * TW, y0 = blockIdx.y * TH;
     const int b = blockIdx.z;
     const int nx = a.nx, ny = a.ny, pvd = a.pvd;
     const size_t o = (size_t)b * nx * ny;
-    for (int e = threadIdx.x; e < HH * HW; e += 256) {
-        const int hj = e / HW, hi = e - hj * HW;
-        const int gi = modi(x0 - 1 + hi, nx);
-        const int gy = y0 - 1 + hj, gj = pvd ? min(max(gy, 0), ny - 1) : modi(gy, ny);
-        passA_cell(a, o, gi, gj, sm[0][hj][hi], sm[1][hj][hi], sm[2][hj][hi], sm[3][hj][hi]);
+    const T* c = a.c + o;
+    const T* phi = a.phi + o;
+    const T* rho = a.rho + o;
+    const T* lc = a.lc + o;
+    const T* lp = a.lp + o;
+    const T* lr = a.lr + o;
+    const Coef<T>& k = a.k;
+    const T dt = k.dt;
+
+    // pass 0: entry (zj, zi) is the cell at column x0 - 2 + zi, row y0 - 2 + zj
+    for (int e = threadIdx.x; e < ZH * ZW; e += 256) {
+        const int zj = e / ZW, zi = e - zj * ZW;
+        const int i = modi(x0 - 2 + zi, nx);
+        const int gy = y0 - 2 + zj, j = pvd ? min(max(gy, 0), ny - 1) : modi(gy, ny);
+        const int iE = wrapi(i + 1, nx), iW = wrapi(i - 1, nx);
+        const int jN = nrow(j + 1, ny, pvd), jS = nrow(j - 1, ny, pvd);
+        T mu, nu, M;
+        potentials(k, ld(c, i, j, nx), ld(c, iE, j, nx), ld(c, iW, j, nx), ld(c, i, jN, nx), ld(c, i, jS, nx),
+                   ld(phi, i, j, nx), ld(phi, iE, j, nx), ld(phi, iW, j, nx), ld(phi, i, jN, nx),
+                   ld(phi, i, jS, nx), mu, nu, M);
+        z[0][zj][zi] = mu;
+        z[1][zj][zi] = M;
     }
     __syncthreads();
+
+    // pass A: entry (hj, hi) is the cell at column x0 - 1 + hi, row y0 - 1 + hj
+    for (int e = threadIdx.x; e < AH * AW; e += 256) {
+        const int hj = e / AW, hi = e - hj * AW;
+        const int i = modi(x0 - 1 + hi, nx);
+        const int gy = y0 - 1 + hj, j = pvd ? min(max(gy, 0), ny - 1) : modi(gy, ny);
+        const int iE = wrapi(i + 1, nx), iW = wrapi(i - 1, nx);
+        const int jN = nrow(j + 1, ny, pvd), jS = nrow(j - 1, ny, pvd);
+        // pass-0 rows of this cell and of its N and S neighbours: the tile's
+        // row offsets follow the wrap rule, at a mirrored edge the row is the
+        // neighbour's own; the columns follow the wrap rule in x
+        const int zc = pvd ? j - y0 + 2 : hj + 1;
+        const int zN = pvd ? jN - y0 + 2 : hj + 2;
+        const int zS = pvd ? jS - y0 + 2 : hj;
+        const int zr[4] = {zc, zc, zN, zS}, zq[4] = {hi + 2, hi, hi + 1, hi + 1};
+        const int ni[4] = {iE, iW, i, i}, nj[4] = {j, j, jN, jS};
+        const T wc = dt * ld(lc, i, j, nx), wp = dt * ld(lp, i, j, nx), wr = dt * ld(lr, i, j, nx);
+        const T M0 = z[1][zc][hi + 1], m0 = z[0][zc][hi + 1];
+        T mb = 0, Mb = 0, lapw = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const T wn = dt * ld(lc, ni[q], nj[q], nx);
+            mb += (M0 + z[1][zr[q]][zq[q]]) * (wn - wc);
+            Mb += (z[0][zr[q]][zq[q]] - m0) * (wc - wn);
+            lapw += dt * ld(lp, ni[q], nj[q], nx) - wp;
+        }
+        sm[0][hj][hi] = k.half_ih2 * mb;
+        sm[1][hj][hi] = k.mphi_h2 * lapw;
+        sm[2][hj][hi] = k.half_ih2 * Mb;
+        sm[3][hj][hi] = (wp - wr) * ld(rho, i, j, nx);
+    }
+    __syncthreads();
+
+    // pass B on the block's own cells
     const int li = threadIdx.x & 63, lj = threadIdx.x >> 6;
     const int i = x0 + li, j = y0 + lj;
     if (i >= nx || j >= ny) return;
-    const Coef<T>& k = a.k;
     const Real rl = a.real[b];
     const T vx2h = (T)rl.vx2h, vy2h = (T)rl.vy2h;
     const int iE = wrapi(i + 1, nx), iW = wrapi(i - 1, nx);
     const bool top = pvd && j == ny - 1, bottom = pvd && j == 0;
     const int jN = nrow(j + 1, ny, pvd), jS = nrow(j - 1, ny, pvd);
     const size_t g = o + (size_t)j * nx + i;
-    const T* phi = a.phi + o;
-    const T* rho = a.rho + o;
-    const T* lr = a.lr + o;
     const T cc = a.c[g], pp = a.phi[g], rr = a.rho[g];
-    const int hi = li + 1, hj = lj + 1;   // this cell in the LDS halo tile
+    const int hi = li + 1, hj = lj + 1;   // this cell in the pass A tile
     const T mb = sm[0][hj][hi], nb = sm[1][hj][hi], Mb = sm[2][hj][hi];
+    T dmc, dmp;
+    mobility_grad(k, cc, pp, dmc, dmp);
 
     // pointwise derivatives of mu_c = W_c p g' - ... and mu_phi = W_c p' g - W_phi phi (1-phi^2) - ...
     const T cg = cc * (T(1) - cc);
@@ -204,8 +193,8 @@ __global__ __launch_bounds__(256) void adj_passAB(AdjArgs<T> a)
     gc += k.kc * (T(4) * mb - ((mE + mW) + (mN + mS)));
     gp += k.kp * (T(4) * nb - ((nE + nW) + (nN + nS)));
     // mobility M_c (its host-scaled coefficients make dMc, dMp derivatives of M_c)
-    gc += Mb * a.dMc[g];
-    gp += Mb * a.dMp[g];
+    gc += Mb * dmc;
+    gp += Mb * dmp;
     // deposition: sig = Sbar rho of every cell whose stencil reads phi here;
     // the mirror ghost row in y turns into an anti-mirrored sig
     const T s0 = sm[3][hj][hi];
@@ -214,16 +203,16 @@ __global__ __launch_bounds__(256) void adj_passAB(AdjArgs<T> a)
     const T sS = bottom ? -s0 : sm[3][hj - 1][hi];
     gp += fmaT(vx2h, sW - sE, vy2h * (sS - sN));
     // rho: deposition, then the transposed transport stencil
-    const T wp = k.dt * a.lp[g], wr = k.dt * a.lr[g];
+    const T wp = dt * a.lp[g], wr = dt * a.lr[g];
     const T dphx = ld(phi, iE, j, nx) - ld(phi, iW, j, nx), dphy = ld(phi, i, jN, nx) - ld(phi, i, jS, nx);
     T gr = (wp - wr) * fmaT(vx2h, dphx, vy2h * dphy);
     const T D = k.D_h2;
-    gr += (D - vx2h) * (k.dt * ld(lr, iW, j, nx)) + (D + vx2h) * (k.dt * ld(lr, iE, j, nx));
+    gr += (D - vx2h) * (dt * ld(lr, iW, j, nx)) + (D + vx2h) * (dt * ld(lr, iE, j, nx));
     if (!pvd) {
-        gr += (D - vy2h) * (k.dt * ld(lr, i, jS, nx)) + (D + vy2h) * (k.dt * ld(lr, i, jN, nx));
+        gr += (D - vy2h) * (dt * ld(lr, i, jS, nx)) + (D + vy2h) * (dt * ld(lr, i, jN, nx));
     } else {
-        if (j > 0) gr += (D - vy2h) * (k.dt * ld(lr, i, j - 1, nx));       // north coefficient of the cell below
-        if (j < ny - 1) gr += (D + vy2h) * (k.dt * ld(lr, i, j + 1, nx));  // south coefficient of the cell above
+        if (j > 0) gr += (D - vy2h) * (dt * ld(lr, i, j - 1, nx));       // north coefficient of the cell below
+        if (j < ny - 1) gr += (D + vy2h) * (dt * ld(lr, i, j + 1, nx));  // south coefficient of the cell above
         if (bottom) gr += (D - vy2h) * wr;                               // own mirror ghost, no advective flux
     }
     gr += T(-4) * D * wr;
@@ -233,7 +222,7 @@ __global__ __launch_bounds__(256) void adj_passAB(AdjArgs<T> a)
     const T dTv = -(a.cosx * (ld(rho, iE, j, nx) - ld(rho, iW, j, nx)) + a.siny * (rN - rSa)) * a.inv2h;
     const T dSv = rr * (a.cosx * dphx + a.siny * dphy) * a.inv2h;
     const size_t cells = (size_t)a.batch * nx * ny;
-    a.gacc[g] += (double)Mb * (double)(a.M[g] * a.Mscale_inv);
+    a.gacc[g] += (double)Mb * (double)(z[1][lj + 2][li + 2] * a.Mscale_inv);
     a.gacc[cells + g] += (double)(wp - wr) * (double)dSv + (double)wr * (double)dTv;
     a.oc[g] = a.lc[g] + gc;
     a.op[g] = a.lp[g] + gp;
@@ -267,19 +256,8 @@ __global__ __launch_bounds__(256) void gsum_kernel(const double* gacc, double* o
 }
 
 template <typename T>
-hipError_t adjoint_launch(AdjArgs<T> a, hipStream_t s)
-{
-    dim3 grid((a.nx + 63) / 64, (a.ny + 3) / 4, a.batch);
-    hipLaunchKernelGGL(adj_pass0<T>, grid, dim3(256), 0, s, a);
-    hipLaunchKernelGGL(adj_passAB<T>, grid, dim3(256), 0, s, a);
-    return hipGetLastError();
-}
-
-}  // namespace
-
-template <typename T>
-hipError_t launch_adjoint(const AdjointIO<T>& io, const StepArgs<T>& st, double Mscale, double cos_th,
-                          double msin_th, double h, int batch, hipStream_t s)
+AdjArgs<T> adj_args(const AdjointIO<T>& io, const StepArgs<T>& st, double Mscale, double cos_th, double msin_th,
+                    double h, int batch)
 {
     AdjArgs<T> a{};
     a.c = io.c;
@@ -291,13 +269,6 @@ hipError_t launch_adjoint(const AdjointIO<T>& io, const StepArgs<T>& st, double 
     a.oc = io.oc;
     a.op = io.op;
     a.orr = io.orr;
-    const size_t n = (size_t)batch * st.nx * st.ny;
-    T* w = io.scratch;
-    a.mu = w;
-    a.nu = w + n;
-    a.M = w + 2 * n;
-    a.dMc = w + 3 * n;
-    a.dMp = w + 4 * n;
     a.gacc = io.gacc;
     a.real = st.real;
     a.k = st.k;
@@ -309,7 +280,21 @@ hipError_t launch_adjoint(const AdjointIO<T>& io, const StepArgs<T>& st, double 
     a.ny = st.ny;
     a.pvd = st.pvd;
     a.batch = batch;
-    return adjoint_launch<T>(a, s);
+    return a;
+}
+
+template <typename T>
+dim3 adj_grid(const AdjArgs<T>& a) { return dim3((a.nx + 63) / 64, (a.ny + 3) / 4, a.batch); }
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_adjoint(const AdjointIO<T>& io, const StepArgs<T>& st, double Mscale, double cos_th,
+                          double msin_th, double h, int batch, hipStream_t s)
+{
+    const AdjArgs<T> a = adj_args<T>(io, st, Mscale, cos_th, msin_th, h, batch);
+    hipLaunchKernelGGL(adj_step<T>, adj_grid(a), dim3(256), 0, s, a);
+    return hipGetLastError();
 }
 template hipError_t launch_adjoint<float>(const AdjointIO<float>&, const StepArgs<float>&, double, double, double,
                                           double, int, hipStream_t);

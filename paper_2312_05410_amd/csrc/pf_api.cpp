@@ -812,7 +812,7 @@ int pf_last_hip_error(const pf_handle* h) { return h ? h->last_hip : 0; }
 namespace {
 
 struct AdjLayout {
-    size_t scratch, gacc, out, total;
+    size_t gacc, out, total;
 };
 
 AdjLayout adj_layout(const pf_params* p)
@@ -825,7 +825,6 @@ AdjLayout adj_layout(const pf_params* p)
         off += round_up(bytes);
         return o;
     };
-    L.scratch = take(5 * cells * esize(p));   // pass 0's intermediates
     L.gacc = take(2 * cells * sizeof(double));
     L.out = take(2 * (size_t)p->batch * sizeof(double));
     L.total = off;
@@ -848,7 +847,6 @@ int adjoint_step_t(pf_handle* h, const void* c, const void* phi, const void* rho
     io.oc = (T*)oc;
     io.op = (T*)op;
     io.orr = (T*)orr;
-    io.scratch = (T*)(ws + L.scratch);
     io.gacc = (double*)(ws + L.gacc);
     const pfk::StepArgs<T> st = step_args<T>(h);
     const double th = p->theta_deg * (3.14159265358979323846 / 180.0);
@@ -903,31 +901,62 @@ int pf_adjoint_reset(pf_handle* h, void* adj_workspace, size_t adj_bytes)
     return hip_fail(h, pfk::launch_gacc_zero((double*)((char*)adj_workspace + L.gacc), 2 * cells, h->stream));
 }
 
-int pf_adjoint_segment(pf_handle* h, void* ring, int64_t len, void* lam_c, void* lam_phi, void* lam_rho,
-                       void* tmp_c, void* tmp_phi, void* tmp_rho, void* adj_workspace, size_t adj_bytes,
-                       int32_t* in_tmp)
+}  // extern "C"
+
+namespace {
+
+// slot t, field k of a ring [len][3][batch][ny][nx]
+void* ring_field(const pf_handle* h, void* ring, int64_t t, int k)
 {
-    if (!h || !ring || !in_tmp || len < 1 || !adj_ws_ok(h, adj_workspace, adj_bytes)) return PF_EINVAL;
     const size_t fb = (size_t)h->p.batch * h->p.nx * h->p.ny * (h->p.precision == PF_F64 ? 8 : 4);
-    char* const base = (char*)ring;
-    auto f = [&](int64_t t, int k) -> void* { return base + (size_t)(3 * t + k) * fb; };
-    // the segment's states, each slot stepped from the one before it
+    return (char*)ring + (size_t)(3 * t + k) * fb;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pf_adjoint_recompute(pf_handle* h, void* ring, int64_t len)
+{
+    if (!h || !ring || len < 1) return PF_EINVAL;
     for (int64_t t = 1; t < len; ++t) {
-        const int rc = pf_step_out(h, f(t - 1, 0), f(t - 1, 1), f(t - 1, 2), f(t, 0), f(t, 1), f(t, 2));
+        const int rc = pf_step_out(h, ring_field(h, ring, t - 1, 0), ring_field(h, ring, t - 1, 1),
+                                   ring_field(h, ring, t - 1, 2), ring_field(h, ring, t, 0),
+                                   ring_field(h, ring, t, 1), ring_field(h, ring, t, 2));
         if (rc != PF_OK) return rc;
     }
-    // then the adjoint steps from the last state to the first, the two
-    // lambda buffers taking turns as input and output
+    return PF_OK;
+}
+
+int pf_adjoint_sweep(pf_handle* h, void* ring, int64_t len, void* lam_c, void* lam_phi, void* lam_rho,
+                     void* tmp_c, void* tmp_phi, void* tmp_rho, void* adj_workspace, size_t adj_bytes,
+                     int32_t* in_tmp)
+{
+    if (!h || !ring || !in_tmp || len < 1 || !adj_ws_ok(h, adj_workspace, adj_bytes)) return PF_EINVAL;
+    // from the last state to the first, the two lambda buffers taking turns
+    // as input and output
     void* cur[3] = {lam_c, lam_phi, lam_rho};
     void* nxt[3] = {tmp_c, tmp_phi, tmp_rho};
     for (int64_t t = len - 1; t >= 0; --t) {
-        const int rc = pf_adjoint_step(h, f(t, 0), f(t, 1), f(t, 2), cur[0], cur[1], cur[2], nxt[0], nxt[1], nxt[2],
+        const int rc = pf_adjoint_step(h, ring_field(h, ring, t, 0), ring_field(h, ring, t, 1),
+                                       ring_field(h, ring, t, 2), cur[0], cur[1], cur[2], nxt[0], nxt[1], nxt[2],
                                        adj_workspace, adj_bytes);
         if (rc != PF_OK) return rc;
         std::swap(cur, nxt);
     }
     *in_tmp = (int32_t)(len & 1);
     return PF_OK;
+}
+
+int pf_adjoint_segment(pf_handle* h, void* ring, int64_t len, void* lam_c, void* lam_phi, void* lam_rho,
+                       void* tmp_c, void* tmp_phi, void* tmp_rho, void* adj_workspace, size_t adj_bytes,
+                       int32_t* in_tmp)
+{
+    if (!h || !ring || !in_tmp || len < 1 || !adj_ws_ok(h, adj_workspace, adj_bytes)) return PF_EINVAL;
+    const int rc = pf_adjoint_recompute(h, ring, len);
+    if (rc != PF_OK) return rc;
+    return pf_adjoint_sweep(h, ring, len, lam_c, lam_phi, lam_rho, tmp_c, tmp_phi, tmp_rho, adj_workspace,
+                            adj_bytes, in_tmp);
 }
 
 int pf_adjoint_grad(pf_handle* h, void* adj_workspace, size_t adj_bytes, double* out)

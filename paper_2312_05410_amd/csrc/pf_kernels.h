@@ -158,7 +158,7 @@ hipError_t launch_reduce(const T* c, const T* phi, const T* rho, const double* Q
 
 // Discrete adjoint of one step: lambda_out = lambda_in + (dR/du)^T dt lambda_in
 // at the state (c, phi, rho); per-cell FP64 parameter gradients accumulate in
-// gacc[2][B][ny][nx] (dM_scale, dv0).  scratch holds 9 [B][ny][nx] arrays.
+// gacc[2][B][ny][nx] (dM_scale, dv0); one launch, no other scratch memory.
 template <typename T>
 struct AdjointIO {
     const T* c;
@@ -170,7 +170,6 @@ struct AdjointIO {
     T* oc;
     T* op;
     T* orr;
-    T* scratch;
     double* gacc;
 };
 template <typename T>

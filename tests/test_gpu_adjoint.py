@@ -66,9 +66,10 @@ def test_adjoint_step_matches_oracle(prec, bc, theta, shape):
 
 @pytest.mark.parametrize("prec,length", [("f32", 7), ("f32", 8), ("f64", 5)])
 def test_adjoint_segment_equals_step_calls(prec, length):
-    """pf_adjoint_segment against the same recomputation and adjoint steps
-    issued one call at a time: bitwise equal lambda and accumulators, for an
-    odd and an even segment length (the result in either buffer)."""
+    """pf_adjoint_segment, and pf_adjoint_recompute followed by
+    pf_adjoint_sweep, against the same recomputation and adjoint steps
+    issued one call at a time: bitwise equal rings, lambda and accumulators,
+    for an odd and an even segment length (the result in either buffer)."""
     import torch
 
     from paper_2312_05410_amd._lib import Simulator
@@ -81,7 +82,7 @@ def test_adjoint_segment_equals_step_calls(prec, length):
     lam0 = uniform01(62, np.arange(3 * nx * ny)).reshape(3, ny, nx) - 0.5
     dtype = torch.float64 if prec == "f64" else torch.float32
     results = []
-    for native in (False, True):
+    for mode in ("steps", "segment", "halves"):
         ring = torch.empty((length, 3, 1, ny, nx), dtype=dtype, device="cuda")
         for f, u in enumerate((c, phi, rho)):
             ring[0, f].copy_(torch.as_tensor(u, dtype=dtype))
@@ -89,8 +90,12 @@ def test_adjoint_segment_equals_step_calls(prec, length):
         ws = sim.adjoint_workspace()
         lam = [torch.as_tensor(l[None], dtype=dtype, device="cuda").contiguous() for l in lam0]
         tmp = [torch.empty_like(t) for t in lam]
-        if native:
+        if mode == "segment":
             if sim.adjoint_segment(ring, length, lam, tmp, ws):
+                lam, tmp = tmp, lam
+        elif mode == "halves":
+            sim.adjoint_recompute(ring, length)
+            if sim.adjoint_sweep(ring, length, lam, tmp, ws):
                 lam, tmp = tmp, lam
         else:
             slot = lambda t: [ring[t, 0], ring[t, 1], ring[t, 2]]
@@ -102,11 +107,46 @@ def test_adjoint_segment_equals_step_calls(prec, length):
         g = sim.adjoint_grad(ws)
         results.append(([t.cpu().numpy() for t in lam], g, ring.cpu().numpy()))
         sim.close()
-    (la, ga, ra), (lb, gb, rb) = results
-    np.testing.assert_array_equal(ra, rb)
-    for x, y in zip(la, lb):
+    la, ga, ra = results[0]
+    for lb, gb, rb in results[1:]:
+        np.testing.assert_array_equal(ra, rb)
+        for x, y in zip(la, lb):
+            np.testing.assert_array_equal(x, y)
+        np.testing.assert_array_equal(ga, gb)
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_overlapped_sweep_equals_serial(prec):
+    """The reverse sweep with the next segment recomputed on a second stream
+    (two rings, events between the streams) against the serial sweep: bitwise
+    equal gradients in M_scale, v0 and the initial state, over 12 segments
+    with a ragged last one (233 steps, checkpoints every 20), so that each
+    ring is refilled while the other is swept."""
+    import torch
+
+    from paper_2312_05410_amd.adjoint import final_state, l2_mismatch
+
+    announce(f"overlapped reverse sweep {prec}")
+    p = PFParams(nx=96, ny=64, precision=prec, theta_deg=70.0, c_noise=0.05)
+    p = p.replace(dt=0.2 * oracle.dt_limit(p.replace(M_scale=1.1)))
+    c, phi, rho = initial_state(p)
+    n, every = 233, 20
+    dtype = torch.float64 if prec == "f64" else torch.float32
+    tgt = [torch.as_tensor(np.asarray(a)[None] * 0.9, dtype=dtype, device="cuda").contiguous()
+           for a in (c[0], phi[0], rho[0])]
+    out = []
+    for overlap in (False, True):
+        u0 = [torch.as_tensor(np.asarray(a)[None], dtype=dtype, device="cuda").contiguous().requires_grad_()
+              for a in (c[0], phi[0], rho[0])]
+        Ms = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
+        v0 = torch.tensor(p.v0, dtype=torch.float64, requires_grad=True)
+        L = l2_mismatch(final_state(Ms, v0, p, u0, n, every, overlap=overlap), tgt, p.h)
+        L.backward()
+        out.append([float(L.detach()), float(Ms.grad), float(v0.grad)] + [u.grad.cpu().numpy() for u in u0])
+    a, b = out
+    assert a[:3] == b[:3]
+    for x, y in zip(a[3:], b[3:]):
         np.testing.assert_array_equal(x, y)
-    np.testing.assert_array_equal(ga, gb)
 
 
 def test_loss_gradient_f64_matches_oracle():
