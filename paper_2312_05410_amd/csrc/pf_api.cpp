@@ -912,6 +912,22 @@ void* ring_field(const pf_handle* h, void* ring, int64_t t, int k)
     return (char*)ring + (size_t)(3 * t + k) * fb;
 }
 
+// two Euler steps out of place in one two-step march launch: q[0..2] the
+// input state, q[3..5] the state after one step, q[6..8] after two (no
+// inflow accumulation, as pf_step_out)
+template <typename T>
+int step_pair(pf_handle* h, void* const q[9])
+{
+    pfk::StepArgs<T> a = step_args<T>(h);
+    a.c = (const T*)q[0], a.phi = (const T*)q[1], a.rho = (const T*)q[2];
+    a.c_mid = (T*)q[3], a.phi_mid = (T*)q[4], a.rho_mid = (T*)q[5];
+    a.c_out = (T*)q[6], a.phi_out = (T*)q[7], a.rho_out = (T*)q[8];
+    a.Qcol = nullptr;
+    a.nsub = 2;
+    a.step = h->step;
+    return hip_fail(h, pfk::launch_march_k2<T>(a, h->k2_ty, h->p.batch, h->stream));
+}
+
 }  // namespace
 
 extern "C" {
@@ -919,11 +935,33 @@ extern "C" {
 int pf_adjoint_recompute(pf_handle* h, void* ring, int64_t len)
 {
     if (!h || !ring || len < 1) return PF_EINVAL;
-    for (int64_t t = 1; t < len; ++t) {
-        const int rc = pf_step_out(h, ring_field(h, ring, t - 1, 0), ring_field(h, ring, t - 1, 1),
-                                   ring_field(h, ring, t - 1, 2), ring_field(h, ring, t, 0),
-                                   ring_field(h, ring, t, 1), ring_field(h, ring, t, 2));
-        if (rc != PF_OK) return rc;
+    // where the handle steps with the two-step register march, one launch
+    // writes two slots (the intermediate state and the one after it; bitwise
+    // those of two single steps); otherwise, and for a last odd slot,
+    // pf_step_out's single-step launch
+    const bool pair = h->K == 2 && h->fused == PF_FUSED_MARCH && h->p.integrator == PF_EULER &&
+                      !(h->p.interface_noise > 0);
+    int64_t t = 1;
+    while (t < len) {
+        if (pair && t + 1 < len) {
+            void* q[9];
+            for (int k = 0; k < 3; ++k) {
+                q[k] = ring_field(h, ring, t - 1, k);
+                q[3 + k] = ring_field(h, ring, t, k);
+                q[6 + k] = ring_field(h, ring, t + 1, k);
+            }
+            for (void* x : q)
+                if (!aligned(x, 16)) return PF_EINVAL;
+            const int rc = h->p.precision == PF_F64 ? step_pair<double>(h, q) : step_pair<float>(h, q);
+            if (rc != PF_OK) return rc;
+            t += 2;
+        } else {
+            const int rc = pf_step_out(h, ring_field(h, ring, t - 1, 0), ring_field(h, ring, t - 1, 1),
+                                       ring_field(h, ring, t - 1, 2), ring_field(h, ring, t, 0),
+                                       ring_field(h, ring, t, 1), ring_field(h, ring, t, 2));
+            if (rc != PF_OK) return rc;
+            t += 1;
+        }
     }
     return PF_OK;
 }

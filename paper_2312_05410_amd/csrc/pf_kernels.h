@@ -56,6 +56,11 @@ struct StepArgs {
     int pvd;             // 1: substrate + inlet boundaries; 0: periodic in y
     int nsub;            // sub-steps in this launch (1..K of the kernel)
     int fast;            // set by the launcher: 16-byte vector loads are valid
+    // two-step march: the state after the first step is also stored here
+    // (null: not stored)
+    T* c_mid;
+    T* phi_mid;
+    T* rho_mid;
 };
 
 // Tile configuration of a stepper instantiation.

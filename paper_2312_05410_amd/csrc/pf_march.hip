@@ -373,10 +373,12 @@ __global__ __launch_bounds__(64) void march2_kernel(StepArgs<float> a)
 // the inlet value for rho at the top) before the second step reads them; the
 // chunk heights divide ny, so those rows sit at fixed chunk positions.  Each
 // cell is evaluated by the same per-cell functions in the same order as in
-// two single-step launches, so the result is bitwise identical.
+// two single-step launches, so the result is bitwise identical.  MID also
+// stores the intermediate state of the chunk's own rows (c_mid, phi_mid,
+// rho_mid): two consecutive states from one launch.
 constexpr int kStripOutK2 = 56;
 
-template <typename T, int TY, int D>
+template <typename T, int TY, int D, bool MID>
 __global__ __launch_bounds__(64) void march_k2_kernel(StepArgs<T> a)
 {
     constexpr int NR = TY + 8;
@@ -406,6 +408,10 @@ __global__ __launch_bounds__(64) void march_k2_kernel(StepArgs<T> a)
     const auto oc = plane_rsrc(a.c_out + (size_t)b * plane, plane);
     const auto op = plane_rsrc(a.phi_out + (size_t)b * plane, plane);
     const auto orr = plane_rsrc(a.rho_out + (size_t)b * plane, plane);
+    // intermediate-state outputs (MID only; otherwise unused)
+    [[maybe_unused]] const auto mc_out = plane_rsrc((MID ? a.c_mid : a.c_out) + (size_t)b * plane, plane);
+    [[maybe_unused]] const auto mp_out = plane_rsrc((MID ? a.phi_mid : a.phi_out) + (size_t)b * plane, plane);
+    [[maybe_unused]] const auto mr_out = plane_rsrc((MID ? a.rho_mid : a.rho_out) + (size_t)b * plane, plane);
     const int vo = gx * (int)sizeof(T);
     const int row_bytes = nx * (int)sizeof(T);
     const Coef<T> k = a.k;
@@ -471,6 +477,14 @@ __global__ __launch_bounds__(64) void march_k2_kernel(StepArgs<T> a)
                    west(r[t]), r[t + 1], r[t - 1], FE, west(FE), FN[t], FN[t - 1], mp[t], east(mp[t]), west(mp[t]),
                    mp[t + 1], mp[t - 1], c1[t], p1[t], r1[t]);
             if (t >= 4 && t < TY + 4) inflow(gj, r[t]);
+            if constexpr (MID) {
+                if (t >= 4 && t < TY + 4 && out_lane) {
+                    const int so = gj * row_bytes;
+                    Buf<T>::st(c1[t], mc_out, vo, so);
+                    Buf<T>::st(p1[t], mp_out, vo, so);
+                    Buf<T>::st(r1[t], mr_out, vo, so);
+                }
+            }
             // the boundary rule on u1: at the top the rows beyond the grid
             // mirror rows already computed; at the substrate rows 2 and 3
             // mirror rows 5 and 4, complete once row 5 is
@@ -591,7 +605,8 @@ template <typename T, int TY>
 hipError_t k2_node_or_launch(StepArgs<T> a, int batch, hipStream_t s, hipGraph_t g, hipGraphNode_t* node,
                              hipGraphNode_t dep)
 {
-    void* fn = (void*)march_k2_kernel<T, TY, lookahead<TY>()>;
+    void* fn = a.c_mid ? (void*)march_k2_kernel<T, TY, lookahead<TY>(), true>
+                       : (void*)march_k2_kernel<T, TY, lookahead<TY>(), false>;
     a.tiles_x = (a.nx + kStripOutK2 - 1) / kStripOutK2;
     a.tiles_y = a.ny / TY;
     void* args[] = {&a};
