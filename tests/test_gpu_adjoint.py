@@ -33,8 +33,11 @@ def announce(msg):
 
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("bc,theta,shape", [("pvd", 60.0, (100, 77)), ("pvd", 90.0, (64, 33)),
-                                            ("periodic", 40.0, (70, 36))])
+                                            ("periodic", 40.0, (70, 36)), ("pvd", 70.0, (512, 258)),
+                                            ("periodic", 50.0, (576, 230))])
 def test_adjoint_step_matches_oracle(prec, bc, theta, shape):
+    """One adjoint step against the oracle's, on small grids and on two
+    grids of over 500 tiles ragged in both directions."""
     import torch
 
     from paper_2312_05410_amd._lib import Simulator
@@ -69,10 +72,12 @@ def test_adjoint_segment_equals_step_calls(prec, length):
     """pf_adjoint_segment, and pf_adjoint_recompute followed by
     pf_adjoint_sweep, against the same recomputation and adjoint steps
     issued one call at a time: bitwise equal rings, lambda and accumulators,
-    for an odd and an even segment length (the result in either buffer)."""
+    for an odd and an even segment length (the result in either buffer).  In
+    FP32 the handle steps with the two-step march, so the recomputation
+    writes two slots per launch (and a last odd slot alone)."""
     import torch
 
-    from paper_2312_05410_amd._lib import Simulator
+    from paper_2312_05410_amd._lib import PF_FUSED_MARCH, Simulator
 
     nx, ny = 64, 40
     announce(f"adjoint segment {prec} length {length}")
@@ -87,6 +92,9 @@ def test_adjoint_segment_equals_step_calls(prec, length):
         for f, u in enumerate((c, phi, rho)):
             ring[0, f].copy_(torch.as_tensor(u, dtype=dtype))
         sim = Simulator(p, tensors=[ring[0, 0], ring[0, 1], ring[0, 2]])
+        if prec == "f32":
+            # the recomputation's two-slot launches (two-step march) are the ones compared
+            assert sim.fused_kernel == PF_FUSED_MARCH and sim.launch[0] == 2
         ws = sim.adjoint_workspace()
         lam = [torch.as_tensor(l[None], dtype=dtype, device="cuda").contiguous() for l in lam0]
         tmp = [torch.empty_like(t) for t in lam]
