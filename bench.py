@@ -119,7 +119,7 @@ def kernel_name(prec: str, K: int, rows: int, base: bool = False, noise: bool = 
     if fused == 3:                                # resident stepper: one launch per call
         return f"resident_kernel<{rows}, {'true' if mid else 'false'}, {'true' if noise else 'false'}>"
     if K == 2 and fused == 2:                     # two steps in the register strip march
-        return f"march_k2_kernel<{t}, {rows}, {rows + 1 if rows <= 8 else 4}>"
+        return f"march_k2_kernel<{t}, {rows}, {rows + 1 if rows <= 8 else 4}, false>"
     if K == 1:
         ahead = rows + 1 if rows <= 8 else 4      # load look-ahead rows of the strip-march kernel
         b = "true" if base else "false"           # second midpoint stage: update added to a base state
