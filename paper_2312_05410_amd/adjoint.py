@@ -100,17 +100,22 @@ class _FinalState(torch.autograd.Function):
                     ready[k] = torch.cuda.Event()
                     ready[k].record(side)
 
-            recompute(nseg - 1)
-            for sg in range(nseg - 1, -1, -1):
-                k = sg % 2
-                if sg > 0:
-                    recompute(sg - 1)
-                main.wait_event(ready[k])
-                if rec.adjoint_sweep(rings[k], lengths[sg], lam, nxt, ws):
-                    lam, nxt = nxt, lam
-                freed[k] = torch.cuda.Event()
-                freed[k].record(main)
-            side_rec.close()
+            try:
+                recompute(nseg - 1)
+                for sg in range(nseg - 1, -1, -1):
+                    k = sg % 2
+                    if sg > 0:
+                        recompute(sg - 1)
+                    main.wait_event(ready[k])
+                    if rec.adjoint_sweep(rings[k], lengths[sg], lam, nxt, ws):
+                        lam, nxt = nxt, lam
+                    freed[k] = torch.cuda.Event()
+                    freed[k].record(main)
+            finally:
+                # the side stream's last recomputation precedes the last
+                # sweep; on an error it may still be writing a ring
+                side.synchronize()
+                side_rec.close()
         g = rec.adjoint_grad(ws).sum(axis=0)
         rec.close()
         ctx.ckpts = None
