@@ -1307,13 +1307,22 @@ __global__ __launch_bounds__(256) void mse_part_kernel(const float* p0, const fl
     if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = sh[threadIdx.x][0];
 }
 
-// part[kLossBlocks][6] -> loss[0] = L, loss[1..3] = 2 / sum tgt^2 per field
-__global__ void mse_finish_kernel(const double* part, double* loss)
+// part[kLossBlocks][6] -> loss[0] = L, loss[1..3] = 2 / sum tgt^2 per field;
+// one thread per block partial, then a fixed LDS tree (deterministic)
+static_assert(kLossBlocks == 256, "one finishing thread per partial");
+__global__ __launch_bounds__(256) void mse_finish_kernel(const double* part, double* loss)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double s[6] = {0, 0, 0, 0, 0, 0};
-    for (int b = 0; b < kLossBlocks; ++b)
-        for (int q = 0; q < 6; ++q) s[q] += part[b * 6 + q];
+    __shared__ double sh[6][256];
+    for (int q = 0; q < 6; ++q) sh[q][threadIdx.x] = part[threadIdx.x * 6 + q];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w)
+            for (int q = 0; q < 6; ++q) sh[q][threadIdx.x] += sh[q][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x != 0) return;
+    double s[6];
+    for (int q = 0; q < 6; ++q) s[q] = sh[q][0];
     double L = 0.0;
     for (int f = 0; f < 3; ++f) {
         const double den = s[2 * f + 1] > 0.0 ? s[2 * f + 1] : 1.0;
@@ -1518,7 +1527,7 @@ hipError_t rel_mse(const float* pc, const float* pphi, const float* prho, const 
 {
     const size_t n = (size_t)N * P;
     hipLaunchKernelGGL(mse_part_kernel, dim3(kLossBlocks), dim3(256), 0, s, pc, pphi, prho, tc, tphi, trho, part, n);
-    hipLaunchKernelGGL(mse_finish_kernel, dim3(1), dim3(64), 0, s, part, loss);
+    hipLaunchKernelGGL(mse_finish_kernel, dim3(1), dim3(256), 0, s, part, loss);
     if (grad && n)
         hipLaunchKernelGGL(mse_grad_kernel, dim3(grid_for(n)), dim3(256), 0, s, pc, pphi, prho, tc, tphi, trho, loss,
                            jump, P, grad, n);

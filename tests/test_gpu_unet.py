@@ -468,6 +468,30 @@ def test_adam_matches_oracle():
     net.close()
 
 
+@pytest.mark.parametrize("H,W,n", [(32, 32, 2), (160, 128, 5)])
+def test_loss_is_the_relative_mse(H, W, n):
+    """The training loss (FP64 block partials and a fixed-order finish)
+    equals sum over the fields of sum (pred - true)^2 / sum true^2 written
+    out in FP64 on the host from the same FP32 prediction and truth, to
+    summation-order rounding."""
+    from paper_2312_05410_amd.unet import UNet
+
+    announce(f"loss {H}x{W} n{n}")
+    net = UNet(_cfg(H, W, 2, 16, 4, n), seed=12)
+    st = _state(61, n, H, W)
+    tgt = _state(71, n, H, W)
+    jump = np.array([1.0, 3.0, 2.0, 0.5, 1.5][:n], dtype=np.float32)
+    pred = net.forward(*(dev_f32(a) for a in st), dev_f32(jump))
+    L = net.backward(pred, [dev_f32(a) for a in tgt])
+    ref = 0.0
+    for p_, t_ in zip(pred, tgt):
+        pv = p_.double().cpu().numpy().ravel()
+        tv = np.asarray(t_, dtype=np.float32).astype(np.float64).ravel()
+        ref += float(np.sum((pv - tv) ** 2) / np.sum(tv ** 2))
+    assert L == pytest.approx(ref, rel=1e-12)
+    net.close()
+
+
 def test_training_reduces_loss():
     import torch
 
