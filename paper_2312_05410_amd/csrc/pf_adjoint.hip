@@ -85,16 +85,18 @@ __device__ __forceinline__ void mobility_grad(const Coef<T>& k, T c, T p, T& dmc
 
 __device__ __forceinline__ int modi(int i, int n) { return ((i % n) + n) % n; }
 
-// One adjoint step for a block's 64 x 4 cells.  Pass 0's mu_c and M_c are
+constexpr int kAdjRows = 8;   // tile rows of the adjoint step (one wave per row)
+
+// One adjoint step for a block's 64 x kAdjRows cells.  Pass 0's mu_c and M_c are
 // formed in LDS for the tile and two rings of cells around it, pass A's
 // cotangents for the tile and one ring, and pass B reads both there.  A ring
 // entry holds the value of the cell that the forward's neighbour rule reads
 // at that place (x wraps; y mirrors under PVD, else wraps); per cell the
 // arithmetic is that of three separate passes over the grid.
 template <typename T>
-__global__ __launch_bounds__(256) void adj_step(AdjArgs<T> a)
+__global__ __launch_bounds__(64 * kAdjRows) void adj_step(AdjArgs<T> a)
 {
-    constexpr int TW = 64, TH = 4;
+    constexpr int TW = 64, TH = kAdjRows, NT = 64 * kAdjRows;
     constexpr int AW = TW + 2, AH = TH + 2;   // pass A tile: one ring
     constexpr int ZW = TW + 4, ZH = TH + 4;   // pass 0 tile: two rings
     __shared__ T z[2][ZH][ZW];                // mu_c, M_c
@@ -113,7 +115,7 @@ __global__ __launch_bounds__(256) void adj_step(AdjArgs<T> a)
     const T dt = k.dt;
 
     // pass 0: entry (zj, zi) is the cell at column x0 - 2 + zi, row y0 - 2 + zj
-    for (int e = threadIdx.x; e < ZH * ZW; e += 256) {
+    for (int e = threadIdx.x; e < ZH * ZW; e += NT) {
         const int zj = e / ZW, zi = e - zj * ZW;
         const int i = modi(x0 - 2 + zi, nx);
         const int gy = y0 - 2 + zj, j = pvd ? min(max(gy, 0), ny - 1) : modi(gy, ny);
@@ -129,7 +131,7 @@ __global__ __launch_bounds__(256) void adj_step(AdjArgs<T> a)
     __syncthreads();
 
     // pass A: entry (hj, hi) is the cell at column x0 - 1 + hi, row y0 - 1 + hj
-    for (int e = threadIdx.x; e < AH * AW; e += 256) {
+    for (int e = threadIdx.x; e < AH * AW; e += NT) {
         const int hj = e / AW, hi = e - hj * AW;
         const int i = modi(x0 - 1 + hi, nx);
         const int gy = y0 - 1 + hj, j = pvd ? min(max(gy, 0), ny - 1) : modi(gy, ny);
@@ -284,7 +286,7 @@ AdjArgs<T> adj_args(const AdjointIO<T>& io, const StepArgs<T>& st, double Mscale
 }
 
 template <typename T>
-dim3 adj_grid(const AdjArgs<T>& a) { return dim3((a.nx + 63) / 64, (a.ny + 3) / 4, a.batch); }
+dim3 adj_grid(const AdjArgs<T>& a) { return dim3((a.nx + 63) / 64, (a.ny + kAdjRows - 1) / kAdjRows, a.batch); }
 
 }  // namespace
 
@@ -293,7 +295,7 @@ hipError_t launch_adjoint(const AdjointIO<T>& io, const StepArgs<T>& st, double 
                           double msin_th, double h, int batch, hipStream_t s)
 {
     const AdjArgs<T> a = adj_args<T>(io, st, Mscale, cos_th, msin_th, h, batch);
-    hipLaunchKernelGGL(adj_step<T>, adj_grid(a), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(adj_step<T>, adj_grid(a), dim3(64 * kAdjRows), 0, s, a);
     return hipGetLastError();
 }
 template hipError_t launch_adjoint<float>(const AdjointIO<float>&, const StepArgs<float>&, double, double, double,
