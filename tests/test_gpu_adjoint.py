@@ -37,7 +37,7 @@ def announce(msg):
                                             ("periodic", 50.0, (576, 230))])
 def test_adjoint_step_matches_oracle(prec, bc, theta, shape):
     """One adjoint step against the oracle's, on small grids and on two
-    grids of over 500 tiles ragged in both directions."""
+    larger grids (over 250 tiles) ragged in both directions."""
     import torch
 
     from paper_2312_05410_amd._lib import Simulator
