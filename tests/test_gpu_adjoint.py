@@ -164,29 +164,29 @@ def test_adjoint_segment_equals_step_calls(prec, length):
         np.testing.assert_array_equal(ga, gb)
 
 
-@pytest.mark.parametrize("prec", ["f32", "f64"])
-def test_overlapped_sweep_equals_serial(prec):
+@pytest.mark.parametrize("prec,batch", [("f32", 1), ("f64", 1), ("f32", 2)])
+def test_overlapped_sweep_equals_serial(prec, batch):
     """The reverse sweep with the next segment recomputed on a second stream
     (two rings, events between the streams) against the serial sweep: bitwise
     equal gradients in M_scale, v0 and the initial state, over 12 segments
     with a ragged last one (233 steps, checkpoints every 20), so that each
-    ring is refilled while the other is swept."""
+    ring is refilled while the other is swept; also with two realisations
+    (rings of [len][3][2][ny][nx])."""
     import torch
 
     from paper_2312_05410_amd.adjoint import final_state, l2_mismatch
 
-    announce(f"overlapped reverse sweep {prec}")
-    p = PFParams(nx=96, ny=64, precision=prec, theta_deg=70.0, c_noise=0.05)
+    announce(f"overlapped reverse sweep {prec} batch {batch}")
+    p = PFParams(nx=96, ny=64, batch=batch, precision=prec, theta_deg=70.0, c_noise=0.05)
     p = p.replace(dt=0.2 * oracle.dt_limit(p.replace(M_scale=1.1)))
     c, phi, rho = initial_state(p)
     n, every = 233, 20
     dtype = torch.float64 if prec == "f64" else torch.float32
-    tgt = [torch.as_tensor(np.asarray(a)[None] * 0.9, dtype=dtype, device="cuda").contiguous()
-           for a in (c[0], phi[0], rho[0])]
+    tgt = [torch.as_tensor(np.asarray(a) * 0.9, dtype=dtype, device="cuda").contiguous() for a in (c, phi, rho)]
     out = []
     for overlap in (False, True):
-        u0 = [torch.as_tensor(np.asarray(a)[None], dtype=dtype, device="cuda").contiguous().requires_grad_()
-              for a in (c[0], phi[0], rho[0])]
+        u0 = [torch.as_tensor(np.asarray(a), dtype=dtype, device="cuda").contiguous().requires_grad_()
+              for a in (c, phi, rho)]
         Ms = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
         v0 = torch.tensor(p.v0, dtype=torch.float64, requires_grad=True)
         L = l2_mismatch(final_state(Ms, v0, p, u0, n, every, overlap=overlap), tgt, p.h)
